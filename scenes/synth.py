@@ -1,0 +1,216 @@
+"""Synthetic street-like scenes and depth maps (inputs only).
+
+Scenes are unions of axis-aligned boxes (a thin box stands in for a plane).
+A camera looks along +z of its own frame (x right, y down, z forward); a
+pixel (x, y) has its centre at integer coordinates, so its ray in the camera
+frame is r = ((x - cx)/fx, (y - cy)/fy, 1) and the depth of a hit is the
+camera-frame z of the hit point, i.e. the ray parameter.
+
+Noise follows a stereo camera: the true depth Z is turned into a disparity
+fx*B/Z, Gaussian noise of sigma pixels is added, and the noisy disparity is
+turned back into depth.  Pixels with no hit, a non-positive noisy disparity,
+a depth beyond max_depth, or drawn invalid at the given rate are 0.
+
+The paper evaluates on KITTI-VO (Section V); that dataset is not available,
+so these seeded scenes stand in for it with the same kind of geometry
+(forward-facing car camera, road plane, facades, parked cars).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Camera:
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+
+
+@dataclass
+class Frames:
+    """A sequence of depth maps with their camera->world poses."""
+    camera: Camera
+    depths: list            # list of float32 [H][W]
+    poses: list             # list of float64 [4][4], camera -> world
+    voxel_size: float
+    mu: float
+    max_depth: float
+    meta: dict = field(default_factory=dict)
+
+
+def pose_translation(tx: float, ty: float, tz: float) -> np.ndarray:
+    T = np.eye(4)
+    T[:3, 3] = (tx, ty, tz)
+    return T
+
+
+def pose_yaw(yaw: float, tx: float, ty: float, tz: float, pitch: float = 0.0) -> np.ndarray:
+    """Camera->world pose rotated by `yaw` about the camera y axis and
+    `pitch` about its x axis (radians), then translated."""
+    cy, sy = np.cos(yaw), np.sin(yaw)
+    cp, sp = np.cos(pitch), np.sin(pitch)
+    Ry = np.array([[cy, 0.0, sy], [0.0, 1.0, 0.0], [-sy, 0.0, cy]])
+    Rx = np.array([[1.0, 0.0, 0.0], [0.0, cp, -sp], [0.0, sp, cp]])
+    T = np.eye(4)
+    T[:3, :3] = Ry @ Rx
+    T[:3, 3] = (tx, ty, tz)
+    return T
+
+
+def _rays_world(cam: Camera, pose: np.ndarray):
+    xs = (np.arange(cam.width, dtype=np.float64) - cam.cx) / cam.fx
+    ys = (np.arange(cam.height, dtype=np.float64) - cam.cy) / cam.fy
+    rx, ry = np.meshgrid(xs, ys)                      # [H][W]
+    r = np.stack([rx, ry, np.ones_like(rx)], axis=-1)  # camera frame, z = 1
+    d = r @ pose[:3, :3].T                             # world direction
+    return pose[:3, 3].copy(), d
+
+
+def true_depth(boxes: np.ndarray, cam: Camera, pose: np.ndarray) -> np.ndarray:
+    """Nearest positive hit parameter of each pixel ray against the boxes
+    (float64 [H][W], +inf where nothing is hit).  boxes: [n][2][3] (lo, hi)."""
+    o, d = _rays_world(cam, pose)
+    best = np.full(d.shape[:2], np.inf)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / d
+        for lo, hi in boxes:
+            t0 = (lo - o) * inv
+            t1 = (hi - o) * inv
+            tn = np.nanmax(np.minimum(t0, t1), axis=-1)
+            tf = np.nanmin(np.maximum(t0, t1), axis=-1)
+            hit = (tn <= tf) & (tn > 1e-6)
+            best = np.where(hit & (tn < best), tn, best)
+    return best
+
+
+def render_depth(boxes, cam: Camera, pose, rng: np.random.Generator,
+                 sigma_px: float, baseline: float, max_depth: float,
+                 invalid_frac: float = 0.0) -> np.ndarray:
+    Z = true_depth(boxes, cam, pose)
+    hit = np.isfinite(Z)
+    disp = np.where(hit, cam.fx * baseline / np.where(hit, Z, 1.0), 0.0)
+    noisy = disp + rng.normal(0.0, sigma_px, size=disp.shape) if sigma_px > 0 else disp
+    with np.errstate(divide="ignore"):
+        Zn = np.where(noisy > 0, cam.fx * baseline / np.where(noisy > 0, noisy, 1.0), 0.0)
+    ok = hit & (noisy > 0) & (Zn <= max_depth) & (Zn > 0)
+    if invalid_frac > 0:
+        ok &= rng.random(size=Zn.shape) >= invalid_frac
+    return np.where(ok, Zn, 0.0).astype(np.float32)
+
+
+def _box(lo, hi):
+    return np.array([lo, hi], dtype=np.float64)
+
+
+# ---------------------------------------------------------------- config 1
+def scene_c1() -> np.ndarray:
+    """Ground plane, two walls and three boxes (the small parity scene)."""
+    b = [
+        _box((-6.0, 1.2, -2.0), (6.0, 1.4, 24.0)),     # ground, y down => below camera
+        _box((-4.2, -2.0, -2.0), (-4.0, 1.2, 24.0)),   # left wall x = -4
+        _box((4.0, -2.0, -2.0), (4.2, 1.2, 24.0)),     # right wall x = +4
+        _box((-2.1, 0.2, 7.4), (-0.9, 1.2, 8.6)),      # box A, centre (-1.5, 0.7, 8)
+        _box((1.3, -0.3, 10.5), (2.3, 1.2, 11.5)),     # box B, centre (1.8, 0.45, 11)
+        _box((-0.8, 0.0, 14.2), (0.8, 1.2, 15.8)),     # box C, centre (0, 0.6, 15)
+    ]
+    return np.stack(b)
+
+
+C1_CAMERA = Camera(300.0, 300.0, 159.5, 47.5, 320, 96)
+
+
+def frames_c1(seed: int = 0, n_frames: int = 4, sigma_px: float = 0.3) -> Frames:
+    """Config 1: 4 depth maps of 320x96 along a 2 m straight path."""
+    boxes = scene_c1()
+    cam = C1_CAMERA
+    depths, poses = [], []
+    for k in range(n_frames):
+        T = pose_translation(0.0, 0.0, 2.0 * k / max(1, n_frames - 1))
+        rng = np.random.default_rng(np.random.SeedSequence([1, seed, k]))
+        depths.append(render_depth(boxes, cam, T, rng, sigma_px, 0.54, 20.0))
+        poses.append(T)
+    return Frames(cam, depths, poses, voxel_size=0.1, mu=0.3, max_depth=20.0,
+                  meta={"config": "c1", "seed": seed})
+
+
+# ------------------------------------------------------------ street scenes
+def scene_street(length: float, seed: int, config_id: int = 2) -> np.ndarray:
+    """Procedural street along +z: road plane, facades with a seeded setback
+    per 10 m segment, parked-car boxes with seeded gaps, and an end wall."""
+    rng = np.random.default_rng(np.random.SeedSequence([config_id, seed, 1_000_003]))
+    b = [_box((-25.0, 1.65, -10.0), (25.0, 1.85, length + 15.0))]          # road
+    nseg = int(np.ceil((length + 10.0) / 10.0))
+    for j in range(nseg):
+        z0, z1 = 10.0 * j - 5.0, 10.0 * j + 5.0
+        for side in (-1.0, 1.0):
+            X = 7.0 + rng.uniform(0.0, 1.5)
+            h = rng.uniform(8.0, 16.0)
+            lo = (side * X, -h, z0) if side > 0 else (-X - 1.0, -h, z0)
+            hi = (side * X + 1.0, 1.65, z1) if side > 0 else (-X, 1.65, z1)
+            b.append(_box(lo, hi))
+    for side in (-1.0, 1.0):
+        z = -3.0 + rng.uniform(0.0, 4.0)
+        while z < length + 5.0:
+            cx = side * 5.5
+            b.append(_box((cx - 0.9, 0.15, z), (cx + 0.9, 1.65, z + 4.2)))
+            z += 4.2 + rng.uniform(1.0, 6.0)
+    b.append(_box((-20.0, -20.0, length + 10.0), (20.0, 1.65, length + 11.0)))  # end wall
+    return np.stack(b)
+
+
+C2_CAMERA = Camera(700.0, 700.0, 620.5, 187.0, 1242, 375)
+
+
+def frames_street(length: float = 100.0, n_frames: int = 100, seed: int = 0,
+                  config_id: int = 2, camera: Camera = C2_CAMERA,
+                  sigma_px: float = 0.5, invalid_frac: float = 0.05,
+                  voxel_size: float = 0.2, mu: float = 0.6,
+                  max_depth: float = 50.0) -> Frames:
+    boxes = scene_street(length, seed, config_id)
+    depths, poses = [], []
+    step = length / max(1, n_frames)
+    for k in range(n_frames):
+        T = pose_translation(0.0, 0.0, k * step)
+        rng = np.random.default_rng(np.random.SeedSequence([config_id, seed, k]))
+        depths.append(render_depth(boxes, camera, T, rng, sigma_px, 0.54,
+                                   max_depth, invalid_frac))
+        poses.append(T)
+    return Frames(camera, depths, poses, voxel_size, mu, max_depth,
+                  meta={"config": f"street{config_id}", "seed": seed,
+                        "length_m": length})
+
+
+def frames_c2(seed: int = 0, n_frames: int = 100) -> Frames:
+    """Config 2: 100 depth maps of 1242x375 along a 100 m street."""
+    return frames_street(100.0, n_frames, seed, config_id=2)
+
+
+# ------------------------------------------------------ direct block fields
+def random_block_field(n_blocks: int, seed: int, extent: int = 6,
+                       omega_frac: float = 0.8, max_w: int = 4):
+    """A random set of distinct block keys inside a cube of `extent` blocks
+    per axis, with random fused values f in [-1, 1] and integer weights
+    w in {0..max_w} (w == 0 marks unobserved voxels).  Used to exercise the
+    operators on arbitrary sparsity patterns without running fusion."""
+    rng = np.random.default_rng(np.random.SeedSequence([7, seed, n_blocks]))
+    cells = rng.choice(extent ** 3, size=n_blocks, replace=False)
+    coords = np.stack([cells % extent, (cells // extent) % extent,
+                       cells // (extent * extent)], axis=1).astype(np.int32)
+    coords -= extent // 2
+    f = rng.uniform(-1.0, 1.0, size=(n_blocks, 512))
+    w = rng.integers(1, max_w + 1, size=(n_blocks, 512)).astype(np.float64)
+    w[rng.random(size=w.shape) >= omega_frac] = 0.0
+    f[w == 0] = 0.0
+    return coords, f, w
+
+
+def c4_block_counts(n: int = 64, seed: int = 0, lo: float = 1e3, hi: float = 5e4):
+    """Sub-map sizes for the batched workload: log-uniform in [lo, hi]."""
+    rng = np.random.default_rng(np.random.SeedSequence([4, seed]))
+    return np.round(np.exp(rng.uniform(np.log(lo), np.log(hi), size=n))).astype(np.int64)
