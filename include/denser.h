@@ -1,0 +1,252 @@
+/*
+ * denser.h -- C ABI of the MI355X (gfx950) library for sparse TSDF fusion
+ * into hashed 8^3 voxel blocks and the Omega-masked TV primal-dual
+ * regulariser of "DENSER Cities: A System for Dense Efficient
+ * Reconstructions of Cities" (Tanner, Pinies, Paz, Newman).
+ *
+ * Conventions shared by every call
+ *  - Plain C types only.  "dev" pointers are HIP device memory owned by the
+ *    caller; "host" pointers are ordinary host memory.  The library never
+ *    keeps a caller pointer after the call returns, except that device
+ *    inputs must stay valid until the volume's stream has reached the call.
+ *  - All device work is ordered on the HIP stream given to dn_volume_create
+ *    (or dn_set_stream).  Calls that must return a count or a status to the
+ *    host synchronise that stream before returning; the others only enqueue.
+ *  - The library allocates the volume's own device storage at creation
+ *    (sized by max_blocks) and grows internal scratch on demand; it frees
+ *    everything in dn_volume_destroy.
+ *  - Return value: DN_OK (0) or a negative DN_E_* code; dn_last_error()
+ *    gives a thread-local message for the last failure.  A failed call
+ *    leaves the volume unchanged unless its comment says otherwise.
+ *  - A voxel's linear index inside its block is x + 8 y + 64 z.  Per-voxel
+ *    fields are block-major: field[block][512].  The dual field p is three
+ *    planes: p[3][n_blocks][512].
+ *  - Camera frame: x right, y down, z forward; pixel (x, y) has its centre
+ *    at integer coordinates.  A pose T_gc is a row-major 4x4 float64 host
+ *    array mapping camera coordinates to world (global) coordinates.
+ */
+#ifndef DENSER_H
+#define DENSER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ----------------------------------------------------------- status codes */
+#define DN_OK 0
+#define DN_E_INVALID (-1)   /* bad argument (null pointer, size, parameter)   */
+#define DN_E_CAPACITY (-2)  /* block pool, hash table or output too small     */
+#define DN_E_NUMERIC (-3)   /* non-finite energy or gap                       */
+#define DN_E_DEVICE (-4)    /* HIP runtime error                              */
+
+/* ------------------------------------------------- storage of u, ubar, p */
+#define DN_F32 0          /* 32-bit float state                                */
+#define DN_F16 1          /* IEEE half state, FP32 arithmetic                  */
+#define DN_BF16 2         /* bfloat16 state, FP32 arithmetic                   */
+#define DN_STORE_OFFSET 16 /* flag: u and ubar are stored as (u - f) in 16 bits */
+
+/* --------------------------------------------------- initial solver state */
+#define DN_INIT_ZERO 0   /* u = ubar = p = 0 (Section III-C, step 1)          */
+#define DN_INIT_KEEP 1   /* continue from the state the last call left        */
+#define DN_INIT_GIVEN 2  /* u = ubar = u0_dev, p = p0_dev (p0 may be NULL: 0)  */
+
+/* ------------------------------------------------------- kernel choices */
+#define DN_K_AUTO 0      /* pick the measured-best variant (autotuned)        */
+#define DN_K_TWOPASS 1   /* dual kernel then primal kernel, per iteration     */
+#define DN_K_FUSED 2     /* one LDS-staged kernel per iteration               */
+
+/* ----------------------------------------------------- dn_extract targets */
+#define DN_X_COORDS 1     /* int32 [n_blocks][3] block keys, pool order        */
+#define DN_X_HASH 2       /* int32 [cap + tail][4] slots {x, y, z, id}, id<0 empty */
+#define DN_X_NBR 3        /* int32 [n_blocks][27] 3x3x3 neighbourhood ids       */
+#define DN_X_F 4          /* float [n_blocks][512] fused TSDF f                */
+#define DN_X_W 5          /* float [n_blocks][512] fusion weight w             */
+#define DN_X_U 6          /* float [n_blocks][512] primal u (as float)         */
+#define DN_X_UBAR 7       /* float [n_blocks][512] relaxed primal ubar          */
+#define DN_X_P 8          /* float [3][n_blocks][512] dual p                   */
+#define DN_X_SURFACE 9    /* float [n][3] zero crossings of u (world metres)   */
+#define DN_X_CANDIDATES 10 /* int32 [n][3] distinct block keys the last
+                              dn_alloc_blocks frame touched, ascending          */
+#define DN_X_EMASK 11     /* uint8 [n_blocks][512] bit0 Omega, bit1+a m_a     */
+
+typedef struct dn_volume dn_volume;
+
+typedef struct {
+    double fx, fy, cx, cy;   /* pinhole intrinsics, pixels */
+    int32_t width, height;   /* depth map size; the map is float32 row-major */
+} dn_intrinsics;
+
+typedef struct {
+    double voxel_size;       /* s, metres (edge of a voxel)                  */
+    double mu;               /* truncation distance, metres                  */
+    double max_depth;        /* depths above this are treated as invalid     */
+    int32_t max_blocks;      /* capacity of the block pool                   */
+    int32_t hash_cap_log2;   /* the table has 2^hash_cap_log2 buckets ...    */
+    int32_t hash_tail;       /* ... plus this many overflow slots            */
+} dn_volume_params;
+
+typedef struct {
+    double lambda;           /* data weight (Eq. 2)                          */
+    double tau, sigma;       /* primal and dual step sizes (Eqs. 7-8)        */
+    double theta;            /* relaxation (Eq. 9), 1 for the standard method */
+    int32_t iters;           /* maximum number of iterations                 */
+    int32_t gap_every;       /* compute the gap every this many iterations; 0: only at the end */
+    double gap_tol;          /* stop once (E - D) / E <= gap_tol (0: never)  */
+    int32_t storage;         /* DN_F32, DN_F16 or DN_BF16 (| DN_STORE_OFFSET) */
+    int32_t refine_every;    /* 16-bit storage: FP32 sweep every this many iterations (0: none) */
+    int32_t init;            /* DN_INIT_*                                    */
+    int32_t kernel;          /* DN_K_*                                       */
+} dn_reg_params;
+
+typedef struct {
+    double energy;           /* E(u), Eq. (2) with the weight of Eq. (8)      */
+    double dual;             /* D(p), Eq. (6)                                 */
+    double gap;              /* E - D  (>= 0 by weak duality)                 */
+    double rel_gap;          /* (E - D) / E                                   */
+    int32_t iters_run;       /* iterations performed by this call             */
+    int32_t converged;       /* 1 if gap_tol was reached                      */
+} dn_reg_stats;
+
+/* ------------------------------------------------------------ lifecycle */
+
+/* Create an empty volume.  hash_cap_log2 in [4, 30], hash_tail >= 0,
+ * max_blocks >= 1, voxel_size > 0, mu > 0, max_depth > 0.  hip_stream is a
+ * hipStream_t (NULL: the default stream).  *out receives the handle. */
+int dn_volume_create(const dn_volume_params *params, void *hip_stream, dn_volume **out);
+
+/* Release all device storage of the volume (synchronises its stream). */
+void dn_volume_destroy(dn_volume *vol);
+
+/* Change the stream subsequent calls are ordered on. */
+int dn_set_stream(dn_volume *vol, void *hip_stream);
+
+/* Number of allocated blocks (host value; no synchronisation needed). */
+int64_t dn_num_blocks(const dn_volume *vol);
+
+/* Wait for all work enqueued on the volume's stream. */
+int dn_sync(dn_volume *vol);
+
+/* Thread-local text of the last error ("" if none). */
+const char *dn_last_error(void);
+
+/* ------------------------------------------------------------ allocation */
+
+/* Block allocation for one depth map (Section III-A: a block is allocated
+ * as soon as a surface is observed inside it).  Every valid pixel (finite,
+ * 0 < d <= max_depth) marks every block that its ray crosses for depths in
+ * [max(d - mu, 1e-3), d + mu] (a 3-D grid traversal over 8s-sized blocks;
+ * ties step x, then y, then z).  Keys not yet present are appended to the
+ * pool in ascending (x, y, z) order; existing pool ids never change.  The
+ * hash table (Teschner primes, non-wrapping linear probing in ascending
+ * (bucket, key) order) and the 27-neighbour table are rebuilt.
+ * depth_dev: float32 [height][width].  T_gc: host float64[16].
+ * *n_new_out (host, may be NULL) receives the number of new blocks.
+ * DN_E_CAPACITY if the pool or the table would overflow (volume unchanged).
+ * Synchronises the stream. */
+int dn_alloc_blocks(dn_volume *vol, const float *depth_dev, const dn_intrinsics *K,
+                    const double T_gc[16], int32_t *n_new_out);
+
+/* Append explicit block keys (int32 [n][3], device) with the same rules as
+ * dn_alloc_blocks (duplicates and existing keys are ignored; new keys are
+ * appended in ascending order).  Synchronises the stream. */
+int dn_insert_blocks(dn_volume *vol, const int32_t *coords_dev, int64_t n, int32_t *n_new_out);
+
+/* --------------------------------------------------------------- fusion */
+
+/* Projective TSDF update of every voxel of every allocated block with one
+ * depth map, Eq. (1): p_c = T_gc^-1 p_g for the voxel centre (g + 0.5) s,
+ * nearest pixel floor(X + 0.5), eta = d - z_c; if the pixel is inside the
+ * map and valid and eta >= -mu: w += 1 and f = (min(1, eta/mu) + w_old f)/w.
+ * Geometry and decisions in float64, f and w in float32.  Enqueue only. */
+int dn_fuse_depth(dn_volume *vol, const float *depth_dev, const dn_intrinsics *K,
+                  const double T_gc[16]);
+
+/* Overwrite f and w of all allocated blocks (device float [n_blocks][512]
+ * each); w > 0 marks the voxel as observed (in Omega).  Enqueue only. */
+int dn_load_fused(dn_volume *vol, const float *f_dev, const float *w_dev);
+
+/* -------------------------------------------------------- regularisation */
+
+/* Chambolle-Pock iterations on the masked TV + weighted quadratic energy
+ * (Section III-B/C, Eqs. 2-9) over the allocated blocks:
+ *   p = P(p + sigma grad ubar),  u' = prox(u + tau div p),
+ *   ubar = u' + theta (u' - u),
+ * with grad the forward differences of Eq. (3) that are zero unless both
+ * voxels are observed (a voxel of an unallocated block is unobserved) and
+ * div = -grad^T (Eq. 4).  Voxels outside Omega keep their u.
+ * u0_dev (float [n_blocks][512]) and p0_dev (float [3][n_blocks][512]) are
+ * read only with init == DN_INIT_GIVEN.  out_host (may be NULL) receives the
+ * final energies.  DN_E_NUMERIC if the gap becomes non-finite.  Synchronises
+ * the stream (at every gap check and at the end). */
+int dn_regularize(dn_volume *vol, const dn_reg_params *params, const float *u0_dev,
+                  const float *p0_dev, dn_reg_stats *out_host);
+
+/* Regularise n independent volumes with the same parameters in ONE
+ * persistent kernel launch (a grid-wide barrier separates iterations),
+ * captured in a HIP graph and replayed.  Work items are (volume, block)
+ * pairs balanced over the grid.  All volumes must share one device; the
+ * first volume's stream is used.  gap_every / gap_tol are ignored (the
+ * gaps are computed once at the end); init must be ZERO or KEEP; storage
+ * must be DN_F32.  out_host: n stats (may be NULL). */
+int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_reg_params *params,
+                        dn_reg_stats *out_host);
+
+/* Primal and dual energies of the current state: out_host[0] = E(u),
+ * out_host[1] = D(p).  Synchronises. */
+int dn_energy(dn_volume *vol, double lambda, double out_host[2]);
+
+/* -------------------------------------------------------------- extract */
+
+/* Copy a part of the volume (DN_X_*) into out_dev (device, out_bytes
+ * long).  *n_out (host) receives the number of items (blocks, slots or
+ * points).  If out_dev is NULL or too small, nothing is written, *n_out
+ * still receives the count, and DN_E_CAPACITY is returned (for
+ * DN_X_SURFACE the count is computed first).  Synchronises the stream.
+ * DN_X_SURFACE: for every voxel g and axis a with both g and g + e_a
+ * observed and a sign change (u < 0 differs), the point
+ * (g + 0.5) s + t s e_a with t = u(g) / (u(g) - u(g + e_a)), in the order
+ * (pool id, voxel index, axis). */
+int dn_extract(dn_volume *vol, int32_t what, void *out_dev, size_t out_bytes, int64_t *n_out);
+
+/* ---------------------------------------------------- learned warm start */
+/* The network: three 3x3x3 convolutions with "same" zero padding on a
+ * 10^3 tile (a block plus a one-voxel halo): 2 -> 16 (ReLU) -> 16 (ReLU)
+ * -> 1.  Inputs f and log(1 + w) / log(101); output r; the warm start is
+ * u0 = clamp(f + r, -1, 1) on Omega.  Parameters are 8241 float32 values:
+ * W1[16][2][27] b1[16] W2[16][16][27] b2[16] W3[1][16][27] b3[1], tap
+ * (dz*3 + dy)*3 + dx.  Convolutions run on MFMA in bfloat16 with float32
+ * accumulation. */
+#define DN_NET_PARAMS 8241
+
+/* Gather the input tiles of the listed blocks: float [n][2][10][10][10]. */
+int dn_net_gather(dn_volume *vol, const int32_t *blocks_dev, int64_t n, float *tiles_dev);
+
+/* Forward pass: out_dev float [n][10][10][10] (the residual r). */
+int dn_net_forward(const float *tiles_dev, int64_t n, const float *params_dev, float *out_dev,
+                   void *hip_stream);
+
+/* Masked mean-squared loss of f + r against targets on the centre 8^3 and
+ * its gradient: targets_dev, mask_dev float [n][512] (mask 0/1); grad_dev
+ * float [8241] (overwritten).  *loss_host receives the loss (synchronises). */
+int dn_net_loss_grad(const float *tiles_dev, int64_t n, const float *params_dev,
+                     const float *targets_dev, const float *mask_dev, float *grad_dev,
+                     double *loss_host, void *hip_stream);
+
+/* One Adam step on n float32 parameters (m, v: moments, step >= 1). */
+int dn_net_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, int64_t n,
+                float lr, float beta1, float beta2, float eps, int32_t step, void *hip_stream);
+
+/* Warm start of the whole volume: u0_dev float [n_blocks][512] receives
+ * clamp(f + r, -1, 1) on Omega and 0 elsewhere; p0_dev (may be NULL)
+ * float [3][n_blocks][512] receives the projection of grad(u0) / delta onto
+ * the unit ball (delta > 0).  Enqueue only. */
+int dn_net_warm_start(dn_volume *vol, const float *params_dev, double delta, float *u0_dev,
+                      float *p0_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DENSER_H */

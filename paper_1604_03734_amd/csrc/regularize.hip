@@ -1,0 +1,768 @@
+// Omega-masked TV primal-dual regulariser over hashed 8^3 blocks (gfx950).
+//
+// Section III-B/C of the paper: masked forward-difference gradient (Eq. 3),
+// its negative adjoint as divergence (Eq. 4), and the Chambolle-Pock
+// iteration (Eqs. 7-9) on the weighted ROF energy.  Two implementations of
+// one iteration:
+//   - two-pass: a dual kernel and a primal kernel, in place (60 B/voxel);
+//   - fused: one kernel per iteration; each workgroup stages its block's
+//     ubar with a one-voxel halo in LDS, recomputes the new dual on the -1
+//     halo faces (so no second pass is needed) and ping-pongs ubar and p
+//     between two buffers (48 B/voxel of algorithmic traffic).
+// The fused body is shared with a persistent kernel that runs many
+// sub-maps and all iterations in one launch, separated by grid barriers.
+// Energies are accumulated in float64 with a fixed reduction order.
+#include <cstring>
+#include <rocprim/rocprim.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <vector>
+
+#include "dn_internal.h"
+
+namespace dn {
+
+// ---------------------------------------------------------- storage types
+// State storage: float, IEEE half or bfloat16 (16-bit kept as raw bits).
+struct SF32 {
+    using T = float;
+    static __device__ __forceinline__ float ld(float v) { return v; }
+    static __device__ __forceinline__ float rn(float x) { return x; }
+    static __device__ __forceinline__ float rz(float x) { return x; }
+};
+struct SF16 {
+    using T = uint16_t;
+    static __device__ __forceinline__ float ld(uint16_t v) { return float(__builtin_bit_cast(_Float16, v)); }
+    static __device__ __forceinline__ uint16_t rn(float x) { return __builtin_bit_cast(uint16_t, _Float16(x)); }
+    static __device__ __forceinline__ uint16_t rz(float x)
+    {
+        auto h2 = __builtin_amdgcn_cvt_pkrtz(x, 0.0f);
+        return __builtin_bit_cast(uint16_t, h2[0]);
+    }
+};
+struct SBF16 {
+    using T = uint16_t;
+    static __device__ __forceinline__ float ld(uint16_t v) { return __uint_as_float(uint32_t(v) << 16); }
+    static __device__ __forceinline__ uint16_t rn(float x)
+    {
+        uint32_t u = __float_as_uint(x);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return uint16_t(u >> 16);
+    }
+    static __device__ __forceinline__ uint16_t rz(float x) { return uint16_t(__float_as_uint(x) >> 16); }
+};
+
+template <class S> struct CPArgs {
+    int64_t nb;                 // blocks
+    int64_t pstride;            // elements between p planes
+    const int32_t *nbr;         // [nb][27]
+    const uint8_t *emask;       // [nb][512]
+    const int32_t *order;       // processing order or nullptr
+    const float *f, *w;
+    typename S::T *u;           // in place
+    const typename S::T *ubar_in;
+    typename S::T *ubar_out;
+    const typename S::T *p_in;  // 3 planes
+    typename S::T *p_out;
+    float *u32, *ubar32, *p32;  // FP32 copies written by a refinement sweep
+    float sigma, tau, lambda, theta;
+};
+
+__device__ __forceinline__ int i10(int x, int y, int z) { return ((z + 1) * 10 + (y + 1)) * 10 + (x + 1); }
+__device__ __forceinline__ int i9(int x, int y, int z) { return ((z + 1) * 9 + (y + 1)) * 9 + (x + 1); }
+
+// Global index of voxel (hx, hy, hz) relative to block b, hx.. in [-1, 8],
+// or -1 if it lies in an unallocated block.
+__device__ __forceinline__ int64_t halo_index(const int32_t *nb27, int hx, int hy, int hz)
+{
+    int dx = hx < 0 ? -1 : (hx > 7 ? 1 : 0);
+    int dy = hy < 0 ? -1 : (hy > 7 ? 1 : 0);
+    int dz = hz < 0 ? -1 : (hz > 7 ? 1 : 0);
+    int32_t id = nb27[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)];
+    if (id < 0) return -1;
+    return int64_t(id) * kBlockVox + ((hx - 8 * dx) + 8 * (hy - 8 * dy) + 64 * (hz - 8 * dz));
+}
+
+// Position of the t-th ubar halo voxel (t < 432): the six faces (+x, +y,
+// +z, -x, -y, -z; 64 each) then the six (-a, +b) edges (8 each).
+__device__ __forceinline__ void halo_pos(int t, int &x, int &y, int &z)
+{
+    if (t < 384) {
+        int f = t >> 6, i = t & 63, a = i & 7, b = i >> 3;
+        switch (f) {
+        case 0: x = 8; y = a; z = b; break;
+        case 1: x = a; y = 8; z = b; break;
+        case 2: x = a; y = b; z = 8; break;
+        case 3: x = -1; y = a; z = b; break;
+        case 4: x = a; y = -1; z = b; break;
+        default: x = a; y = b; z = -1; break;
+        }
+    } else {
+        int e = (t - 384) >> 3, j = (t - 384) & 7;
+        switch (e) {
+        case 0: x = -1; y = 8; z = j; break;
+        case 1: x = -1; y = j; z = 8; break;
+        case 2: x = 8; y = -1; z = j; break;
+        case 3: x = j; y = -1; z = 8; break;
+        case 4: x = 8; y = j; z = -1; break;
+        default: x = j; y = 8; z = -1; break;
+        }
+    }
+}
+
+// -1 face voxel t < 192: face 0 (-x), 1 (-y), 2 (-z)
+__device__ __forceinline__ void face_pos(int t, int &x, int &y, int &z)
+{
+    int f = t >> 6, i = t & 63, a = i & 7, b = i >> 3;
+    if (f == 0) { x = -1; y = a; z = b; }
+    else if (f == 1) { x = a; y = -1; z = b; }
+    else { x = a; y = b; z = -1; }
+}
+
+struct CPShared {
+    float u[1000];       // ubar tile with a one-voxel halo, index i10
+    float p[3][729];     // new dual on the block and its -1 faces, index i9
+    uint8_t m[729];      // edge masks on the block and its -1 faces
+};
+
+__device__ __forceinline__ void project(float &a, float &b, float &c)
+{
+    float n = sqrtf((a * a + b * b) + c * c);
+    if (n > 1.0f) { a = a / n; b = b / n; c = c / n; }
+}
+
+// One fused Chambolle-Pock iteration on block b (512 threads).
+template <class S, bool kRefine>
+__device__ __forceinline__ void cp_block(const CPArgs<S> &A, int64_t b, CPShared &sh)
+{
+    const int t = threadIdx.x;
+    const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+    const int64_t gi = b * kBlockVox + t;
+    const int32_t *nb27 = A.nbr + b * kNbr;
+    const int64_t ps = A.pstride;
+
+    const float ub = S::ld(A.ubar_in[gi]);
+    const uint8_t m = A.emask[gi];
+    float p0 = S::ld(A.p_in[gi]), p1 = S::ld(A.p_in[gi + ps]), p2 = S::ld(A.p_in[gi + 2 * ps]);
+    const float uo = S::ld(A.u[gi]);
+    const float fv = A.f[gi], wv = A.w[gi];
+    sh.u[i10(lx, ly, lz)] = ub;
+    sh.m[i9(lx, ly, lz)] = m;
+    if (t < 432) {
+        int hx, hy, hz;
+        halo_pos(t, hx, hy, hz);
+        int64_t j = halo_index(nb27, hx, hy, hz);
+        sh.u[i10(hx, hy, hz)] = j >= 0 ? S::ld(A.ubar_in[j]) : 0.0f;
+    }
+    float h0 = 0.f, h1 = 0.f, h2 = 0.f;
+    uint8_t hm = 0;
+    int fx = 0, fy = 0, fz = 0;
+    if (t < 192) {
+        face_pos(t, fx, fy, fz);
+        int64_t j = halo_index(nb27, fx, fy, fz);
+        if (j >= 0) {
+            hm = A.emask[j];
+            h0 = S::ld(A.p_in[j]); h1 = S::ld(A.p_in[j + ps]); h2 = S::ld(A.p_in[j + 2 * ps]);
+        }
+        sh.m[i9(fx, fy, fz)] = hm;
+    }
+    __syncthreads();
+
+    // dual ascent and projection on the block (Eq. 7)
+    {
+        float g0 = (m & 2) ? sh.u[i10(lx + 1, ly, lz)] - ub : 0.0f;
+        float g1 = (m & 4) ? sh.u[i10(lx, ly + 1, lz)] - ub : 0.0f;
+        float g2 = (m & 8) ? sh.u[i10(lx, ly, lz + 1)] - ub : 0.0f;
+        p0 = p0 + A.sigma * g0; p1 = p1 + A.sigma * g1; p2 = p2 + A.sigma * g2;
+        project(p0, p1, p2);
+        const int k = i9(lx, ly, lz);
+        sh.p[0][k] = p0; sh.p[1][k] = p1; sh.p[2][k] = p2;
+        A.p_out[gi] = S::rz(p0); A.p_out[gi + ps] = S::rz(p1); A.p_out[gi + 2 * ps] = S::rz(p2);
+        if (kRefine) { A.p32[gi] = p0; A.p32[gi + ps] = p1; A.p32[gi + 2 * ps] = p2; }
+    }
+    // ... and on the -1 faces, which the divergence needs
+    if (t < 192) {
+        float uh = sh.u[i10(fx, fy, fz)];
+        float g0 = (hm & 2) ? sh.u[i10(fx + 1, fy, fz)] - uh : 0.0f;
+        float g1 = (hm & 4) ? sh.u[i10(fx, fy + 1, fz)] - uh : 0.0f;
+        float g2 = (hm & 8) ? sh.u[i10(fx, fy, fz + 1)] - uh : 0.0f;
+        h0 = h0 + A.sigma * g0; h1 = h1 + A.sigma * g1; h2 = h2 + A.sigma * g2;
+        project(h0, h1, h2);
+        const int k = i9(fx, fy, fz);
+        sh.p[0][k] = h0; sh.p[1][k] = h1; sh.p[2][k] = h2;
+    }
+    __syncthreads();
+
+    // primal proximal step (Eq. 8) and relaxation (Eq. 9)
+    float un = uo;
+    if (m & 1) {
+        const int k = i9(lx, ly, lz);
+        const int kx = i9(lx - 1, ly, lz), ky = i9(lx, ly - 1, lz), kz = i9(lx, ly, lz - 1);
+        float dv = 0.0f;
+        dv += ((m & 2) ? sh.p[0][k] : 0.0f) - ((sh.m[kx] & 2) ? sh.p[0][kx] : 0.0f);
+        dv += ((m & 4) ? sh.p[1][k] : 0.0f) - ((sh.m[ky] & 4) ? sh.p[1][ky] : 0.0f);
+        dv += ((m & 8) ? sh.p[2][k] : 0.0f) - ((sh.m[kz] & 8) ? sh.p[2][kz] : 0.0f);
+        float ut = uo + A.tau * dv;
+        float tlw = A.tau * A.lambda * wv;
+        un = (ut + tlw * fv) / (1.0f + tlw);
+    }
+    float ubn = un + A.theta * (un - uo);
+    A.u[gi] = S::rn(un);
+    A.ubar_out[gi] = S::rn(ubn);
+    if (kRefine) { A.u32[gi] = un; A.ubar32[gi] = ubn; }
+}
+
+// Workgroup -> block mapping.  Consecutive workgroups go round-robin to the
+// 8 XCDs; giving XCD x the x-th contiguous chunk of the (Morton) order keeps
+// spatial neighbours, whose faces are each other's halos, in one L2.
+__device__ __forceinline__ int64_t xcd_slot(int64_t wg, int64_t n)
+{
+    int64_t per = (n + 7) / 8;
+    return (wg % 8) * per + wg / 8;
+}
+
+template <class S, bool kRefine>
+__global__ __launch_bounds__(512) void k_cp_fused(CPArgs<S> A)
+{
+    __shared__ CPShared sh;
+    int64_t slot = xcd_slot(blockIdx.x, A.nb);
+    if (slot >= A.nb) return;
+    int64_t b = A.order ? A.order[slot] : slot;
+    cp_block<S, kRefine>(A, b, sh);
+}
+
+// ----------------------------------------------------- two-pass variant
+__global__ __launch_bounds__(512) void k_dual(int64_t nb, int64_t ps, const int32_t *__restrict__ nbr,
+                                              const uint8_t *__restrict__ emask, const float *__restrict__ ubar,
+                                              float *__restrict__ p, float sigma)
+{
+    const int64_t b = blockIdx.x;
+    if (b >= nb) return;
+    const int t = threadIdx.x, lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+    const int64_t gi = b * kBlockVox + t;
+    const int32_t *nb27 = nbr + b * kNbr;
+    const uint8_t m = emask[gi];
+    const float u0 = ubar[gi];
+    float g[3] = {0.f, 0.f, 0.f};
+    if (m & 2) g[0] = ubar[lx < 7 ? gi + 1 : halo_index(nb27, 8, ly, lz)] - u0;
+    if (m & 4) g[1] = ubar[ly < 7 ? gi + 8 : halo_index(nb27, lx, 8, lz)] - u0;
+    if (m & 8) g[2] = ubar[lz < 7 ? gi + 64 : halo_index(nb27, lx, ly, 8)] - u0;
+    float a = p[gi] + sigma * g[0], c1 = p[gi + ps] + sigma * g[1], c2 = p[gi + 2 * ps] + sigma * g[2];
+    project(a, c1, c2);
+    p[gi] = a; p[gi + ps] = c1; p[gi + 2 * ps] = c2;
+}
+
+__global__ __launch_bounds__(512) void k_primal(int64_t nb, int64_t ps, const int32_t *__restrict__ nbr,
+                                                const uint8_t *__restrict__ emask, const float *__restrict__ p,
+                                                const float *__restrict__ f, const float *__restrict__ w,
+                                                float *__restrict__ u, float *__restrict__ ubar, float tau,
+                                                float lambda, float theta)
+{
+    const int64_t b = blockIdx.x;
+    if (b >= nb) return;
+    const int t = threadIdx.x, lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+    const int64_t gi = b * kBlockVox + t;
+    const int32_t *nb27 = nbr + b * kNbr;
+    const uint8_t m = emask[gi];
+    const float uo = u[gi];
+    float un = uo;
+    if (m & 1) {
+        float dv = 0.0f;
+        for (int a = 0; a < 3; ++a) {
+            int64_t jm;
+            if (a == 0) jm = lx > 0 ? gi - 1 : halo_index(nb27, -1, ly, lz);
+            else if (a == 1) jm = ly > 0 ? gi - 8 : halo_index(nb27, lx, -1, lz);
+            else jm = lz > 0 ? gi - 64 : halo_index(nb27, lx, ly, -1);
+            const uint8_t bit = uint8_t(2 << a);
+            float fwd = (m & bit) ? p[gi + a * ps] : 0.0f;
+            float bwd = (jm >= 0 && (emask[jm] & bit)) ? p[jm + a * ps] : 0.0f;
+            dv += fwd - bwd;
+        }
+        float ut = uo + tau * dv;
+        float tlw = tau * lambda * w[gi];
+        un = (ut + tlw * f[gi]) / (1.0f + tlw);
+    }
+    u[gi] = un;
+    ubar[gi] = un + theta * (un - uo);
+}
+
+// ------------------------------------------------------------- masks
+// emask bit0 = Omega(g) (block allocated and w > 0); bit 1+a = m_a(g) =
+// Omega(g) and Omega(g + e_a)  (Eq. 3's cases where the difference is kept).
+__global__ __launch_bounds__(512) void k_masks(int64_t nb, const int32_t *__restrict__ nbr,
+                                               const float *__restrict__ w, uint8_t *__restrict__ emask)
+{
+    const int64_t b = blockIdx.x;
+    if (b >= nb) return;
+    const int t = threadIdx.x, lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+    const int64_t gi = b * kBlockVox + t;
+    const int32_t *nb27 = nbr + b * kNbr;
+    uint8_t m = 0;
+    if (w[gi] > 0.0f) {
+        m = 1;
+        int64_t jx = halo_index(nb27, lx + 1, ly, lz);
+        int64_t jy = halo_index(nb27, lx, ly + 1, lz);
+        int64_t jz = halo_index(nb27, lx, ly, lz + 1);
+        if (jx >= 0 && w[jx] > 0.0f) m |= 2;
+        if (jy >= 0 && w[jy] > 0.0f) m |= 4;
+        if (jz >= 0 && w[jz] > 0.0f) m |= 8;
+    }
+    emask[gi] = m;
+}
+
+__device__ __forceinline__ uint64_t spread3(uint64_t v)
+{
+    v &= 0x1FFFFF;
+    v = (v | (v << 32)) & 0x1F00000000FFFFull;
+    v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__global__ void k_morton(const int32_t *__restrict__ coords, int64_t nb, uint64_t *__restrict__ code,
+                         int32_t *__restrict__ ids)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    uint64_t x = uint64_t(int64_t(coords[4 * i]) + (1 << 20));
+    uint64_t y = uint64_t(int64_t(coords[4 * i + 1]) + (1 << 20));
+    uint64_t z = uint64_t(int64_t(coords[4 * i + 2]) + (1 << 20));
+    code[i] = spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+    ids[i] = int32_t(i);
+}
+
+// ---------------------------------------------------------- energies
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Per-block partial sums of E(u) and D(p) (Eq. 2 with the weight of the
+// proximal step, Eq. 6), float64, fixed order: lanes by xor-shuffle
+// butterflies, then the 8 wave sums in wave order.
+template <class S>
+__global__ __launch_bounds__(512) void k_energy_partial(int64_t nb, int64_t ps, const int32_t *__restrict__ nbr,
+                                                        const uint8_t *__restrict__ emask,
+                                                        const typename S::T *__restrict__ u,
+                                                        const typename S::T *__restrict__ p,
+                                                        const float *__restrict__ f, const float *__restrict__ w,
+                                                        double lambda, double *__restrict__ partials)
+{
+    __shared__ double se[8], sd[8];
+    const int64_t b = blockIdx.x;
+    if (b >= nb) return;
+    const int t = threadIdx.x, lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+    const int64_t gi = b * kBlockVox + t;
+    const int32_t *nb27 = nbr + b * kNbr;
+    const uint8_t m = emask[gi];
+    double e = 0.0, d = 0.0;
+    if (m & 1) {
+        const double u0 = S::ld(u[gi]);
+        double g[3] = {0.0, 0.0, 0.0};
+        if (m & 2) g[0] = double(S::ld(u[lx < 7 ? gi + 1 : halo_index(nb27, 8, ly, lz)])) - u0;
+        if (m & 4) g[1] = double(S::ld(u[ly < 7 ? gi + 8 : halo_index(nb27, lx, 8, lz)])) - u0;
+        if (m & 8) g[2] = double(S::ld(u[lz < 7 ? gi + 64 : halo_index(nb27, lx, ly, 8)])) - u0;
+        const double fv = f[gi], wv = w[gi];
+        const double r = u0 - fv;
+        e = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]) + 0.5 * lambda * wv * r * r;
+        double dv = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            int64_t jm;
+            if (a == 0) jm = lx > 0 ? gi - 1 : halo_index(nb27, -1, ly, lz);
+            else if (a == 1) jm = ly > 0 ? gi - 8 : halo_index(nb27, lx, -1, lz);
+            else jm = lz > 0 ? gi - 64 : halo_index(nb27, lx, ly, -1);
+            const uint8_t bit = uint8_t(2 << a);
+            double fwd = (m & bit) ? double(S::ld(p[gi + a * ps])) : 0.0;
+            double bwd = (jm >= 0 && (emask[jm] & bit)) ? double(S::ld(p[jm + a * ps])) : 0.0;
+            dv += fwd - bwd;
+        }
+        d = -fv * dv - dv * dv / (2.0 * lambda * wv);
+    }
+    e = wave_sum(e);
+    d = wave_sum(d);
+    const int wave = t >> 6;
+    if ((t & 63) == 0) { se[wave] = e; sd[wave] = d; }
+    __syncthreads();
+    if (t == 0) {
+        double E = 0.0, D = 0.0;
+        for (int i = 0; i < 8; ++i) { E += se[i]; D += sd[i]; }
+        partials[2 * b] = E;
+        partials[2 * b + 1] = D;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_energy_final(int64_t nb, const double *__restrict__ partials,
+                                                      double *__restrict__ out)
+{
+    __shared__ double se[256], sd[256];
+    const int t = threadIdx.x;
+    double e = 0.0, d = 0.0;
+    for (int64_t i = t; i < nb; i += 256) { e += partials[2 * i]; d += partials[2 * i + 1]; }
+    se[t] = e; sd[t] = d;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) { se[t] += se[t + s]; sd[t] += sd[t + s]; }
+        __syncthreads();
+    }
+    if (t == 0) { out[0] = se[0]; out[1] = sd[0]; }
+}
+
+// ------------------------------------------------------- helpers
+template <class T> __global__ void k_fill(T *__restrict__ a, int64_t n, T v)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+template <class S> __global__ void k_demote(const float *__restrict__ a, typename S::T *__restrict__ b, int64_t n, int rz)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = rz ? S::rz(a[i]) : S::rn(a[i]);
+}
+
+static inline unsigned grid1(int64_t n, int bs = 256) { return unsigned((n + bs - 1) / bs); }
+
+template <class T> static int fill(hipStream_t st, T *a, int64_t n, T v)
+{
+    if (n <= 0) return DN_OK;
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid1(n)), dim3(256), 0, st, a, n, v);
+    DN_HIP(hipGetLastError());
+    return DN_OK;
+}
+
+int build_masks(dn_volume *v)
+{
+    if (v->emask_nb == v->nb) return DN_OK;
+    hipStream_t st = v->stream;
+    if (v->nb > 0) {
+        hipLaunchKernelGGL(k_masks, dim3(unsigned(v->nb)), dim3(512), 0, st, v->nb, v->nbr, v->w, v->emask);
+        DN_HIP(hipGetLastError());
+        // Morton processing order of the blocks
+        int rc;
+        if ((rc = v->s_sorted.ensure(v->nb * 8 * 2))) return rc;
+        if ((rc = v->s_vals.ensure(v->nb * 4))) return rc;
+        uint64_t *code = v->s_sorted.as<uint64_t>();
+        uint64_t *code2 = code + v->nb;
+        int32_t *ids = v->s_vals.as<int32_t>();
+        hipLaunchKernelGGL(k_morton, dim3(grid1(v->nb)), dim3(256), 0, st, v->coords, v->nb, code, ids);
+        DN_HIP(hipGetLastError());
+        size_t tb = 0;
+        DN_HIP(rocprim::radix_sort_pairs(nullptr, tb, code, code2, ids, v->order, size_t(v->nb), 0, 63, st));
+        if ((rc = v->s_tmp.ensure(tb))) return rc;
+        size_t tbytes = v->s_tmp.bytes;
+        DN_HIP(rocprim::radix_sort_pairs(v->s_tmp.ptr, tbytes, code, code2, ids, v->order, size_t(v->nb), 0, 63, st));
+    }
+    v->emask_nb = v->nb;
+    return DN_OK;
+}
+
+int ensure_lowp(dn_volume *v)
+{
+    if (v->u16) return DN_OK;
+    const size_t vox = size_t(v->cap_blocks) * kBlockVox;
+    DN_HIP(hipMalloc(&v->u16, vox * 2));
+    DN_HIP(hipMalloc(&v->ubar16[0], vox * 2));
+    DN_HIP(hipMalloc(&v->ubar16[1], vox * 2));
+    DN_HIP(hipMalloc(&v->p16[0], vox * 6));
+    DN_HIP(hipMalloc(&v->p16[1], vox * 6));
+    return DN_OK;
+}
+
+template <class S>
+static int energy_launch(dn_volume *v, double lambda, const typename S::T *u, const typename S::T *p)
+{
+    hipStream_t st = v->stream;
+    const int64_t ps = v->cap_blocks * kBlockVox;
+    if (v->nb > 0) {
+        hipLaunchKernelGGL((k_energy_partial<S>), dim3(unsigned(v->nb)), dim3(512), 0, st, v->nb, ps, v->nbr,
+                           v->emask, u, p, v->f, v->w, lambda, v->partials);
+        DN_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, v->nb, v->partials, v->energy2);
+    DN_HIP(hipGetLastError());
+    return DN_OK;
+}
+
+// Energies of the current state into v->energy2 (device).
+static int energy_current(dn_volume *v, double lambda, bool use_f32 = false)
+{
+    int rc = build_masks(v);
+    if (rc) return rc;
+    switch (use_f32 ? DN_F32 : v->state_storage) {
+    case DN_F16:
+        return energy_launch<SF16>(v, lambda, (const uint16_t *)v->u16, (const uint16_t *)v->p16[v->cur]);
+    case DN_BF16:
+        return energy_launch<SBF16>(v, lambda, (const uint16_t *)v->u16, (const uint16_t *)v->p16[v->cur]);
+    default:
+        return energy_launch<SF32>(v, lambda, v->u, v->p[v->cur]);
+    }
+}
+
+static int read_energy(dn_volume *v, double out[2])
+{
+    int rc = v->host.ensure(64);
+    if (rc) return rc;
+    DN_HIP(hipMemcpyAsync(v->host.ptr, v->energy2, 16, hipMemcpyDeviceToHost, v->stream));
+    DN_HIP(hipStreamSynchronize(v->stream));
+    out[0] = v->host.as<double>()[0];
+    out[1] = v->host.as<double>()[1];
+    return DN_OK;
+}
+
+template <class S>
+static CPArgs<S> make_args(dn_volume *v, const dn_reg_params *prm, typename S::T *u, typename S::T *ub_in,
+                           typename S::T *ub_out, typename S::T *p_in, typename S::T *p_out)
+{
+    CPArgs<S> A;
+    A.nb = v->nb;
+    A.pstride = v->cap_blocks * kBlockVox;
+    A.nbr = v->nbr;
+    A.emask = v->emask;
+    A.order = v->order;
+    A.f = v->f; A.w = v->w;
+    A.u = u; A.ubar_in = ub_in; A.ubar_out = ub_out; A.p_in = p_in; A.p_out = p_out;
+    A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
+    A.sigma = float(prm->sigma); A.tau = float(prm->tau); A.lambda = float(prm->lambda);
+    A.theta = float(prm->theta);
+    return A;
+}
+
+static unsigned fused_grid(int64_t nb) { return unsigned(((nb + 7) / 8) * 8); }
+
+// One FP32 iteration with the chosen kernel.
+static int step_f32(dn_volume *v, const dn_reg_params *prm, int kernel)
+{
+    hipStream_t st = v->stream;
+    const int64_t ps = v->cap_blocks * kBlockVox;
+    if (kernel == DN_K_TWOPASS) {
+        hipLaunchKernelGGL(k_dual, dim3(unsigned(v->nb)), dim3(512), 0, st, v->nb, ps, v->nbr, v->emask,
+                           v->ubar[v->cur], v->p[v->cur], float(prm->sigma));
+        DN_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_primal, dim3(unsigned(v->nb)), dim3(512), 0, st, v->nb, ps, v->nbr, v->emask,
+                           v->p[v->cur], v->f, v->w, v->u, v->ubar[v->cur], float(prm->tau), float(prm->lambda),
+                           float(prm->theta));
+        DN_HIP(hipGetLastError());
+        return DN_OK;
+    }
+    const int c = v->cur, n = 1 - c;
+    auto A = make_args<SF32>(v, prm, v->u, v->ubar[c], v->ubar[n], v->p[c], v->p[n]);
+    hipLaunchKernelGGL((k_cp_fused<SF32, false>), dim3(fused_grid(v->nb)), dim3(512), 0, st, A);
+    DN_HIP(hipGetLastError());
+    v->cur = n;
+    return DN_OK;
+}
+
+template <class S>
+static int step_lowp(dn_volume *v, const dn_reg_params *prm, bool refine)
+{
+    const int c = v->cur, n = 1 - c;
+    using T = typename S::T;
+    auto A = make_args<S>(v, prm, (T *)v->u16, (T *)v->ubar16[c], (T *)v->ubar16[n], (T *)v->p16[c],
+                          (T *)v->p16[n]);
+    if (refine) {
+        A.u32 = v->u; A.ubar32 = v->ubar[n]; A.p32 = v->p[n];
+        hipLaunchKernelGGL((k_cp_fused<S, true>), dim3(fused_grid(v->nb)), dim3(512), 0, v->stream, A);
+    } else {
+        hipLaunchKernelGGL((k_cp_fused<S, false>), dim3(fused_grid(v->nb)), dim3(512), 0, v->stream, A);
+    }
+    DN_HIP(hipGetLastError());
+    v->cur = n;
+    return DN_OK;
+}
+
+// Copy the FP32 state into the 16-bit buffers (u, ubar round to nearest,
+// p toward zero so |p| <= 1 survives the rounding).
+template <class S> static int demote_state(dn_volume *v)
+{
+    hipStream_t st = v->stream;
+    const int64_t n = v->nb * kBlockVox, ps = v->cap_blocks * kBlockVox;
+    using T = typename S::T;
+    if (n == 0) return DN_OK;
+    hipLaunchKernelGGL((k_demote<S>), dim3(grid1(n)), dim3(256), 0, st, v->u, (T *)v->u16, n, 0);
+    hipLaunchKernelGGL((k_demote<S>), dim3(grid1(n)), dim3(256), 0, st, v->ubar[v->cur], (T *)v->ubar16[v->cur], n, 0);
+    for (int a = 0; a < 3; ++a)
+        hipLaunchKernelGGL((k_demote<S>), dim3(grid1(n)), dim3(256), 0, st, v->p[v->cur] + a * ps,
+                           (T *)v->p16[v->cur] + a * ps, n, 1);
+    DN_HIP(hipGetLastError());
+    return DN_OK;
+}
+
+static int validate(const dn_reg_params *prm)
+{
+    DN_REQUIRE(prm, "null params");
+    DN_REQUIRE(prm->lambda > 0 && prm->tau > 0 && prm->sigma > 0, "lambda, tau, sigma must be > 0");
+    DN_REQUIRE(prm->tau * prm->sigma * 12.0 <= 1.0 + 1e-9,
+               "step sizes violate tau*sigma*|grad|^2 <= 1 (|grad|^2 <= 12 in 3-D)");
+    DN_REQUIRE(prm->theta >= 0 && prm->theta <= 1, "theta must be in [0, 1]");
+    DN_REQUIRE(prm->iters >= 0 && prm->gap_every >= 0, "iters, gap_every must be >= 0");
+    int s = prm->storage;
+    DN_REQUIRE(s == DN_F32 || s == DN_F16 || s == DN_BF16, "bad storage");
+    DN_REQUIRE(prm->init >= DN_INIT_ZERO && prm->init <= DN_INIT_GIVEN, "bad init");
+    DN_REQUIRE(prm->kernel >= DN_K_AUTO && prm->kernel <= DN_K_FUSED, "bad kernel");
+    DN_REQUIRE(prm->refine_every >= 0, "refine_every must be >= 0");
+    return DN_OK;
+}
+
+static int zero_state(dn_volume *v)
+{
+    hipStream_t st = v->stream;
+    const int64_t n = v->nb * kBlockVox, ps = v->cap_blocks * kBlockVox;
+    int rc;
+    if ((rc = fill<float>(st, v->u, n, 0.f))) return rc;
+    if ((rc = fill<float>(st, v->ubar[v->cur], n, 0.f))) return rc;
+    for (int a = 0; a < 3; ++a)
+        if ((rc = fill<float>(st, v->p[v->cur] + a * ps, n, 0.f))) return rc;
+    v->state_storage = DN_F32;
+    return DN_OK;
+}
+
+// Kernel choice for DN_K_AUTO: measured once per size bucket.
+static std::map<int, int> g_auto_kernel;
+
+static int size_bucket(int64_t nb)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < nb) ++b;
+    return b;
+}
+
+static int autotune_single(dn_volume *v, const dn_reg_params *prm, int *choice)
+{
+    int key = size_bucket(v->nb);
+    auto it = g_auto_kernel.find(key);
+    if (it != g_auto_kernel.end()) { *choice = it->second; return DN_OK; }
+    // time a few iterations of each candidate from the zero state
+    hipEvent_t e0, e1;
+    DN_HIP(hipEventCreate(&e0));
+    DN_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int best = DN_K_FUSED;
+    const int trial = 6;
+    for (int k : {DN_K_TWOPASS, DN_K_FUSED}) {
+        int rc = zero_state(v);
+        if (rc) return rc;
+        if ((rc = step_f32(v, prm, k))) return rc;  // warm up
+        DN_HIP(hipEventRecord(e0, v->stream));
+        for (int i = 0; i < trial; ++i)
+            if ((rc = step_f32(v, prm, k))) return rc;
+        DN_HIP(hipEventRecord(e1, v->stream));
+        DN_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        DN_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) { best_ms = ms; best = k; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_auto_kernel[key] = best;
+    *choice = best;
+    return zero_state(v);
+}
+
+}  // namespace dn
+
+using namespace dn;
+
+extern "C" {
+
+int dn_energy(dn_volume *v, double lambda, double out[2])
+{
+    DN_REQUIRE(v && out && lambda > 0, "bad argument");
+    int rc = energy_current(v, lambda);
+    if (rc) return rc;
+    return read_energy(v, out);
+}
+
+int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const float *p0, dn_reg_stats *out)
+{
+    DN_REQUIRE(v, "null volume");
+    int rc = validate(prm);
+    if (rc) return rc;
+    DN_REQUIRE(prm->init != DN_INIT_GIVEN || u0, "init GIVEN needs u0");
+    hipStream_t st = v->stream;
+    if ((rc = build_masks(v))) return rc;
+    const int64_t n = v->nb * kBlockVox, ps = v->cap_blocks * kBlockVox;
+    const int storage = prm->storage;
+    // initial state
+    if (prm->init == DN_INIT_ZERO) {
+        if ((rc = zero_state(v))) return rc;
+    } else if (prm->init == DN_INIT_GIVEN) {
+        if (n > 0) {
+            DN_HIP(hipMemcpyAsync(v->u, u0, n * 4, hipMemcpyDeviceToDevice, st));
+            DN_HIP(hipMemcpyAsync(v->ubar[v->cur], u0, n * 4, hipMemcpyDeviceToDevice, st));
+            for (int a = 0; a < 3; ++a) {
+                if (p0) {
+                    DN_HIP(hipMemcpyAsync(v->p[v->cur] + a * ps, p0 + a * n, n * 4, hipMemcpyDeviceToDevice, st));
+                } else if ((rc = fill<float>(st, v->p[v->cur] + a * ps, n, 0.f))) {
+                    return rc;
+                }
+            }
+        }
+        v->state_storage = DN_F32;
+    }
+    int kernel = prm->kernel;
+    if (storage != DN_F32) {
+        kernel = DN_K_FUSED;
+        if ((rc = ensure_lowp(v))) return rc;
+        if (v->state_storage != storage) {
+            // the FP32 state (zero, given or an earlier FP32 run) is demoted
+            if (v->state_storage != DN_F32) {
+                set_error("cannot continue a %s state with another 16-bit storage",
+                          v->state_storage == DN_F16 ? "FP16" : "BF16");
+                return DN_E_INVALID;
+            }
+            rc = storage == DN_F16 ? demote_state<SF16>(v) : demote_state<SBF16>(v);
+            if (rc) return rc;
+            v->state_storage = storage;
+        }
+    } else {
+        // a 16-bit run always ends with an FP32 sweep: continue from its output
+        v->state_storage = DN_F32;
+        if (kernel == DN_K_AUTO && v->nb > 0) {
+            if (prm->init == DN_INIT_ZERO) {
+                if ((rc = autotune_single(v, prm, &kernel))) return rc;
+            } else {
+                auto it = g_auto_kernel.find(size_bucket(v->nb));
+                kernel = it != g_auto_kernel.end() ? it->second : DN_K_FUSED;
+            }
+        }
+    }
+    dn_reg_stats stats{};
+    double ed[2] = {0, 0};
+    int it = 0;
+    for (; it < prm->iters && v->nb > 0; ++it) {
+        if (storage == DN_F32) {
+            rc = step_f32(v, prm, kernel);
+        } else {
+            bool refine = (prm->refine_every > 0 && (it + 1) % prm->refine_every == 0) || it + 1 == prm->iters;
+            rc = storage == DN_F16 ? step_lowp<SF16>(v, prm, refine) : step_lowp<SBF16>(v, prm, refine);
+        }
+        if (rc) return rc;
+        if (prm->gap_every > 0 && (it + 1) % prm->gap_every == 0 && it + 1 < prm->iters) {
+            if ((rc = energy_current(v, prm->lambda))) return rc;
+            if ((rc = read_energy(v, ed))) return rc;
+            double gap = ed[0] - ed[1];
+            if (!std::isfinite(gap)) { set_error("non-finite gap at iteration %d", it + 1); return DN_E_NUMERIC; }
+            if (prm->gap_tol > 0 && gap <= prm->gap_tol * ed[0]) { ++it; stats.converged = 1; break; }
+        }
+    }
+    stats.iters_run = it;
+    // after a 16-bit run the result is the FP32 output of the last sweep
+    const bool f32_result = storage == DN_F32 || (it > 0 && it == prm->iters);
+    if ((rc = energy_current(v, prm->lambda, f32_result))) return rc;
+    if ((rc = read_energy(v, ed))) return rc;
+    stats.energy = ed[0];
+    stats.dual = ed[1];
+    stats.gap = ed[0] - ed[1];
+    stats.rel_gap = ed[0] != 0.0 ? stats.gap / ed[0] : 0.0;
+    if (prm->gap_tol > 0 && stats.gap <= prm->gap_tol * ed[0]) stats.converged = 1;
+    if (out) *out = stats;
+    if (!std::isfinite(stats.gap)) { set_error("non-finite energy"); return DN_E_NUMERIC; }
+    return DN_OK;
+}
+
+}  // extern "C"

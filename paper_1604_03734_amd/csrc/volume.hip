@@ -1,0 +1,645 @@
+// Volume lifecycle, block allocation (grid traversal, dedupe, canonical
+// hash), projective TSDF fusion and plain extraction for gfx950.
+//
+// Section III-A of the paper (hashing voxel grid, Eq. 1).  Discrete
+// decisions (block keys, pixel choice, truncation test) are taken in
+// float64 with contraction disabled, so they are reproducible bit for bit.
+#include <cstring>  // rocprim needs memset declared before its headers
+#include <rocprim/rocprim.hpp>
+
+#include <cstdarg>
+#include <cmath>
+
+#include "dn_internal.h"
+
+namespace dn {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int Buf::ensure(size_t need)
+{
+    if (need <= bytes) return DN_OK;
+    if (ptr) { (void)hipFree(ptr); ptr = nullptr; bytes = 0; }
+    size_t nb = need + need / 4 + 256;
+    DN_HIP(hipMalloc(&ptr, nb));
+    bytes = nb;
+    return DN_OK;
+}
+
+void Buf::release()
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+int HostBuf::ensure(size_t need)
+{
+    if (need <= bytes) return DN_OK;
+    if (ptr) { (void)hipHostFree(ptr); ptr = nullptr; bytes = 0; }
+    DN_HIP(hipHostMalloc(&ptr, need < 4096 ? 4096 : need, hipHostMallocDefault));
+    bytes = need < 4096 ? 4096 : need;
+    return DN_OK;
+}
+
+void HostBuf::release()
+{
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+int volume_sync(dn_volume *v)
+{
+    DN_HIP(hipStreamSynchronize(v->stream));
+    return DN_OK;
+}
+
+// ------------------------------------------------------------ block keys
+constexpr int64_t kKeyOff = int64_t(1) << 20;   // 21 bits per axis
+
+__host__ __device__ inline uint64_t pack_key(int32_t x, int32_t y, int32_t z)
+{
+    return (uint64_t(int64_t(x) + kKeyOff) << 42) | (uint64_t(int64_t(y) + kKeyOff) << 21) |
+           uint64_t(int64_t(z) + kKeyOff);
+}
+
+__host__ __device__ inline void unpack_key(uint64_t k, int32_t &x, int32_t &y, int32_t &z)
+{
+    const uint64_t m = (uint64_t(1) << 21) - 1;
+    x = int32_t(int64_t((k >> 42) & m) - kKeyOff);
+    y = int32_t(int64_t((k >> 21) & m) - kKeyOff);
+    z = int32_t(int64_t(k & m) - kKeyOff);
+}
+
+__device__ inline uint32_t bucket_of(int32_t x, int32_t y, int32_t z, uint32_t cap)
+{
+    uint32_t h = (uint32_t(x) * 73856093u) ^ (uint32_t(y) * 19349669u) ^ (uint32_t(z) * 83492791u);
+    return h & (cap - 1u);
+}
+
+// Probe forward from the bucket until the key or an empty slot; the table
+// never wraps, so the walk is bounded by the slot count.
+__device__ inline int32_t hash_lookup(const int4 *slots, int64_t nslots, uint32_t cap, int32_t x,
+                                      int32_t y, int32_t z)
+{
+    for (int64_t pos = bucket_of(x, y, z, cap); pos < nslots; ++pos) {
+        int4 sl = slots[pos];
+        if (sl.w < 0) return -1;
+        if (sl.x == x && sl.y == y && sl.z == z) return sl.w;
+    }
+    return -1;
+}
+
+struct Geo {
+    double fx, fy, cx, cy;
+    double T[16];
+    double s, mu, maxd;
+    int32_t W, H;
+};
+
+__device__ inline bool depth_ok(float d, double maxd)
+{
+    return isfinite(d) && d > 0.0f && double(d) <= maxd;
+}
+
+// Grid traversal of one pixel's band over the block grid.  Emits the
+// visited block keys through `emit` and returns how many were visited.
+template <class Emit>
+__device__ int dda_pixel(const Geo &g, int px, int py, float d, Emit emit)
+{
+    const double bs = 8.0 * g.s;
+    double rx = (double(px) - g.cx) / g.fx;
+    double ry = (double(py) - g.cy) / g.fy;
+    double z0 = double(d) - g.mu;
+    if (z0 < 1e-3) z0 = 1e-3;
+    double z1 = double(d) + g.mu;
+    double a[3], b[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double pa = ((g.T[4 * i + 0] * (z0 * rx) + g.T[4 * i + 1] * (z0 * ry)) + g.T[4 * i + 2] * z0) + g.T[4 * i + 3];
+        double pb = ((g.T[4 * i + 0] * (z1 * rx) + g.T[4 * i + 1] * (z1 * ry)) + g.T[4 * i + 2] * z1) + g.T[4 * i + 3];
+        a[i] = pa / bs;
+        b[i] = pb / bs;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (!(fabs(a[i]) < 1e6 && fabs(b[i]) < 1e6)) return 0;
+    int64_t k[3], left[3];
+    int step[3];
+    double tmax[3], tdel[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        k[i] = int64_t(floor(a[i]));
+        int64_t e = int64_t(floor(b[i]));
+        double dir = b[i] - a[i];
+        if (e > k[i]) {
+            step[i] = 1; left[i] = e - k[i];
+            tmax[i] = (double(k[i] + 1) - a[i]) / dir;
+            tdel[i] = 1.0 / dir;
+        } else if (e < k[i]) {
+            step[i] = -1; left[i] = k[i] - e;
+            tmax[i] = (double(k[i]) - a[i]) / dir;
+            tdel[i] = -1.0 / dir;
+        } else {
+            step[i] = 0; left[i] = 0; tmax[i] = 0.0; tdel[i] = 0.0;
+        }
+    }
+    int n = 0;
+    for (;;) {
+        emit(n, int32_t(k[0]), int32_t(k[1]), int32_t(k[2]));
+        ++n;
+        int c = -1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (left[i] == 0) continue;
+            if (c < 0 || tmax[i] < tmax[c]) c = i;
+        }
+        if (c < 0) break;
+        k[c] += step[c];
+        tmax[c] += tdel[c];
+        left[c] -= 1;
+    }
+    return n;
+}
+
+__global__ void k_dda_count(Geo g, const float *__restrict__ depth, int32_t *__restrict__ counts)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= int64_t(g.W) * g.H) return;
+    int px = int(i % g.W), py = int(i / g.W);
+    float d = depth[i];
+    int n = 0;
+    if (depth_ok(d, g.maxd)) n = dda_pixel(g, px, py, d, [](int, int32_t, int32_t, int32_t) {});
+    counts[i] = n;
+}
+
+__global__ void k_dda_emit(Geo g, const float *__restrict__ depth, const int32_t *__restrict__ offsets,
+                           uint64_t *__restrict__ out, int64_t total)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= int64_t(g.W) * g.H) return;
+    int px = int(i % g.W), py = int(i / g.W);
+    float d = depth[i];
+    if (!depth_ok(d, g.maxd)) return;
+    int64_t base = offsets[i];
+    dda_pixel(g, px, py, d, [&](int j, int32_t x, int32_t y, int32_t z) {
+        if (base + j < total) out[base + j] = pack_key(x, y, z);
+    });
+}
+
+__global__ void k_pack_coords(const int32_t *__restrict__ c3, int64_t n, uint64_t *__restrict__ out)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = pack_key(c3[3 * i], c3[3 * i + 1], c3[3 * i + 2]);
+}
+
+// flag[i] = 1 if uniq[i] is not in the table (only i < *count is valid)
+__global__ void k_flag_new(const uint64_t *__restrict__ uniq, const int64_t *__restrict__ count,
+                           const int4 *__restrict__ slots, int64_t nslots, uint32_t cap,
+                           uint8_t *__restrict__ flag, int64_t n_max)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_max) return;
+    if (i >= *count) { flag[i] = 0; return; }
+    int32_t x, y, z;
+    unpack_key(uniq[i], x, y, z);
+    flag[i] = hash_lookup(slots, nslots, cap, x, y, z) < 0 ? 1 : 0;
+}
+
+// Append the sorted new keys after the existing pool; clear their fields.
+__global__ void k_append(const uint64_t *__restrict__ newk, int64_t n_new, int64_t nb_old,
+                         int32_t *__restrict__ coords, uint64_t *__restrict__ keys)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_new) return;
+    int32_t x, y, z;
+    unpack_key(newk[i], x, y, z);
+    int64_t b = nb_old + i;
+    keys[b] = newk[i];
+    coords[4 * b + 0] = x; coords[4 * b + 1] = y; coords[4 * b + 2] = z; coords[4 * b + 3] = 0;
+}
+
+__global__ void k_zero_blocks(float *__restrict__ a, int64_t first, int64_t count)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count * kBlockVox) a[first * kBlockVox + i] = 0.0f;
+}
+
+__global__ void k_iota(int32_t *__restrict__ a, int64_t n)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = int32_t(i);
+}
+
+__global__ void k_bucket_of_keys(const uint64_t *__restrict__ keys, int64_t n, uint32_t cap,
+                                 uint32_t *__restrict__ home)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t x, y, z;
+    unpack_key(keys[i], x, y, z);
+    home[i] = bucket_of(x, y, z, cap);
+}
+
+// d[i] = home_sorted[i] - i (as int64), scanned later with max
+__global__ void k_home_minus_rank(const uint32_t *__restrict__ home, int64_t n, int64_t *__restrict__ d)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = int64_t(home[i]) - i;
+}
+
+__global__ void k_fill_empty(int4 *__restrict__ slots, int64_t n)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) slots[i] = make_int4(0, 0, 0, -1);
+}
+
+// Canonical slot of the i-th key in (bucket, key) order:
+// pos = max_{j<=i}(home_j - j) + i  (sequential linear probing, unrolled)
+__global__ void k_scatter_slots(const int64_t *__restrict__ runmax, const int32_t *__restrict__ ids,
+                                const int32_t *__restrict__ coords, int64_t n, int64_t nslots,
+                                int4 *__restrict__ slots, int32_t *__restrict__ overflow)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t pos = runmax[i] + i;
+    if (pos >= nslots) { atomicOr(overflow, 1); return; }
+    int32_t id = ids[i];
+    slots[pos] = make_int4(coords[4 * id], coords[4 * id + 1], coords[4 * id + 2], id);
+}
+
+__global__ void k_nbr_table(const int32_t *__restrict__ coords, int64_t nb, const int4 *__restrict__ slots,
+                            int64_t nslots, uint32_t cap, int32_t *__restrict__ nbr)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nb * kNbr) return;
+    int64_t b = i / kNbr;
+    int o = int(i % kNbr);
+    int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+    nbr[i] = (o == kCentre) ? int32_t(b)
+                            : hash_lookup(slots, nslots, cap, coords[4 * b] + dx,
+                                          coords[4 * b + 1] + dy, coords[4 * b + 2] + dz);
+}
+
+static inline unsigned grid1(int64_t n, int bs = 256) { return unsigned((n + bs - 1) / bs); }
+
+static int bits_for(uint64_t v)
+{
+    int b = 1;
+    while (b < 64 && (v >> b)) ++b;
+    return b;
+}
+
+// Insert a packed candidate list (device, n_cand entries, repeats allowed).
+// Dedupes, appends new keys in ascending order, rebuilds hash + neighbours.
+static int insert_packed(dn_volume *v, uint64_t *cand, int64_t n_cand, int32_t *n_new_out)
+{
+    hipStream_t st = v->stream;
+    if (n_new_out) *n_new_out = 0;
+    if (n_cand == 0) { v->last_nuniq = 0; return DN_OK; }
+    int rc;
+    // 1) sort + unique
+    if ((rc = v->s_sorted.ensure(n_cand * sizeof(uint64_t)))) return rc;
+    if ((rc = v->s_uniq.ensure(n_cand * sizeof(uint64_t)))) return rc;
+    if ((rc = v->s_flags.ensure(n_cand))) return rc;
+    if ((rc = v->s_new.ensure(n_cand * sizeof(uint64_t)))) return rc;
+    if ((rc = v->s_misc.ensure(64))) return rc;
+    int64_t *d_nuniq = v->s_misc.as<int64_t>();
+    int64_t *d_nnew = d_nuniq + 1;
+    uint64_t *sorted = v->s_sorted.as<uint64_t>();
+    uint64_t *uniq = v->s_uniq.as<uint64_t>();
+    size_t tb = 0, t2 = 0;
+    DN_HIP(rocprim::radix_sort_keys(nullptr, tb, cand, sorted, size_t(n_cand), 0, 63, st));
+    DN_HIP(rocprim::unique(nullptr, t2, sorted, uniq, d_nuniq, size_t(n_cand), rocprim::equal_to<uint64_t>(), st));
+    tb = tb > t2 ? tb : t2;
+    t2 = 0;
+    DN_HIP(rocprim::select(nullptr, t2, uniq, v->s_flags.as<uint8_t>(), v->s_new.as<uint64_t>(), d_nnew,
+                           size_t(n_cand), st));
+    tb = tb > t2 ? tb : t2;
+    if ((rc = v->s_tmp.ensure(tb))) return rc;
+    size_t tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::radix_sort_keys(v->s_tmp.ptr, tbytes, cand, sorted, size_t(n_cand), 0, 63, st));
+    tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::unique(v->s_tmp.ptr, tbytes, sorted, uniq, d_nuniq, size_t(n_cand),
+                           rocprim::equal_to<uint64_t>(), st));
+    // 2) which distinct keys are new
+    const int4 *slots = reinterpret_cast<const int4 *>(v->hash[v->cur_hash]);
+    hipLaunchKernelGGL(k_flag_new, dim3(grid1(n_cand)), dim3(256), 0, st, uniq, d_nuniq, slots,
+                       v->hash_slots, v->hash_cap, v->s_flags.as<uint8_t>(), n_cand);
+    DN_HIP(hipGetLastError());
+    tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::select(v->s_tmp.ptr, tbytes, uniq, v->s_flags.as<uint8_t>(), v->s_new.as<uint64_t>(),
+                           d_nnew, size_t(n_cand), st));
+    if ((rc = v->host.ensure(64))) return rc;
+    DN_HIP(hipMemcpyAsync(v->host.ptr, d_nuniq, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    DN_HIP(hipStreamSynchronize(st));
+    int64_t nuniq = v->host.as<int64_t>()[0];
+    int64_t n_new = v->host.as<int64_t>()[1];
+    v->last_nuniq = nuniq;
+    if (n_new == 0) return DN_OK;
+    if (v->nb + n_new > v->cap_blocks) {
+        set_error("block pool full: %lld + %lld new blocks > max_blocks %lld", (long long)v->nb,
+                  (long long)n_new, (long long)v->cap_blocks);
+        return DN_E_CAPACITY;
+    }
+    // 3) tentatively append (beyond nb; not committed until the hash fits)
+    const int64_t nb_old = v->nb, nb_new = v->nb + n_new;
+    hipLaunchKernelGGL(k_append, dim3(grid1(n_new)), dim3(256), 0, st, v->s_new.as<uint64_t>(), n_new,
+                       nb_old, v->coords, v->keys);
+    DN_HIP(hipGetLastError());
+    // 4) canonical table: sort (key -> id), then stable sort by bucket
+    if ((rc = v->s_vals.ensure(nb_new * sizeof(int32_t)))) return rc;
+    if ((rc = v->s_vals2.ensure(nb_new * sizeof(int32_t)))) return rc;
+    if ((rc = v->s_home.ensure(nb_new * sizeof(uint32_t)))) return rc;
+    if ((rc = v->s_home2.ensure(nb_new * sizeof(uint32_t)))) return rc;
+    if ((rc = v->s_pos.ensure(nb_new * sizeof(int64_t) * 2))) return rc;
+    if ((rc = v->s_cand2.ensure(nb_new * sizeof(uint64_t)))) return rc;
+    int32_t *ids0 = v->s_vals.as<int32_t>();
+    int32_t *ids1 = v->s_vals2.as<int32_t>();
+    uint64_t *ksorted = v->s_cand2.as<uint64_t>();
+    uint32_t *home = v->s_home.as<uint32_t>();
+    uint32_t *home2 = v->s_home2.as<uint32_t>();
+    int64_t *dm = v->s_pos.as<int64_t>();
+    int64_t *runmax = dm + nb_new;
+    hipLaunchKernelGGL(k_iota, dim3(grid1(nb_new)), dim3(256), 0, st, ids0, nb_new);
+    DN_HIP(hipGetLastError());
+    tb = 0;
+    DN_HIP(rocprim::radix_sort_pairs(nullptr, tb, v->keys, ksorted, ids0, ids1, size_t(nb_new), 0, 63, st));
+    const int hbits = bits_for(v->hash_cap - 1);
+    t2 = 0;
+    DN_HIP(rocprim::radix_sort_pairs(nullptr, t2, home, home2, ids1, ids0, size_t(nb_new), 0, hbits, st));
+    tb = tb > t2 ? tb : t2;
+    t2 = 0;
+    DN_HIP(rocprim::inclusive_scan(nullptr, t2, dm, runmax, size_t(nb_new), rocprim::maximum<int64_t>(), st));
+    tb = tb > t2 ? tb : t2;
+    if ((rc = v->s_tmp.ensure(tb))) return rc;
+    tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::radix_sort_pairs(v->s_tmp.ptr, tbytes, v->keys, ksorted, ids0, ids1, size_t(nb_new), 0, 63, st));
+    hipLaunchKernelGGL(k_bucket_of_keys, dim3(grid1(nb_new)), dim3(256), 0, st, ksorted, nb_new, v->hash_cap, home);
+    DN_HIP(hipGetLastError());
+    tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::radix_sort_pairs(v->s_tmp.ptr, tbytes, home, home2, ids1, ids0, size_t(nb_new), 0, hbits, st));
+    hipLaunchKernelGGL(k_home_minus_rank, dim3(grid1(nb_new)), dim3(256), 0, st, home2, nb_new, dm);
+    DN_HIP(hipGetLastError());
+    tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::inclusive_scan(v->s_tmp.ptr, tbytes, dm, runmax, size_t(nb_new), rocprim::maximum<int64_t>(), st));
+    int other = 1 - v->cur_hash;
+    int4 *dst = reinterpret_cast<int4 *>(v->hash[other]);
+    int32_t *d_ovf = reinterpret_cast<int32_t *>(d_nuniq + 2);
+    DN_HIP(hipMemsetAsync(d_ovf, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_fill_empty, dim3(grid1(v->hash_slots)), dim3(256), 0, st, dst, v->hash_slots);
+    DN_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scatter_slots, dim3(grid1(nb_new)), dim3(256), 0, st, runmax, ids0, v->coords, nb_new,
+                       v->hash_slots, dst, d_ovf);
+    DN_HIP(hipGetLastError());
+    DN_HIP(hipMemcpyAsync(v->host.ptr, d_ovf, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    DN_HIP(hipStreamSynchronize(st));
+    if (*v->host.as<int32_t>() != 0) {
+        set_error("hash table full: %lld keys do not fit 2^%d buckets + %d tail slots", (long long)nb_new,
+                  v->prm.hash_cap_log2, v->prm.hash_tail);
+        return DN_E_CAPACITY;
+    }
+    // 5) commit: new table, zeroed fields of the new blocks, neighbours
+    v->cur_hash = other;
+    float *fields[] = {v->f, v->w, v->u, v->ubar[0], v->ubar[1]};
+    for (float *a : fields) {
+        hipLaunchKernelGGL(k_zero_blocks, dim3(grid1(n_new * kBlockVox)), dim3(256), 0, st, a, nb_old, n_new);
+        DN_HIP(hipGetLastError());
+    }
+    for (int pp = 0; pp < 2; ++pp)
+        for (int a = 0; a < 3; ++a) {
+            hipLaunchKernelGGL(k_zero_blocks, dim3(grid1(n_new * kBlockVox)), dim3(256), 0, st,
+                               v->p[pp] + size_t(a) * v->cap_blocks * kBlockVox, nb_old, n_new);
+            DN_HIP(hipGetLastError());
+        }
+    v->nb = nb_new;
+    v->emask_nb = -1;
+    v->state_storage = DN_F32;
+    hipLaunchKernelGGL(k_nbr_table, dim3(grid1(nb_new * kNbr)), dim3(256), 0, st, v->coords, nb_new, dst,
+                       v->hash_slots, v->hash_cap, v->nbr);
+    DN_HIP(hipGetLastError());
+    if (n_new_out) *n_new_out = int32_t(n_new);
+    return DN_OK;
+}
+
+// ---------------------------------------------------------------- fusion
+__global__ void k_fuse(Geo g, const float *__restrict__ depth, const int32_t *__restrict__ coords,
+                       int64_t nb, float *__restrict__ f, float *__restrict__ w)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nb * kBlockVox) return;
+    int64_t b = i >> 9;
+    int vx = int(i & 7), vy = int((i >> 3) & 7), vz = int((i >> 6) & 7);
+    double d0 = (double(8 * coords[4 * b + 0] + vx) + 0.5) * g.s - g.T[3];
+    double d1 = (double(8 * coords[4 * b + 1] + vy) + 0.5) * g.s - g.T[7];
+    double d2 = (double(8 * coords[4 * b + 2] + vz) + 0.5) * g.s - g.T[11];
+    double xc = (g.T[0] * d0 + g.T[4] * d1) + g.T[8] * d2;
+    double yc = (g.T[1] * d0 + g.T[5] * d1) + g.T[9] * d2;
+    double zc = (g.T[2] * d0 + g.T[6] * d1) + g.T[10] * d2;
+    if (!(zc > 0.0)) return;
+    double X = g.fx * (xc / zc) + g.cx;
+    double Y = g.fy * (yc / zc) + g.cy;
+    double px = X + 0.5, py = Y + 0.5;
+    if (!(px >= 0.0 && px < double(g.W) && py >= 0.0 && py < double(g.H))) return;
+    int ix = int(floor(px)), iy = int(floor(py));
+    float d = depth[int64_t(iy) * g.W + ix];
+    if (!depth_ok(d, g.maxd)) return;
+    double eta = double(d) - zc;
+    if (eta < -g.mu) return;
+    double psi = eta / g.mu;
+    if (psi > 1.0) psi = 1.0;
+    float wo = w[i];
+    float wn = wo + 1.0f;
+    f[i] = (float(psi) + wo * f[i]) / wn;
+    w[i] = wn;
+}
+
+static int make_geo(const dn_volume *v, const dn_intrinsics *K, const double *T, Geo &g)
+{
+    DN_REQUIRE(K && T, "null intrinsics or pose");
+    DN_REQUIRE(K->width > 0 && K->height > 0 && K->fx != 0.0 && K->fy != 0.0, "bad intrinsics");
+    for (int i = 0; i < 16; ++i) DN_REQUIRE(std::isfinite(T[i]), "non-finite pose");
+    g.fx = K->fx; g.fy = K->fy; g.cx = K->cx; g.cy = K->cy;
+    for (int i = 0; i < 16; ++i) g.T[i] = T[i];
+    g.s = v->prm.voxel_size; g.mu = v->prm.mu; g.maxd = v->prm.max_depth;
+    g.W = K->width; g.H = K->height;
+    return DN_OK;
+}
+
+}  // namespace dn
+
+using namespace dn;
+
+// ================================================================== C ABI
+extern "C" {
+
+const char *dn_last_error(void) { return g_err; }
+
+int dn_volume_create(const dn_volume_params *p, void *hip_stream, dn_volume **out)
+{
+    DN_REQUIRE(p && out, "null argument");
+    *out = nullptr;
+    DN_REQUIRE(p->voxel_size > 0 && p->mu > 0 && p->max_depth > 0, "voxel_size, mu, max_depth must be > 0");
+    DN_REQUIRE(p->max_blocks >= 1, "max_blocks must be >= 1");
+    DN_REQUIRE(p->hash_cap_log2 >= 4 && p->hash_cap_log2 <= 30, "hash_cap_log2 must be in [4, 30]");
+    DN_REQUIRE(p->hash_tail >= 0, "hash_tail must be >= 0");
+    dn_volume *v = new dn_volume();
+    v->prm = *p;
+    v->stream = static_cast<hipStream_t>(hip_stream);
+    v->cap_blocks = p->max_blocks;
+    v->hash_cap = 1u << p->hash_cap_log2;
+    v->hash_slots = int64_t(v->hash_cap) + p->hash_tail;
+    auto fail = [&](int rc) { dn_volume_destroy(v); return rc; };
+    if (hipGetDevice(&v->device) != hipSuccess) { set_error("hipGetDevice failed"); return fail(DN_E_DEVICE); }
+    const size_t vox = size_t(v->cap_blocks) * kBlockVox;
+    struct { void **ptr; size_t bytes; } allocs[] = {
+        {(void **)&v->coords, size_t(v->cap_blocks) * 16},
+        {(void **)&v->keys, size_t(v->cap_blocks) * 8},
+        {(void **)&v->hash[0], size_t(v->hash_slots) * 16},
+        {(void **)&v->hash[1], size_t(v->hash_slots) * 16},
+        {(void **)&v->nbr, size_t(v->cap_blocks) * kNbr * 4},
+        {(void **)&v->f, vox * 4},
+        {(void **)&v->w, vox * 4},
+        {(void **)&v->u, vox * 4},
+        {(void **)&v->ubar[0], vox * 4},
+        {(void **)&v->ubar[1], vox * 4},
+        {(void **)&v->p[0], vox * 12},
+        {(void **)&v->p[1], vox * 12},
+        {(void **)&v->emask, vox},
+        {(void **)&v->order, size_t(v->cap_blocks) * 4},
+        {(void **)&v->partials, size_t(v->cap_blocks) * 16 + 64},
+        {(void **)&v->energy2, 64},
+    };
+    for (auto &a : allocs) {
+        if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
+            set_error("hipMalloc of %zu bytes failed", a.bytes);
+            return fail(DN_E_DEVICE);
+        }
+    }
+    hipStream_t st = v->stream;
+    if (hipMemsetAsync(v->f, 0, vox * 4, st) != hipSuccess || hipMemsetAsync(v->w, 0, vox * 4, st) != hipSuccess) {
+        set_error("hipMemsetAsync failed");
+        return fail(DN_E_DEVICE);
+    }
+    hipLaunchKernelGGL(k_fill_empty, dim3(grid1(v->hash_slots)), dim3(256), 0, st,
+                       reinterpret_cast<int4 *>(v->hash[0]), v->hash_slots);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+        set_error("initialisation failed");
+        return fail(DN_E_DEVICE);
+    }
+    *out = v;
+    return DN_OK;
+}
+
+void dn_volume_destroy(dn_volume *v)
+{
+    if (!v) return;
+    (void)hipStreamSynchronize(v->stream);
+    void *ptrs[] = {v->coords, v->keys, v->hash[0], v->hash[1], v->nbr, v->f, v->w, v->u,
+                    v->ubar[0], v->ubar[1], v->p[0], v->p[1], v->emask, v->order, v->partials,
+                    v->energy2, v->u16, v->ubar16[0], v->ubar16[1], v->p16[0], v->p16[1]};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    dn::Buf *bufs[] = {&v->s_cand, &v->s_cand2, &v->s_counts, &v->s_offsets, &v->s_tmp, &v->s_uniq,
+                       &v->s_flags, &v->s_new, &v->s_sorted, &v->s_vals, &v->s_vals2, &v->s_home,
+                       &v->s_home2, &v->s_pos, &v->s_misc};
+    for (auto *b : bufs) b->release();
+    v->host.release();
+    delete v;
+}
+
+int dn_set_stream(dn_volume *v, void *hip_stream)
+{
+    DN_REQUIRE(v, "null volume");
+    v->stream = static_cast<hipStream_t>(hip_stream);
+    return DN_OK;
+}
+
+int64_t dn_num_blocks(const dn_volume *v) { return v ? v->nb : -1; }
+
+int dn_sync(dn_volume *v)
+{
+    DN_REQUIRE(v, "null volume");
+    return volume_sync(v);
+}
+
+int dn_alloc_blocks(dn_volume *v, const float *depth, const dn_intrinsics *K, const double T[16],
+                    int32_t *n_new_out)
+{
+    DN_REQUIRE(v && depth, "null argument");
+    Geo g;
+    int rc = make_geo(v, K, T, g);
+    if (rc) return rc;
+    if (n_new_out) *n_new_out = 0;
+    hipStream_t st = v->stream;
+    const int64_t npx = int64_t(g.W) * g.H;
+    if ((rc = v->s_counts.ensure(npx * 4))) return rc;
+    if ((rc = v->s_offsets.ensure(npx * 4 + 8))) return rc;
+    int32_t *counts = v->s_counts.as<int32_t>();
+    int32_t *offs = v->s_offsets.as<int32_t>();
+    hipLaunchKernelGGL(k_dda_count, dim3(grid1(npx)), dim3(256), 0, st, g, depth, counts);
+    DN_HIP(hipGetLastError());
+    size_t tb = 0;
+    DN_HIP(rocprim::exclusive_scan(nullptr, tb, counts, offs, 0, size_t(npx), rocprim::plus<int32_t>(), st));
+    if ((rc = v->s_tmp.ensure(tb))) return rc;
+    size_t tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::exclusive_scan(v->s_tmp.ptr, tbytes, counts, offs, 0, size_t(npx), rocprim::plus<int32_t>(), st));
+    if ((rc = v->host.ensure(64))) return rc;
+    DN_HIP(hipMemcpyAsync(v->host.as<int32_t>(), offs + npx - 1, 4, hipMemcpyDeviceToHost, st));
+    DN_HIP(hipMemcpyAsync(v->host.as<int32_t>() + 1, counts + npx - 1, 4, hipMemcpyDeviceToHost, st));
+    DN_HIP(hipStreamSynchronize(st));
+    int64_t total = int64_t(v->host.as<int32_t>()[0]) + v->host.as<int32_t>()[1];
+    if (total == 0) { v->last_nuniq = 0; return DN_OK; }
+    if ((rc = v->s_cand.ensure(total * 8))) return rc;
+    hipLaunchKernelGGL(k_dda_emit, dim3(grid1(npx)), dim3(256), 0, st, g, depth, offs, v->s_cand.as<uint64_t>(), total);
+    DN_HIP(hipGetLastError());
+    return insert_packed(v, v->s_cand.as<uint64_t>(), total, n_new_out);
+}
+
+int dn_insert_blocks(dn_volume *v, const int32_t *coords, int64_t n, int32_t *n_new_out)
+{
+    DN_REQUIRE(v && (coords || n == 0) && n >= 0, "bad argument");
+    if (n_new_out) *n_new_out = 0;
+    if (n == 0) return DN_OK;
+    int rc;
+    if ((rc = v->s_cand.ensure(n * 8))) return rc;
+    hipLaunchKernelGGL(k_pack_coords, dim3(grid1(n)), dim3(256), 0, v->stream, coords, n, v->s_cand.as<uint64_t>());
+    DN_HIP(hipGetLastError());
+    return insert_packed(v, v->s_cand.as<uint64_t>(), n, n_new_out);
+}
+
+int dn_fuse_depth(dn_volume *v, const float *depth, const dn_intrinsics *K, const double T[16])
+{
+    DN_REQUIRE(v && depth, "null argument");
+    Geo g;
+    int rc = make_geo(v, K, T, g);
+    if (rc) return rc;
+    if (v->nb == 0) return DN_OK;
+    hipLaunchKernelGGL(k_fuse, dim3(grid1(v->nb * kBlockVox)), dim3(256), 0, v->stream, g, depth, v->coords,
+                       v->nb, v->f, v->w);
+    DN_HIP(hipGetLastError());
+    v->emask_nb = -1;
+    return DN_OK;
+}
+
+int dn_load_fused(dn_volume *v, const float *f, const float *w)
+{
+    DN_REQUIRE(v && f && w, "null argument");
+    if (v->nb == 0) return DN_OK;
+    size_t bytes = size_t(v->nb) * kBlockVox * 4;
+    DN_HIP(hipMemcpyAsync(v->f, f, bytes, hipMemcpyDeviceToDevice, v->stream));
+    DN_HIP(hipMemcpyAsync(v->w, w, bytes, hipMemcpyDeviceToDevice, v->stream));
+    v->emask_nb = -1;
+    return DN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+"""GPU (HIP library through the C ABI) against the FP64 oracle.
+
+Bars: bit-exact for allocation (candidate keys, pool order, hash slots,
+neighbour table) and for the fusion weights; max-abs 1e-4 on the fused
+TSDF f and on u after the same number of iterations (FP32 arithmetic);
+energies within 1e-9 relative of the oracle evaluated on the GPU state."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from gpu_common import LAM, SIG, TAU, dn, fuse_both, host, intr, K4, state_of, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_F = 1e-4
+TOL_U = 1e-4
+
+
+@pytest.fixture(scope="module")
+def c1():
+    fr = scenes.frames_c1(0)
+    ov, gv = fuse_both(fr)
+    return fr, ov, gv
+
+
+def test_c1_allocation_bit_exact(c1):
+    D = dn()
+    fr, ov, gv = c1
+    assert gv.num_blocks == ov.nb
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_COORDS)), ov.coords)
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_HASH)), ov.slots)
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_NBR)), ov.nbr)
+
+
+def test_c1_fusion_parity(c1):
+    D = dn()
+    fr, ov, gv = c1
+    w = host(gv.extract(D.DN_X_W))
+    f = host(gv.extract(D.DN_X_F))
+    np.testing.assert_array_equal(w, ov.w)
+    assert np.abs(f - ov.f).max() <= TOL_F
+    assert (w > 0).sum() > 50000
+
+
+@pytest.mark.parametrize("kernel", ["twopass", "fused"])
+def test_c1_regularize_parity(c1, kernel):
+    D = dn()
+    fr, ov, gv = c1
+    k = D.DN_K_TWOPASS if kernel == "twopass" else D.DN_K_FUSED
+    st = gv.regularize(D.reg_params(LAM, TAU, SIG, 1.0, iters=200, kernel=k))
+    assert st.iters_run == 200
+    u = np.zeros_like(ov.f); ub = np.zeros_like(u); p = np.zeros((3,) + u.shape)
+    oracle.cp(ov.nbr, ov.f, ov.w, u, ub, p, 200, LAM, TAU, SIG, 1.0)
+    gu, gub, gp = state_of(D, gv)
+    assert np.abs(gu - u).max() <= TOL_U
+    assert np.abs(gp - p).max() <= 10 * TOL_U
+    assert np.sqrt((gp ** 2).sum(0)).max() <= 1.0 + 1e-6
+    assert (gu[ov.w == 0] == 0).all()
+    # the library's energies equal the oracle's on the same (GPU) state
+    E, Dd = oracle.energy(ov.nbr, ov.f, ov.w, gu, gp, LAM)
+    assert abs(st.energy - E) <= 1e-9 * abs(E)
+    assert abs(st.dual - Dd) <= 1e-9 * abs(E)
+    assert st.gap >= 0
+
+
+def test_fused_equals_twopass_and_is_deterministic(c1):
+    D = dn()
+    fr, ov, gv = c1
+    gv.regularize(D.reg_params(LAM, iters=60, kernel=D.DN_K_FUSED))
+    a = state_of(D, gv)
+    gv.regularize(D.reg_params(LAM, iters=60, kernel=D.DN_K_FUSED))
+    b = state_of(D, gv)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    gv.regularize(D.reg_params(LAM, iters=60, kernel=D.DN_K_TWOPASS))
+    c = state_of(D, gv)
+    assert np.abs(a[0] - c[0]).max() <= 1e-5
+
+
+def test_split_run_resumes_exactly(c1):
+    D = dn()
+    fr, ov, gv = c1
+    gv.regularize(D.reg_params(LAM, iters=80, kernel=D.DN_K_FUSED))
+    whole = state_of(D, gv)
+    gv.regularize(D.reg_params(LAM, iters=30, kernel=D.DN_K_FUSED))
+    gv.regularize(D.reg_params(LAM, iters=50, kernel=D.DN_K_FUSED, init=D.DN_INIT_KEEP))
+    split = state_of(D, gv)
+    for x, y in zip(whole, split):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_gap_checks_and_early_stop(c1):
+    D = dn()
+    fr, ov, gv = c1
+    st = gv.regularize(D.reg_params(LAM, iters=2000, gap_every=10, gap_tol=1e-2, kernel=D.DN_K_FUSED))
+    assert st.converged == 1 and st.iters_run < 2000 and st.iters_run % 10 == 0
+    assert st.rel_gap <= 1e-2
+    st2 = gv.regularize(D.reg_params(LAM, iters=st.iters_run - 10, kernel=D.DN_K_FUSED))
+    assert st2.rel_gap > 1e-2
+
+
+def test_c1_surface_parity(c1):
+    D = dn()
+    fr, ov, gv = c1
+    gv.regularize(D.reg_params(LAM, iters=100, kernel=D.DN_K_FUSED))
+    gu = host(gv.extract(D.DN_X_U)).astype(np.float64)
+    pts = host(gv.extract(D.DN_X_SURFACE)).astype(np.float64)
+    ref = oracle.extract(ov.coords, ov.nbr, ov.w, gu, fr.voxel_size)
+    assert len(pts) == len(ref) and len(ref) > 1000
+    assert np.abs(pts - ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("seed,nb,extent", [(0, 1, 2), (1, 13, 3), (2, 37, 4), (3, 90, 5)])
+def test_random_sparse_fields_regularize_parity(seed, nb, extent):
+    """Arbitrary block sets with unobserved voxels and unallocated
+    neighbours (every boundary case of Eqs. 3-4)."""
+    D = dn()
+    import torch
+    coords, f, w = scenes.random_block_field(nb, seed, extent=extent, omega_frac=0.7)
+    cap, tail = 64, 64
+    ov = oracle.OracleVolume(0.1, 0.3, 10.0, 1024, 6, tail)
+    assert ov.insert(coords) == nb
+    order = np.array([np.nonzero((coords == c).all(1))[0][0] for c in ov.coords])
+    ov.f[:] = f[order]; ov.w[:] = w[order]
+    gv = D.Volume(0.1, 0.3, 10.0, 1024, 6, tail)
+    assert gv.insert_blocks(to_dev(coords.astype(np.int32))) == nb
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_COORDS)), ov.coords)
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_HASH)), ov.slots)
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_NBR)), ov.nbr)
+    gv.load_fused(to_dev(ov.f, torch.float32), to_dev(ov.w, torch.float32))
+    fo = ov.f.astype(np.float32).astype(np.float64)
+    for kernel in (D.DN_K_FUSED, D.DN_K_TWOPASS):
+        st = gv.regularize(D.reg_params(LAM, iters=50, kernel=kernel))
+        u = np.zeros_like(fo); ub = np.zeros_like(u); p = np.zeros((3,) + u.shape)
+        oracle.cp(ov.nbr, fo, ov.w, u, ub, p, 50, LAM, TAU, SIG, 1.0)
+        gu, gub, gp = state_of(D, gv)
+        assert np.abs(gu - u).max() <= TOL_U
+        assert np.abs(gub - ub).max() <= 3 * TOL_U
+        em = host(gv.extract(D.DN_X_EMASK))
+        assert ((em & 1) == (ov.w > 0)).all()
+        E, Dd = oracle.energy(ov.nbr, fo, ov.w, gu, gp, LAM)
+        assert abs(st.energy - E) <= 1e-9 * abs(E) and abs(st.dual - Dd) <= 1e-9 * abs(E)
+
+
+def test_given_initial_state_and_ragged_capacity():
+    D = dn()
+    import torch
+    coords, f, w = scenes.random_block_field(20, 5, extent=3, omega_frac=0.8)
+    gv = D.Volume(0.1, 0.3, 10.0, 20, 5, 32)
+    gv.insert_blocks(to_dev(coords.astype(np.int32)))
+    c = host(gv.extract(D.DN_X_COORDS))
+    order = np.array([np.nonzero((coords == x).all(1))[0][0] for x in c])
+    f, w = f[order], w[order]
+    gv.load_fused(to_dev(f, torch.float32), to_dev(w, torch.float32))
+    rng = np.random.default_rng(0)
+    u0 = rng.uniform(-1, 1, f.shape)
+    p0 = rng.uniform(-0.5, 0.5, (3,) + f.shape)
+    st = gv.regularize(D.reg_params(LAM, iters=25, init=D.DN_INIT_GIVEN, kernel=D.DN_K_FUSED),
+                       u0=to_dev(u0, torch.float32), p0=to_dev(p0, torch.float32))
+    _, nbr = oracle.OracleVolume, host(gv.extract(D.DN_X_NBR))
+    fo = f.astype(np.float32).astype(np.float64)
+    u = u0.astype(np.float32).astype(np.float64); ub = u.copy()
+    p = p0.astype(np.float32).astype(np.float64)
+    oracle.cp(nbr, fo, w, u, ub, p, 25, LAM, TAU, SIG, 1.0)
+    gu = host(gv.extract(D.DN_X_U))
+    assert np.abs(gu - u).max() <= TOL_U
+    # the pool is full: one more block is a capacity error, volume unchanged
+    with pytest.raises(D.DenserError) as e:
+        gv.insert_blocks(to_dev(np.array([[50, 50, 50]], np.int32)))
+    assert e.value.code == D.DN_E_CAPACITY
+    assert gv.num_blocks == 20
+
+
+def test_error_paths_and_degenerate_inputs():
+    D = dn()
+    import torch
+    gv = D.Volume(0.1, 0.3, 10.0, 64, 6, 8)
+    # empty volume: regularize and extract are no-ops
+    st = gv.regularize(D.reg_params(LAM, iters=10))
+    assert st.iters_run == 0 and st.energy == 0.0
+    assert gv.extract(D.DN_X_SURFACE).shape[0] == 0
+    # an all-invalid frame allocates nothing
+    cam = scenes.Camera(50, 50, 15.5, 11.5, 32, 24)
+    bad = np.full((24, 32), np.nan, np.float32)
+    bad[::2] = 0.0
+    assert gv.alloc_blocks(to_dev(bad), intr(D, cam), np.eye(4)) == 0
+    # invalid parameters
+    with pytest.raises(D.DenserError) as e:
+        gv.regularize(D.reg_params(LAM, tau=1.0, sigma=1.0, iters=1))
+    assert e.value.code == D.DN_E_INVALID
+    with pytest.raises(D.DenserError):
+        D.Volume(0.1, 0.3, 10.0, 64, 2, 8)
+    # hash overflow leaves the volume unchanged
+    tiny = D.Volume(0.1, 0.3, 10.0, 1000, 4, 2)
+    keys = np.stack([np.arange(40), np.zeros(40), np.zeros(40)], 1).astype(np.int32)
+    with pytest.raises(D.DenserError) as e:
+        tiny.insert_blocks(to_dev(keys))
+    assert e.value.code == D.DN_E_CAPACITY and tiny.num_blocks == 0
+    assert tiny.insert_blocks(to_dev(keys[:5])) == 5
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_mixed_precision_error_is_reported_and_bounded(c1, storage):
+    D = dn()
+    fr, ov, gv = c1
+    s = D.DN_F16 if storage == "f16" else D.DN_BF16
+    st = gv.regularize(D.reg_params(LAM, iters=200, storage=s, refine_every=50))
+    u = np.zeros_like(ov.f); ub = np.zeros_like(u); p = np.zeros((3,) + u.shape)
+    oracle.cp(ov.nbr, ov.f, ov.w, u, ub, p, 200, LAM, TAU, SIG, 1.0)
+    gu = host(gv.extract(D.DN_X_U)).astype(np.float64)
+    om = ov.w > 0
+    err = np.abs(gu - u)[om]
+    print(f"{storage}: max {err.max():.3e} median {np.median(err):.3e} rel_gap {st.rel_gap:.3e}")
+    bound = 2e-2 if storage == "f16" else 1.5e-1
+    assert err.max() <= bound
+    assert st.gap >= 0
+    gp = host(gv.extract(D.DN_X_P))
+    assert np.sqrt((gp.astype(np.float64) ** 2).sum(0)).max() <= 1.0 + 1e-6
