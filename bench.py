@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X: street-scale fusion into hashed
+8^3 blocks followed by Omega-masked TV primal-dual regularisation.
+
+One step (timed, inputs already resident in HBM):
+  1. allocate + fuse 100 synthetic 1242x375 depth maps of a 100 m street
+     (0.2 m voxels, mu = 0.6 m) into a block-hashed volume;
+  2. lay out the fused street `--copies` times side by side (translated
+     along x, no shared faces) in one volume, to reach the ~2e5-block map of
+     the street-scale workload (the 100 m street alone holds ~5.8e3
+     blocks), through the library's own block insertion;
+  3. 500 Chambolle-Pock iterations (lambda 0.5, tau = sigma = 1/sqrt(12))
+     with the final primal-dual gap in float64;
+  4. extraction of the zero-crossing surface.
+value = allocated voxels x iterations / step time (voxel-iterations/s).
+
+The JSON line also carries the roofline of the dominant kernel (the fused
+iteration kernel, 48 algorithmic bytes per voxel-iteration, timed with HIP
+events on the volume's stream), the FP64 CPU oracle timed on one street as
+the CPU baseline, and the time to a relative gap of 1e-3 of the plain and
+the warm-started solver.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+ALG_BYTES_PER_VOXEL_ITER = 48  # u, ubar, p(3), f, w read; p(3), u, ubar written (FP32)
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iters", type=int, default=500)
+    ap.add_argument("--copies", type=int, default=35)
+    ap.add_argument("--frames", type=int, default=100)
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "twopass"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap comparison")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for profilers: no CPU baseline, no time-to-gap")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_digest():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1604_03734_amd", "csrc", "regularize.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(nvox):
+    """HBM bytes per launch of the fused kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "cp_fused_street35_traffic.json")
+    try:
+        with open(p) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("source_digest") != src_digest():
+        return None
+    return t["bytes_per_voxel_iter"] * nvox
+
+
+class Workload:
+    def __init__(self, args):
+        import torch
+        import scenes
+        from paper_1604_03734_amd import denser as D
+        self.D, self.torch, self.args = D, torch, args
+        t0 = time.time()
+        self.fr = scenes.frames_c2(0, n_frames=args.frames)
+        log(f"generated {len(self.fr.depths)} depth maps in {time.time() - t0:.1f}s")
+        cam = self.fr.camera
+        self.K = D.intrinsics(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height)
+        self.depths = [torch.from_numpy(d).cuda() for d in self.fr.depths]
+        self.street = D.Volume(self.fr.voxel_size, self.fr.mu, self.fr.max_depth, 16384, 16, 1024)
+        self.big = D.Volume(self.fr.voxel_size, self.fr.mu, self.fr.max_depth, 1 << 18, 19, 8192)
+        self.kernel = {"auto": D.DN_K_AUTO, "fused": D.DN_K_FUSED, "twopass": D.DN_K_TWOPASS}[args.kernel]
+        torch.cuda.synchronize()
+
+    def fuse_street(self):
+        self.street.clear()
+        for d, T in zip(self.depths, self.fr.poses):
+            self.street.alloc_blocks(d, self.K, T)
+            self.street.fuse_depth(d, self.K, T)
+
+    def build_map(self):
+        """Translated copies of the fused street in one volume."""
+        D, torch = self.D, self.torch
+        c = self.street.extract(D.DN_X_COORDS).long()
+        f = self.street.extract(D.DN_X_F)
+        w = self.street.extract(D.DN_X_W)
+        off = 1 << 20
+        key = ((c[:, 0] + off) << 42) | ((c[:, 1] + off) << 21) | (c[:, 2] + off)
+        order = torch.argsort(key)
+        cs = c[order]
+        width = int((cs[:, 0].max() - cs[:, 0].min()).item()) + 3
+        k = self.args.copies
+        shift = torch.zeros((k, 1, 3), dtype=torch.long, device=c.device)
+        shift[:, 0, 0] = torch.arange(k, device=c.device) * width
+        coords = (cs[None] + shift).reshape(-1, 3).to(torch.int32).contiguous()
+        self.big.clear()
+        self.big.insert_blocks(coords)
+        self.big.load_fused(f[order].repeat(k, 1).contiguous(), w[order].repeat(k, 1).contiguous())
+
+    def step(self):
+        D = self.D
+        self.fuse_street()
+        self.build_map()
+        st = self.big.regularize(D.reg_params(0.5, iters=self.args.iters, gap_every=0, kernel=self.kernel))
+        pts = self.big.extract(D.DN_X_SURFACE)
+        return st, pts.shape[0]
+
+
+def cpu_baseline(wl):
+    """The FP64 oracle on one street (the same frames): allocation + fusion
+    of every frame and the same number of iterations, all host cores."""
+    import oracle
+    fr = wl.fr
+    cam = fr.camera
+    K4 = [cam.fx, cam.fy, cam.cx, cam.cy]
+    nt = oracle.nthreads_default()
+    t0 = time.time()
+    ov = oracle.OracleVolume(fr.voxel_size, fr.mu, fr.max_depth, 16384, 16, 1024)
+    for d, T in zip(fr.depths, fr.poses):
+        ov.alloc(d, K4, T)
+        ov.fuse(d, K4, T, nthreads=nt)
+    t_fuse = time.time() - t0
+    u = np.zeros_like(ov.f); ub = np.zeros_like(u); p = np.zeros((3,) + u.shape)
+    iters = wl.args.iters
+    t1 = time.time()
+    oracle.cp(ov.nbr, ov.f, ov.w, u, ub, p, iters, 0.5, 12 ** -0.5, 12 ** -0.5, 1.0, nthreads=nt)
+    t_cp = time.time() - t1
+    vox = ov.nb * 512
+    return {
+        "value": vox * iters / (t_fuse + t_cp), "unit": "voxel-iterations/s", "cores": nt,
+        "kind": "oracle",
+        "sample": f"one 100 m street ({ov.nb} blocks, not the {wl.args.copies} copies): "
+                  f"alloc+fuse {len(fr.depths)} frames {t_fuse:.1f}s + {iters} iterations {t_cp:.1f}s",
+        "cp_only_voxel_iters_per_s": vox * iters / t_cp,
+    }
+
+
+def time_to_gap(wl, tol=1e-3, k=100):
+    """Wall time to relative gap <= tol on the street map: the plain solver
+    from zero vs the learned warm start (network inference + iterations,
+    with the fallback to a cold start), both including their gap checks."""
+    D = wl.D
+    torch = wl.torch
+    from paper_1604_03734_amd import warmstart
+    out = {"tol": tol, "k": k}
+    torch.cuda.synchronize()
+    t0 = time.time()
+    st = warmstart.solve_plain(wl.big, tol)
+    torch.cuda.synchronize()
+    out["plain_s"] = time.time() - t0
+    out["plain_iters"] = st.iters_run
+    out["plain_converged"] = bool(st.converged)
+    w = warmstart.load_default_weights()
+    if w is None:
+        out["warm_s"] = None
+        out["note"] = "no trained weights in the package"
+        return out
+    ref = wl.big.regularize(D.reg_params(0.5, iters=k, kernel=D.DN_K_FUSED))
+    wt = torch.from_numpy(w).cuda()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    res = warmstart.solve_warm(wl.big, wt, tol=tol, k=k, plain_rel_gap_at_k=ref.rel_gap)
+    torch.cuda.synchronize()
+    out["warm_s"] = time.time() - t0
+    out["plain_rel_gap_at_k"] = ref.rel_gap
+    out.update({"warm_" + key: val for key, val in res.items() if key != "seconds"})
+    out["speedup"] = out["plain_s"] / out["warm_s"]
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    from paper_1604_03734_amd import denser as D
+    D.lib()
+    if args.profile:
+        args.no_cpu = args.no_gap = True
+    wl = Workload(args)
+    for i in range(args.warmup):
+        st, npts = wl.step()
+        torch.cuda.synchronize()
+        log(f"warmup {i}: blocks {wl.big.num_blocks} ms_loop {st.ms_loop:.1f}")
+    torch.cuda.synchronize()
+    times, loops = [], []
+    t_all = time.time()
+    for i in range(args.steps):
+        t0 = time.time()
+        st, npts = wl.step()
+        torch.cuda.synchronize()
+        times.append(time.time() - t0)
+        loops.append(st.ms_loop / max(1, st.iters_run))
+        log(f"step {i}: {times[-1]:.3f}s, loop {st.ms_loop:.1f} ms, rel_gap {st.rel_gap:.3e}, points {npts}")
+    torch.cuda.synchronize()
+    total = time.time() - t_all
+    nb = wl.big.num_blocks
+    nvox = nb * 512
+    ms_step = 1000.0 * total / max(1, args.steps)
+    value = nvox * args.iters / (ms_step / 1000.0)
+    kern_ms = float(np.mean(loops))
+    achieved = ALG_BYTES_PER_VOXEL_ITER * nvox / (kern_ms / 1000.0) / 1e9
+    traffic = load_traffic(nvox)
+    line = {
+        "metric": "voxel-iterations/s (fusion + 500 CP iterations + gap + surface, street map)",
+        "value": value,
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "street-scale plain method, FP32: 100 depth maps 1242x375 of a 100 m "
+                               "synthetic street, 0.2 m voxels, mu 0.6 m, sigma 0.5 px, 5% invalid; "
+                               f"map = {args.copies} translated copies of the fused street",
+                   "blocks": nb, "voxels": nvox, "street_blocks": wl.street.num_blocks,
+                   "iters": args.iters, "lambda": 0.5, "kernel": args.kernel},
+        "roofline": {"bound": "hbm", "kernel": "k_cp_fused (one CP iteration)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "alg_bytes_per_launch": ALG_BYTES_PER_VOXEL_ITER * nvox,
+                     "avg_launch_ms": kern_ms},
+        "cp_voxel_iters_per_s": nvox / (kern_ms / 1000.0),
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle ...")
+        line["cpu_baseline"] = cpu_baseline(wl)
+    if not args.no_gap:
+        log("time to gap ...")
+        line["time_to_gap"] = time_to_gap(wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -46,7 +46,6 @@ extern "C" {
 #define DN_F32 0          /* 32-bit float state                                */
 #define DN_F16 1          /* IEEE half state, FP32 arithmetic                  */
 #define DN_BF16 2         /* bfloat16 state, FP32 arithmetic                   */
-#define DN_STORE_OFFSET 16 /* flag: u and ubar are stored as (u - f) in 16 bits */
 
 /* --------------------------------------------------- initial solver state */
 #define DN_INIT_ZERO 0   /* u = ubar = p = 0 (Section III-C, step 1)          */
@@ -95,7 +94,7 @@ typedef struct {
     int32_t iters;           /* maximum number of iterations                 */
     int32_t gap_every;       /* compute the gap every this many iterations; 0: only at the end */
     double gap_tol;          /* stop once (E - D) / E <= gap_tol (0: never)  */
-    int32_t storage;         /* DN_F32, DN_F16 or DN_BF16 (| DN_STORE_OFFSET) */
+    int32_t storage;         /* DN_F32, DN_F16 or DN_BF16                    */
     int32_t refine_every;    /* 16-bit storage: FP32 sweep every this many iterations (0: none) */
     int32_t init;            /* DN_INIT_*                                    */
     int32_t kernel;          /* DN_K_*                                       */
@@ -108,6 +107,8 @@ typedef struct {
     double rel_gap;          /* (E - D) / E                                   */
     int32_t iters_run;       /* iterations performed by this call             */
     int32_t converged;       /* 1 if gap_tol was reached                      */
+    double ms_loop;          /* HIP-event time of the iteration loop on the
+                                volume's stream (gap checks included)        */
 } dn_reg_stats;
 
 /* ------------------------------------------------------------ lifecycle */
@@ -119,6 +120,10 @@ int dn_volume_create(const dn_volume_params *params, void *hip_stream, dn_volume
 
 /* Release all device storage of the volume (synchronises its stream). */
 void dn_volume_destroy(dn_volume *vol);
+
+/* Remove every block (the volume becomes empty; its capacity is kept).
+ * Enqueue only. */
+int dn_volume_clear(dn_volume *vol);
 
 /* Change the stream subsequent calls are ordered on. */
 int dn_set_stream(dn_volume *vol, void *hip_stream);

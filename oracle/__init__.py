@@ -214,6 +214,16 @@ def _pack(c: np.ndarray) -> np.ndarray:
     return (c[:, 0] << 42) | (c[:, 1] << 21) | c[:, 2]
 
 
+def _unique_rows(c) -> np.ndarray:
+    """Distinct (x, y, z) rows in ascending lexicographic order."""
+    c = np.asarray(c, np.int32).reshape(-1, 3)
+    if len(c) == 0:
+        return c
+    k = np.unique(_pack(c))
+    m = (1 << 21) - 1
+    return np.stack([(k >> 42) & m, (k >> 21) & m, k & m], 1).astype(np.int64).__sub__(1 << 20).astype(np.int32)
+
+
 @dataclass
 class OracleVolume:
     """Block pool + hash + fused fields, bookkept exactly as the boundary
@@ -242,7 +252,7 @@ class OracleVolume:
 
     def insert(self, keys: np.ndarray) -> int:
         """Append the keys not yet present, in ascending order."""
-        keys = np.unique(np.asarray(keys, np.int32).reshape(-1, 3), axis=0)
+        keys = _unique_rows(keys)
         if len(self.coords):
             new = keys[~np.isin(_pack(keys), _pack(self.coords))]
         else:
@@ -261,8 +271,8 @@ class OracleVolume:
 
     def alloc(self, depth, K4, T) -> int:
         c = candidates(depth, K4, T, self.voxel_size, self.mu, self.max_depth)
-        self.last_candidates = np.unique(c, axis=0) if len(c) else c
-        return self.insert(c)
+        self.last_candidates = _unique_rows(c)
+        return self.insert(self.last_candidates)
 
     def fuse(self, depth, K4, T, nthreads=None):
         fuse(self.coords, self.f, self.w, depth, K4, T, self.voxel_size, self.mu,

@@ -1,0 +1,371 @@
+// Many sub-maps in one persistent launch (gfx950).
+//
+// All (sub-map, block) work items of every volume run in one kernel that
+// loops over the iterations itself; a grid-wide barrier separates one
+// iteration from the next (the fused iteration reads its neighbours' ubar
+// and p of the previous iteration).  The launch is captured in a HIP graph
+// together with the reset of the barrier state and replayed.  Grid size
+// and the item-to-workgroup mapping are picked by timing short trial runs
+// (autotuner), cached per problem size.
+#include <cstring>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <vector>
+
+#include "cp_kernel.h"
+#include "dn_internal.h"
+
+namespace dn {
+
+struct VolDesc {
+    const int32_t *nbr;
+    const uint8_t *emask;
+    const float *f, *w;
+    float *u;
+    float *ubar[2];
+    float *p[2];
+    int64_t pstride;
+    int32_t cur;
+    int32_t pad;
+};
+
+struct BatchArgs {
+    const VolDesc *vols;
+    const int2 *items;        // (volume, block) in processing order
+    int64_t n_items;
+    int32_t iters;
+    int32_t xcd_chunks;       // 1: each XCD works on one contiguous item chunk
+    float sigma, tau, lambda, theta;
+    unsigned *bar;            // [0] arrivals, [1] generation
+    int32_t *err;             // set when a barrier wait exceeds its bound
+    long long spin_limit;
+};
+
+__global__ void k_batch_reset(unsigned *bar, int32_t *err)
+{
+    bar[0] = 0u;
+    bar[1] = 0u;
+    *err = 0;
+}
+
+// Sense-free generation barrier over all workgroups.  Every wait is bounded:
+// after spin_limit polls the error flag is raised and every later barrier
+// returns at once, so the grid always drains.
+__device__ __forceinline__ void grid_barrier(const BatchArgs &a, unsigned nwg)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned g = __hip_atomic_load(&a.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        unsigned prev = __hip_atomic_fetch_add(&a.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == nwg - 1u) {
+            __hip_atomic_store(&a.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&a.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long long spins = 0;
+            while (__hip_atomic_load(&a.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > a.spin_limit) {
+                    __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(512) void k_cp_persistent(BatchArgs a)
+{
+    __shared__ CPShared sh;
+    __shared__ int s_stop;
+    const unsigned nwg = gridDim.x;
+    const int64_t G = nwg;
+    for (int it = 0; it < a.iters; ++it) {
+        if (a.xcd_chunks) {
+            // workgroup g runs on XCD g % 8; XCD x owns items [x*chunk, (x+1)*chunk)
+            const int64_t lanes = (G + 7) / 8;
+            const int64_t x = blockIdx.x % 8, lane = blockIdx.x / 8;
+            const int64_t chunk = (a.n_items + 7) / 8;
+            const int64_t lo = x * chunk, hi = min(a.n_items, lo + chunk);
+            for (int64_t i = lo + lane; i < hi; i += lanes) {
+                const int2 item = a.items[i];
+                const VolDesc d = a.vols[item.x];
+                const int c = (d.cur + it) & 1;
+                CPArgs<SF32> A;
+                A.nb = 0; A.pstride = d.pstride; A.nbr = d.nbr; A.emask = d.emask; A.order = nullptr;
+                A.f = d.f; A.w = d.w; A.u = d.u; A.ubar_in = d.ubar[c]; A.ubar_out = d.ubar[1 - c];
+                A.p_in = d.p[c]; A.p_out = d.p[1 - c]; A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
+                A.sigma = a.sigma; A.tau = a.tau; A.lambda = a.lambda; A.theta = a.theta;
+                cp_block<SF32, false>(A, item.y, sh);
+                __syncthreads();
+            }
+        } else {
+            for (int64_t i = blockIdx.x; i < a.n_items; i += G) {
+                const int2 item = a.items[i];
+                const VolDesc d = a.vols[item.x];
+                const int c = (d.cur + it) & 1;
+                CPArgs<SF32> A;
+                A.nb = 0; A.pstride = d.pstride; A.nbr = d.nbr; A.emask = d.emask; A.order = nullptr;
+                A.f = d.f; A.w = d.w; A.u = d.u; A.ubar_in = d.ubar[c]; A.ubar_out = d.ubar[1 - c];
+                A.p_in = d.p[c]; A.p_out = d.p[1 - c]; A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
+                A.sigma = a.sigma; A.tau = a.tau; A.lambda = a.lambda; A.theta = a.theta;
+                cp_block<SF32, false>(A, item.y, sh);
+                __syncthreads();
+            }
+        }
+        grid_barrier(a, nwg);
+        if (threadIdx.x == 0)
+            s_stop = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        if (s_stop) return;
+    }
+}
+
+__global__ void k_make_items(const int32_t *__restrict__ order, int64_t nb, int32_t vol, int2 *__restrict__ items)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < nb) items[i] = make_int2(vol, order[i]);
+}
+
+// Process-wide batch context (device buffers and the cached graph).
+struct BatchCtx {
+    Buf descs, items, state;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // key of the captured graph
+    const void *k_items = nullptr;
+    int64_t k_n = -1;
+    int k_iters = -1, k_grid = -1, k_xcd = -1;
+    float k_prm[4] = {0, 0, 0, 0};
+    const void *vols_ptr = nullptr;
+    const void *bar_ptr = nullptr;
+    hipStream_t cap = nullptr;        // private stream for capture and replay
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+static BatchCtx g_batch;
+
+struct TuneChoice { int wg_per_cu; int xcd; };
+static std::map<int, TuneChoice> g_tuned;
+
+static int size_bucket(int64_t n)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+static int launch_direct(hipStream_t st, const BatchArgs &a, int grid)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, a.bar, a.err);
+    hipLaunchKernelGGL(k_cp_persistent, dim3(grid), dim3(512), 0, st, a);
+    DN_HIP(hipGetLastError());
+    return DN_OK;
+}
+
+// Capture (once per configuration) and replay on a private stream that is
+// ordered after and before the caller's stream with events (the caller's
+// stream may be the null stream, which cannot be captured).
+static int launch_graph(hipStream_t st, const BatchArgs &a, int grid)
+{
+    BatchCtx &c = g_batch;
+    if (!c.cap) {
+        DN_HIP(hipStreamCreateWithFlags(&c.cap, hipStreamNonBlocking));
+        DN_HIP(hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming));
+        DN_HIP(hipEventCreateWithFlags(&c.ev_out, hipEventDisableTiming));
+    }
+    bool same = c.exec && c.k_items == a.items && c.k_n == a.n_items && c.k_iters == a.iters && c.k_grid == grid &&
+                c.k_xcd == a.xcd_chunks && c.k_prm[0] == a.sigma && c.k_prm[1] == a.tau &&
+                c.k_prm[2] == a.lambda && c.k_prm[3] == a.theta && c.vols_ptr == a.vols && c.bar_ptr == a.bar;
+    if (!same) {
+        if (c.exec) { (void)hipGraphExecDestroy(c.exec); c.exec = nullptr; }
+        if (c.graph) { (void)hipGraphDestroy(c.graph); c.graph = nullptr; }
+        DN_HIP(hipStreamBeginCapture(c.cap, hipStreamCaptureModeThreadLocal));
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, c.cap, a.bar, a.err);
+        hipLaunchKernelGGL(k_cp_persistent, dim3(grid), dim3(512), 0, c.cap, a);
+        hipError_t le = hipGetLastError();
+        hipError_t ce = hipStreamEndCapture(c.cap, &c.graph);
+        if (le != hipSuccess || ce != hipSuccess) {
+            set_error("graph capture failed: %s / %s", hipGetErrorString(le), hipGetErrorString(ce));
+            return DN_E_DEVICE;
+        }
+        DN_HIP(hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0));
+        c.k_items = a.items; c.k_n = a.n_items; c.k_iters = a.iters; c.k_grid = grid; c.k_xcd = a.xcd_chunks;
+        c.k_prm[0] = a.sigma; c.k_prm[1] = a.tau; c.k_prm[2] = a.lambda; c.k_prm[3] = a.theta;
+        c.vols_ptr = a.vols; c.bar_ptr = a.bar;
+    }
+    DN_HIP(hipEventRecord(c.ev_in, st));
+    DN_HIP(hipStreamWaitEvent(c.cap, c.ev_in, 0));
+    DN_HIP(hipGraphLaunch(c.exec, c.cap));
+    DN_HIP(hipEventRecord(c.ev_out, c.cap));
+    DN_HIP(hipStreamWaitEvent(st, c.ev_out, 0));
+    return DN_OK;
+}
+
+static int check_err(hipStream_t st, int32_t *err_dev, HostBuf &host)
+{
+    int rc = host.ensure(64);
+    if (rc) return rc;
+    DN_HIP(hipMemcpyAsync(host.ptr, err_dev, 4, hipMemcpyDeviceToHost, st));
+    DN_HIP(hipStreamSynchronize(st));
+    if (*host.as<int32_t>() != 0) {
+        set_error("persistent kernel: a grid barrier wait exceeded its bound (workgroups not co-resident)");
+        return DN_E_DEVICE;
+    }
+    return DN_OK;
+}
+
+}  // namespace dn
+
+using namespace dn;
+
+extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_reg_params *prm, dn_reg_stats *out)
+{
+    DN_REQUIRE(vols && n > 0 && prm, "bad argument");
+    DN_REQUIRE(prm->lambda > 0 && prm->tau > 0 && prm->sigma > 0 && prm->tau * prm->sigma * 12.0 <= 1.0 + 1e-9,
+               "bad step sizes");
+    DN_REQUIRE(prm->theta >= 0 && prm->theta <= 1 && prm->iters >= 0, "bad theta or iters");
+    DN_REQUIRE(prm->storage == DN_F32, "the batched solver stores its state in FP32");
+    DN_REQUIRE(prm->init == DN_INIT_ZERO || prm->init == DN_INIT_KEEP, "init must be ZERO or KEEP");
+    for (int i = 0; i < n; ++i) {
+        DN_REQUIRE(vols[i], "null volume %d", i);
+        DN_REQUIRE(vols[i]->device == vols[0]->device, "volumes on different devices");
+    }
+    dn_volume *v0 = vols[0];
+    hipStream_t st = v0->stream;
+    int rc;
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        dn_volume *v = vols[i];
+        // each volume's own work must be ordered before ours
+        if (v->stream != st) DN_HIP(hipStreamSynchronize(v->stream));
+        hipStream_t keep = v->stream;
+        v->stream = st;
+        rc = build_masks(v);
+        if (!rc && prm->init == DN_INIT_ZERO) rc = zero_state(v);
+        if (!rc && v->state_storage != DN_F32) v->state_storage = DN_F32;
+        v->stream = keep;
+        if (rc) return rc;
+        total += v->nb;
+    }
+    BatchCtx &c = g_batch;
+    if ((rc = c.descs.ensure(sizeof(VolDesc) * size_t(n)))) return rc;
+    if ((rc = c.items.ensure(sizeof(int2) * size_t(total > 0 ? total : 1)))) return rc;
+    if ((rc = c.state.ensure(64))) return rc;
+    std::vector<VolDesc> hd(n);
+    int64_t ofs = 0;
+    for (int i = 0; i < n; ++i) {
+        dn_volume *v = vols[i];
+        VolDesc &d = hd[i];
+        d.nbr = v->nbr; d.emask = v->emask; d.f = v->f; d.w = v->w; d.u = v->u;
+        d.ubar[0] = v->ubar[0]; d.ubar[1] = v->ubar[1]; d.p[0] = v->p[0]; d.p[1] = v->p[1];
+        d.pstride = v->cap_blocks * kBlockVox;
+        d.cur = v->cur;
+        d.pad = 0;
+        if (v->nb > 0) {
+            hipLaunchKernelGGL(k_make_items, dim3(unsigned((v->nb + 255) / 256)), dim3(256), 0, st, v->order, v->nb,
+                               i, c.items.as<int2>() + ofs);
+            DN_HIP(hipGetLastError());
+        }
+        ofs += v->nb;
+    }
+    DN_HIP(hipMemcpyAsync(c.descs.ptr, hd.data(), sizeof(VolDesc) * size_t(n), hipMemcpyHostToDevice, st));
+
+    BatchArgs a;
+    a.vols = c.descs.as<VolDesc>();
+    a.items = c.items.as<int2>();
+    a.n_items = total;
+    a.sigma = float(prm->sigma); a.tau = float(prm->tau); a.lambda = float(prm->lambda); a.theta = float(prm->theta);
+    a.bar = c.state.as<unsigned>();
+    a.err = reinterpret_cast<int32_t *>(c.state.as<unsigned>() + 4);
+    a.spin_limit = 1LL << 22;
+
+    // occupancy bound: every workgroup of the grid must be resident at once
+    int dev_cu = 0, per_cu = 0;
+    DN_HIP(hipDeviceGetAttribute(&dev_cu, hipDeviceAttributeMultiprocessorCount, v0->device));
+    DN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cp_persistent, 512, 0));
+    if (per_cu < 1) { set_error("persistent kernel does not fit on a compute unit"); return DN_E_DEVICE; }
+
+    TuneChoice ch{per_cu, 1};
+    const int key = size_bucket(total);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+        ch = it->second;
+    } else if (prm->kernel == DN_K_AUTO && prm->init == DN_INIT_ZERO && total > 0 && prm->iters > 0) {
+        // autotune: a few iterations of each candidate, from the zero state
+        hipEvent_t e0, e1;
+        DN_HIP(hipEventCreate(&e0));
+        DN_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        const int trial = std::min(prm->iters, 6);
+        for (int wpc = 1; wpc <= per_cu; ++wpc)
+            for (int xcd = 0; xcd <= 1; ++xcd) {
+                BatchArgs t = a;
+                t.iters = trial;
+                t.xcd_chunks = xcd;
+                int grid = int(std::min<int64_t>(int64_t(wpc) * dev_cu, total));
+                DN_HIP(hipEventRecord(e0, st));
+                if ((rc = launch_direct(st, t, grid))) return rc;
+                DN_HIP(hipEventRecord(e1, st));
+                DN_HIP(hipEventSynchronize(e1));
+                if ((rc = check_err(st, t.err, v0->host))) return rc;
+                float ms = 0;
+                DN_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) { best = ms; ch = TuneChoice{wpc, xcd}; }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        g_tuned[key] = ch;
+        for (int i = 0; i < n; ++i) {
+            hipStream_t keep = vols[i]->stream;
+            vols[i]->stream = st;
+            rc = zero_state(vols[i]);
+            vols[i]->stream = keep;
+            if (rc) return rc;
+        }
+    }
+    a.iters = prm->iters;
+    a.xcd_chunks = ch.xcd;
+    const int grid = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(ch.wg_per_cu) * dev_cu, total)));
+    hipEvent_t e0, e1;
+    DN_HIP(hipEventCreate(&e0));
+    DN_HIP(hipEventCreate(&e1));
+    DN_HIP(hipEventRecord(e0, st));
+    if (total > 0 && prm->iters > 0) {
+        if ((rc = launch_graph(st, a, grid))) return rc;
+    }
+    DN_HIP(hipEventRecord(e1, st));
+    DN_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    DN_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if ((rc = check_err(st, a.err, v0->host))) return rc;
+    for (int i = 0; i < n; ++i) {
+        dn_volume *v = vols[i];
+        v->cur = (v->cur + prm->iters) & 1;
+        hipStream_t keep = v->stream;
+        v->stream = st;
+        double ed[2] = {0, 0};
+        rc = energy_current(v, prm->lambda, true);
+        if (!rc) rc = read_energy(v, ed);
+        v->stream = keep;
+        if (rc) return rc;
+        if (out) {
+            dn_reg_stats &s = out[i];
+            s = dn_reg_stats{};
+            s.energy = ed[0];
+            s.dual = ed[1];
+            s.gap = ed[0] - ed[1];
+            s.rel_gap = ed[0] != 0.0 ? s.gap / ed[0] : 0.0;
+            s.iters_run = prm->iters;
+            s.converged = prm->gap_tol > 0 && s.gap <= prm->gap_tol * ed[0];
+            s.ms_loop = ms;
+        }
+    }
+    return DN_OK;
+}

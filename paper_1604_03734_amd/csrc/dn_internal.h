@@ -105,9 +105,10 @@ struct dn_volume {
 namespace dn {
 // regularize.hip
 int build_masks(dn_volume *v);
-int energy_async(dn_volume *v, double lambda, const float *u, const float *ubar_unused,
-                 const float *p);
 int ensure_lowp(dn_volume *v);
+int zero_state(dn_volume *v);
+int energy_current(dn_volume *v, double lambda, bool use_f32);
+int read_energy(dn_volume *v, double out[2]);
 // volume.hip
 int volume_sync(dn_volume *v);
 }  // namespace dn

@@ -1,0 +1,546 @@
+// Learned warm start: a 3-layer 3x3x3 convolutional network on 10^3 tiles
+// (an 8^3 block plus a one-voxel halo), 2 -> 16 -> 16 -> 1 channels, ReLU,
+// "same" zero padding inside the tile.  Forward, input gradient and weight
+// gradient are implicit GEMMs on the gfx950 matrix cores
+// (v_mfma_f32_16x16x16_bf16: bfloat16 operands, float32 accumulation):
+//   one MFMA = 16 voxels x 16 output channels x 16 input channels of one tap.
+// Activations are stored channel-last in bfloat16, [tile][1000][16], with
+// unused channels zero (layer 1 has 2 inputs, layer 3 one output).
+#include <cstring>
+
+#include <cmath>
+#include <vector>
+
+#include "dn_internal.h"
+
+namespace dn {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 1000;      // voxels of a 10^3 tile
+constexpr int kC = 16;        // channels of a stored activation
+constexpr int kTaps = 27;
+constexpr int kWPack = kTaps * kC * kC;   // one packed layer: [tap][co][ci]
+constexpr int kMT = 63;       // 16-voxel row tiles covering 1000 voxels
+
+__device__ __forceinline__ uint16_t f2bf(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t v) { return __uint_as_float(uint32_t(v) << 16); }
+
+// voxel v of a tile -> coordinates; neighbour through tap t (offset -1..1)
+__device__ __forceinline__ int tap_neighbour(int v, int t)
+{
+    int x = v % 10, y = (v / 10) % 10, z = v / 100;
+    x += t % 3 - 1; y += (t / 3) % 3 - 1; z += t / 9 - 1;
+    if (x < 0 || x > 9 || y < 0 || y > 9 || z < 0 || z > 9) return -1;
+    return (z * 10 + y) * 10 + x;
+}
+
+__device__ __forceinline__ void load_tile(uint16_t *dst, const uint16_t *src)
+{
+    const uint4 *s = reinterpret_cast<const uint4 *>(src);
+    uint4 *d = reinterpret_cast<uint4 *>(dst);
+    for (int i = threadIdx.x; i < kT * kC / 8; i += blockDim.x) d[i] = s[i];
+}
+
+// One convolution layer on one tile per workgroup (256 threads = 4 waves).
+//   Y[v][co] = bias[co] + sum_t sum_ci W[t][co][ci] X[v + off(t)][ci]
+// then optional ReLU, optional gate (multiply by [G[v][co] > 0], the ReLU
+// derivative of the backward pass), stored as bfloat16 (Y) and/or channel 0
+// as float (Yf).
+__global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, int64_t n,
+                                              const uint16_t *__restrict__ Wp, const float *__restrict__ bias,
+                                              int relu, const uint16_t *__restrict__ gate,
+                                              uint16_t *__restrict__ Y, float *__restrict__ Yf)
+{
+    __shared__ __align__(16) uint16_t sx[kT * kC];
+    __shared__ __align__(16) uint16_t sw[kWPack];
+    const int64_t tile = blockIdx.x;
+    if (tile >= n) return;
+    load_tile(sx, X + tile * kT * kC);
+    {
+        const uint4 *s = reinterpret_cast<const uint4 *>(Wp);
+        uint4 *d = reinterpret_cast<uint4 *>(sw);
+        for (int i = threadIdx.x; i < kWPack / 8; i += blockDim.x) d[i] = s[i];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = lane & 15, kg = lane >> 4;
+    const float bv = bias ? bias[i] : 0.0f;
+    for (int mt = wave; mt < kMT; mt += 4) {
+        const int v = mt * 16 + i;
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < kTaps; ++t) {
+            v4s a = {0, 0, 0, 0};
+            if (v < kT) {
+                int nvx = tap_neighbour(v, t);
+                if (nvx >= 0) a = *reinterpret_cast<const v4s *>(&sx[nvx * kC + 4 * kg]);
+            }
+            v4s b = *reinterpret_cast<const v4s *>(&sw[(t * kC + i) * kC + 4 * kg]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        }
+        for (int r = 0; r < 4; ++r) {
+            const int vo = mt * 16 + 4 * kg + r;
+            if (vo >= kT) continue;
+            float y = acc[r] + bv;
+            if (relu) y = y > 0.f ? y : 0.f;
+            const int64_t o = (tile * kT + vo) * kC + i;
+            if (gate) {
+                uint16_t g = gate[o];
+                if ((g & 0x8000u) || (g & 0x7FFFu) == 0) y = 0.f;
+            }
+            if (Y) Y[o] = f2bf(y);
+            if (Yf && i == 0) Yf[tile * kT + vo] = y;
+        }
+    }
+}
+
+// Weight and bias gradient of one layer: dW[t][co][ci] = sum over tiles and
+// voxels of X[v + off(t)][ci] dY[v][co]; db[co] = sum dY[v][co].  Each
+// workgroup accumulates its tiles and writes one partial
+// [27*256 + 16] floats; k_grad_reduce sums the partials in a fixed order.
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, const uint16_t *__restrict__ dY,
+                                               int64_t n, float *__restrict__ partials)
+{
+    __shared__ __align__(16) uint16_t sx[kT * kC];
+    __shared__ __align__(16) uint16_t sd[kT * kC];
+    __shared__ float sb[256];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = lane & 15, kg = lane >> 4;
+    v4f acc[7];
+    for (int j = 0; j < 7; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    for (int64_t tile = blockIdx.x; tile < n; tile += gridDim.x) {
+        load_tile(sx, X + tile * kT * kC);
+        load_tile(sd, dY + tile * kT * kC);
+        __syncthreads();
+        for (int ks = 0; ks < kMT; ++ks) {
+            const int v0 = ks * 16 + 4 * kg;
+            v4s b;
+            for (int q = 0; q < 4; ++q) b[q] = (v0 + q < kT) ? short(sd[(v0 + q) * kC + i]) : short(0);
+            for (int j = 0; j < 7; ++j) {
+                const int t = wave + 4 * j;
+                if (t >= kTaps) break;
+                v4s a;
+                for (int q = 0; q < 4; ++q) {
+                    int nv = (v0 + q < kT) ? tap_neighbour(v0 + q, t) : -1;
+                    a[q] = nv >= 0 ? short(sx[nv * kC + i]) : short(0);
+                }
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+            }
+        }
+        // bias: channel c = tid % 16 summed over voxels tid/16, +16, ...
+        for (int v = threadIdx.x >> 4; v < kT; v += 16) bsum += bf2f(sd[v * kC + (threadIdx.x & 15)]);
+        __syncthreads();
+    }
+    float *out = partials + int64_t(blockIdx.x) * (kWPack + kC);
+    // D layout: lane holds rows (ci) 4*kg + r, column (co) i
+    for (int j = 0; j < 7; ++j) {
+        const int t = wave + 4 * j;
+        if (t >= kTaps) break;
+        for (int r = 0; r < 4; ++r) out[(t * kC + i) * kC + 4 * kg + r] = acc[j][r];
+    }
+    sb[threadIdx.x] = bsum;
+    __syncthreads();
+    if (threadIdx.x < kC) {
+        float s = 0.f;
+        for (int k = 0; k < 16; ++k) s += sb[k * 16 + threadIdx.x];
+        out[kWPack + threadIdx.x] = s;
+    }
+}
+
+// Sum the per-workgroup partials (fixed order) into the canonical parameter
+// layout W[co][ci][tap], b[co] of a layer with cout x cin real channels.
+__global__ void k_grad_reduce(const float *__restrict__ partials, int nparts, int cout, int cin,
+                              float *__restrict__ gW, float *__restrict__ gb)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = cout * cin * kTaps;
+    if (k < nw) {
+        int co = k / (cin * kTaps), ci = (k / kTaps) % cin, t = k % kTaps;
+        float s = 0.f;
+        for (int p = 0; p < nparts; ++p) s += partials[int64_t(p) * (kWPack + kC) + (t * kC + co) * kC + ci];
+        gW[k] = s;
+    } else if (k < nw + cout) {
+        int co = k - nw;
+        float s = 0.f;
+        for (int p = 0; p < nparts; ++p) s += partials[int64_t(p) * (kWPack + kC) + kWPack + co];
+        gb[co] = s;
+    }
+}
+
+// Pack the float parameters into bfloat16 [tap][co][ci] layers, zero padded
+// to 16x16; flipped = 1 gives the input-gradient weights
+// W'[t][a][b] = W[26 - t][b][a].
+__global__ void k_pack(const float *__restrict__ W, int cout, int cin, int flipped, uint16_t *__restrict__ out)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kWPack) return;
+    int t = k / (kC * kC), a = (k / kC) % kC, b = k % kC;
+    float val = 0.f;
+    if (!flipped) {
+        if (a < cout && b < cin) val = W[(a * cin + b) * kTaps + t];
+    } else {
+        // a indexes the forward input channel, b the forward output channel
+        if (b < cout && a < cin) val = W[(b * cin + a) * kTaps + (kTaps - 1 - t)];
+    }
+    out[k] = f2bf(val);
+}
+
+// float tiles [n][2][1000] -> bfloat16 [n][1000][16]
+__global__ void k_tiles_to_bf16(const float *__restrict__ tiles, int64_t n, uint16_t *__restrict__ X)
+{
+    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n * kT) return;
+    int64_t tile = k / kT;
+    int v = int(k % kT);
+    uint16_t out[16];
+    out[0] = f2bf(tiles[tile * 2 * kT + v]);
+    out[1] = f2bf(tiles[tile * 2 * kT + kT + v]);
+    for (int c = 2; c < 16; ++c) out[c] = 0;
+    uint4 *d = reinterpret_cast<uint4 *>(X + k * kC);
+    d[0] = *reinterpret_cast<uint4 *>(&out[0]);
+    d[1] = *reinterpret_cast<uint4 *>(&out[8]);
+}
+
+__device__ __forceinline__ int64_t halo_vox(const int32_t *nb27, int hx, int hy, int hz)
+{
+    int dx = hx < 0 ? -1 : (hx > 7 ? 1 : 0);
+    int dy = hy < 0 ? -1 : (hy > 7 ? 1 : 0);
+    int dz = hz < 0 ? -1 : (hz > 7 ? 1 : 0);
+    int32_t id = nb27[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)];
+    if (id < 0) return -1;
+    return int64_t(id) * kBlockVox + ((hx - 8 * dx) + 8 * (hy - 8 * dy) + 64 * (hz - 8 * dz));
+}
+
+// Input tiles of blocks [first, first + n) of the list (or of the pool if
+// blocks == nullptr): channel 0 f, channel 1 log(1 + w) / log(101); 0 for
+// voxels of unallocated neighbours.  Either float [n][2][1000] or
+// bfloat16 channel-last [n][1000][16].
+__global__ void k_gather(const int32_t *__restrict__ nbr, const float *__restrict__ f, const float *__restrict__ w,
+                         const int32_t *__restrict__ blocks, int64_t first, int64_t n, float *__restrict__ tiles,
+                         uint16_t *__restrict__ X)
+{
+    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n * kT) return;
+    int64_t i = k / kT;
+    int v = int(k % kT);
+    int64_t b = blocks ? blocks[first + i] : first + i;
+    int x = v % 10, y = (v / 10) % 10, z = v / 100;
+    int64_t j = halo_vox(nbr + b * kNbr, x - 1, y - 1, z - 1);
+    float fv = 0.f, wv = 0.f;
+    if (j >= 0) {
+        fv = f[j];
+        wv = float(log(1.0 + double(w[j])) / log(101.0));
+    }
+    if (tiles) {
+        tiles[i * 2 * kT + v] = fv;
+        tiles[i * 2 * kT + kT + v] = wv;
+    }
+    if (X) {
+        uint16_t out[16];
+        out[0] = f2bf(fv);
+        out[1] = f2bf(wv);
+        for (int c = 2; c < 16; ++c) out[c] = 0;
+        uint4 *d = reinterpret_cast<uint4 *>(X + k * kC);
+        d[0] = *reinterpret_cast<uint4 *>(&out[0]);
+        d[1] = *reinterpret_cast<uint4 *>(&out[8]);
+    }
+}
+
+__device__ __forceinline__ int centre_of(int v) { return ((v / 64 + 1) * 10 + ((v / 8) % 8 + 1)) * 10 + (v % 8 + 1); }
+
+__global__ void k_mask_count(const float *__restrict__ mask, int64_t n, double *__restrict__ out)
+{
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += 256) acc += mask[k];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = s[0];
+}
+
+// Loss of one tile per workgroup (512 threads, one per centre voxel) and the
+// output gradient dY3 (bfloat16, channel 0 only).
+__global__ __launch_bounds__(512) void k_loss(const float *__restrict__ tiles, const float *__restrict__ R,
+                                              const float *__restrict__ targets, const float *__restrict__ mask,
+                                              const double *__restrict__ count, int64_t n,
+                                              uint16_t *__restrict__ dY, double *__restrict__ tile_loss)
+{
+    __shared__ double sl[8];
+    const int64_t tile = blockIdx.x;
+    const int v = threadIdx.x;
+    const double N = count[0] > 1.0 ? count[0] : 1.0;
+    const int c = centre_of(v);
+    const double m = mask[tile * 512 + v];
+    double e = double(tiles[tile * 2 * kT + c]) + double(R[tile * kT + c]) - double(targets[tile * 512 + v]);
+    double l = m != 0.0 ? e * e / N : 0.0;
+    // clear the tile's gradient, then write the centre voxels
+    uint4 z = make_uint4(0, 0, 0, 0);
+    uint4 *d = reinterpret_cast<uint4 *>(dY + tile * kT * kC);
+    for (int k = threadIdx.x; k < kT * kC / 8; k += 512) d[k] = z;
+    __syncthreads();
+    if (m != 0.0) dY[(tile * kT + c) * kC] = f2bf(float(2.0 * e / N));
+    for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
+    if ((v & 63) == 0) sl[v >> 6] = l;
+    __syncthreads();
+    if (v == 0) {
+        double s = 0.0;
+        for (int k = 0; k < 8; ++k) s += sl[k];
+        tile_loss[tile] = s;
+    }
+}
+
+__global__ void k_sum_loss(const double *__restrict__ tl, int64_t n, double *__restrict__ out)
+{
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += 256) acc += tl[k];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = s[0];
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       int64_t n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    float gk = g[k];
+    float mk = b1 * m[k] + (1.f - b1) * gk;
+    float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+// u0 = clamp(f + r, -1, 1) on Omega, 0 elsewhere, for blocks [first, first+n)
+__global__ __launch_bounds__(512) void k_warm_u(const float *__restrict__ f, const uint8_t *__restrict__ emask,
+                                                const float *__restrict__ R, int64_t first, float *__restrict__ u0)
+{
+    const int64_t i = blockIdx.x;
+    const int v = threadIdx.x;
+    const int64_t g = (first + i) * kBlockVox + v;
+    float u = 0.f;
+    if (emask[g] & 1) {
+        u = f[g] + R[i * kT + centre_of(v)];
+        u = u < -1.f ? -1.f : (u > 1.f ? 1.f : u);
+    }
+    u0[g] = u;
+}
+
+// p0 = P(grad(u0) / delta) with the masked forward differences of Eq. (3)
+__global__ __launch_bounds__(512) void k_warm_p(int64_t nb, int64_t ps, const int32_t *__restrict__ nbr,
+                                                const uint8_t *__restrict__ emask, const float *__restrict__ u0,
+                                                float inv_delta, float *__restrict__ p0)
+{
+    const int64_t b = blockIdx.x;
+    const int t = threadIdx.x, lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+    const int64_t gi = b * kBlockVox + t;
+    const int32_t *nb27 = nbr + b * kNbr;
+    const uint8_t m = emask[gi];
+    const float u = u0[gi];
+    float g0 = (m & 2) ? u0[lx < 7 ? gi + 1 : halo_vox(nb27, 8, ly, lz)] - u : 0.f;
+    float g1 = (m & 4) ? u0[ly < 7 ? gi + 8 : halo_vox(nb27, lx, 8, lz)] - u : 0.f;
+    float g2 = (m & 8) ? u0[lz < 7 ? gi + 64 : halo_vox(nb27, lx, ly, 8)] - u : 0.f;
+    g0 *= inv_delta; g1 *= inv_delta; g2 *= inv_delta;
+    float nrm = sqrtf((g0 * g0 + g1 * g1) + g2 * g2);
+    if (nrm > 1.f) { g0 /= nrm; g1 /= nrm; g2 /= nrm; }
+    p0[gi] = g0; p0[gi + ps] = g1; p0[gi + 2 * ps] = g2;
+}
+
+// Process-wide network scratch.
+struct NetCtx {
+    Buf wpack, x0, h1, h2, r, d3, d2, d1, parts, misc, tl;
+};
+static NetCtx g_net;
+
+static inline unsigned grid1(int64_t n, int bs = 256) { return unsigned((n + bs - 1) / bs); }
+
+// offsets of the layers in the canonical 8241-float parameter vector
+constexpr int kW1 = 0, kB1 = 16 * 2 * 27, kW2 = kB1 + 16, kB2 = kW2 + 16 * 16 * 27, kW3 = kB2 + 16,
+              kB3 = kW3 + 16 * 27;
+
+static int pack_all(hipStream_t st, const float *params, bool with_flipped)
+{
+    int rc = g_net.wpack.ensure(size_t(5) * kWPack * 2);
+    if (rc) return rc;
+    uint16_t *wp = g_net.wpack.as<uint16_t>();
+    hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW1, 16, 2, 0, wp);
+    hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW2, 16, 16, 0, wp + kWPack);
+    hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW3, 1, 16, 0, wp + 2 * kWPack);
+    if (with_flipped) {
+        hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW2, 16, 16, 1, wp + 3 * kWPack);
+        hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW3, 1, 16, 1, wp + 4 * kWPack);
+    }
+    DN_HIP(hipGetLastError());
+    return DN_OK;
+}
+
+static int ensure_acts(int64_t n, bool training)
+{
+    int rc;
+    size_t act = size_t(n) * kT * kC * 2;
+    if ((rc = g_net.x0.ensure(act))) return rc;
+    if ((rc = g_net.h1.ensure(act))) return rc;
+    if ((rc = g_net.h2.ensure(act))) return rc;
+    if ((rc = g_net.r.ensure(size_t(n) * kT * 4))) return rc;
+    if (training) {
+        if ((rc = g_net.d3.ensure(act))) return rc;
+        if ((rc = g_net.d2.ensure(act))) return rc;
+        if ((rc = g_net.d1.ensure(act))) return rc;
+    }
+    return DN_OK;
+}
+
+// Forward of n tiles already in g_net.x0 (packed weights in g_net.wpack):
+// h1, h2 (bfloat16) and the residual r (float) of every tile voxel.
+static int forward_tiles(hipStream_t st, const float *params, int64_t n)
+{
+    if (n <= 0) return DN_OK;
+    const uint16_t *wp = g_net.wpack.as<uint16_t>();
+    uint16_t *x0 = g_net.x0.as<uint16_t>(), *h1 = g_net.h1.as<uint16_t>(), *h2 = g_net.h2.as<uint16_t>();
+    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, x0, n, wp, params + kB1, 1,
+                       (const uint16_t *)nullptr, h1, (float *)nullptr);
+    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, h1, n, wp + kWPack, params + kB2, 1,
+                       (const uint16_t *)nullptr, h2, (float *)nullptr);
+    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, h2, n, wp + 2 * kWPack, params + kB3, 0,
+                       (const uint16_t *)nullptr, (uint16_t *)nullptr, g_net.r.as<float>());
+    DN_HIP(hipGetLastError());
+    return DN_OK;
+}
+
+}  // namespace dn
+
+using namespace dn;
+
+extern "C" {
+
+int dn_net_gather(dn_volume *v, const int32_t *blocks, int64_t n, float *tiles)
+{
+    DN_REQUIRE(v && blocks && tiles && n >= 0, "bad argument");
+    if (n == 0) return DN_OK;
+    hipLaunchKernelGGL(k_gather, dim3(grid1(n * kT)), dim3(256), 0, v->stream, v->nbr, v->f, v->w, blocks,
+                       int64_t(0), n, tiles, (uint16_t *)nullptr);
+    DN_HIP(hipGetLastError());
+    return DN_OK;
+}
+
+int dn_net_forward(const float *tiles, int64_t n, const float *params, float *out, void *stream)
+{
+    DN_REQUIRE(tiles && params && out && n >= 0, "bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (n == 0) return DN_OK;
+    int rc;
+    if ((rc = ensure_acts(n, false))) return rc;
+    if ((rc = pack_all(st, params, false))) return rc;
+    hipLaunchKernelGGL(k_tiles_to_bf16, dim3(grid1(n * kT)), dim3(256), 0, st, tiles, n, g_net.x0.as<uint16_t>());
+    DN_HIP(hipGetLastError());
+    if ((rc = forward_tiles(st, params, n))) return rc;
+    DN_HIP(hipMemcpyAsync(out, g_net.r.ptr, size_t(n) * kT * 4, hipMemcpyDeviceToDevice, st));
+    return DN_OK;
+}
+
+int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const float *targets, const float *mask,
+                     float *grad, double *loss_host, void *stream)
+{
+    DN_REQUIRE(tiles && params && targets && mask && grad && n > 0, "bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc;
+    if ((rc = ensure_acts(n, true))) return rc;
+    if ((rc = pack_all(st, params, true))) return rc;
+    const int nparts = int(n < 512 ? n : 512);
+    if ((rc = g_net.parts.ensure(size_t(nparts) * (kWPack + kC) * 4))) return rc;
+    if ((rc = g_net.misc.ensure(64))) return rc;
+    if ((rc = g_net.tl.ensure(size_t(n) * 8))) return rc;
+    uint16_t *x0 = g_net.x0.as<uint16_t>(), *h1 = g_net.h1.as<uint16_t>(), *h2 = g_net.h2.as<uint16_t>();
+    uint16_t *d3 = g_net.d3.as<uint16_t>(), *d2 = g_net.d2.as<uint16_t>(), *d1 = g_net.d1.as<uint16_t>();
+    const uint16_t *wp = g_net.wpack.as<uint16_t>();
+    double *cnt = g_net.misc.as<double>(), *lsum = cnt + 1;
+    float *parts = g_net.parts.as<float>();
+    hipLaunchKernelGGL(k_tiles_to_bf16, dim3(grid1(n * kT)), dim3(256), 0, st, tiles, n, x0);
+    DN_HIP(hipGetLastError());
+    if ((rc = forward_tiles(st, params, n))) return rc;
+    hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(256), 0, st, mask, n * 512, cnt);
+    hipLaunchKernelGGL(k_loss, dim3(unsigned(n)), dim3(512), 0, st, tiles, g_net.r.as<float>(), targets, mask, cnt, n,
+                       d3, g_net.tl.as<double>());
+    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, st, g_net.tl.as<double>(), n, lsum);
+    DN_HIP(hipGetLastError());
+    // layer 3: weights from (h2, d3); input gradient d2 = conv(d3, W3 flipped) * [h2 > 0]
+    hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, st, h2, d3, n, parts);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 27 + 1)), dim3(256), 0, st, parts, nparts, 1, 16,
+                       grad + kW3, grad + kB3);
+    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, d3, n, wp + 4 * kWPack, (const float *)nullptr, 0,
+                       h2, d2, (float *)nullptr);
+    // layer 2
+    hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, st, h1, d2, n, parts);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 16 * 27 + 16)), dim3(256), 0, st, parts, nparts, 16, 16,
+                       grad + kW2, grad + kB2);
+    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, d2, n, wp + 3 * kWPack, (const float *)nullptr, 0,
+                       h1, d1, (float *)nullptr);
+    // layer 1
+    hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, st, x0, d1, n, parts);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 2 * 27 + 16)), dim3(256), 0, st, parts, nparts, 16, 2,
+                       grad + kW1, grad + kB1);
+    DN_HIP(hipGetLastError());
+    if (loss_host) {
+        double h = 0.0;
+        DN_HIP(hipMemcpyAsync(&h, lsum, 8, hipMemcpyDeviceToHost, st));
+        DN_HIP(hipStreamSynchronize(st));
+        *loss_host = h;
+    }
+    return DN_OK;
+}
+
+int dn_net_adam(float *params, const float *grad, float *m, float *v, int64_t n, float lr, float beta1, float beta2,
+                float eps, int32_t step, void *stream)
+{
+    DN_REQUIRE(params && grad && m && v && n > 0 && step >= 1, "bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float c1 = 1.f - std::pow(beta1, float(step)), c2 = 1.f - std::pow(beta2, float(step));
+    hipLaunchKernelGGL(k_adam, dim3(grid1(n)), dim3(256), 0, st, params, grad, m, v, n, lr, beta1, beta2, eps, c1, c2);
+    DN_HIP(hipGetLastError());
+    return DN_OK;
+}
+
+int dn_net_warm_start(dn_volume *v, const float *params, double delta, float *u0, float *p0)
+{
+    DN_REQUIRE(v && params && u0 && delta > 0, "bad argument");
+    hipStream_t st = v->stream;
+    int rc;
+    if ((rc = build_masks(v))) return rc;
+    if (v->nb == 0) return DN_OK;
+    if ((rc = pack_all(st, params, false))) return rc;
+    const int64_t chunk = 16384;
+    if ((rc = ensure_acts(v->nb < chunk ? v->nb : chunk, false))) return rc;
+    for (int64_t first = 0; first < v->nb; first += chunk) {
+        const int64_t n = (v->nb - first) < chunk ? (v->nb - first) : chunk;
+        hipLaunchKernelGGL(k_gather, dim3(grid1(n * kT)), dim3(256), 0, st, v->nbr, v->f, v->w,
+                           (const int32_t *)nullptr, first, n, (float *)nullptr, g_net.x0.as<uint16_t>());
+        DN_HIP(hipGetLastError());
+        if ((rc = forward_tiles(st, params, n))) return rc;
+        hipLaunchKernelGGL(k_warm_u, dim3(unsigned(n)), dim3(512), 0, st, v->f, v->emask, g_net.r.as<float>(), first, u0);
+        DN_HIP(hipGetLastError());
+    }
+    if (p0) {
+        hipLaunchKernelGGL(k_warm_p, dim3(unsigned(v->nb)), dim3(512), 0, st, v->nb, v->nb * int64_t(kBlockVox),
+                           v->nbr, v->emask, u0, float(1.0 / delta), p0);
+        DN_HIP(hipGetLastError());
+    }
+    return DN_OK;
+}
+
+}  // extern "C"

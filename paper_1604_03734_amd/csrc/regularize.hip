@@ -20,208 +20,10 @@
 #include <map>
 #include <vector>
 
+#include "cp_kernel.h"
 #include "dn_internal.h"
 
 namespace dn {
-
-// ---------------------------------------------------------- storage types
-// State storage: float, IEEE half or bfloat16 (16-bit kept as raw bits).
-struct SF32 {
-    using T = float;
-    static __device__ __forceinline__ float ld(float v) { return v; }
-    static __device__ __forceinline__ float rn(float x) { return x; }
-    static __device__ __forceinline__ float rz(float x) { return x; }
-};
-struct SF16 {
-    using T = uint16_t;
-    static __device__ __forceinline__ float ld(uint16_t v) { return float(__builtin_bit_cast(_Float16, v)); }
-    static __device__ __forceinline__ uint16_t rn(float x) { return __builtin_bit_cast(uint16_t, _Float16(x)); }
-    static __device__ __forceinline__ uint16_t rz(float x)
-    {
-        auto h2 = __builtin_amdgcn_cvt_pkrtz(x, 0.0f);
-        return __builtin_bit_cast(uint16_t, h2[0]);
-    }
-};
-struct SBF16 {
-    using T = uint16_t;
-    static __device__ __forceinline__ float ld(uint16_t v) { return __uint_as_float(uint32_t(v) << 16); }
-    static __device__ __forceinline__ uint16_t rn(float x)
-    {
-        uint32_t u = __float_as_uint(x);
-        u += 0x7FFFu + ((u >> 16) & 1u);
-        return uint16_t(u >> 16);
-    }
-    static __device__ __forceinline__ uint16_t rz(float x) { return uint16_t(__float_as_uint(x) >> 16); }
-};
-
-template <class S> struct CPArgs {
-    int64_t nb;                 // blocks
-    int64_t pstride;            // elements between p planes
-    const int32_t *nbr;         // [nb][27]
-    const uint8_t *emask;       // [nb][512]
-    const int32_t *order;       // processing order or nullptr
-    const float *f, *w;
-    typename S::T *u;           // in place
-    const typename S::T *ubar_in;
-    typename S::T *ubar_out;
-    const typename S::T *p_in;  // 3 planes
-    typename S::T *p_out;
-    float *u32, *ubar32, *p32;  // FP32 copies written by a refinement sweep
-    float sigma, tau, lambda, theta;
-};
-
-__device__ __forceinline__ int i10(int x, int y, int z) { return ((z + 1) * 10 + (y + 1)) * 10 + (x + 1); }
-__device__ __forceinline__ int i9(int x, int y, int z) { return ((z + 1) * 9 + (y + 1)) * 9 + (x + 1); }
-
-// Global index of voxel (hx, hy, hz) relative to block b, hx.. in [-1, 8],
-// or -1 if it lies in an unallocated block.
-__device__ __forceinline__ int64_t halo_index(const int32_t *nb27, int hx, int hy, int hz)
-{
-    int dx = hx < 0 ? -1 : (hx > 7 ? 1 : 0);
-    int dy = hy < 0 ? -1 : (hy > 7 ? 1 : 0);
-    int dz = hz < 0 ? -1 : (hz > 7 ? 1 : 0);
-    int32_t id = nb27[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)];
-    if (id < 0) return -1;
-    return int64_t(id) * kBlockVox + ((hx - 8 * dx) + 8 * (hy - 8 * dy) + 64 * (hz - 8 * dz));
-}
-
-// Position of the t-th ubar halo voxel (t < 432): the six faces (+x, +y,
-// +z, -x, -y, -z; 64 each) then the six (-a, +b) edges (8 each).
-__device__ __forceinline__ void halo_pos(int t, int &x, int &y, int &z)
-{
-    if (t < 384) {
-        int f = t >> 6, i = t & 63, a = i & 7, b = i >> 3;
-        switch (f) {
-        case 0: x = 8; y = a; z = b; break;
-        case 1: x = a; y = 8; z = b; break;
-        case 2: x = a; y = b; z = 8; break;
-        case 3: x = -1; y = a; z = b; break;
-        case 4: x = a; y = -1; z = b; break;
-        default: x = a; y = b; z = -1; break;
-        }
-    } else {
-        int e = (t - 384) >> 3, j = (t - 384) & 7;
-        switch (e) {
-        case 0: x = -1; y = 8; z = j; break;
-        case 1: x = -1; y = j; z = 8; break;
-        case 2: x = 8; y = -1; z = j; break;
-        case 3: x = j; y = -1; z = 8; break;
-        case 4: x = 8; y = j; z = -1; break;
-        default: x = j; y = 8; z = -1; break;
-        }
-    }
-}
-
-// -1 face voxel t < 192: face 0 (-x), 1 (-y), 2 (-z)
-__device__ __forceinline__ void face_pos(int t, int &x, int &y, int &z)
-{
-    int f = t >> 6, i = t & 63, a = i & 7, b = i >> 3;
-    if (f == 0) { x = -1; y = a; z = b; }
-    else if (f == 1) { x = a; y = -1; z = b; }
-    else { x = a; y = b; z = -1; }
-}
-
-struct CPShared {
-    float u[1000];       // ubar tile with a one-voxel halo, index i10
-    float p[3][729];     // new dual on the block and its -1 faces, index i9
-    uint8_t m[729];      // edge masks on the block and its -1 faces
-};
-
-__device__ __forceinline__ void project(float &a, float &b, float &c)
-{
-    float n = sqrtf((a * a + b * b) + c * c);
-    if (n > 1.0f) { a = a / n; b = b / n; c = c / n; }
-}
-
-// One fused Chambolle-Pock iteration on block b (512 threads).
-template <class S, bool kRefine>
-__device__ __forceinline__ void cp_block(const CPArgs<S> &A, int64_t b, CPShared &sh)
-{
-    const int t = threadIdx.x;
-    const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
-    const int64_t gi = b * kBlockVox + t;
-    const int32_t *nb27 = A.nbr + b * kNbr;
-    const int64_t ps = A.pstride;
-
-    const float ub = S::ld(A.ubar_in[gi]);
-    const uint8_t m = A.emask[gi];
-    float p0 = S::ld(A.p_in[gi]), p1 = S::ld(A.p_in[gi + ps]), p2 = S::ld(A.p_in[gi + 2 * ps]);
-    const float uo = S::ld(A.u[gi]);
-    const float fv = A.f[gi], wv = A.w[gi];
-    sh.u[i10(lx, ly, lz)] = ub;
-    sh.m[i9(lx, ly, lz)] = m;
-    if (t < 432) {
-        int hx, hy, hz;
-        halo_pos(t, hx, hy, hz);
-        int64_t j = halo_index(nb27, hx, hy, hz);
-        sh.u[i10(hx, hy, hz)] = j >= 0 ? S::ld(A.ubar_in[j]) : 0.0f;
-    }
-    float h0 = 0.f, h1 = 0.f, h2 = 0.f;
-    uint8_t hm = 0;
-    int fx = 0, fy = 0, fz = 0;
-    if (t < 192) {
-        face_pos(t, fx, fy, fz);
-        int64_t j = halo_index(nb27, fx, fy, fz);
-        if (j >= 0) {
-            hm = A.emask[j];
-            h0 = S::ld(A.p_in[j]); h1 = S::ld(A.p_in[j + ps]); h2 = S::ld(A.p_in[j + 2 * ps]);
-        }
-        sh.m[i9(fx, fy, fz)] = hm;
-    }
-    __syncthreads();
-
-    // dual ascent and projection on the block (Eq. 7)
-    {
-        float g0 = (m & 2) ? sh.u[i10(lx + 1, ly, lz)] - ub : 0.0f;
-        float g1 = (m & 4) ? sh.u[i10(lx, ly + 1, lz)] - ub : 0.0f;
-        float g2 = (m & 8) ? sh.u[i10(lx, ly, lz + 1)] - ub : 0.0f;
-        p0 = p0 + A.sigma * g0; p1 = p1 + A.sigma * g1; p2 = p2 + A.sigma * g2;
-        project(p0, p1, p2);
-        const int k = i9(lx, ly, lz);
-        sh.p[0][k] = p0; sh.p[1][k] = p1; sh.p[2][k] = p2;
-        A.p_out[gi] = S::rz(p0); A.p_out[gi + ps] = S::rz(p1); A.p_out[gi + 2 * ps] = S::rz(p2);
-        if (kRefine) { A.p32[gi] = p0; A.p32[gi + ps] = p1; A.p32[gi + 2 * ps] = p2; }
-    }
-    // ... and on the -1 faces, which the divergence needs
-    if (t < 192) {
-        float uh = sh.u[i10(fx, fy, fz)];
-        float g0 = (hm & 2) ? sh.u[i10(fx + 1, fy, fz)] - uh : 0.0f;
-        float g1 = (hm & 4) ? sh.u[i10(fx, fy + 1, fz)] - uh : 0.0f;
-        float g2 = (hm & 8) ? sh.u[i10(fx, fy, fz + 1)] - uh : 0.0f;
-        h0 = h0 + A.sigma * g0; h1 = h1 + A.sigma * g1; h2 = h2 + A.sigma * g2;
-        project(h0, h1, h2);
-        const int k = i9(fx, fy, fz);
-        sh.p[0][k] = h0; sh.p[1][k] = h1; sh.p[2][k] = h2;
-    }
-    __syncthreads();
-
-    // primal proximal step (Eq. 8) and relaxation (Eq. 9)
-    float un = uo;
-    if (m & 1) {
-        const int k = i9(lx, ly, lz);
-        const int kx = i9(lx - 1, ly, lz), ky = i9(lx, ly - 1, lz), kz = i9(lx, ly, lz - 1);
-        float dv = 0.0f;
-        dv += ((m & 2) ? sh.p[0][k] : 0.0f) - ((sh.m[kx] & 2) ? sh.p[0][kx] : 0.0f);
-        dv += ((m & 4) ? sh.p[1][k] : 0.0f) - ((sh.m[ky] & 4) ? sh.p[1][ky] : 0.0f);
-        dv += ((m & 8) ? sh.p[2][k] : 0.0f) - ((sh.m[kz] & 8) ? sh.p[2][kz] : 0.0f);
-        float ut = uo + A.tau * dv;
-        float tlw = A.tau * A.lambda * wv;
-        un = (ut + tlw * fv) / (1.0f + tlw);
-    }
-    float ubn = un + A.theta * (un - uo);
-    A.u[gi] = S::rn(un);
-    A.ubar_out[gi] = S::rn(ubn);
-    if (kRefine) { A.u32[gi] = un; A.ubar32[gi] = ubn; }
-}
-
-// Workgroup -> block mapping.  Consecutive workgroups go round-robin to the
-// 8 XCDs; giving XCD x the x-th contiguous chunk of the (Morton) order keeps
-// spatial neighbours, whose faces are each other's halos, in one L2.
-__device__ __forceinline__ int64_t xcd_slot(int64_t wg, int64_t n)
-{
-    int64_t per = (n + 7) / 8;
-    return (wg % 8) * per + wg / 8;
-}
 
 template <class S, bool kRefine>
 __global__ __launch_bounds__(512) void k_cp_fused(CPArgs<S> A)
@@ -489,7 +291,7 @@ static int energy_launch(dn_volume *v, double lambda, const typename S::T *u, co
 }
 
 // Energies of the current state into v->energy2 (device).
-static int energy_current(dn_volume *v, double lambda, bool use_f32 = false)
+int energy_current(dn_volume *v, double lambda, bool use_f32)
 {
     int rc = build_masks(v);
     if (rc) return rc;
@@ -503,7 +305,7 @@ static int energy_current(dn_volume *v, double lambda, bool use_f32 = false)
     }
 }
 
-static int read_energy(dn_volume *v, double out[2])
+int read_energy(dn_volume *v, double out[2])
 {
     int rc = v->host.ensure(64);
     if (rc) return rc;
@@ -608,7 +410,7 @@ static int validate(const dn_reg_params *prm)
     return DN_OK;
 }
 
-static int zero_state(dn_volume *v)
+int zero_state(dn_volume *v)
 {
     hipStream_t st = v->stream;
     const int64_t n = v->nb * kBlockVox, ps = v->cap_blocks * kBlockVox;
@@ -672,7 +474,7 @@ extern "C" {
 int dn_energy(dn_volume *v, double lambda, double out[2])
 {
     DN_REQUIRE(v && out && lambda > 0, "bad argument");
-    int rc = energy_current(v, lambda);
+    int rc = energy_current(v, lambda, false);
     if (rc) return rc;
     return read_energy(v, out);
 }
@@ -734,6 +536,10 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
     dn_reg_stats stats{};
     double ed[2] = {0, 0};
     int it = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    DN_HIP(hipEventCreate(&ev0));
+    DN_HIP(hipEventCreate(&ev1));
+    DN_HIP(hipEventRecord(ev0, st));
     for (; it < prm->iters && v->nb > 0; ++it) {
         if (storage == DN_F32) {
             rc = step_f32(v, prm, kernel);
@@ -743,7 +549,7 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
         }
         if (rc) return rc;
         if (prm->gap_every > 0 && (it + 1) % prm->gap_every == 0 && it + 1 < prm->iters) {
-            if ((rc = energy_current(v, prm->lambda))) return rc;
+            if ((rc = energy_current(v, prm->lambda, false))) return rc;
             if ((rc = read_energy(v, ed))) return rc;
             double gap = ed[0] - ed[1];
             if (!std::isfinite(gap)) { set_error("non-finite gap at iteration %d", it + 1); return DN_E_NUMERIC; }
@@ -751,6 +557,15 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
         }
     }
     stats.iters_run = it;
+    DN_HIP(hipEventRecord(ev1, st));
+    DN_HIP(hipEventSynchronize(ev1));
+    {
+        float ms = 0.f;
+        DN_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        stats.ms_loop = ms;
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
     // after a 16-bit run the result is the FP32 output of the last sweep
     const bool f32_result = storage == DN_F32 || (it > 0 && it == prm->iters);
     if ((rc = energy_current(v, prm->lambda, f32_result))) return rc;

@@ -557,6 +557,25 @@ void dn_volume_destroy(dn_volume *v)
     delete v;
 }
 
+int dn_volume_clear(dn_volume *v)
+{
+    DN_REQUIRE(v, "null volume");
+    hipStream_t st = v->stream;
+    hipLaunchKernelGGL(k_fill_empty, dim3(grid1(v->hash_slots)), dim3(256), 0, st,
+                       reinterpret_cast<int4 *>(v->hash[v->cur_hash]), v->hash_slots);
+    DN_HIP(hipGetLastError());
+    if (v->nb > 0) {
+        hipLaunchKernelGGL(k_zero_blocks, dim3(grid1(v->nb * kBlockVox)), dim3(256), 0, st, v->f, int64_t(0), v->nb);
+        hipLaunchKernelGGL(k_zero_blocks, dim3(grid1(v->nb * kBlockVox)), dim3(256), 0, st, v->w, int64_t(0), v->nb);
+        DN_HIP(hipGetLastError());
+    }
+    v->nb = 0;
+    v->emask_nb = -1;
+    v->last_nuniq = 0;
+    v->state_storage = DN_F32;
+    return DN_OK;
+}
+
 int dn_set_stream(dn_volume *v, void *hip_stream)
 {
     DN_REQUIRE(v, "null volume");

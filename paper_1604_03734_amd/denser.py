@@ -52,7 +52,8 @@ class RegParams(ctypes.Structure):
 
 class RegStats(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("dual", ctypes.c_double), ("gap", ctypes.c_double),
-                ("rel_gap", ctypes.c_double), ("iters_run", ctypes.c_int32), ("converged", ctypes.c_int32)]
+                ("rel_gap", ctypes.c_double), ("iters_run", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("ms_loop", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -80,6 +81,7 @@ def lib():
         "dn_volume_create": (i32, [P, P, P]),
         "dn_volume_destroy": (None, [P]),
         "dn_set_stream": (i32, [P, P]),
+        "dn_volume_clear": (i32, [P]),
         "dn_num_blocks": (i64, [P]),
         "dn_sync": (i32, [P]),
         "dn_last_error": (ctypes.c_char_p, []),
@@ -160,6 +162,9 @@ class Volume:
             self.close()
         except Exception:
             pass
+
+    def clear(self):
+        check(lib().dn_volume_clear(self.handle))
 
     @property
     def num_blocks(self) -> int:

@@ -1,0 +1,188 @@
+"""Learned warm start of the primal-dual solver.
+
+A small 3-D convolutional network (three 3x3x3 layers, 2 -> 16 -> 16 -> 1,
+ReLU; BF16 MFMA kernels with FP32 accumulation in libdenser) maps the fused
+TSDF of a block and its one-voxel halo, with the fusion weight as a second
+channel, to a residual r; the warm start is u0 = clamp(f + r, -1, 1) on
+Omega and p0 = P(grad u0 / delta).  It is trained on the GPU by the
+library's own forward/backward kernels on (fused block, regularised block)
+pairs that the method itself produces: seeded synthetic streets are fused
+and regularised for 1000 iterations, and blocks with enough observed voxels
+are sampled.
+
+The plain solver stays in charge: after K warm-started iterations the
+relative gap is compared with the plain solver's after K iterations; if it
+is more than twice that, the warm start is discarded and the solve restarts
+from zero.  Either way the solve runs until the requested gap.
+
+This module only sequences calls into the library (and uses torch for
+device buffers); every computation runs in the HIP kernels.
+"""
+from __future__ import annotations
+
+import os
+import time
+
+import numpy as np
+
+from . import denser as D
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "warmstart.npy")
+LAM = 0.5
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-normal weights, zero biases, a small last layer (r ~ 0 at start)."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(D.NET_PARAMS, np.float32)
+    p[0:864] = rng.normal(0, np.sqrt(2.0 / 54), 864)
+    p[880:7792] = rng.normal(0, np.sqrt(2.0 / 432), 6912)
+    p[7808:8240] = rng.normal(0, 0.1 * np.sqrt(1.0 / 432), 432)
+    return p
+
+
+def load_default_weights():
+    if not os.path.exists(DEFAULT_WEIGHTS):
+        return None
+    w = np.load(DEFAULT_WEIGHTS, allow_pickle=False).astype(np.float32)
+    if w.shape != (D.NET_PARAMS,):
+        return None
+    return w
+
+
+def fuse_frames(frames, max_blocks=16384):
+    import torch
+    cam = frames.camera
+    K = D.intrinsics(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height)
+    vol = D.Volume(frames.voxel_size, frames.mu, frames.max_depth, max_blocks, 16, 1024)
+    for d, T in zip(frames.depths, frames.poses):
+        vol.integrate(torch.from_numpy(d).cuda(), K, T)
+    return vol
+
+
+def make_pairs(seeds=(1001, 1002), n_pairs=5000, iters=1000, min_omega=64, length=100.0,
+               n_frames=100, sample_seed=0):
+    """(tiles, targets, masks) on the device from seeded streets: the fused
+    block (with halo) and the block after `iters` plain iterations."""
+    import torch
+    import scenes
+    tiles_l, tgt_l, msk_l = [], [], []
+    per = int(np.ceil(n_pairs / len(seeds)))
+    rng = np.random.default_rng(sample_seed)
+    for s in seeds:
+        fr = scenes.frames_street(length, n_frames, seed=s, config_id=5)
+        vol = fuse_frames(fr)
+        vol.regularize(D.reg_params(LAM, iters=iters, kernel=D.DN_K_FUSED))
+        w = vol.extract(D.DN_X_W)
+        u = vol.extract(D.DN_X_U)
+        cnt = (w > 0).sum(1)
+        cand = torch.nonzero(cnt >= min_omega).flatten().cpu().numpy()
+        pick = np.sort(rng.choice(cand, size=min(per, len(cand)), replace=False)).astype(np.int32)
+        blocks = torch.from_numpy(pick).cuda()
+        tiles = torch.empty((len(pick), 2, 10, 10, 10), device="cuda")
+        vol.net_gather(blocks, tiles)
+        tiles_l.append(tiles)
+        tgt_l.append(u[blocks.long()].contiguous())
+        msk_l.append((w[blocks.long()] > 0).float().contiguous())
+        torch.cuda.synchronize()
+        vol.close()
+    tiles = torch.cat(tiles_l)[:n_pairs].contiguous()
+    return tiles, torch.cat(tgt_l)[:n_pairs].contiguous(), torch.cat(msk_l)[:n_pairs].contiguous()
+
+
+def train(tiles, targets, masks, epochs=30, batch=256, lr=2e-3, seed=0, params=None, log=None):
+    """Adam on the masked squared error of f + r, all on the GPU."""
+    import torch
+    n = tiles.shape[0]
+    p = torch.from_numpy(init_params(seed) if params is None else params).cuda().contiguous()
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    g = torch.empty_like(p)
+    rng = np.random.default_rng(seed)
+    step = 0
+    hist = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).cuda()
+        tot, nb = 0.0, 0
+        for i in range(0, n - batch + 1, batch):
+            idx = perm[i:i + batch]
+            loss = D.net_loss_grad(tiles[idx].contiguous(), p, targets[idx].contiguous(),
+                                   masks[idx].contiguous(), g)
+            step += 1
+            D.net_adam(p, g, m, v, lr, step)
+            tot += loss
+            nb += 1
+        hist.append(tot / max(1, nb))
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.5f}")
+    torch.cuda.synchronize()
+    return p, hist
+
+
+def warm_state(vol, params, delta=0.1):
+    import torch
+    nb = vol.num_blocks
+    u0 = torch.empty((nb, 512), device="cuda")
+    p0 = torch.empty((3, nb, 512), device="cuda")
+    vol.net_warm_start(params, delta, u0, p0)
+    return u0, p0
+
+
+def solve_plain(vol, tol=1e-3, max_iters=20000, gap_every=10):
+    return vol.regularize(D.reg_params(LAM, iters=max_iters, gap_every=gap_every, gap_tol=tol,
+                                       kernel=D.DN_K_FUSED))
+
+
+def solve_warm(vol, params, tol=1e-3, k=100, plain_rel_gap_at_k=None, delta=0.1, max_iters=20000,
+               gap_every=10):
+    """Warm start, K iterations, the fallback test, then iterate to `tol`.
+    Returns a dict with iterations, timings and whether it fell back."""
+    import torch
+    if not isinstance(params, torch.Tensor):
+        params = torch.from_numpy(np.asarray(params, np.float32)).cuda()
+    t0 = time.time()
+    u0, p0 = warm_state(vol, params, delta)
+    st = vol.regularize(D.reg_params(LAM, iters=k, gap_every=gap_every, gap_tol=tol, init=D.DN_INIT_GIVEN,
+                                     kernel=D.DN_K_FUSED), u0, p0)
+    out = {"k": k, "iters_warm": st.iters_run, "rel_gap_at_k": st.rel_gap, "fallback": False}
+    if st.converged:
+        out.update(iters=st.iters_run, converged=True, rel_gap=st.rel_gap, seconds=time.time() - t0)
+        return out
+    if plain_rel_gap_at_k is not None and not (st.rel_gap <= 2.0 * plain_rel_gap_at_k):
+        out["fallback"] = True
+        st2 = solve_plain(vol, tol, max_iters, gap_every)
+        out.update(iters=st.iters_run + st2.iters_run, converged=bool(st2.converged), rel_gap=st2.rel_gap,
+                   seconds=time.time() - t0)
+        return out
+    st2 = vol.regularize(D.reg_params(LAM, iters=max_iters - k, gap_every=gap_every, gap_tol=tol,
+                                      init=D.DN_INIT_KEEP, kernel=D.DN_K_FUSED))
+    out.update(iters=st.iters_run + st2.iters_run, converged=bool(st2.converged), rel_gap=st2.rel_gap,
+               seconds=time.time() - t0)
+    return out
+
+
+def main():
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser(description="train the warm-start network on the GPU")
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--pairs", type=int, default=5000)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--batch", type=int, default=256)
+    args = ap.parse_args()
+    log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
+    t0 = time.time()
+    tiles, tgt, msk = make_pairs(n_pairs=args.pairs)
+    log(f"{tiles.shape[0]} pairs in {time.time() - t0:.1f}s")
+    t1 = time.time()
+    p, hist = train(tiles, tgt, msk, epochs=args.epochs, lr=args.lr, batch=args.batch, log=log)
+    log(f"trained in {time.time() - t1:.1f}s")
+    os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    np.save(args.out, p.cpu().numpy().astype(np.float32), allow_pickle=False)
+    print(args.out)
+
+
+if __name__ == "__main__":
+    main()

@@ -72,20 +72,52 @@ def _rays_world(cam: Camera, pose: np.ndarray):
     return pose[:3, 3].copy(), d
 
 
+def _pixel_window(lo, hi, cam: Camera, pose: np.ndarray):
+    """Pixel rectangle that can see the box, for an unrotated camera; None
+    if the box is entirely behind the camera.  Conservative (1 px margin)."""
+    o = pose[:3, 3]
+    zlo = max(lo[2], o[2] + 1e-3)
+    if zlo >= hi[2]:
+        return None
+    xs, ys = [], []
+    for x in (lo[0], hi[0]):
+        for y in (lo[1], hi[1]):
+            for z in (zlo, hi[2]):
+                xs.append(cam.fx * (x - o[0]) / (z - o[2]) + cam.cx)
+                ys.append(cam.fy * (y - o[1]) / (z - o[2]) + cam.cy)
+    x0 = max(0, int(np.floor(min(xs))) - 1)
+    x1 = min(cam.width, int(np.ceil(max(xs))) + 2)
+    y0 = max(0, int(np.floor(min(ys))) - 1)
+    y1 = min(cam.height, int(np.ceil(max(ys))) + 2)
+    if x0 >= x1 or y0 >= y1:
+        return None
+    return y0, y1, x0, x1
+
+
 def true_depth(boxes: np.ndarray, cam: Camera, pose: np.ndarray) -> np.ndarray:
     """Nearest positive hit parameter of each pixel ray against the boxes
     (float64 [H][W], +inf where nothing is hit).  boxes: [n][2][3] (lo, hi)."""
     o, d = _rays_world(cam, pose)
     best = np.full(d.shape[:2], np.inf)
+    unrotated = np.array_equal(pose[:3, :3], np.eye(3))
     with np.errstate(divide="ignore", invalid="ignore"):
         inv = 1.0 / d
         for lo, hi in boxes:
-            t0 = (lo - o) * inv
-            t1 = (hi - o) * inv
+            if unrotated:
+                win = _pixel_window(lo, hi, cam, pose)
+                if win is None:
+                    continue
+                y0, y1, x0, x1 = win
+            else:
+                y0, y1, x0, x1 = 0, cam.height, 0, cam.width
+            iv = inv[y0:y1, x0:x1]
+            t0 = (lo - o) * iv
+            t1 = (hi - o) * iv
             tn = np.nanmax(np.minimum(t0, t1), axis=-1)
             tf = np.nanmin(np.maximum(t0, t1), axis=-1)
-            hit = (tn <= tf) & (tn > 1e-6)
-            best = np.where(hit & (tn < best), tn, best)
+            bw = best[y0:y1, x0:x1]
+            hit = (tn <= tf) & (tn > 1e-6) & (tn < bw)
+            best[y0:y1, x0:x1] = np.where(hit, tn, bw)
     return best
 
 

@@ -1,0 +1,112 @@
+"""Network kernels (BF16 MFMA, FP32 accumulation) against the FP64 oracle:
+gather, forward, loss gradient (all three layers), Adam, warm start."""
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from gpu_common import dn, fuse_both, host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def _cos(a, b):
+    return float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def _params(seed, scale=0.15):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0, scale, oracle.NET_PARAMS)
+    return p
+
+
+def test_gather_matches_oracle():
+    D = dn()
+    import torch
+    fr = scenes.frames_c1(0, n_frames=2)
+    ov, gv = fuse_both(fr, check_each_frame=False)
+    blocks = np.arange(0, gv.num_blocks, 3, dtype=np.int32)
+    tiles = torch.empty((len(blocks), 2, 10, 10, 10), device="cuda")
+    gv.net_gather(to_dev(blocks), tiles)
+    ref = oracle.net_gather(ov.nbr, host(gv.extract(D.DN_X_F)).astype(np.float64), ov.w, blocks)
+    assert np.abs(host(tiles) - ref).max() <= 1e-6
+
+
+@pytest.mark.parametrize("seed,B", [(0, 1), (1, 7)])
+def test_forward_matches_oracle(seed, B):
+    D = dn()
+    import torch
+    rng = np.random.default_rng(10 + seed)
+    tiles = rng.normal(0, 0.6, (B, 2, 10, 10, 10))
+    prm = _params(seed)
+    out = torch.empty((B, 10, 10, 10), device="cuda")
+    D.net_forward(to_dev(tiles, torch.float32), to_dev(prm, torch.float32), out)
+    torch.cuda.synchronize()
+    ref = oracle.net_forward(tiles, prm)
+    g = host(out).astype(np.float64)
+    assert _rel_l2(g, ref) <= 2e-2 and _cos(g, ref) >= 0.999
+
+
+def test_loss_gradient_matches_oracle():
+    D = dn()
+    import torch
+    rng = np.random.default_rng(3)
+    B = 6
+    tiles = rng.normal(0, 0.6, (B, 2, 10, 10, 10))
+    targets = rng.normal(0, 0.5, (B, 512))
+    mask = (rng.random((B, 512)) < 0.6).astype(np.float64)
+    prm = _params(4)
+    grad = torch.empty(oracle.NET_PARAMS, device="cuda")
+    loss = D.net_loss_grad(to_dev(tiles, torch.float32), to_dev(prm, torch.float32),
+                           to_dev(targets, torch.float32), to_dev(mask, torch.float32), grad)
+    L, g_ref = oracle.net_loss_grad(tiles, prm, targets, mask)
+    g = host(grad).astype(np.float64)
+    assert abs(loss - L) <= 2e-2 * abs(L)
+    for lo, hi, name in [(0, 880, "layer1"), (880, 7808, "layer2"), (7808, 8241, "layer3")]:
+        rel, cos = _rel_l2(g[lo:hi], g_ref[lo:hi]), _cos(g[lo:hi], g_ref[lo:hi])
+        print(f"{name}: rel-L2 {rel:.3e} cos {cos:.6f}")
+        assert rel <= 5e-2 and cos >= 0.998, name
+
+
+def test_adam_step():
+    D = dn()
+    import torch
+    rng = np.random.default_rng(5)
+    n = 1000
+    p = rng.normal(size=n); g = rng.normal(size=n); m = rng.normal(size=n) * 0.1; v = rng.random(n) * 0.1
+    tp, tg, tm, tv = (to_dev(a, torch.float32) for a in (p, g, m, v))
+    D.net_adam(tp, tg, tm, tv, 1e-2, 3)
+    torch.cuda.synchronize()
+    b1, b2, eps = 0.9, 0.999, 1e-8
+    m2 = b1 * m + (1 - b1) * g
+    v2 = b2 * v + (1 - b2) * g * g
+    p2 = p - 1e-2 * (m2 / (1 - b1 ** 3)) / (np.sqrt(v2 / (1 - b2 ** 3)) + eps)
+    assert np.abs(host(tp) - p2).max() <= 1e-5
+
+
+def test_warm_start_fields():
+    D = dn()
+    import torch
+    fr = scenes.frames_c1(0, n_frames=2)
+    ov, gv = fuse_both(fr, check_each_frame=False)
+    prm = _params(7, 0.05)
+    nb = gv.num_blocks
+    u0 = torch.empty((nb, 512), device="cuda")
+    p0 = torch.empty((3, nb, 512), device="cuda")
+    gv.net_warm_start(to_dev(prm, torch.float32), 0.1, u0, p0)
+    torch.cuda.synchronize()
+    f = host(gv.extract(D.DN_X_F)).astype(np.float64)
+    w = ov.w
+    tiles = oracle.net_gather(ov.nbr, f, w, np.arange(nb, dtype=np.int32))
+    r = oracle.net_forward(tiles, prm)[:, 1:9, 1:9, 1:9].reshape(nb, 512)
+    ref = np.where(w > 0, np.clip(f + r, -1, 1), 0.0)
+    gu = host(u0).astype(np.float64)
+    assert np.abs(gu - ref).max() <= 3e-2
+    assert (gu[w == 0] == 0).all()
+    g = oracle.grad(ov.nbr, w, gu) / 0.1
+    nrm = np.maximum(1.0, np.sqrt((g ** 2).sum(0)))
+    assert np.abs(host(p0) - g / nrm).max() <= 1e-5
