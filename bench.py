@@ -35,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 ALG_BYTES_PER_VOXEL_ITER = 48  # u, ubar, p(3), f, w read; p(3), u, ubar written (FP32)
+ALG_BYTES_PER_VOXEL_ITER_16 = 28  # the same with u, ubar, p stored in 16 bits (f, w FP32)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -46,9 +47,17 @@ def parse():
     ap.add_argument("--iters", type=int, default=500)
     ap.add_argument("--copies", type=int, default=35)
     ap.add_argument("--frames", type=int, default=100)
-    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "twopass"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused256", "twopass"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"],
+                    help="storage of u, ubar, p (arithmetic is FP32 in every case)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap comparison")
+    ap.add_argument("--workload", default="street", choices=["street", "batched"],
+                    help="street: the street-scale map (default); batched: 64 uneven sub-maps "
+                         "in one persistent launch")
+    ap.add_argument("--submaps", type=int, default=64)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only copy 1 GiB device to device (HBM counter calibration) and exit")
     ap.add_argument("--profile", action="store_true",
                     help="short run for profilers: no CPU baseline, no time-to-gap")
     return ap.parse_args()
@@ -93,7 +102,8 @@ class Workload:
         self.depths = [torch.from_numpy(d).cuda() for d in self.fr.depths]
         self.street = D.Volume(self.fr.voxel_size, self.fr.mu, self.fr.max_depth, 16384, 16, 1024)
         self.big = D.Volume(self.fr.voxel_size, self.fr.mu, self.fr.max_depth, 1 << 18, 19, 8192)
-        self.kernel = {"auto": D.DN_K_AUTO, "fused": D.DN_K_FUSED, "twopass": D.DN_K_TWOPASS}[args.kernel]
+        self.kernel = {"auto": D.DN_K_AUTO, "fused": D.DN_K_FUSED, "fused256": D.DN_K_FUSED256,
+                       "twopass": D.DN_K_TWOPASS}[args.kernel]
         torch.cuda.synchronize()
 
     def fuse_street(self):
@@ -125,9 +135,65 @@ class Workload:
         D = self.D
         self.fuse_street()
         self.build_map()
-        st = self.big.regularize(D.reg_params(0.5, iters=self.args.iters, gap_every=0, kernel=self.kernel))
+        storage = {"f32": D.DN_F32, "f16": D.DN_F16, "bf16": D.DN_BF16}[self.args.storage]
+        st = self.big.regularize(D.reg_params(0.5, iters=self.args.iters, gap_every=0, kernel=self.kernel,
+                                              storage=storage, refine_every=50))
         pts = self.big.extract(D.DN_X_SURFACE)
         return st, pts.shape[0]
+
+
+class BatchedWorkload(Workload):
+    """64 sub-maps with block counts drawn log-uniform in [1e3, 5e4]; each is
+    a street segment: the n_i blocks nearest the start of a row of
+    translated copies of the fused street.  All regularised by one
+    persistent launch of 300 iterations (HIP graph, autotuned)."""
+
+    def __init__(self, args):
+        super().__init__(args)
+        import scenes
+        self.counts = scenes.c4_block_counts(args.submaps, seed=0)
+        self.subs = []
+        cap = int(self.counts.max())
+        for n in self.counts:
+            self.subs.append(self.D.Volume(self.fr.voxel_size, self.fr.mu, self.fr.max_depth, int(n),
+                                           max(10, int(np.ceil(np.log2(n))) + 1), 4096))
+        self.fuse_street()
+        self._layout()
+
+    def _layout(self):
+        D, torch = self.D, self.torch
+        c = self.street.extract(D.DN_X_COORDS).long()
+        f = self.street.extract(D.DN_X_F)
+        w = self.street.extract(D.DN_X_W)
+        zlen = int((c[:, 2].max() - c[:, 2].min()).item()) + 3
+        self.parts = []
+        for n in self.counts:
+            reps = int(np.ceil(n / c.shape[0]))
+            shift = torch.zeros((reps, 1, 3), dtype=torch.long, device=c.device)
+            shift[:, 0, 2] = torch.arange(reps, device=c.device) * zlen
+            cc = (c[None] + shift).reshape(-1, 3)
+            # the segment: the n blocks with the smallest z (ties by x, y)
+            off = 1 << 20
+            key = ((cc[:, 2] + off) << 42) | ((cc[:, 0] + off) << 21) | (cc[:, 1] + off)
+            sel = torch.argsort(key)[: int(n)]
+            cc = cc[sel]
+            # the library appends in ascending (x, y, z): order f, w likewise
+            key2 = ((cc[:, 0] + off) << 42) | ((cc[:, 1] + off) << 21) | (cc[:, 2] + off)
+            o2 = torch.argsort(key2)
+            src = sel[o2] % c.shape[0]
+            self.parts.append((cc[o2].to(torch.int32).contiguous(), f[src].contiguous(), w[src].contiguous()))
+
+    def step(self):
+        D = self.D
+        for vol, (cc, f, w) in zip(self.subs, self.parts):
+            vol.clear()
+            vol.insert_blocks(cc)
+            vol.load_fused(f, w)
+        stats = D.regularize_batch(self.subs, D.reg_params(0.5, iters=self.args.iters, kernel=D.DN_K_AUTO))
+        return stats[0], 0
+
+    def voxels(self):
+        return int(sum(v.num_blocks for v in self.subs)) * 512
 
 
 def cpu_baseline(wl):
@@ -202,15 +268,29 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calib_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.neg(x, out=y)  # one elementwise kernel: reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": x.numel() * 4}))
+        return
     from paper_1604_03734_amd import denser as D
     D.lib()
     if args.profile:
         args.no_cpu = args.no_gap = True
-    wl = Workload(args)
+    if args.workload == "batched":
+        if "--iters" not in sys.argv:
+            args.iters = 300
+        args.no_gap = True
+        wl = BatchedWorkload(args)
+    else:
+        wl = Workload(args)
     for i in range(args.warmup):
         st, npts = wl.step()
         torch.cuda.synchronize()
-        log(f"warmup {i}: blocks {wl.big.num_blocks} ms_loop {st.ms_loop:.1f}")
+        log(f"warmup {i}: ms_loop {st.ms_loop:.1f}")
     torch.cuda.synchronize()
     times, loops = [], []
     t_all = time.time()
@@ -223,15 +303,35 @@ def main():
         log(f"step {i}: {times[-1]:.3f}s, loop {st.ms_loop:.1f} ms, rel_gap {st.rel_gap:.3e}, points {npts}")
     torch.cuda.synchronize()
     total = time.time() - t_all
-    nb = wl.big.num_blocks
-    nvox = nb * 512
+    if args.workload == "batched":
+        nvox = wl.voxels()
+        nb = nvox // 512
+    else:
+        nb = wl.big.num_blocks
+        nvox = nb * 512
     ms_step = 1000.0 * total / max(1, args.steps)
     value = nvox * args.iters / (ms_step / 1000.0)
     kern_ms = float(np.mean(loops))
-    achieved = ALG_BYTES_PER_VOXEL_ITER * nvox / (kern_ms / 1000.0) / 1e9
+    alg_bytes = ALG_BYTES_PER_VOXEL_ITER if args.storage == "f32" else ALG_BYTES_PER_VOXEL_ITER_16
+    achieved = alg_bytes * nvox / (kern_ms / 1000.0) / 1e9
     traffic = load_traffic(nvox)
+    if args.workload == "batched":
+        metric = f"voxel-iterations/s ({args.submaps} sub-maps, {args.iters} CP iterations, one persistent launch)"
+        config = {"workload": f"batched sub-maps: {args.submaps} street segments with block counts "
+                              "log-uniform in [1e3, 5e4] (0.2 m voxels), one persistent launch in a HIP "
+                              "graph, autotuned grid", "blocks": nb, "voxels": nvox,
+                  "iters": args.iters, "lambda": 0.5}
+        kname = "k_cp_persistent (one CP iteration of every sub-map)"
+    else:
+        metric = "voxel-iterations/s (fusion + 500 CP iterations + gap + surface, street map)"
+        config = {"workload": "street-scale plain method, FP32: 100 depth maps 1242x375 of a 100 m "
+                              "synthetic street, 0.2 m voxels, mu 0.6 m, sigma 0.5 px, 5% invalid; "
+                              f"map = {args.copies} translated copies of the fused street",
+                  "blocks": nb, "voxels": nvox, "street_blocks": wl.street.num_blocks,
+                  "iters": args.iters, "lambda": 0.5, "kernel": args.kernel, "storage": args.storage}
+        kname = "k_cp_fused (one CP iteration)"
     line = {
-        "metric": "voxel-iterations/s (fusion + 500 CP iterations + gap + surface, street map)",
+        "metric": metric,
         "value": value,
         "unit": "voxel-iterations/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -239,16 +339,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "street-scale plain method, FP32: 100 depth maps 1242x375 of a 100 m "
-                               "synthetic street, 0.2 m voxels, mu 0.6 m, sigma 0.5 px, 5% invalid; "
-                               f"map = {args.copies} translated copies of the fused street",
-                   "blocks": nb, "voxels": nvox, "street_blocks": wl.street.num_blocks,
-                   "iters": args.iters, "lambda": 0.5, "kernel": args.kernel},
-        "roofline": {"bound": "hbm", "kernel": "k_cp_fused (one CP iteration)",
+        "config": config,
+        "roofline": {"bound": "hbm", "kernel": kname,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "alg_bytes_per_launch": ALG_BYTES_PER_VOXEL_ITER * nvox,
+                     "traffic": traffic if (args.workload == "street" and args.storage == "f32") else None,
+                     "alg_bytes_per_launch": alg_bytes * nvox,
                      "avg_launch_ms": kern_ms},
         "cp_voxel_iters_per_s": nvox / (kern_ms / 1000.0),
     }

@@ -55,7 +55,8 @@ extern "C" {
 /* ------------------------------------------------------- kernel choices */
 #define DN_K_AUTO 0      /* pick the measured-best variant (autotuned)        */
 #define DN_K_TWOPASS 1   /* dual kernel then primal kernel, per iteration     */
-#define DN_K_FUSED 2     /* one LDS-staged kernel per iteration               */
+#define DN_K_FUSED 2     /* one LDS-staged kernel per iteration, 512 threads  */
+#define DN_K_FUSED256 3  /* the same with 256 threads, two voxels per thread  */
 
 /* ----------------------------------------------------- dn_extract targets */
 #define DN_X_COORDS 1     /* int32 [n_blocks][3] block keys, pool order        */
@@ -98,6 +99,14 @@ typedef struct {
     int32_t refine_every;    /* 16-bit storage: FP32 sweep every this many iterations (0: none) */
     int32_t init;            /* DN_INIT_*                                    */
     int32_t kernel;          /* DN_K_*                                       */
+    double gamma;            /* 0: fixed steps (tau, sigma, theta).  > 0: the
+                                accelerated variant for a uniformly convex
+                                data term with modulus gamma (lambda * min w
+                                over Omega): theta_n = 1/sqrt(1 + 2 gamma
+                                tau_n), tau_{n+1} = theta_n tau_n,
+                                sigma_{n+1} = sigma_n / theta_n, starting
+                                from (tau, sigma); the schedule continues
+                                across calls with DN_INIT_KEEP           */
 } dn_reg_params;
 
 typedef struct {

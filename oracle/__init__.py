@@ -58,6 +58,7 @@ def lib():
             "or_div": (None, [P, i64, P, P, P]),
             "or_cp": (None, [P, i64, P, P, P, P, P, i32, f64, f64, f64, f64, i32]),
             "or_energy": (None, [P, i64, P, P, P, P, f64, P, i32]),
+            "or_cp_accel": (None, [P, i64, P, P, P, P, P, i32, f64, f64, P, i32]),
             "or_extract": (i64, [P, P, i64, P, P, f64, P, i64]),
             "or_net_forward": (None, [P, i64, P, P, P]),
             "or_net_loss_grad": (f64, [P, i64, P, P, P, P]),
@@ -155,6 +156,16 @@ def cp(nbr, f, w, u, ubar, p, iters, lam, tau, sigma, theta=1.0, nthreads=None):
     lib().or_cp(_p(_c(nbr, np.int32)), nb, _p(_c(f, np.float64)), _p(_c(w, np.float64)),
                 _p(u), _p(ubar), _p(p), int(iters), lam, tau, sigma, theta,
                 nthreads or nthreads_default())
+
+
+def cp_accel(nbr, f, w, u, ubar, p, iters, lam, gamma, state, nthreads=None):
+    """Accelerated iterations; state = float64 [tau_n, sigma_n], updated."""
+    for a in (u, ubar, p, state):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    nb = len(nbr)
+    lib().or_cp_accel(_p(_c(nbr, np.int32)), nb, _p(_c(f, np.float64)), _p(_c(w, np.float64)),
+                      _p(u), _p(ubar), _p(p), int(iters), lam, gamma, _p(state),
+                      nthreads or nthreads_default())
 
 
 def energy(nbr, f, w, u, p, lam, nthreads=None):

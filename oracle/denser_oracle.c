@@ -380,6 +380,30 @@ void or_cp(const int32_t *nbr, int64_t nb, const double *f, const double *w, dou
 }
 
 /* ---------------------------------------------------------------------
+ * Accelerated variant (the paper's reference [Chambolle & Pock 2011], the
+ * algorithm for a uniformly convex primal term): the data term
+ * (lambda/2) w (u - f)^2 is uniformly convex with modulus gamma = lambda
+ * min_Omega w, which allows step sizes that adapt every iteration:
+ *   theta_n = 1 / sqrt(1 + 2 gamma tau_n),
+ *   tau_{n+1} = theta_n tau_n,  sigma_{n+1} = sigma_n / theta_n,
+ * with the dual and primal steps of or_cp using sigma_n, tau_n and the
+ * relaxation using theta_n.  state[0..1] = (tau_n, sigma_n) on entry and
+ * on exit, so a split run resumes exactly.
+ * ------------------------------------------------------------------- */
+void or_cp_accel(const int32_t *nbr, int64_t nb, const double *f, const double *w, double *u,
+                 double *ubar, double *p, int32_t iters, double lambda, double gamma, double *state,
+                 int32_t nthreads)
+{
+    for (int32_t it = 0; it < iters; ++it) {
+        double tau = state[0], sigma = state[1];
+        double theta = 1.0 / sqrt(1.0 + 2.0 * gamma * tau);
+        or_cp(nbr, nb, f, w, u, ubar, p, 1, lambda, tau, sigma, theta, nthreads);
+        state[0] = theta * tau;
+        state[1] = sigma / theta;
+    }
+}
+
+/* ---------------------------------------------------------------------
  * Primal and dual energies, Eq. (2) and Eqs. (5)-(6).
  * Reading: Eq. (2) prints lambda |f - u|^2 without the weight, but the
  * update of Eq. (8) is the proximal map of (lambda/2) w (u - f)^2; the

@@ -38,6 +38,8 @@ struct BatchArgs {
     int32_t iters;
     int32_t xcd_chunks;       // 1: each XCD works on one contiguous item chunk
     float sigma, tau, lambda, theta;
+    double gamma;             // > 0: accelerated schedule from (tau, sigma)
+    double tau0, sigma0;      // schedule state at the start of the launch
     unsigned *bar;            // [0] arrivals, [1] generation
     int32_t *err;             // set when a barrier wait exceeds its bound
     long long spin_limit;
@@ -85,11 +87,22 @@ __global__ __launch_bounds__(512) void k_cp_persistent(BatchArgs a)
     __shared__ int s_stop;
     const unsigned nwg = gridDim.x;
     const int64_t G = nwg;
+    double acc_tau = a.tau0, acc_sigma = a.sigma0;
     for (int it = 0; it < a.iters; ++it) {
-        if (a.xcd_chunks) {
+        float sigma = a.sigma, tau = a.tau, theta = a.theta;
+        if (a.gamma > 0.0) {
+            const double th = 1.0 / sqrt(1.0 + 2.0 * a.gamma * acc_tau);
+            tau = float(acc_tau);
+            sigma = float(acc_sigma);
+            theta = float(th);
+            acc_tau = th * acc_tau;
+            acc_sigma = acc_sigma / th;
+        }
+        if (a.xcd_chunks && G >= 8) {
             // workgroup g runs on XCD g % 8; XCD x owns items [x*chunk, (x+1)*chunk)
-            const int64_t lanes = (G + 7) / 8;
+            // and has exactly (G - x + 7) / 8 workgroups to stride over them
             const int64_t x = blockIdx.x % 8, lane = blockIdx.x / 8;
+            const int64_t lanes = (G - x + 7) / 8;
             const int64_t chunk = (a.n_items + 7) / 8;
             const int64_t lo = x * chunk, hi = min(a.n_items, lo + chunk);
             for (int64_t i = lo + lane; i < hi; i += lanes) {
@@ -100,7 +113,7 @@ __global__ __launch_bounds__(512) void k_cp_persistent(BatchArgs a)
                 A.nb = 0; A.pstride = d.pstride; A.nbr = d.nbr; A.emask = d.emask; A.order = nullptr;
                 A.f = d.f; A.w = d.w; A.u = d.u; A.ubar_in = d.ubar[c]; A.ubar_out = d.ubar[1 - c];
                 A.p_in = d.p[c]; A.p_out = d.p[1 - c]; A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
-                A.sigma = a.sigma; A.tau = a.tau; A.lambda = a.lambda; A.theta = a.theta;
+                A.sigma = sigma; A.tau = tau; A.lambda = a.lambda; A.theta = theta;
                 cp_block<SF32, false>(A, item.y, sh);
                 __syncthreads();
             }
@@ -113,7 +126,7 @@ __global__ __launch_bounds__(512) void k_cp_persistent(BatchArgs a)
                 A.nb = 0; A.pstride = d.pstride; A.nbr = d.nbr; A.emask = d.emask; A.order = nullptr;
                 A.f = d.f; A.w = d.w; A.u = d.u; A.ubar_in = d.ubar[c]; A.ubar_out = d.ubar[1 - c];
                 A.p_in = d.p[c]; A.p_out = d.p[1 - c]; A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
-                A.sigma = a.sigma; A.tau = a.tau; A.lambda = a.lambda; A.theta = a.theta;
+                A.sigma = sigma; A.tau = tau; A.lambda = a.lambda; A.theta = theta;
                 cp_block<SF32, false>(A, item.y, sh);
                 __syncthreads();
             }
@@ -142,6 +155,7 @@ struct BatchCtx {
     int64_t k_n = -1;
     int k_iters = -1, k_grid = -1, k_xcd = -1;
     float k_prm[4] = {0, 0, 0, 0};
+    double k_acc[3] = {0, 0, 0};
     const void *vols_ptr = nullptr;
     const void *bar_ptr = nullptr;
     hipStream_t cap = nullptr;        // private stream for capture and replay
@@ -180,7 +194,8 @@ static int launch_graph(hipStream_t st, const BatchArgs &a, int grid)
     }
     bool same = c.exec && c.k_items == a.items && c.k_n == a.n_items && c.k_iters == a.iters && c.k_grid == grid &&
                 c.k_xcd == a.xcd_chunks && c.k_prm[0] == a.sigma && c.k_prm[1] == a.tau &&
-                c.k_prm[2] == a.lambda && c.k_prm[3] == a.theta && c.vols_ptr == a.vols && c.bar_ptr == a.bar;
+                c.k_prm[2] == a.lambda && c.k_prm[3] == a.theta && c.vols_ptr == a.vols && c.bar_ptr == a.bar &&
+                c.k_acc[0] == a.gamma && c.k_acc[1] == a.tau0 && c.k_acc[2] == a.sigma0;
     if (!same) {
         if (c.exec) { (void)hipGraphExecDestroy(c.exec); c.exec = nullptr; }
         if (c.graph) { (void)hipGraphDestroy(c.graph); c.graph = nullptr; }
@@ -196,6 +211,7 @@ static int launch_graph(hipStream_t st, const BatchArgs &a, int grid)
         DN_HIP(hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0));
         c.k_items = a.items; c.k_n = a.n_items; c.k_iters = a.iters; c.k_grid = grid; c.k_xcd = a.xcd_chunks;
         c.k_prm[0] = a.sigma; c.k_prm[1] = a.tau; c.k_prm[2] = a.lambda; c.k_prm[3] = a.theta;
+        c.k_acc[0] = a.gamma; c.k_acc[1] = a.tau0; c.k_acc[2] = a.sigma0;
         c.vols_ptr = a.vols; c.bar_ptr = a.bar;
     }
     DN_HIP(hipEventRecord(c.ev_in, st));
@@ -231,6 +247,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     DN_REQUIRE(prm->theta >= 0 && prm->theta <= 1 && prm->iters >= 0, "bad theta or iters");
     DN_REQUIRE(prm->storage == DN_F32, "the batched solver stores its state in FP32");
     DN_REQUIRE(prm->init == DN_INIT_ZERO || prm->init == DN_INIT_KEEP, "init must be ZERO or KEEP");
+    DN_REQUIRE(prm->gamma >= 0 && std::isfinite(prm->gamma), "gamma must be >= 0");
     for (int i = 0; i < n; ++i) {
         DN_REQUIRE(vols[i], "null volume %d", i);
         DN_REQUIRE(vols[i]->device == vols[0]->device, "volumes on different devices");
@@ -280,6 +297,11 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     a.items = c.items.as<int2>();
     a.n_items = total;
     a.sigma = float(prm->sigma); a.tau = float(prm->tau); a.lambda = float(prm->lambda); a.theta = float(prm->theta);
+    // the accelerated schedule of the batch lives in the first volume
+    if (prm->init != DN_INIT_KEEP || v0->acc_tau <= 0.0) { v0->acc_tau = prm->tau; v0->acc_sigma = prm->sigma; }
+    a.gamma = prm->gamma;
+    a.tau0 = v0->acc_tau;
+    a.sigma0 = v0->acc_sigma;
     a.bar = c.state.as<unsigned>();
     a.err = reinterpret_cast<int32_t *>(c.state.as<unsigned>() + 4);
     a.spin_limit = 1LL << 22;
@@ -345,6 +367,12 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if ((rc = check_err(st, a.err, v0->host))) return rc;
+    if (prm->gamma > 0.0)
+        for (int k = 0; k < prm->iters; ++k) {
+            const double th = 1.0 / std::sqrt(1.0 + 2.0 * prm->gamma * v0->acc_tau);
+            v0->acc_tau = th * v0->acc_tau;
+            v0->acc_sigma = v0->acc_sigma / th;
+        }
     for (int i = 0; i < n; ++i) {
         dn_volume *v = vols[i];
         v->cur = (v->cur + prm->iters) & 1;

@@ -117,26 +117,38 @@ __device__ __forceinline__ void project(float &a, float &b, float &c)
     if (n > 1.0f) { a = a / n; b = b / n; c = c / n; }
 }
 
-// One fused Chambolle-Pock iteration on block b (512 threads).
-template <class S, bool kRefine>
+// One fused Chambolle-Pock iteration on block b by NT threads (512: one
+// voxel per thread; 256: two voxels per thread, z layers l and l + 4).
+template <class S, bool kRefine, int NT = 512>
 __device__ __forceinline__ void cp_block(const CPArgs<S> &A, int64_t b, CPShared &sh)
 {
+    constexpr int VPT = kBlockVox / NT;
     const int t = threadIdx.x;
-    const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
-    const int64_t gi = b * kBlockVox + t;
+    const int64_t g0i = b * kBlockVox;
     const int32_t *nb27 = A.nbr + b * kNbr;
     const int64_t ps = A.pstride;
 
-    const float ub = S::ld(A.ubar_in[gi]);
-    const uint8_t m = A.emask[gi];
-    float p0 = S::ld(A.p_in[gi]), p1 = S::ld(A.p_in[gi + ps]), p2 = S::ld(A.p_in[gi + 2 * ps]);
-    const float uo = S::ld(A.u[gi]);
-    const float fv = A.f[gi], wv = A.w[gi];
-    sh.u[i10(lx, ly, lz)] = ub;
-    sh.m[i9(lx, ly, lz)] = m;
-    if (t < 432) {
+    float ub[VPT], p0[VPT], p1[VPT], p2[VPT], uo[VPT], fv[VPT], wv[VPT];
+    uint8_t m[VPT];
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v = t + k * NT;
+        const int64_t gi = g0i + v;
+        ub[k] = S::ld(A.ubar_in[gi]);
+        m[k] = A.emask[gi];
+        p0[k] = S::ld(A.p_in[gi]); p1[k] = S::ld(A.p_in[gi + ps]); p2[k] = S::ld(A.p_in[gi + 2 * ps]);
+        uo[k] = S::ld(A.u[gi]);
+        fv[k] = A.f[gi]; wv[k] = A.w[gi];
+    }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v = t + k * NT, lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
+        sh.u[i10(lx, ly, lz)] = ub[k];
+        sh.m[i9(lx, ly, lz)] = m[k];
+    }
+    for (int h = t; h < 432; h += NT) {
         int hx, hy, hz;
-        halo_pos(t, hx, hy, hz);
+        halo_pos(h, hx, hy, hz);
         int64_t j = halo_index(nb27, hx, hy, hz);
         sh.u[i10(hx, hy, hz)] = j >= 0 ? S::ld(A.ubar_in[j]) : 0.0f;
     }
@@ -155,16 +167,19 @@ __device__ __forceinline__ void cp_block(const CPArgs<S> &A, int64_t b, CPShared
     __syncthreads();
 
     // dual ascent and projection on the block (Eq. 7)
-    {
-        float g0 = (m & 2) ? sh.u[i10(lx + 1, ly, lz)] - ub : 0.0f;
-        float g1 = (m & 4) ? sh.u[i10(lx, ly + 1, lz)] - ub : 0.0f;
-        float g2 = (m & 8) ? sh.u[i10(lx, ly, lz + 1)] - ub : 0.0f;
-        p0 = p0 + A.sigma * g0; p1 = p1 + A.sigma * g1; p2 = p2 + A.sigma * g2;
-        project(p0, p1, p2);
-        const int k = i9(lx, ly, lz);
-        sh.p[0][k] = p0; sh.p[1][k] = p1; sh.p[2][k] = p2;
-        A.p_out[gi] = S::rz(p0); A.p_out[gi + ps] = S::rz(p1); A.p_out[gi + 2 * ps] = S::rz(p2);
-        if (kRefine) { A.p32[gi] = p0; A.p32[gi + ps] = p1; A.p32[gi + 2 * ps] = p2; }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v = t + k * NT, lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
+        const int64_t gi = g0i + v;
+        float g0 = (m[k] & 2) ? sh.u[i10(lx + 1, ly, lz)] - ub[k] : 0.0f;
+        float g1 = (m[k] & 4) ? sh.u[i10(lx, ly + 1, lz)] - ub[k] : 0.0f;
+        float g2 = (m[k] & 8) ? sh.u[i10(lx, ly, lz + 1)] - ub[k] : 0.0f;
+        float a0 = p0[k] + A.sigma * g0, a1 = p1[k] + A.sigma * g1, a2 = p2[k] + A.sigma * g2;
+        project(a0, a1, a2);
+        const int q = i9(lx, ly, lz);
+        sh.p[0][q] = a0; sh.p[1][q] = a1; sh.p[2][q] = a2;
+        A.p_out[gi] = S::rz(a0); A.p_out[gi + ps] = S::rz(a1); A.p_out[gi + 2 * ps] = S::rz(a2);
+        if (kRefine) { A.p32[gi] = a0; A.p32[gi + ps] = a1; A.p32[gi + 2 * ps] = a2; }
     }
     // ... and on the -1 faces, which the divergence needs
     if (t < 192) {
@@ -174,28 +189,33 @@ __device__ __forceinline__ void cp_block(const CPArgs<S> &A, int64_t b, CPShared
         float g2 = (hm & 8) ? sh.u[i10(fx, fy, fz + 1)] - uh : 0.0f;
         h0 = h0 + A.sigma * g0; h1 = h1 + A.sigma * g1; h2 = h2 + A.sigma * g2;
         project(h0, h1, h2);
-        const int k = i9(fx, fy, fz);
-        sh.p[0][k] = h0; sh.p[1][k] = h1; sh.p[2][k] = h2;
+        const int q = i9(fx, fy, fz);
+        sh.p[0][q] = h0; sh.p[1][q] = h1; sh.p[2][q] = h2;
     }
     __syncthreads();
 
     // primal proximal step (Eq. 8) and relaxation (Eq. 9)
-    float un = uo;
-    if (m & 1) {
-        const int k = i9(lx, ly, lz);
-        const int kx = i9(lx - 1, ly, lz), ky = i9(lx, ly - 1, lz), kz = i9(lx, ly, lz - 1);
-        float dv = 0.0f;
-        dv += ((m & 2) ? sh.p[0][k] : 0.0f) - ((sh.m[kx] & 2) ? sh.p[0][kx] : 0.0f);
-        dv += ((m & 4) ? sh.p[1][k] : 0.0f) - ((sh.m[ky] & 4) ? sh.p[1][ky] : 0.0f);
-        dv += ((m & 8) ? sh.p[2][k] : 0.0f) - ((sh.m[kz] & 8) ? sh.p[2][kz] : 0.0f);
-        float ut = uo + A.tau * dv;
-        float tlw = A.tau * A.lambda * wv;
-        un = (ut + tlw * fv) / (1.0f + tlw);
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v = t + k * NT, lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
+        const int64_t gi = g0i + v;
+        float un = uo[k];
+        if (m[k] & 1) {
+            const int q = i9(lx, ly, lz);
+            const int qx = i9(lx - 1, ly, lz), qy = i9(lx, ly - 1, lz), qz = i9(lx, ly, lz - 1);
+            float dv = 0.0f;
+            dv += ((m[k] & 2) ? sh.p[0][q] : 0.0f) - ((sh.m[qx] & 2) ? sh.p[0][qx] : 0.0f);
+            dv += ((m[k] & 4) ? sh.p[1][q] : 0.0f) - ((sh.m[qy] & 4) ? sh.p[1][qy] : 0.0f);
+            dv += ((m[k] & 8) ? sh.p[2][q] : 0.0f) - ((sh.m[qz] & 8) ? sh.p[2][qz] : 0.0f);
+            float ut = uo[k] + A.tau * dv;
+            float tlw = A.tau * A.lambda * wv[k];
+            un = (ut + tlw * fv[k]) / (1.0f + tlw);
+        }
+        float ubn = un + A.theta * (un - uo[k]);
+        A.u[gi] = S::rn(un);
+        A.ubar_out[gi] = S::rn(ubn);
+        if (kRefine) { A.u32[gi] = un; A.ubar32[gi] = ubn; }
     }
-    float ubn = un + A.theta * (un - uo);
-    A.u[gi] = S::rn(un);
-    A.ubar_out[gi] = S::rn(ubn);
-    if (kRefine) { A.u32[gi] = un; A.ubar32[gi] = ubn; }
 }
 
 // Workgroup -> block mapping.  Consecutive workgroups go round-robin to the

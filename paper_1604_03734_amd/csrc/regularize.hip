@@ -32,7 +32,19 @@ __global__ __launch_bounds__(512) void k_cp_fused(CPArgs<S> A)
     int64_t slot = xcd_slot(blockIdx.x, A.nb);
     if (slot >= A.nb) return;
     int64_t b = A.order ? A.order[slot] : slot;
-    cp_block<S, kRefine>(A, b, sh);
+    cp_block<S, kRefine, 512>(A, b, sh);
+}
+
+// The same iteration with 256 threads per block (two voxels per thread):
+// twice the loads in flight per thread and twice the workgroups per CU.
+template <class S, bool kRefine>
+__global__ __launch_bounds__(256) void k_cp_fused256(CPArgs<S> A)
+{
+    __shared__ CPShared sh;
+    int64_t slot = xcd_slot(blockIdx.x, A.nb);
+    if (slot >= A.nb) return;
+    int64_t b = A.order ? A.order[slot] : slot;
+    cp_block<S, kRefine, 256>(A, b, sh);
 }
 
 // ----------------------------------------------------- two-pass variant
@@ -353,24 +365,34 @@ static int step_f32(dn_volume *v, const dn_reg_params *prm, int kernel)
     }
     const int c = v->cur, n = 1 - c;
     auto A = make_args<SF32>(v, prm, v->u, v->ubar[c], v->ubar[n], v->p[c], v->p[n]);
-    hipLaunchKernelGGL((k_cp_fused<SF32, false>), dim3(fused_grid(v->nb)), dim3(512), 0, st, A);
+    if (kernel == DN_K_FUSED256)
+        hipLaunchKernelGGL((k_cp_fused256<SF32, false>), dim3(fused_grid(v->nb)), dim3(256), 0, st, A);
+    else
+        hipLaunchKernelGGL((k_cp_fused<SF32, false>), dim3(fused_grid(v->nb)), dim3(512), 0, st, A);
     DN_HIP(hipGetLastError());
     v->cur = n;
     return DN_OK;
 }
 
 template <class S>
-static int step_lowp(dn_volume *v, const dn_reg_params *prm, bool refine)
+static int step_lowp(dn_volume *v, const dn_reg_params *prm, bool refine, int kernel)
 {
     const int c = v->cur, n = 1 - c;
     using T = typename S::T;
     auto A = make_args<S>(v, prm, (T *)v->u16, (T *)v->ubar16[c], (T *)v->ubar16[n], (T *)v->p16[c],
                           (T *)v->p16[n]);
+    const dim3 grid(fused_grid(v->nb));
     if (refine) {
         A.u32 = v->u; A.ubar32 = v->ubar[n]; A.p32 = v->p[n];
-        hipLaunchKernelGGL((k_cp_fused<S, true>), dim3(fused_grid(v->nb)), dim3(512), 0, v->stream, A);
+        if (kernel == DN_K_FUSED256)
+            hipLaunchKernelGGL((k_cp_fused256<S, true>), grid, dim3(256), 0, v->stream, A);
+        else
+            hipLaunchKernelGGL((k_cp_fused<S, true>), grid, dim3(512), 0, v->stream, A);
     } else {
-        hipLaunchKernelGGL((k_cp_fused<S, false>), dim3(fused_grid(v->nb)), dim3(512), 0, v->stream, A);
+        if (kernel == DN_K_FUSED256)
+            hipLaunchKernelGGL((k_cp_fused256<S, false>), grid, dim3(256), 0, v->stream, A);
+        else
+            hipLaunchKernelGGL((k_cp_fused<S, false>), grid, dim3(512), 0, v->stream, A);
     }
     DN_HIP(hipGetLastError());
     v->cur = n;
@@ -405,8 +427,9 @@ static int validate(const dn_reg_params *prm)
     int s = prm->storage;
     DN_REQUIRE(s == DN_F32 || s == DN_F16 || s == DN_BF16, "bad storage");
     DN_REQUIRE(prm->init >= DN_INIT_ZERO && prm->init <= DN_INIT_GIVEN, "bad init");
-    DN_REQUIRE(prm->kernel >= DN_K_AUTO && prm->kernel <= DN_K_FUSED, "bad kernel");
+    DN_REQUIRE(prm->kernel >= DN_K_AUTO && prm->kernel <= DN_K_FUSED256, "bad kernel");
     DN_REQUIRE(prm->refine_every >= 0, "refine_every must be >= 0");
+    DN_REQUIRE(prm->gamma >= 0 && std::isfinite(prm->gamma), "gamma must be >= 0");
     return DN_OK;
 }
 
@@ -445,7 +468,7 @@ static int autotune_single(dn_volume *v, const dn_reg_params *prm, int *choice)
     float best_ms = 1e30f;
     int best = DN_K_FUSED;
     const int trial = 6;
-    for (int k : {DN_K_TWOPASS, DN_K_FUSED}) {
+    for (int k : {DN_K_TWOPASS, DN_K_FUSED, DN_K_FUSED256}) {
         int rc = zero_state(v);
         if (rc) return rc;
         if ((rc = step_f32(v, prm, k))) return rc;  // warm up
@@ -506,9 +529,13 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
         }
         v->state_storage = DN_F32;
     }
+    if (prm->init != DN_INIT_KEEP || v->acc_tau <= 0.0) {
+        v->acc_tau = prm->tau;
+        v->acc_sigma = prm->sigma;
+    }
     int kernel = prm->kernel;
     if (storage != DN_F32) {
-        kernel = DN_K_FUSED;
+        if (kernel != DN_K_FUSED256) kernel = DN_K_FUSED;
         if ((rc = ensure_lowp(v))) return rc;
         if (v->state_storage != storage) {
             // the FP32 state (zero, given or an earlier FP32 run) is demoted
@@ -540,12 +567,23 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
     DN_HIP(hipEventCreate(&ev0));
     DN_HIP(hipEventCreate(&ev1));
     DN_HIP(hipEventRecord(ev0, st));
+    dn_reg_params step_prm = *prm;
     for (; it < prm->iters && v->nb > 0; ++it) {
+        if (prm->gamma > 0.0) {
+            // accelerated schedule: this iteration's (sigma_n, tau_n, theta_n)
+            const double th = 1.0 / std::sqrt(1.0 + 2.0 * prm->gamma * v->acc_tau);
+            step_prm.tau = v->acc_tau;
+            step_prm.sigma = v->acc_sigma;
+            step_prm.theta = th;
+            v->acc_tau = th * v->acc_tau;
+            v->acc_sigma = v->acc_sigma / th;
+        }
         if (storage == DN_F32) {
-            rc = step_f32(v, prm, kernel);
+            rc = step_f32(v, &step_prm, kernel);
         } else {
             bool refine = (prm->refine_every > 0 && (it + 1) % prm->refine_every == 0) || it + 1 == prm->iters;
-            rc = storage == DN_F16 ? step_lowp<SF16>(v, prm, refine) : step_lowp<SBF16>(v, prm, refine);
+            rc = storage == DN_F16 ? step_lowp<SF16>(v, &step_prm, refine, kernel)
+                                   : step_lowp<SBF16>(v, &step_prm, refine, kernel);
         }
         if (rc) return rc;
         if (prm->gap_every > 0 && (it + 1) % prm->gap_every == 0 && it + 1 < prm->iters) {

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libdenser.so")
 DN_OK, DN_E_INVALID, DN_E_CAPACITY, DN_E_NUMERIC, DN_E_DEVICE = 0, -1, -2, -3, -4
 DN_F32, DN_F16, DN_BF16 = 0, 1, 2
 DN_INIT_ZERO, DN_INIT_KEEP, DN_INIT_GIVEN = 0, 1, 2
-DN_K_AUTO, DN_K_TWOPASS, DN_K_FUSED = 0, 1, 2
+DN_K_AUTO, DN_K_TWOPASS, DN_K_FUSED, DN_K_FUSED256 = 0, 1, 2, 3
 (DN_X_COORDS, DN_X_HASH, DN_X_NBR, DN_X_F, DN_X_W, DN_X_U, DN_X_UBAR, DN_X_P, DN_X_SURFACE,
  DN_X_CANDIDATES, DN_X_EMASK) = range(1, 12)
 NET_PARAMS = 8241
@@ -47,7 +47,8 @@ class RegParams(ctypes.Structure):
     _fields_ = [("lam", ctypes.c_double), ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("theta", ctypes.c_double), ("iters", ctypes.c_int32), ("gap_every", ctypes.c_int32),
                 ("gap_tol", ctypes.c_double), ("storage", ctypes.c_int32),
-                ("refine_every", ctypes.c_int32), ("init", ctypes.c_int32), ("kernel", ctypes.c_int32)]
+                ("refine_every", ctypes.c_int32), ("init", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("gamma", ctypes.c_double)]
 
 
 class RegStats(ctypes.Structure):
@@ -60,10 +61,11 @@ class RegStats(ctypes.Structure):
 
 
 def reg_params(lam=0.5, tau=None, sigma=None, theta=1.0, iters=200, gap_every=0, gap_tol=0.0,
-               storage=DN_F32, refine_every=50, init=DN_INIT_ZERO, kernel=DN_K_AUTO) -> RegParams:
+               storage=DN_F32, refine_every=50, init=DN_INIT_ZERO, kernel=DN_K_AUTO, gamma=0.0) -> RegParams:
     tau = 1.0 / np.sqrt(12.0) if tau is None else tau
     sigma = 1.0 / np.sqrt(12.0) if sigma is None else sigma
-    return RegParams(lam, tau, sigma, theta, iters, gap_every, gap_tol, storage, refine_every, init, kernel)
+    return RegParams(lam, tau, sigma, theta, iters, gap_every, gap_tol, storage, refine_every, init, kernel,
+                     gamma)
 
 
 _lib = None

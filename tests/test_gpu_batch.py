@@ -55,3 +55,15 @@ def test_batch_keep_resumes_and_graph_replays():
         for h, ref in zip(handles, whole):
             for a, b in zip(state_of(D, h), ref):
                 np.testing.assert_array_equal(a, b)
+
+
+def test_batch_accelerated_matches_single():
+    D = dn()
+    vols = [_make(D, *s) for s in SIZES[:4]]
+    handles = [v[0] for v in vols]
+    D.regularize_batch(handles, D.reg_params(LAM, iters=40, kernel=D.DN_K_AUTO, gamma=LAM))
+    batched = [state_of(D, h) for h in handles]
+    for h, ref in zip(handles, batched):
+        h.regularize(D.reg_params(LAM, iters=40, kernel=D.DN_K_FUSED, gamma=LAM))
+        for a, b in zip(state_of(D, h), ref):
+            np.testing.assert_array_equal(a, b)

@@ -1,0 +1,83 @@
+"""Parity at the street workload's full size, in the launch configuration
+bench.py times: 100 depth maps of 1242x375, 0.2 m voxels, then the map of 35
+translated copies regularised for 500 iterations with the same kernel
+choice.  Allocation and weights are checked bit-exactly against the oracle
+on the whole street; the regularised map through properties that hold at
+any size (every copy equals every other bit for bit, |p| <= 1, weak
+duality, unobserved voxels untouched) and copy 0 against the oracle run on
+the single street."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import LAM, SIG, TAU, dn, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def street():
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    import torch
+
+    import types
+    args = types.SimpleNamespace(frames=100, copies=35, iters=500, kernel="auto", storage="f32")
+    wl = bench.Workload(args)
+    st, npts = wl.step()
+    torch.cuda.synchronize()
+    return wl, st, npts
+
+
+def test_street_allocation_and_fusion_bit_exact(street):
+    D = dn()
+    wl, st, npts = street
+    fr = wl.fr
+    cam = fr.camera
+    K4 = [cam.fx, cam.fy, cam.cx, cam.cy]
+    ov = oracle.OracleVolume(fr.voxel_size, fr.mu, fr.max_depth, 16384, 16, 1024)
+    for d, T in zip(fr.depths, fr.poses):
+        assert ov.alloc(d, K4, T) >= 0
+        ov.fuse(d, K4, T)
+    g = wl.street
+    assert g.num_blocks == ov.nb
+    np.testing.assert_array_equal(host(g.extract(D.DN_X_COORDS)), ov.coords)
+    np.testing.assert_array_equal(host(g.extract(D.DN_X_HASH)), ov.slots)
+    np.testing.assert_array_equal(host(g.extract(D.DN_X_NBR)), ov.nbr)
+    np.testing.assert_array_equal(host(g.extract(D.DN_X_W)), ov.w)
+    assert np.abs(host(g.extract(D.DN_X_F)) - ov.f).max() <= 1e-4
+
+
+def test_street_map_regularised_properties_and_copy_parity(street):
+    D = dn()
+    wl, st, npts = street
+    big = wl.big
+    k = wl.args.copies
+    nb1 = wl.street.num_blocks
+    assert big.num_blocks == k * nb1
+    u = host(big.extract(D.DN_X_U)).reshape(k, nb1, 512)
+    w = host(big.extract(D.DN_X_W)).reshape(k, nb1, 512)
+    p = host(big.extract(D.DN_X_P)).reshape(3, k, nb1, 512)
+    for c in range(1, k):
+        np.testing.assert_array_equal(u[c], u[0])
+        np.testing.assert_array_equal(p[:, c], p[:, 0])
+    assert np.sqrt((p.astype(np.float64) ** 2).sum(0)).max() <= 1.0 + 1e-6
+    assert (u[w == 0] == 0).all()
+    assert st.gap >= 0 and st.iters_run == 500 and npts > 0
+    # copy 0 against the oracle on the single street (same f, w, same order)
+    f1 = host(big.extract(D.DN_X_F)).reshape(k, nb1, 512)[0].astype(np.float64)
+    c1 = host(big.extract(D.DN_X_COORDS)).reshape(k, nb1, 3)[0]
+    ov = oracle.OracleVolume(0.2, 0.6, 50.0, nb1, 16, 1024)
+    assert ov.insert(c1) == nb1
+    np.testing.assert_array_equal(ov.coords, c1)
+    uo = np.zeros_like(f1); ubo = np.zeros_like(uo); po = np.zeros((3,) + uo.shape)
+    oracle.cp(ov.nbr, f1, w[0].astype(np.float64), uo, ubo, po, 500, LAM, TAU, SIG, 1.0)
+    err = np.abs(u[0] - uo).max()
+    print(f"street copy 0 vs oracle after 500 iterations: max |du| = {err:.3e}")
+    assert err <= 1e-4
+    E1, D1 = oracle.energy(ov.nbr, f1, w[0].astype(np.float64), u[0].astype(np.float64),
+                           p[:, 0].astype(np.float64), LAM)
+    assert abs(st.energy - k * E1) <= 1e-9 * abs(k * E1)
+    assert abs(st.dual - k * D1) <= 1e-9 * abs(k * E1)

@@ -76,6 +76,10 @@ def test_fused_equals_twopass_and_is_deterministic(c1):
     gv.regularize(D.reg_params(LAM, iters=60, kernel=D.DN_K_TWOPASS))
     c = state_of(D, gv)
     assert np.abs(a[0] - c[0]).max() <= 1e-5
+    # 256 threads x 2 voxels computes each voxel with the same arithmetic
+    gv.regularize(D.reg_params(LAM, iters=60, kernel=D.DN_K_FUSED256))
+    for x, y in zip(a, state_of(D, gv)):
+        np.testing.assert_array_equal(x, y)
 
 
 def test_split_run_resumes_exactly(c1):
@@ -217,3 +221,28 @@ def test_mixed_precision_error_is_reported_and_bounded(c1, storage):
     assert st.gap >= 0
     gp = host(gv.extract(D.DN_X_P))
     assert np.sqrt((gp.astype(np.float64) ** 2).sum(0)).max() <= 1.0 + 1e-6
+
+
+def test_accelerated_variant_parity_and_resume(c1):
+    D = dn()
+    fr, ov, gv = c1
+    gam = LAM * 1.0  # lambda * min w over Omega (w counts frames, >= 1)
+    st = gv.regularize(D.reg_params(LAM, iters=200, kernel=D.DN_K_FUSED, gamma=gam))
+    u = np.zeros_like(ov.f); ub = np.zeros_like(u); p = np.zeros((3,) + u.shape)
+    state = np.array([TAU, SIG])
+    oracle.cp_accel(ov.nbr, ov.f, ov.w, u, ub, p, 200, LAM, gam, state)
+    gu, gub, gp = state_of(D, gv)
+    assert np.abs(gu - u).max() <= TOL_U
+    assert np.sqrt((gp ** 2).sum(0)).max() <= 1.0 + 1e-6
+    E, Dd = oracle.energy(ov.nbr, ov.f, ov.w, u, p, LAM)
+    assert abs(st.rel_gap - (E - Dd) / E) <= 1e-3 * (E - Dd) / E + 1e-7
+    # split run continues the schedule exactly
+    gv.regularize(D.reg_params(LAM, iters=120, kernel=D.DN_K_FUSED, gamma=gam))
+    gv.regularize(D.reg_params(LAM, iters=80, kernel=D.DN_K_FUSED, gamma=gam, init=D.DN_INIT_KEEP))
+    for x, y in zip(state_of(D, gv), (gu, gub, gp)):
+        np.testing.assert_array_equal(x, y)
+    # it reaches the gap target in far fewer iterations than fixed steps
+    a = gv.regularize(D.reg_params(LAM, iters=3000, gap_every=10, gap_tol=1e-3, kernel=D.DN_K_FUSED, gamma=gam))
+    b = gv.regularize(D.reg_params(LAM, iters=3000, gap_every=10, gap_tol=1e-3, kernel=D.DN_K_FUSED))
+    print(f"iterations to rel gap 1e-3: accelerated {a.iters_run}, fixed steps {b.iters_run}")
+    assert a.converged and b.converged and 3 * a.iters_run < b.iters_run
