@@ -68,9 +68,11 @@ def log(*a):
 
 
 def src_digest():
+    """Digest of the sources of the iteration kernels."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1604_03734_amd", "csrc", "regularize.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("cp_kernel.h", "regularize.hip"):
+        with open(os.path.join(ROOT, "paper_1604_03734_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -348,6 +350,11 @@ def main():
                      "avg_launch_ms": kern_ms},
         "cp_voxel_iters_per_s": nvox / (kern_ms / 1000.0),
     }
+    if args.workload == "street":
+        names = {1: "twopass", 2: "fused512", 3: "fused256x2"}
+        line["config"]["kernel_used"] = names.get(st.kernel_used, str(st.kernel_used))
+        line["config"]["layout_used"] = {"order": "pool" if st.layout_used & 1 else "morton",
+                                         "xcd_chunks": not (st.layout_used & 2)}
     if not args.no_cpu:
         log("timing the CPU oracle ...")
         line["cpu_baseline"] = cpu_baseline(wl)

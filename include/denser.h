@@ -118,6 +118,9 @@ typedef struct {
     int32_t converged;       /* 1 if gap_tol was reached                      */
     double ms_loop;          /* HIP-event time of the iteration loop on the
                                 volume's stream (gap checks included)        */
+    int32_t kernel_used;     /* DN_K_* that ran (after autotuning)            */
+    int32_t layout_used;     /* bit 0: pool order (else Morton order); bit 1:
+                                plain workgroup map (else XCD chunks)        */
 } dn_reg_stats;
 
 /* ------------------------------------------------------------ lifecycle */

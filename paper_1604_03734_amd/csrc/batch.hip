@@ -110,7 +110,7 @@ __global__ __launch_bounds__(512) void k_cp_persistent(BatchArgs a)
                 const VolDesc d = a.vols[item.x];
                 const int c = (d.cur + it) & 1;
                 CPArgs<SF32> A;
-                A.nb = 0; A.pstride = d.pstride; A.nbr = d.nbr; A.emask = d.emask; A.order = nullptr;
+                A.nb = 0; A.pstride = d.pstride; A.nbr = d.nbr; A.emask = d.emask; A.order = nullptr; A.xcd = 0;
                 A.f = d.f; A.w = d.w; A.u = d.u; A.ubar_in = d.ubar[c]; A.ubar_out = d.ubar[1 - c];
                 A.p_in = d.p[c]; A.p_out = d.p[1 - c]; A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
                 A.sigma = sigma; A.tau = tau; A.lambda = a.lambda; A.theta = theta;
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(512) void k_cp_persistent(BatchArgs a)
                 const VolDesc d = a.vols[item.x];
                 const int c = (d.cur + it) & 1;
                 CPArgs<SF32> A;
-                A.nb = 0; A.pstride = d.pstride; A.nbr = d.nbr; A.emask = d.emask; A.order = nullptr;
+                A.nb = 0; A.pstride = d.pstride; A.nbr = d.nbr; A.emask = d.emask; A.order = nullptr; A.xcd = 0;
                 A.f = d.f; A.w = d.w; A.u = d.u; A.ubar_in = d.ubar[c]; A.ubar_out = d.ubar[1 - c];
                 A.p_in = d.p[c]; A.p_out = d.p[1 - c]; A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
                 A.sigma = sigma; A.tau = tau; A.lambda = a.lambda; A.theta = theta;

@@ -43,7 +43,8 @@ template <class S> struct CPArgs {
     int64_t pstride;            // elements between p planes
     const int32_t *nbr;         // [nb][27]
     const uint8_t *emask;       // [nb][512]
-    const int32_t *order;       // processing order or nullptr
+    const int32_t *order;       // processing order or nullptr (pool order)
+    int32_t xcd;                // 1: XCD-chunked workgroup -> block map
     const float *f, *w;
     typename S::T *u;           // in place
     const typename S::T *ubar_in;
@@ -225,6 +226,11 @@ __device__ __forceinline__ int64_t xcd_slot(int64_t wg, int64_t n)
 {
     int64_t per = (n + 7) / 8;
     return (wg % 8) * per + wg / 8;
+}
+
+__device__ __forceinline__ int64_t block_slot(int64_t wg, int64_t n, int xcd)
+{
+    return xcd ? xcd_slot(wg, n) : wg;
 }
 
 }  // namespace dn

@@ -93,6 +93,7 @@ struct dn_volume {
     uint8_t *emask = nullptr;           // [max][512]
     int64_t emask_nb = -1;              // nb for which emask/order are valid
     int32_t *order = nullptr;           // [max] processing order (Morton)
+    int layout = 0;                     // chosen by the autotuner, see regularize.hip
     double *partials = nullptr;         // [max][2]
     double *energy2 = nullptr;          // [2] device
 

@@ -29,7 +29,7 @@ template <class S, bool kRefine>
 __global__ __launch_bounds__(512) void k_cp_fused(CPArgs<S> A)
 {
     __shared__ CPShared sh;
-    int64_t slot = xcd_slot(blockIdx.x, A.nb);
+    int64_t slot = block_slot(blockIdx.x, A.nb, A.xcd);
     if (slot >= A.nb) return;
     int64_t b = A.order ? A.order[slot] : slot;
     cp_block<S, kRefine, 512>(A, b, sh);
@@ -41,7 +41,7 @@ template <class S, bool kRefine>
 __global__ __launch_bounds__(256) void k_cp_fused256(CPArgs<S> A)
 {
     __shared__ CPShared sh;
-    int64_t slot = xcd_slot(blockIdx.x, A.nb);
+    int64_t slot = block_slot(blockIdx.x, A.nb, A.xcd);
     if (slot >= A.nb) return;
     int64_t b = A.order ? A.order[slot] : slot;
     cp_block<S, kRefine, 256>(A, b, sh);
@@ -337,7 +337,8 @@ static CPArgs<S> make_args(dn_volume *v, const dn_reg_params *prm, typename S::T
     A.pstride = v->cap_blocks * kBlockVox;
     A.nbr = v->nbr;
     A.emask = v->emask;
-    A.order = v->order;
+    A.order = v->layout & 1 ? nullptr : v->order;
+    A.xcd = (v->layout & 2) ? 0 : 1;
     A.f = v->f; A.w = v->w;
     A.u = u; A.ubar_in = ub_in; A.ubar_out = ub_out; A.p_in = p_in; A.p_out = p_out;
     A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
@@ -446,8 +447,11 @@ int zero_state(dn_volume *v)
     return DN_OK;
 }
 
-// Kernel choice for DN_K_AUTO: measured once per size bucket.
-static std::map<int, int> g_auto_kernel;
+// Kernel choice for DN_K_AUTO: measured once per size bucket.  A choice is
+// (kernel variant, layout) with layout bit 0 = pool order instead of Morton
+// order, bit 1 = plain workgroup -> block map instead of XCD chunks.
+struct AutoChoice { int kernel; int layout; };
+static std::map<int, AutoChoice> g_auto_kernel;
 
 static int size_bucket(int64_t nb)
 {
@@ -460,31 +464,39 @@ static int autotune_single(dn_volume *v, const dn_reg_params *prm, int *choice)
 {
     int key = size_bucket(v->nb);
     auto it = g_auto_kernel.find(key);
-    if (it != g_auto_kernel.end()) { *choice = it->second; return DN_OK; }
+    if (it != g_auto_kernel.end()) {
+        *choice = it->second.kernel;
+        v->layout = it->second.layout;
+        return DN_OK;
+    }
     // time a few iterations of each candidate from the zero state
     hipEvent_t e0, e1;
     DN_HIP(hipEventCreate(&e0));
     DN_HIP(hipEventCreate(&e1));
     float best_ms = 1e30f;
-    int best = DN_K_FUSED;
+    AutoChoice best{DN_K_FUSED, 0};
     const int trial = 6;
-    for (int k : {DN_K_TWOPASS, DN_K_FUSED, DN_K_FUSED256}) {
-        int rc = zero_state(v);
-        if (rc) return rc;
-        if ((rc = step_f32(v, prm, k))) return rc;  // warm up
-        DN_HIP(hipEventRecord(e0, v->stream));
-        for (int i = 0; i < trial; ++i)
-            if ((rc = step_f32(v, prm, k))) return rc;
-        DN_HIP(hipEventRecord(e1, v->stream));
-        DN_HIP(hipEventSynchronize(e1));
-        float ms = 0;
-        DN_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) { best_ms = ms; best = k; }
-    }
+    for (int k : {DN_K_TWOPASS, DN_K_FUSED, DN_K_FUSED256})
+        for (int layout = 0; layout < 4; ++layout) {
+            if (k == DN_K_TWOPASS && layout != 0) continue;   // the two-pass kernels use pool order
+            v->layout = layout;
+            int rc = zero_state(v);
+            if (rc) return rc;
+            if ((rc = step_f32(v, prm, k))) return rc;  // warm up
+            DN_HIP(hipEventRecord(e0, v->stream));
+            for (int i = 0; i < trial; ++i)
+                if ((rc = step_f32(v, prm, k))) return rc;
+            DN_HIP(hipEventRecord(e1, v->stream));
+            DN_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            DN_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) { best_ms = ms; best = AutoChoice{k, layout}; }
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     g_auto_kernel[key] = best;
-    *choice = best;
+    *choice = best.kernel;
+    v->layout = best.layout;
     return zero_state(v);
 }
 
@@ -556,7 +568,8 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
                 if ((rc = autotune_single(v, prm, &kernel))) return rc;
             } else {
                 auto it = g_auto_kernel.find(size_bucket(v->nb));
-                kernel = it != g_auto_kernel.end() ? it->second : DN_K_FUSED;
+                kernel = it != g_auto_kernel.end() ? it->second.kernel : DN_K_FUSED;
+                if (it != g_auto_kernel.end()) v->layout = it->second.layout;
             }
         }
     }
@@ -613,6 +626,8 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
     stats.gap = ed[0] - ed[1];
     stats.rel_gap = ed[0] != 0.0 ? stats.gap / ed[0] : 0.0;
     if (prm->gap_tol > 0 && stats.gap <= prm->gap_tol * ed[0]) stats.converged = 1;
+    stats.kernel_used = kernel;
+    stats.layout_used = v->layout;
     if (out) *out = stats;
     if (!std::isfinite(stats.gap)) { set_error("non-finite energy"); return DN_E_NUMERIC; }
     return DN_OK;

@@ -54,7 +54,7 @@ class RegParams(ctypes.Structure):
 class RegStats(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("dual", ctypes.c_double), ("gap", ctypes.c_double),
                 ("rel_gap", ctypes.c_double), ("iters_run", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("ms_loop", ctypes.c_double)]
+                ("ms_loop", ctypes.c_double), ("kernel_used", ctypes.c_int32), ("layout_used", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
