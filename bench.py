@@ -227,6 +227,29 @@ def cpu_baseline(wl):
     }
 
 
+def accuracy(wl, iters=500):
+    """Synthetic analogue of the paper's error statistics (Section V,
+    Table III): distance of the zero-crossing surface of the street to the
+    analytic scene, before (u = f) and after regularisation."""
+    import scenes
+    D, torch = wl.D, wl.torch
+    vol = wl.street
+    boxes = scenes.scene_street(100.0, 0, 2)
+    f = vol.extract(D.DN_X_F)
+    out = {}
+    for name, prm, u0 in (("raw", D.reg_params(0.5, iters=0, init=D.DN_INIT_GIVEN), f),
+                          ("regularised", D.reg_params(0.5, iters=iters, kernel=D.DN_K_AUTO), None)):
+        vol.regularize(prm, u0=u0)
+        pts = vol.extract(D.DN_X_SURFACE).cpu().numpy()
+        d = scenes.distance_to_scene(pts, boxes) * 100.0
+        out[name] = {"points": int(len(pts)), "median_cm": float(np.median(d)),
+                     "p75_cm": float(np.percentile(d, 75)), "mean_cm": float(d.mean())}
+    r, g = out["raw"], out["regularised"]
+    out["median_change"] = g["median_cm"] / r["median_cm"] - 1.0
+    out["points_change"] = g["points"] / r["points"] - 1.0
+    return out
+
+
 def time_to_gap(wl, tol=1e-3, k=100):
     """Wall time to relative gap <= tol on the street map: the plain solver
     from zero vs the learned warm start (network inference + iterations,
@@ -358,6 +381,9 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle ...")
         line["cpu_baseline"] = cpu_baseline(wl)
+    if args.workload == "street" and not args.profile:
+        log("accuracy against the analytic scene ...")
+        line["accuracy"] = accuracy(wl)
     if not args.no_gap:
         log("time to gap ...")
         line["time_to_gap"] = time_to_gap(wl)

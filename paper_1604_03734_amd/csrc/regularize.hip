@@ -157,45 +157,73 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // Per-block partial sums of E(u) and D(p) (Eq. 2 with the weight of the
-// proximal step, Eq. 6), float64, fixed order: lanes by xor-shuffle
-// butterflies, then the 8 wave sums in wave order.
+// proximal step, Eq. 6), float64.  256 threads, two voxels each; u with its
+// +1 faces, p and the edge masks with their -1 faces are staged in LDS.
+// Fixed reduction order: lanes by xor-shuffle butterflies, then the 4 wave
+// sums in wave order.
 template <class S>
-__global__ __launch_bounds__(512) void k_energy_partial(int64_t nb, int64_t ps, const int32_t *__restrict__ nbr,
+__global__ __launch_bounds__(256) void k_energy_partial(int64_t nb, int64_t ps, const int32_t *__restrict__ nbr,
                                                         const uint8_t *__restrict__ emask,
                                                         const typename S::T *__restrict__ u,
                                                         const typename S::T *__restrict__ p,
                                                         const float *__restrict__ f, const float *__restrict__ w,
                                                         double lambda, double *__restrict__ partials)
 {
-    __shared__ double se[8], sd[8];
+    __shared__ float su[729];        // u on [0, 8]^3, index ((z*9)+y)*9+x
+    __shared__ float sp[3][729];     // p on [-1, 7]^3, index i9
+    __shared__ uint8_t sm[729];      // edge masks on [-1, 7]^3, index i9
+    __shared__ double se[4], sd[4];
     const int64_t b = blockIdx.x;
     if (b >= nb) return;
-    const int t = threadIdx.x, lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
-    const int64_t gi = b * kBlockVox + t;
+    const int t = threadIdx.x;
     const int32_t *nb27 = nbr + b * kNbr;
-    const uint8_t m = emask[gi];
+    auto iu = [](int x, int y, int z) { return (z * 9 + y) * 9 + x; };
+    for (int k = 0; k < 2; ++k) {
+        const int v = t + 256 * k, lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
+        const int64_t gi = b * kBlockVox + v;
+        su[iu(lx, ly, lz)] = S::ld(u[gi]);
+        const int q = i9(lx, ly, lz);
+        sm[q] = emask[gi];
+        sp[0][q] = S::ld(p[gi]); sp[1][q] = S::ld(p[gi + ps]); sp[2][q] = S::ld(p[gi + 2 * ps]);
+    }
+    if (t < 192) {
+        // +1 faces of u: face a = t / 64
+        const int a = t >> 6, i = t & 63, c0 = i & 7, c1 = i >> 3;
+        int x, y, z;
+        if (a == 0) { x = 8; y = c0; z = c1; }
+        else if (a == 1) { x = c0; y = 8; z = c1; }
+        else { x = c0; y = c1; z = 8; }
+        int64_t j = halo_index(nb27, x, y, z);
+        su[iu(x, y, z)] = j >= 0 ? S::ld(u[j]) : 0.0f;
+        // -1 faces: the normal component of p and the edge mask
+        int hx, hy, hz;
+        face_pos(t, hx, hy, hz);
+        int64_t jm = halo_index(nb27, hx, hy, hz);
+        const int q = i9(hx, hy, hz);
+        sm[q] = jm >= 0 ? emask[jm] : uint8_t(0);
+        sp[a][q] = jm >= 0 ? S::ld(p[jm + a * ps]) : 0.0f;
+    }
+    __syncthreads();
     double e = 0.0, d = 0.0;
-    if (m & 1) {
-        const double u0 = S::ld(u[gi]);
-        double g[3] = {0.0, 0.0, 0.0};
-        if (m & 2) g[0] = double(S::ld(u[lx < 7 ? gi + 1 : halo_index(nb27, 8, ly, lz)])) - u0;
-        if (m & 4) g[1] = double(S::ld(u[ly < 7 ? gi + 8 : halo_index(nb27, lx, 8, lz)])) - u0;
-        if (m & 8) g[2] = double(S::ld(u[lz < 7 ? gi + 64 : halo_index(nb27, lx, ly, 8)])) - u0;
+    for (int k = 0; k < 2; ++k) {
+        const int v = t + 256 * k, lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
+        const int q = i9(lx, ly, lz);
+        const uint8_t m = sm[q];
+        if (!(m & 1)) continue;
+        const int64_t gi = b * kBlockVox + v;
+        const double u0 = su[iu(lx, ly, lz)];
+        const double g0 = (m & 2) ? double(su[iu(lx + 1, ly, lz)]) - u0 : 0.0;
+        const double g1 = (m & 4) ? double(su[iu(lx, ly + 1, lz)]) - u0 : 0.0;
+        const double g2 = (m & 8) ? double(su[iu(lx, ly, lz + 1)]) - u0 : 0.0;
         const double fv = f[gi], wv = w[gi];
         const double r = u0 - fv;
-        e = sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]) + 0.5 * lambda * wv * r * r;
+        e += sqrt((g0 * g0 + g1 * g1) + g2 * g2) + 0.5 * lambda * wv * r * r;
+        const int qx = i9(lx - 1, ly, lz), qy = i9(lx, ly - 1, lz), qz = i9(lx, ly, lz - 1);
         double dv = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            int64_t jm;
-            if (a == 0) jm = lx > 0 ? gi - 1 : halo_index(nb27, -1, ly, lz);
-            else if (a == 1) jm = ly > 0 ? gi - 8 : halo_index(nb27, lx, -1, lz);
-            else jm = lz > 0 ? gi - 64 : halo_index(nb27, lx, ly, -1);
-            const uint8_t bit = uint8_t(2 << a);
-            double fwd = (m & bit) ? double(S::ld(p[gi + a * ps])) : 0.0;
-            double bwd = (jm >= 0 && (emask[jm] & bit)) ? double(S::ld(p[jm + a * ps])) : 0.0;
-            dv += fwd - bwd;
-        }
-        d = -fv * dv - dv * dv / (2.0 * lambda * wv);
+        dv += ((m & 2) ? double(sp[0][q]) : 0.0) - ((sm[qx] & 2) ? double(sp[0][qx]) : 0.0);
+        dv += ((m & 4) ? double(sp[1][q]) : 0.0) - ((sm[qy] & 4) ? double(sp[1][qy]) : 0.0);
+        dv += ((m & 8) ? double(sp[2][q]) : 0.0) - ((sm[qz] & 8) ? double(sp[2][qz]) : 0.0);
+        d += -fv * dv - dv * dv / (2.0 * lambda * wv);
     }
     e = wave_sum(e);
     d = wave_sum(d);
@@ -203,27 +231,30 @@ __global__ __launch_bounds__(512) void k_energy_partial(int64_t nb, int64_t ps, 
     if ((t & 63) == 0) { se[wave] = e; sd[wave] = d; }
     __syncthreads();
     if (t == 0) {
-        double E = 0.0, D = 0.0;
-        for (int i = 0; i < 8; ++i) { E += se[i]; D += sd[i]; }
-        partials[2 * b] = E;
-        partials[2 * b + 1] = D;
+        partials[2 * b] = ((se[0] + se[1]) + se[2]) + se[3];
+        partials[2 * b + 1] = ((sd[0] + sd[1]) + sd[2]) + sd[3];
     }
 }
 
-__global__ __launch_bounds__(256) void k_energy_final(int64_t nb, const double *__restrict__ partials,
-                                                      double *__restrict__ out)
+// Fixed-order reduction of n (E, D) pairs: workgroup g sums pairs
+// [1024 g, 1024 g + 1024): each thread adds 4 consecutive pairs, then a
+// tree over the 256 threads.
+__global__ __launch_bounds__(256) void k_energy_reduce(int64_t n, const double *__restrict__ in,
+                                                       double *__restrict__ out)
 {
     __shared__ double se[256], sd[256];
     const int t = threadIdx.x;
+    const int64_t base = int64_t(blockIdx.x) * 1024 + 4 * t;
     double e = 0.0, d = 0.0;
-    for (int64_t i = t; i < nb; i += 256) { e += partials[2 * i]; d += partials[2 * i + 1]; }
+    for (int k = 0; k < 4; ++k)
+        if (base + k < n) { e += in[2 * (base + k)]; d += in[2 * (base + k) + 1]; }
     se[t] = e; sd[t] = d;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) { se[t] += se[t + s]; sd[t] += sd[t + s]; }
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) { se[t] += se[t + h]; sd[t] += sd[t + h]; }
         __syncthreads();
     }
-    if (t == 0) { out[0] = se[0]; out[1] = sd[0]; }
+    if (t == 0) { out[2 * blockIdx.x] = se[0]; out[2 * blockIdx.x + 1] = sd[0]; }
 }
 
 // ------------------------------------------------------- helpers
@@ -292,13 +323,30 @@ static int energy_launch(dn_volume *v, double lambda, const typename S::T *u, co
 {
     hipStream_t st = v->stream;
     const int64_t ps = v->cap_blocks * kBlockVox;
-    if (v->nb > 0) {
-        hipLaunchKernelGGL((k_energy_partial<S>), dim3(unsigned(v->nb)), dim3(512), 0, st, v->nb, ps, v->nbr,
-                           v->emask, u, p, v->f, v->w, lambda, v->partials);
+    if (v->nb == 0) {
+        hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(256), 0, st, v->energy2, int64_t(2), 0.0);
         DN_HIP(hipGetLastError());
+        return DN_OK;
     }
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, st, v->nb, v->partials, v->energy2);
+    hipLaunchKernelGGL((k_energy_partial<S>), dim3(unsigned(v->nb)), dim3(256), 0, st, v->nb, ps, v->nbr,
+                       v->emask, u, p, v->f, v->w, lambda, v->partials);
     DN_HIP(hipGetLastError());
+    // reduce the per-block pairs level by level (ping-pong inside the scratch
+    // that follows the per-block partials) until one pair is left
+    int64_t n = v->nb;
+    double *src = v->partials;
+    double *bufs[2] = {v->partials + 2 * v->cap_blocks, v->partials + 2 * v->cap_blocks + 2 * ((v->cap_blocks + 1023) / 1024 + 1)};
+    int which = 0;
+    while (n > 1) {
+        const int64_t g = (n + 1023) / 1024;
+        double *dst = (g == 1) ? v->energy2 : bufs[which];
+        hipLaunchKernelGGL(k_energy_reduce, dim3(unsigned(g)), dim3(256), 0, st, n, src, dst);
+        DN_HIP(hipGetLastError());
+        src = dst;
+        which ^= 1;
+        n = g;
+    }
+    if (src != v->energy2) DN_HIP(hipMemcpyAsync(v->energy2, src, 16, hipMemcpyDeviceToDevice, st));
     return DN_OK;
 }
 

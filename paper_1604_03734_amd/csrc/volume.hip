@@ -516,7 +516,7 @@ int dn_volume_create(const dn_volume_params *p, void *hip_stream, dn_volume **ou
         {(void **)&v->p[1], vox * 12},
         {(void **)&v->emask, vox},
         {(void **)&v->order, size_t(v->cap_blocks) * 4},
-        {(void **)&v->partials, size_t(v->cap_blocks) * 16 + 64},
+        {(void **)&v->partials, size_t(v->cap_blocks) * 16 + 2 * (size_t((v->cap_blocks + 1023) / 1024) + 1) * 16 + 64},
         {(void **)&v->energy2, 64},
     };
     for (auto &a : allocs) {

@@ -129,13 +129,13 @@ def warm_state(vol, params, delta=0.1):
     return u0, p0
 
 
-def solve_plain(vol, tol=1e-3, max_iters=20000, gap_every=10):
+def solve_plain(vol, tol=1e-3, max_iters=20000, gap_every=10, gamma=0.0, kernel=D.DN_K_AUTO):
     return vol.regularize(D.reg_params(LAM, iters=max_iters, gap_every=gap_every, gap_tol=tol,
-                                       kernel=D.DN_K_FUSED))
+                                       kernel=kernel, gamma=gamma))
 
 
 def solve_warm(vol, params, tol=1e-3, k=100, plain_rel_gap_at_k=None, delta=0.1, max_iters=20000,
-               gap_every=10):
+               gap_every=10, gamma=0.0, kernel=D.DN_K_AUTO):
     """Warm start, K iterations, the fallback test, then iterate to `tol`.
     Returns a dict with iterations, timings and whether it fell back."""
     import torch
@@ -144,19 +144,19 @@ def solve_warm(vol, params, tol=1e-3, k=100, plain_rel_gap_at_k=None, delta=0.1,
     t0 = time.time()
     u0, p0 = warm_state(vol, params, delta)
     st = vol.regularize(D.reg_params(LAM, iters=k, gap_every=gap_every, gap_tol=tol, init=D.DN_INIT_GIVEN,
-                                     kernel=D.DN_K_FUSED), u0, p0)
+                                     kernel=kernel, gamma=gamma), u0, p0)
     out = {"k": k, "iters_warm": st.iters_run, "rel_gap_at_k": st.rel_gap, "fallback": False}
     if st.converged:
         out.update(iters=st.iters_run, converged=True, rel_gap=st.rel_gap, seconds=time.time() - t0)
         return out
     if plain_rel_gap_at_k is not None and not (st.rel_gap <= 2.0 * plain_rel_gap_at_k):
         out["fallback"] = True
-        st2 = solve_plain(vol, tol, max_iters, gap_every)
+        st2 = solve_plain(vol, tol, max_iters, gap_every, gamma, kernel)
         out.update(iters=st.iters_run + st2.iters_run, converged=bool(st2.converged), rel_gap=st2.rel_gap,
                    seconds=time.time() - t0)
         return out
     st2 = vol.regularize(D.reg_params(LAM, iters=max_iters - k, gap_every=gap_every, gap_tol=tol,
-                                      init=D.DN_INIT_KEEP, kernel=D.DN_K_FUSED))
+                                      init=D.DN_INIT_KEEP, kernel=kernel, gamma=gamma))
     out.update(iters=st.iters_run + st2.iters_run, converged=bool(st2.converged), rel_gap=st2.rel_gap,
                seconds=time.time() - t0)
     return out

@@ -246,3 +246,19 @@ def c4_block_counts(n: int = 64, seed: int = 0, lo: float = 1e3, hi: float = 5e4
     """Sub-map sizes for the batched workload: log-uniform in [lo, hi]."""
     rng = np.random.default_rng(np.random.SeedSequence([4, seed]))
     return np.round(np.exp(rng.uniform(np.log(lo), np.log(hi), size=n))).astype(np.int64)
+
+
+def distance_to_scene(points: np.ndarray, boxes: np.ndarray, chunk: int = 65536) -> np.ndarray:
+    """Unsigned distance of each point (float [n][3], metres) to the nearest
+    box surface of the scene (ground truth for accuracy statistics)."""
+    out = np.empty(len(points))
+    for s0 in range(0, len(points), chunk):
+        P = np.asarray(points[s0:s0 + chunk], np.float64)
+        best = np.full(len(P), np.inf)
+        for lo, hi in boxes:
+            d_out = np.linalg.norm(np.maximum(np.maximum(lo - P, P - hi), 0.0), axis=1)
+            d_in = np.min(np.minimum(P - lo, hi - P), axis=1)
+            d = np.where(d_out > 0, d_out, np.maximum(d_in, 0.0))
+            best = np.minimum(best, d)
+        out[s0:s0 + chunk] = best
+    return out
