@@ -251,35 +251,38 @@ def accuracy(wl, iters=500):
 
 
 def time_to_gap(wl, tol=1e-3, k=100):
-    """Wall time to relative gap <= tol on the street map: the plain solver
-    from zero vs the learned warm start (network inference + iterations,
-    with the fallback to a cold start), both including their gap checks."""
+    """Wall time to relative gap <= tol on the street map, from zero (plain)
+    and from the learned warm start (network inference + iterations, with
+    the fallback to a cold start), both with their gap checks (every 10
+    iterations).  For the configured fixed steps (tau = sigma = 1/sqrt(12))
+    and for the accelerated variant (gamma = lambda)."""
     D = wl.D
     torch = wl.torch
     from paper_1604_03734_amd import warmstart
-    out = {"tol": tol, "k": k}
-    torch.cuda.synchronize()
-    t0 = time.time()
-    st = warmstart.solve_plain(wl.big, tol)
-    torch.cuda.synchronize()
-    out["plain_s"] = time.time() - t0
-    out["plain_iters"] = st.iters_run
-    out["plain_converged"] = bool(st.converged)
     w = warmstart.load_default_weights()
-    if w is None:
-        out["warm_s"] = None
-        out["note"] = "no trained weights in the package"
-        return out
-    ref = wl.big.regularize(D.reg_params(0.5, iters=k, kernel=D.DN_K_FUSED))
-    wt = torch.from_numpy(w).cuda()
-    torch.cuda.synchronize()
-    t0 = time.time()
-    res = warmstart.solve_warm(wl.big, wt, tol=tol, k=k, plain_rel_gap_at_k=ref.rel_gap)
-    torch.cuda.synchronize()
-    out["warm_s"] = time.time() - t0
-    out["plain_rel_gap_at_k"] = ref.rel_gap
-    out.update({"warm_" + key: val for key, val in res.items() if key != "seconds"})
-    out["speedup"] = out["plain_s"] / out["warm_s"]
+    wt = torch.from_numpy(w).cuda() if w is not None else None
+    out = {"tol": tol, "k": k, "weights": "paper_1604_03734_amd/weights/warmstart.npy" if w is not None else None}
+    for name, gam in (("fixed_steps", 0.0), ("accelerated", 0.5)):
+        r = {}
+        torch.cuda.synchronize()
+        t0 = time.time()
+        st = warmstart.solve_plain(wl.big, tol, gamma=gam)
+        torch.cuda.synchronize()
+        r["plain_s"] = time.time() - t0
+        r["plain_iters"] = st.iters_run
+        r["plain_converged"] = bool(st.converged)
+        if wt is not None:
+            ref = wl.big.regularize(D.reg_params(0.5, iters=k, gamma=gam))
+            torch.cuda.synchronize()
+            t0 = time.time()
+            res = warmstart.solve_warm(wl.big, wt, tol=tol, k=k, plain_rel_gap_at_k=ref.rel_gap, gamma=gam)
+            torch.cuda.synchronize()
+            r["warm_s"] = time.time() - t0
+            r["warm_iters"] = res["iters"]
+            r["warm_converged"] = res["converged"]
+            r["warm_fallback"] = res["fallback"]
+            r["speedup"] = r["plain_s"] / r["warm_s"]
+        out[name] = r
     return out
 
 

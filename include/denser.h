@@ -51,6 +51,11 @@ extern "C" {
 #define DN_INIT_ZERO 0   /* u = ubar = p = 0 (Section III-C, step 1)          */
 #define DN_INIT_KEEP 1   /* continue from the state the last call left        */
 #define DN_INIT_GIVEN 2  /* u = ubar = u0_dev, p = p0_dev (p0 may be NULL: 0)  */
+#define DN_INIT_CONTINUE 3 /* regularisation interleaved with fusion (Section II:
+                              the map is continuously regularised): blocks that
+                              a previous call regularised keep their state,
+                              blocks allocated since start at u = ubar = f,
+                              p = 0; the step schedule restarts               */
 
 /* ------------------------------------------------------- kernel choices */
 #define DN_K_AUTO 0      /* pick the measured-best variant (autotuned)        */
@@ -238,30 +243,42 @@ int dn_extract(dn_volume *vol, int32_t what, void *out_dev, size_t out_bytes, in
  * accumulation. */
 #define DN_NET_PARAMS 8241
 
-/* Gather the input tiles of the listed blocks: float [n][2][10][10][10]. */
-int dn_net_gather(dn_volume *vol, const int32_t *blocks_dev, int64_t n, float *tiles_dev);
+/* Gather the input tiles of the listed blocks: float [n][2][10][10][10]
+ * (channel, z, y, x).  perm exchanges the tile's x axis with the volume's
+ * y axis (1) or z axis (2); 0 keeps the axes.  Exchanging axes leaves the
+ * energy unchanged, so one network serves every axis. */
+int dn_net_gather(dn_volume *vol, const int32_t *blocks_dev, int64_t n, int32_t perm, float *tiles_dev);
 
 /* Forward pass: out_dev float [n][10][10][10] (the residual r). */
 int dn_net_forward(const float *tiles_dev, int64_t n, const float *params_dev, float *out_dev,
                    void *hip_stream);
 
-/* Masked mean-squared loss of f + r against targets on the centre 8^3 and
- * its gradient: targets_dev, mask_dev float [n][512] (mask 0/1); grad_dev
- * float [8241] (overwritten).  *loss_host receives the loss (synchronises). */
+/* Masked mean-squared loss on the centre 8^3 and its gradient: the
+ * prediction is f + r (kind 0, a primal residual) or r (kind 1, a dual
+ * component); targets_dev, mask_dev float [n][512] in the tile's centre
+ * order (mask 0/1); grad_dev float [8241] (overwritten).  *loss_host
+ * receives the loss (synchronises). */
 int dn_net_loss_grad(const float *tiles_dev, int64_t n, const float *params_dev,
-                     const float *targets_dev, const float *mask_dev, float *grad_dev,
+                     const float *targets_dev, const float *mask_dev, int32_t kind, float *grad_dev,
                      double *loss_host, void *hip_stream);
 
 /* One Adam step on n float32 parameters (m, v: moments, step >= 1). */
 int dn_net_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, int64_t n,
                 float lr, float beta1, float beta2, float eps, int32_t step, void *hip_stream);
 
-/* Warm start of the whole volume: u0_dev float [n_blocks][512] receives
- * clamp(f + r, -1, 1) on Omega and 0 elsewhere; p0_dev (may be NULL)
- * float [3][n_blocks][512] receives the projection of grad(u0) / delta onto
- * the unit ball (delta > 0).  Enqueue only. */
-int dn_net_warm_start(dn_volume *vol, const float *params_dev, double delta, float *u0_dev,
-                      float *p0_dev);
+/* Warm start of the whole volume (u0_dev float [n_blocks][512], p0_dev
+ * float [3][n_blocks][512]):
+ *  DN_WARM_PRIMAL: u0 = clamp(f + r, -1, 1) on Omega (0 elsewhere); p0
+ *    (may be NULL) = projection of grad(u0) / delta onto the unit ball.
+ *  DN_WARM_DUAL: the network runs once per axis a on tiles whose x axis is
+ *    the volume's axis a and its output is taken as the dual component p_a
+ *    (kept where m_a = 1); p0 is projected onto the unit ball and u0 = f on
+ *    Omega.  delta is unused.
+ * Enqueue only. */
+#define DN_WARM_PRIMAL 0
+#define DN_WARM_DUAL 1
+int dn_net_warm_start(dn_volume *vol, const float *params_dev, int32_t mode, double delta,
+                      float *u0_dev, float *p0_dev);
 
 #ifdef __cplusplus
 }

@@ -61,8 +61,8 @@ def lib():
             "or_cp_accel": (None, [P, i64, P, P, P, P, P, i32, f64, f64, P, i32]),
             "or_extract": (i64, [P, P, i64, P, P, f64, P, i64]),
             "or_net_forward": (None, [P, i64, P, P, P]),
-            "or_net_loss_grad": (f64, [P, i64, P, P, P, P]),
-            "or_net_gather": (None, [P, P, P, P, i64, P]),
+            "or_net_loss_grad": (f64, [P, i64, P, P, P, P, i32]),
+            "or_net_gather": (None, [P, P, P, P, i64, P, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -202,20 +202,21 @@ def net_forward(tiles, params):
     return out
 
 
-def net_loss_grad(tiles, params, targets, mask):
+def net_loss_grad(tiles, params, targets, mask, kind=0):
+    """kind 0: prediction f + r (primal residual); kind 1: prediction r."""
     tiles = _c(tiles, np.float64)
     B = tiles.shape[0]
     g = np.empty(NET_PARAMS)
     L = lib().or_net_loss_grad(_p(tiles), B, _p(_c(params, np.float64)),
-                               _p(_c(targets, np.float64)), _p(_c(mask, np.float64)), _p(g))
+                               _p(_c(targets, np.float64)), _p(_c(mask, np.float64)), _p(g), int(kind))
     return float(L), g
 
 
-def net_gather(nbr, f, w, blocks):
+def net_gather(nbr, f, w, blocks, perm=0):
     blocks = _c(blocks, np.int32)
     tiles = np.empty((len(blocks), 2, 10, 10, 10))
     lib().or_net_gather(_p(_c(nbr, np.int32)), _p(_c(f, np.float64)), _p(_c(w, np.float64)),
-                        _p(blocks), len(blocks), _p(tiles))
+                        _p(blocks), len(blocks), _p(tiles), int(perm))
     return tiles
 
 

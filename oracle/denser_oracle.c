@@ -563,11 +563,13 @@ static void conv_same_backward(const double *x, int cin, const double *Wt, int c
 
 /* Masked mean-squared loss on the centre 8^3 of each tile and its gradient
  * with respect to all parameters:
- *   pred = f_centre + r_centre,  L = sum_mask (pred - target)^2 / max(1, n_mask)
- * targets, mask: [B][512] (block voxel order); mask is 0/1.
- * grad: [8241], overwritten.  Returns L. */
+ *   pred = f_centre + r_centre (kind 0: the network is a primal residual) or
+ *   pred = r_centre (kind 1: the network predicts a dual component),
+ *   L = sum_mask (pred - target)^2 / max(1, n_mask)
+ * targets, mask: [B][512] (block voxel order of the tile's centre); mask is
+ * 0/1.  grad: [8241], overwritten.  Returns L. */
 double or_net_loss_grad(const double *tiles, int64_t B, const double *params, const double *targets,
-                        const double *mask, double *grad)
+                        const double *mask, double *grad, int32_t kind)
 {
     const double *W1 = params, *W2 = params + HID * 2 * 27 + HID, *W3 = W2 + HID * HID * 27 + HID;
     double *gW1 = grad, *gb1 = gW1 + HID * 2 * 27, *gW2 = gb1 + HID, *gb2 = gW2 + HID * HID * 27,
@@ -591,7 +593,7 @@ double or_net_loss_grad(const double *tiles, int64_t B, const double *params, co
             int t = (z * T10 + y) * T10 + x;
             double m = mask[bi * 512 + v];
             if (m == 0.0) continue;
-            double pred = tiles[bi * 2 * T3 + t] + out[bi * T3 + t];
+            double pred = (kind == 0 ? tiles[bi * 2 * T3 + t] : 0.0) + out[bi * T3 + t];
             double e = pred - targets[bi * 512 + v];
             loss += e * e / norm;
             d3[t] = 2.0 * e / norm;
@@ -614,9 +616,12 @@ double or_net_loss_grad(const double *tiles, int64_t B, const double *params, co
 
 /* Gather the network input tile of each listed block: channel 0 = f,
  * channel 1 = log(1 + w) / log(1 + 100), over the block and a one-voxel
- * halo; voxels of unallocated neighbours are 0 in both channels. */
+ * halo; voxels of unallocated neighbours are 0 in both channels.
+ * perm turns the volume so that one of its axes becomes the tile's x axis:
+ * 0 none, 1 x and y exchanged, 2 x and z exchanged (the energy is
+ * unchanged by exchanging axes, so one network serves every axis). */
 void or_net_gather(const int32_t *nbr, const double *f, const double *w, const int32_t *blocks,
-                   int64_t n, double *tiles)
+                   int64_t n, double *tiles, int32_t perm)
 {
     const double wn = log(101.0);
     for (int64_t i = 0; i < n; ++i) {
@@ -625,7 +630,10 @@ void or_net_gather(const int32_t *nbr, const double *f, const double *w, const i
             for (int y = 0; y < T10; ++y)
                 for (int x = 0; x < T10; ++x) {
                     int t = (z * T10 + y) * T10 + x;
-                    int64_t idx = vox_at(nbr, b, x - 1, y - 1, z - 1);
+                    int vx = x, vy = y, vz = z;
+                    if (perm == 1) { vx = y; vy = x; }
+                    if (perm == 2) { vx = z; vz = x; }
+                    int64_t idx = vox_at(nbr, b, vx - 1, vy - 1, vz - 1);
                     double fv = 0.0, wv = 0.0;
                     if (idx >= 0) { fv = f[idx]; wv = log(1.0 + w[idx]) / wn; }
                     tiles[i * 2 * T3 + t] = fv;

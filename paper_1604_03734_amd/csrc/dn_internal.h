@@ -89,6 +89,7 @@ struct dn_volume {
     void *p16[2] = {nullptr, nullptr};
     int state_storage = DN_F32;         // where the current state lives
     double acc_tau = 0, acc_sigma = 0;  // accelerated schedule (tau_n, sigma_n)
+    int64_t nb_state = 0;               // blocks whose solver state a regularize call set
 
     uint8_t *emask = nullptr;           // [max][512]
     int64_t emask_nb = -1;              // nb for which emask/order are valid

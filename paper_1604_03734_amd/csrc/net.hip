@@ -222,9 +222,10 @@ __device__ __forceinline__ int64_t halo_vox(const int32_t *nb27, int hx, int hy,
 // blocks == nullptr): channel 0 f, channel 1 log(1 + w) / log(101); 0 for
 // voxels of unallocated neighbours.  Either float [n][2][1000] or
 // bfloat16 channel-last [n][1000][16].
+// perm exchanges the tile's x axis with the volume's y (1) or z (2) axis.
 __global__ void k_gather(const int32_t *__restrict__ nbr, const float *__restrict__ f, const float *__restrict__ w,
                          const int32_t *__restrict__ blocks, int64_t first, int64_t n, float *__restrict__ tiles,
-                         uint16_t *__restrict__ X)
+                         uint16_t *__restrict__ X, int perm)
 {
     int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n * kT) return;
@@ -232,6 +233,8 @@ __global__ void k_gather(const int32_t *__restrict__ nbr, const float *__restric
     int v = int(k % kT);
     int64_t b = blocks ? blocks[first + i] : first + i;
     int x = v % 10, y = (v / 10) % 10, z = v / 100;
+    if (perm == 1) { int s = x; x = y; y = s; }
+    if (perm == 2) { int s = x; x = z; z = s; }
     int64_t j = halo_vox(nbr + b * kNbr, x - 1, y - 1, z - 1);
     float fv = 0.f, wv = 0.f;
     if (j >= 0) {
@@ -273,7 +276,7 @@ __global__ void k_mask_count(const float *__restrict__ mask, int64_t n, double *
 // output gradient dY3 (bfloat16, channel 0 only).
 __global__ __launch_bounds__(512) void k_loss(const float *__restrict__ tiles, const float *__restrict__ R,
                                               const float *__restrict__ targets, const float *__restrict__ mask,
-                                              const double *__restrict__ count, int64_t n,
+                                              const double *__restrict__ count, int64_t n, int kind,
                                               uint16_t *__restrict__ dY, double *__restrict__ tile_loss)
 {
     __shared__ double sl[8];
@@ -282,7 +285,8 @@ __global__ __launch_bounds__(512) void k_loss(const float *__restrict__ tiles, c
     const double N = count[0] > 1.0 ? count[0] : 1.0;
     const int c = centre_of(v);
     const double m = mask[tile * 512 + v];
-    double e = double(tiles[tile * 2 * kT + c]) + double(R[tile * kT + c]) - double(targets[tile * 512 + v]);
+    double e = (kind == 0 ? double(tiles[tile * 2 * kT + c]) : 0.0) + double(R[tile * kT + c]) -
+               double(targets[tile * 512 + v]);
     double l = m != 0.0 ? e * e / N : 0.0;
     // clear the tile's gradient, then write the centre voxels
     uint4 z = make_uint4(0, 0, 0, 0);
@@ -362,6 +366,34 @@ __global__ __launch_bounds__(512) void k_warm_p(int64_t nb, int64_t ps, const in
     p0[gi] = g0; p0[gi + ps] = g1; p0[gi + 2 * ps] = g2;
 }
 
+// Dual warm start, axis a: the network ran on tiles whose x axis is the
+// volume's axis a (perm a); its centre output is p_a, kept where m_a = 1.
+__global__ __launch_bounds__(512) void k_warm_pdual(const uint8_t *__restrict__ emask, const float *__restrict__ R,
+                                                    int64_t first, int a, int64_t ps, float *__restrict__ p0)
+{
+    const int64_t i = blockIdx.x;
+    const int v = threadIdx.x;
+    int x = v & 7, y = (v >> 3) & 7, z = v >> 6;
+    if (a == 1) { int s = x; x = y; y = s; }
+    if (a == 2) { int s = x; x = z; z = s; }
+    const int64_t g = (first + i) * kBlockVox + v;
+    const float r = R[i * kT + ((z + 1) * 10 + (y + 1)) * 10 + (x + 1)];
+    p0[a * ps + g] = ((emask[g] >> (a + 1)) & 1) ? r : 0.0f;
+}
+
+// p0 onto the unit ball; u0 = f on Omega, 0 elsewhere
+__global__ void k_warm_finish(int64_t n, int64_t ps, const uint8_t *__restrict__ emask, const float *__restrict__ f,
+                              float *__restrict__ p0, float *__restrict__ u0)
+{
+    int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    float a = p0[g], b = p0[g + ps], c = p0[g + 2 * ps];
+    float nrm = sqrtf((a * a + b * b) + c * c);
+    if (nrm > 1.f) { a /= nrm; b /= nrm; c /= nrm; }
+    p0[g] = a; p0[g + ps] = b; p0[g + 2 * ps] = c;
+    u0[g] = (emask[g] & 1) ? f[g] : 0.f;
+}
+
 // Process-wide network scratch.
 struct NetCtx {
     Buf wpack, x0, h1, h2, r, d3, d2, d1, parts, misc, tl;
@@ -429,12 +461,12 @@ using namespace dn;
 
 extern "C" {
 
-int dn_net_gather(dn_volume *v, const int32_t *blocks, int64_t n, float *tiles)
+int dn_net_gather(dn_volume *v, const int32_t *blocks, int64_t n, int32_t perm, float *tiles)
 {
-    DN_REQUIRE(v && blocks && tiles && n >= 0, "bad argument");
+    DN_REQUIRE(v && blocks && tiles && n >= 0 && perm >= 0 && perm <= 2, "bad argument");
     if (n == 0) return DN_OK;
     hipLaunchKernelGGL(k_gather, dim3(grid1(n * kT)), dim3(256), 0, v->stream, v->nbr, v->f, v->w, blocks,
-                       int64_t(0), n, tiles, (uint16_t *)nullptr);
+                       int64_t(0), n, tiles, (uint16_t *)nullptr, int(perm));
     DN_HIP(hipGetLastError());
     return DN_OK;
 }
@@ -455,9 +487,9 @@ int dn_net_forward(const float *tiles, int64_t n, const float *params, float *ou
 }
 
 int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const float *targets, const float *mask,
-                     float *grad, double *loss_host, void *stream)
+                     int32_t kind, float *grad, double *loss_host, void *stream)
 {
-    DN_REQUIRE(tiles && params && targets && mask && grad && n > 0, "bad argument");
+    DN_REQUIRE(tiles && params && targets && mask && grad && n > 0 && (kind == 0 || kind == 1), "bad argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     int rc;
     if ((rc = ensure_acts(n, true))) return rc;
@@ -476,7 +508,7 @@ int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const f
     if ((rc = forward_tiles(st, params, n))) return rc;
     hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(256), 0, st, mask, n * 512, cnt);
     hipLaunchKernelGGL(k_loss, dim3(unsigned(n)), dim3(512), 0, st, tiles, g_net.r.as<float>(), targets, mask, cnt, n,
-                       d3, g_net.tl.as<double>());
+                       int(kind), d3, g_net.tl.as<double>());
     hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, st, g_net.tl.as<double>(), n, lsum);
     DN_HIP(hipGetLastError());
     // layer 3: weights from (h2, d3); input gradient d2 = conv(d3, W3 flipped) * [h2 > 0]
@@ -516,9 +548,10 @@ int dn_net_adam(float *params, const float *grad, float *m, float *v, int64_t n,
     return DN_OK;
 }
 
-int dn_net_warm_start(dn_volume *v, const float *params, double delta, float *u0, float *p0)
+int dn_net_warm_start(dn_volume *v, const float *params, int32_t mode, double delta, float *u0, float *p0)
 {
-    DN_REQUIRE(v && params && u0 && delta > 0, "bad argument");
+    DN_REQUIRE(v && params && u0 && (mode == DN_WARM_PRIMAL || mode == DN_WARM_DUAL), "bad argument");
+    DN_REQUIRE(mode == DN_WARM_DUAL ? p0 != nullptr : delta > 0, "dual mode needs p0; primal mode needs delta > 0");
     hipStream_t st = v->stream;
     int rc;
     if ((rc = build_masks(v))) return rc;
@@ -526,18 +559,29 @@ int dn_net_warm_start(dn_volume *v, const float *params, double delta, float *u0
     if ((rc = pack_all(st, params, false))) return rc;
     const int64_t chunk = 16384;
     if ((rc = ensure_acts(v->nb < chunk ? v->nb : chunk, false))) return rc;
-    for (int64_t first = 0; first < v->nb; first += chunk) {
-        const int64_t n = (v->nb - first) < chunk ? (v->nb - first) : chunk;
-        hipLaunchKernelGGL(k_gather, dim3(grid1(n * kT)), dim3(256), 0, st, v->nbr, v->f, v->w,
-                           (const int32_t *)nullptr, first, n, (float *)nullptr, g_net.x0.as<uint16_t>());
+    const int64_t ps = v->nb * int64_t(kBlockVox);
+    const int axes = mode == DN_WARM_DUAL ? 3 : 1;
+    for (int a = 0; a < axes; ++a)
+        for (int64_t first = 0; first < v->nb; first += chunk) {
+            const int64_t n = (v->nb - first) < chunk ? (v->nb - first) : chunk;
+            hipLaunchKernelGGL(k_gather, dim3(grid1(n * kT)), dim3(256), 0, st, v->nbr, v->f, v->w,
+                               (const int32_t *)nullptr, first, n, (float *)nullptr, g_net.x0.as<uint16_t>(), a);
+            DN_HIP(hipGetLastError());
+            if ((rc = forward_tiles(st, params, n))) return rc;
+            if (mode == DN_WARM_DUAL)
+                hipLaunchKernelGGL(k_warm_pdual, dim3(unsigned(n)), dim3(512), 0, st, v->emask, g_net.r.as<float>(),
+                                   first, a, ps, p0);
+            else
+                hipLaunchKernelGGL(k_warm_u, dim3(unsigned(n)), dim3(512), 0, st, v->f, v->emask, g_net.r.as<float>(),
+                                   first, u0);
+            DN_HIP(hipGetLastError());
+        }
+    if (mode == DN_WARM_DUAL) {
+        hipLaunchKernelGGL(k_warm_finish, dim3(grid1(ps)), dim3(256), 0, st, ps, ps, v->emask, v->f, p0, u0);
         DN_HIP(hipGetLastError());
-        if ((rc = forward_tiles(st, params, n))) return rc;
-        hipLaunchKernelGGL(k_warm_u, dim3(unsigned(n)), dim3(512), 0, st, v->f, v->emask, g_net.r.as<float>(), first, u0);
-        DN_HIP(hipGetLastError());
-    }
-    if (p0) {
-        hipLaunchKernelGGL(k_warm_p, dim3(unsigned(v->nb)), dim3(512), 0, st, v->nb, v->nb * int64_t(kBlockVox),
-                           v->nbr, v->emask, u0, float(1.0 / delta), p0);
+    } else if (p0) {
+        hipLaunchKernelGGL(k_warm_p, dim3(unsigned(v->nb)), dim3(512), 0, st, v->nb, ps, v->nbr, v->emask, u0,
+                           float(1.0 / delta), p0);
         DN_HIP(hipGetLastError());
     }
     return DN_OK;

@@ -475,7 +475,7 @@ static int validate(const dn_reg_params *prm)
     DN_REQUIRE(prm->iters >= 0 && prm->gap_every >= 0, "iters, gap_every must be >= 0");
     int s = prm->storage;
     DN_REQUIRE(s == DN_F32 || s == DN_F16 || s == DN_BF16, "bad storage");
-    DN_REQUIRE(prm->init >= DN_INIT_ZERO && prm->init <= DN_INIT_GIVEN, "bad init");
+    DN_REQUIRE(prm->init >= DN_INIT_ZERO && prm->init <= DN_INIT_CONTINUE, "bad init");
     DN_REQUIRE(prm->kernel >= DN_K_AUTO && prm->kernel <= DN_K_FUSED256, "bad kernel");
     DN_REQUIRE(prm->refine_every >= 0, "refine_every must be >= 0");
     DN_REQUIRE(prm->gamma >= 0 && std::isfinite(prm->gamma), "gamma must be >= 0");
@@ -588,6 +588,19 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
             }
         }
         v->state_storage = DN_F32;
+    } else if (prm->init == DN_INIT_CONTINUE) {
+        // a 16-bit run ended with an FP32 sweep: continue from its output
+        v->state_storage = DN_F32;
+        const int64_t first = v->nb_state < v->nb ? v->nb_state : v->nb;
+        const int64_t cnt = (v->nb - first) * kBlockVox;
+        if (cnt > 0) {
+            DN_HIP(hipMemcpyAsync(v->u + first * kBlockVox, v->f + first * kBlockVox, cnt * 4,
+                                  hipMemcpyDeviceToDevice, st));
+            DN_HIP(hipMemcpyAsync(v->ubar[v->cur] + first * kBlockVox, v->f + first * kBlockVox, cnt * 4,
+                                  hipMemcpyDeviceToDevice, st));
+            for (int a = 0; a < 3; ++a)
+                if ((rc = fill<float>(st, v->p[v->cur] + a * ps + first * kBlockVox, cnt, 0.f))) return rc;
+        }
     }
     if (prm->init != DN_INIT_KEEP || v->acc_tau <= 0.0) {
         v->acc_tau = prm->tau;
@@ -656,6 +669,7 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
         }
     }
     stats.iters_run = it;
+    v->nb_state = v->nb;
     DN_HIP(hipEventRecord(ev1, st));
     DN_HIP(hipEventSynchronize(ev1));
     {

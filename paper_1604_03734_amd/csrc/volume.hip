@@ -570,6 +570,7 @@ int dn_volume_clear(dn_volume *v)
         DN_HIP(hipGetLastError());
     }
     v->nb = 0;
+    v->nb_state = 0;
     v->emask_nb = -1;
     v->last_nuniq = 0;
     v->state_storage = DN_F32;

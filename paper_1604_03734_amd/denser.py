@@ -19,11 +19,12 @@ LIB_PATH = os.path.join(_HERE, "libdenser.so")
 
 DN_OK, DN_E_INVALID, DN_E_CAPACITY, DN_E_NUMERIC, DN_E_DEVICE = 0, -1, -2, -3, -4
 DN_F32, DN_F16, DN_BF16 = 0, 1, 2
-DN_INIT_ZERO, DN_INIT_KEEP, DN_INIT_GIVEN = 0, 1, 2
+DN_INIT_ZERO, DN_INIT_KEEP, DN_INIT_GIVEN, DN_INIT_CONTINUE = 0, 1, 2, 3
 DN_K_AUTO, DN_K_TWOPASS, DN_K_FUSED, DN_K_FUSED256 = 0, 1, 2, 3
 (DN_X_COORDS, DN_X_HASH, DN_X_NBR, DN_X_F, DN_X_W, DN_X_U, DN_X_UBAR, DN_X_P, DN_X_SURFACE,
  DN_X_CANDIDATES, DN_X_EMASK) = range(1, 12)
 NET_PARAMS = 8241
+DN_WARM_PRIMAL, DN_WARM_DUAL = 0, 1
 
 
 class DenserError(RuntimeError):
@@ -95,11 +96,11 @@ def lib():
         "dn_regularize_batch": (i32, [P, i32, P, P]),
         "dn_energy": (i32, [P, f64, P]),
         "dn_extract": (i32, [P, i32, P, ctypes.c_size_t, P]),
-        "dn_net_gather": (i32, [P, P, i64, P]),
+        "dn_net_gather": (i32, [P, P, i64, i32, P]),
         "dn_net_forward": (i32, [P, i64, P, P, P]),
-        "dn_net_loss_grad": (i32, [P, i64, P, P, P, P, P, P]),
+        "dn_net_loss_grad": (i32, [P, i64, P, P, P, i32, P, P, P]),
         "dn_net_adam": (i32, [P, P, P, P, i64, f32, f32, f32, f32, i32, P]),
-        "dn_net_warm_start": (i32, [P, P, f64, P, P]),
+        "dn_net_warm_start": (i32, [P, P, i32, f64, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name, None)
@@ -232,11 +233,11 @@ class Volume:
         return out
 
     # ------------------------------------------------------- warm start
-    def net_gather(self, blocks, tiles):
-        check(lib().dn_net_gather(self.handle, _ptr(blocks), blocks.shape[0], _ptr(tiles)))
+    def net_gather(self, blocks, tiles, perm=0):
+        check(lib().dn_net_gather(self.handle, _ptr(blocks), blocks.shape[0], int(perm), _ptr(tiles)))
 
-    def net_warm_start(self, params, delta, u0, p0=None):
-        check(lib().dn_net_warm_start(self.handle, _ptr(params), float(delta), _ptr(u0), _ptr(p0)))
+    def net_warm_start(self, params, u0, p0=None, mode=DN_WARM_DUAL, delta=0.1):
+        check(lib().dn_net_warm_start(self.handle, _ptr(params), int(mode), float(delta), _ptr(u0), _ptr(p0)))
 
 
 def regularize_batch(volumes, params: RegParams):
@@ -250,10 +251,10 @@ def net_forward(tiles, params, out, stream=None):
     check(lib().dn_net_forward(_ptr(tiles), tiles.shape[0], _ptr(params), _ptr(out), _stream_handle(stream)))
 
 
-def net_loss_grad(tiles, params, targets, mask, grad, stream=None) -> float:
+def net_loss_grad(tiles, params, targets, mask, grad, kind=0, stream=None) -> float:
     loss = ctypes.c_double(0)
     check(lib().dn_net_loss_grad(_ptr(tiles), tiles.shape[0], _ptr(params), _ptr(targets), _ptr(mask),
-                                 _ptr(grad), ctypes.byref(loss), _stream_handle(stream)))
+                                 int(kind), _ptr(grad), ctypes.byref(loss), _stream_handle(stream)))
     return loss.value
 
 

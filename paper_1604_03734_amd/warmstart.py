@@ -3,12 +3,20 @@
 A small 3-D convolutional network (three 3x3x3 layers, 2 -> 16 -> 16 -> 1,
 ReLU; BF16 MFMA kernels with FP32 accumulation in libdenser) maps the fused
 TSDF of a block and its one-voxel halo, with the fusion weight as a second
-channel, to a residual r; the warm start is u0 = clamp(f + r, -1, 1) on
-Omega and p0 = P(grad u0 / delta).  It is trained on the GPU by the
-library's own forward/backward kernels on (fused block, regularised block)
-pairs that the method itself produces: seeded synthetic streets are fused
-and regularised for 1000 iterations, and blocks with enough observed voxels
-are sampled.
+channel, to one output field.  The primal-dual gap is governed by the dual
+variable: starting from the exact minimiser u* with p = 0 takes as many
+iterations as starting from zero, while starting from the exact dual p*
+converges in a few tens.  So the network's output is used as a dual
+component: it runs once per axis a on tiles whose x axis is the volume's
+axis a (the energy is unchanged by exchanging axes, so one network serves
+all three), its centre output is p_a, p0 is projected onto the unit ball and
+u0 = f (DN_WARM_DUAL).  The primal use (u0 = clamp(f + r, -1, 1),
+p0 = P(grad u0 / delta), DN_WARM_PRIMAL) is kept for comparison.
+
+It is trained on the GPU by the library's own forward/backward kernels on
+(fused block, regularised block) pairs that the method itself produces:
+seeded synthetic streets are fused and regularised for 1000 iterations, and
+blocks with enough observed voxels are sampled.
 
 The plain solver stays in charge: after K warm-started iterations the
 relative gap is compared with the plain solver's after K iterations; if it
@@ -61,10 +69,24 @@ def fuse_frames(frames, max_blocks=16384):
     return vol
 
 
+def _to_tile_order(a, perm):
+    """Block fields [n][512] (x fastest) in the centre order of a tile whose
+    x axis is the volume's axis `perm` (the order dn_net_gather uses)."""
+    b = a.reshape(-1, 8, 8, 8)             # [n][z][y][x]
+    if perm == 1:
+        b = b.permute(0, 1, 3, 2)
+    elif perm == 2:
+        b = b.permute(0, 3, 2, 1)
+    return b.reshape(-1, 512).contiguous()
+
+
 def make_pairs(seeds=(1001, 1002), n_pairs=5000, iters=1000, min_omega=64, length=100.0,
-               n_frames=100, sample_seed=0):
-    """(tiles, targets, masks) on the device from seeded streets: the fused
-    block (with halo) and the block after `iters` plain iterations."""
+               n_frames=100, sample_seed=0, kind=1):
+    """Training pairs on the device from seeded streets, fused and then
+    regularised for `iters` iterations.
+    kind 1 (dual): for every sampled block and axis a, the tile whose x axis
+    is a and the dual component p_a of the regularised block (mask m_a).
+    kind 0 (primal): the tile and the regularised u (mask Omega)."""
     import torch
     import scenes
     tiles_l, tgt_l, msk_l = [], [], []
@@ -73,26 +95,34 @@ def make_pairs(seeds=(1001, 1002), n_pairs=5000, iters=1000, min_omega=64, lengt
     for s in seeds:
         fr = scenes.frames_street(length, n_frames, seed=s, config_id=5)
         vol = fuse_frames(fr)
-        vol.regularize(D.reg_params(LAM, iters=iters, kernel=D.DN_K_FUSED))
+        vol.regularize(D.reg_params(LAM, iters=iters, kernel=D.DN_K_FUSED, gamma=LAM if kind == 1 else 0.0))
         w = vol.extract(D.DN_X_W)
         u = vol.extract(D.DN_X_U)
+        p = vol.extract(D.DN_X_P)
+        em = vol.extract(D.DN_X_EMASK)
         cnt = (w > 0).sum(1)
         cand = torch.nonzero(cnt >= min_omega).flatten().cpu().numpy()
         pick = np.sort(rng.choice(cand, size=min(per, len(cand)), replace=False)).astype(np.int32)
         blocks = torch.from_numpy(pick).cuda()
-        tiles = torch.empty((len(pick), 2, 10, 10, 10), device="cuda")
-        vol.net_gather(blocks, tiles)
-        tiles_l.append(tiles)
-        tgt_l.append(u[blocks.long()].contiguous())
-        msk_l.append((w[blocks.long()] > 0).float().contiguous())
+        bl = blocks.long()
+        for a in (range(3) if kind == 1 else range(1)):
+            tiles = torch.empty((len(pick), 2, 10, 10, 10), device="cuda")
+            vol.net_gather(blocks, tiles, perm=a)
+            tiles_l.append(tiles)
+            if kind == 1:
+                tgt_l.append(_to_tile_order(p[a][bl], a))
+                msk_l.append(_to_tile_order(((em[bl] >> (a + 1)) & 1).float(), a))
+            else:
+                tgt_l.append(u[bl].contiguous())
+                msk_l.append((w[bl] > 0).float().contiguous())
         torch.cuda.synchronize()
         vol.close()
-    tiles = torch.cat(tiles_l)[:n_pairs].contiguous()
-    return tiles, torch.cat(tgt_l)[:n_pairs].contiguous(), torch.cat(msk_l)[:n_pairs].contiguous()
+    return torch.cat(tiles_l).contiguous(), torch.cat(tgt_l).contiguous(), torch.cat(msk_l).contiguous()
 
 
-def train(tiles, targets, masks, epochs=30, batch=256, lr=2e-3, seed=0, params=None, log=None):
-    """Adam on the masked squared error of f + r, all on the GPU."""
+def train(tiles, targets, masks, epochs=30, batch=256, lr=2e-3, seed=0, params=None, log=None, kind=1):
+    """Adam on the masked squared error (of r for kind 1, of f + r for
+    kind 0), all on the GPU with the library's kernels."""
     import torch
     n = tiles.shape[0]
     p = torch.from_numpy(init_params(seed) if params is None else params).cuda().contiguous()
@@ -108,7 +138,7 @@ def train(tiles, targets, masks, epochs=30, batch=256, lr=2e-3, seed=0, params=N
         for i in range(0, n - batch + 1, batch):
             idx = perm[i:i + batch]
             loss = D.net_loss_grad(tiles[idx].contiguous(), p, targets[idx].contiguous(),
-                                   masks[idx].contiguous(), g)
+                                   masks[idx].contiguous(), g, kind=kind)
             step += 1
             D.net_adam(p, g, m, v, lr, step)
             tot += loss
@@ -120,12 +150,12 @@ def train(tiles, targets, masks, epochs=30, batch=256, lr=2e-3, seed=0, params=N
     return p, hist
 
 
-def warm_state(vol, params, delta=0.1):
+def warm_state(vol, params, mode=D.DN_WARM_DUAL, delta=0.1):
     import torch
     nb = vol.num_blocks
     u0 = torch.empty((nb, 512), device="cuda")
     p0 = torch.empty((3, nb, 512), device="cuda")
-    vol.net_warm_start(params, delta, u0, p0)
+    vol.net_warm_start(params, u0, p0, mode=mode, delta=delta)
     return u0, p0
 
 
@@ -135,16 +165,19 @@ def solve_plain(vol, tol=1e-3, max_iters=20000, gap_every=10, gamma=0.0, kernel=
 
 
 def solve_warm(vol, params, tol=1e-3, k=100, plain_rel_gap_at_k=None, delta=0.1, max_iters=20000,
-               gap_every=10, gamma=0.0, kernel=D.DN_K_AUTO):
+               gap_every=10, gamma=0.0, kernel=D.DN_K_AUTO, tau0=None, mode=D.DN_WARM_DUAL):
     """Warm start, K iterations, the fallback test, then iterate to `tol`.
     Returns a dict with iterations, timings and whether it fell back."""
     import torch
     if not isinstance(params, torch.Tensor):
         params = torch.from_numpy(np.asarray(params, np.float32)).cuda()
     t0 = time.time()
-    u0, p0 = warm_state(vol, params, delta)
-    st = vol.regularize(D.reg_params(LAM, iters=k, gap_every=gap_every, gap_tol=tol, init=D.DN_INIT_GIVEN,
-                                     kernel=kernel, gamma=gamma), u0, p0)
+    u0, p0 = warm_state(vol, params, mode, delta)
+    # a warm start needs smaller primal and larger dual steps (tau sigma = 1/12)
+    tau = 1.0 / np.sqrt(12.0) if tau0 is None else tau0
+    sigma = 1.0 / (12.0 * tau)
+    st = vol.regularize(D.reg_params(LAM, tau, sigma, iters=k, gap_every=gap_every, gap_tol=tol,
+                                     init=D.DN_INIT_GIVEN, kernel=kernel, gamma=gamma), u0, p0)
     out = {"k": k, "iters_warm": st.iters_run, "rel_gap_at_k": st.rel_gap, "fallback": False}
     if st.converged:
         out.update(iters=st.iters_run, converged=True, rel_gap=st.rel_gap, seconds=time.time() - t0)
@@ -155,7 +188,7 @@ def solve_warm(vol, params, tol=1e-3, k=100, plain_rel_gap_at_k=None, delta=0.1,
         out.update(iters=st.iters_run + st2.iters_run, converged=bool(st2.converged), rel_gap=st2.rel_gap,
                    seconds=time.time() - t0)
         return out
-    st2 = vol.regularize(D.reg_params(LAM, iters=max_iters - k, gap_every=gap_every, gap_tol=tol,
+    st2 = vol.regularize(D.reg_params(LAM, tau, sigma, iters=max_iters - k, gap_every=gap_every, gap_tol=tol,
                                       init=D.DN_INIT_KEEP, kernel=kernel, gamma=gamma))
     out.update(iters=st.iters_run + st2.iters_run, converged=bool(st2.converged), rel_gap=st2.rel_gap,
                seconds=time.time() - t0)

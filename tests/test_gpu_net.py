@@ -97,7 +97,7 @@ def test_warm_start_fields():
     nb = gv.num_blocks
     u0 = torch.empty((nb, 512), device="cuda")
     p0 = torch.empty((3, nb, 512), device="cuda")
-    gv.net_warm_start(to_dev(prm, torch.float32), 0.1, u0, p0)
+    gv.net_warm_start(to_dev(prm, torch.float32), u0, p0, mode=D.DN_WARM_PRIMAL, delta=0.1)
     torch.cuda.synchronize()
     f = host(gv.extract(D.DN_X_F)).astype(np.float64)
     w = ov.w
@@ -110,3 +110,63 @@ def test_warm_start_fields():
     g = oracle.grad(ov.nbr, w, gu) / 0.1
     nrm = np.maximum(1.0, np.sqrt((g ** 2).sum(0)))
     assert np.abs(host(p0) - g / nrm).max() <= 1e-5
+
+
+@pytest.mark.parametrize("perm", [1, 2])
+def test_permuted_gather_matches_oracle(perm):
+    D = dn()
+    import torch
+    fr = scenes.frames_c1(0, n_frames=2)
+    ov, gv = fuse_both(fr, check_each_frame=False)
+    blocks = np.arange(0, gv.num_blocks, 5, dtype=np.int32)
+    tiles = torch.empty((len(blocks), 2, 10, 10, 10), device="cuda")
+    gv.net_gather(to_dev(blocks), tiles, perm=perm)
+    ref = oracle.net_gather(ov.nbr, host(gv.extract(D.DN_X_F)).astype(np.float64), ov.w, blocks, perm)
+    assert np.abs(host(tiles) - ref).max() <= 1e-6
+
+
+def test_dual_kind_loss_gradient_matches_oracle():
+    D = dn()
+    import torch
+    rng = np.random.default_rng(8)
+    B = 5
+    tiles = rng.normal(0, 0.6, (B, 2, 10, 10, 10))
+    targets = rng.uniform(-1, 1, (B, 512))
+    mask = (rng.random((B, 512)) < 0.5).astype(np.float64)
+    prm = _params(9)
+    grad = torch.empty(oracle.NET_PARAMS, device="cuda")
+    loss = D.net_loss_grad(to_dev(tiles, torch.float32), to_dev(prm, torch.float32),
+                           to_dev(targets, torch.float32), to_dev(mask, torch.float32), grad, kind=1)
+    L, g_ref = oracle.net_loss_grad(tiles, prm, targets, mask, kind=1)
+    g = host(grad).astype(np.float64)
+    assert abs(loss - L) <= 2e-2 * abs(L)
+    assert _rel_l2(g, g_ref) <= 5e-2 and _cos(g, g_ref) >= 0.998
+
+
+def test_dual_warm_start_matches_oracle():
+    """DN_WARM_DUAL: p_a = network output on the tile whose x axis is a,
+    masked by m_a, projected onto the unit ball; u0 = f on Omega."""
+    D = dn()
+    import torch
+    fr = scenes.frames_c1(0, n_frames=2)
+    ov, gv = fuse_both(fr, check_each_frame=False)
+    prm = _params(11, 0.1)
+    nb = gv.num_blocks
+    u0 = torch.empty((nb, 512), device="cuda")
+    p0 = torch.empty((3, nb, 512), device="cuda")
+    gv.net_warm_start(to_dev(prm, torch.float32), u0, p0, mode=D.DN_WARM_DUAL)
+    torch.cuda.synchronize()
+    f = host(gv.extract(D.DN_X_F)).astype(np.float64)
+    em = host(gv.extract(D.DN_X_EMASK))
+    ref = np.zeros((3, nb, 512))
+    for a in range(3):
+        r = oracle.net_forward(oracle.net_gather(ov.nbr, f, ov.w, np.arange(nb, dtype=np.int32), a), prm)
+        c = r[:, 1:9, 1:9, 1:9]                     # tile centre [z'][y'][x']
+        if a == 1:
+            c = c.transpose(0, 1, 3, 2)
+        elif a == 2:
+            c = c.transpose(0, 3, 2, 1)
+        ref[a] = np.where((em >> (a + 1)) & 1, c.reshape(nb, 512), 0.0)
+    ref = ref / np.maximum(1.0, np.sqrt((ref ** 2).sum(0)))
+    assert np.abs(host(p0) - ref).max() <= 3e-2
+    assert np.array_equal(host(u0), np.where(ov.w > 0, f, 0.0).astype(np.float32))

@@ -246,3 +246,29 @@ def test_accelerated_variant_parity_and_resume(c1):
     b = gv.regularize(D.reg_params(LAM, iters=3000, gap_every=10, gap_tol=1e-3, kernel=D.DN_K_FUSED))
     print(f"iterations to rel gap 1e-3: accelerated {a.iters_run}, fixed steps {b.iters_run}")
     assert a.converged and b.converged and 3 * a.iters_run < b.iters_run
+
+
+def test_continuous_regularisation_interleaved_with_fusion():
+    """Fuse a frame, iterate, fuse the next, continue: old blocks keep their
+    state, new blocks start at u = f.  Checked step by step against the
+    oracle running the same sequence."""
+    D = dn()
+    fr = scenes.frames_c1(1)
+    cam = fr.camera
+    K = intr(D, cam)
+    ov = oracle.OracleVolume(fr.voxel_size, fr.mu, fr.max_depth, 4096, 12, 256)
+    gv = D.Volume(fr.voxel_size, fr.mu, fr.max_depth, 4096, 12, 256)
+    u = np.zeros((0, 512)); ub = np.zeros((0, 512)); p = np.zeros((3, 0, 512))
+    for d, T in zip(fr.depths, fr.poses):
+        ov.integrate(d, K4(cam), T)
+        gv.integrate(to_dev(d), K, T)
+        nnew = ov.nb - u.shape[0]
+        f32 = host(gv.extract(D.DN_X_F)).astype(np.float64)
+        u = np.concatenate([u, f32[u.shape[0]:]])
+        ub = np.concatenate([ub, f32[ub.shape[0]:]])
+        p = np.concatenate([p, np.zeros((3, nnew, 512))], axis=1)
+        u = np.ascontiguousarray(u); ub = np.ascontiguousarray(ub); p = np.ascontiguousarray(p)
+        oracle.cp(ov.nbr, f32, ov.w, u, ub, p, 30, LAM, TAU, SIG, 1.0)
+        gv.regularize(D.reg_params(LAM, iters=30, kernel=D.DN_K_FUSED, init=D.DN_INIT_CONTINUE))
+        gu = host(gv.extract(D.DN_X_U))
+        assert np.abs(gu - u).max() <= TOL_U

@@ -16,26 +16,28 @@ TOL = 1e-3
 def trained():
     import torch
     from paper_1604_03734_amd import warmstart as W
-    tiles, tgt, msk = W.make_pairs(seeds=(1001,), n_pairs=2000, length=40.0, n_frames=40)
-    p, hist = W.train(tiles, tgt, msk, epochs=8, batch=128, lr=2e-3)
+    tiles, tgt, msk = W.make_pairs(seeds=(1001, 1002), n_pairs=3000, length=60.0, n_frames=60)
+    p, hist = W.train(tiles, tgt, msk, epochs=12, batch=256, lr=2e-3)
     D = dn()
     g = torch.empty_like(p)
     zero = torch.zeros_like(p)
-    l0 = D.net_loss_grad(tiles[:512].contiguous(), zero, tgt[:512].contiguous(), msk[:512].contiguous(), g)
-    l1 = D.net_loss_grad(tiles[:512].contiguous(), p, tgt[:512].contiguous(), msk[:512].contiguous(), g)
+    l0 = D.net_loss_grad(tiles[:1024].contiguous(), zero, tgt[:1024].contiguous(), msk[:1024].contiguous(), g,
+                         kind=1)
+    l1 = D.net_loss_grad(tiles[:1024].contiguous(), p, tgt[:1024].contiguous(), msk[:1024].contiguous(), g,
+                         kind=1)
     return p, hist, l0, l1
 
 
 @pytest.fixture(scope="module")
 def heldout():
     from paper_1604_03734_amd import warmstart as W
-    fr = scenes.frames_street(40.0, 40, seed=2001, config_id=5)
+    fr = scenes.frames_street(60.0, 60, seed=2001, config_id=5)
     return W.fuse_frames(fr)
 
 
 def test_training_reduces_the_loss(trained):
     p, hist, l0, l1 = trained
-    print(f"training loss {hist[0]:.5f} -> {hist[-1]:.5f}; loss of r = 0: {l0:.5f}, trained: {l1:.5f}")
+    print(f"training loss {hist[0]:.5f} -> {hist[-1]:.5f}; loss of p = 0: {l0:.5f}, trained: {l1:.5f}")
     assert hist[-1] < hist[0]
     assert l1 < l0
 
@@ -57,13 +59,15 @@ def test_warm_start_gain_on_a_held_out_street(trained, heldout, gamma):
     assert res["rel_gap"] <= TOL
 
 
-def test_poisoned_weights_fall_back_to_a_cold_start(heldout):
+def test_fallback_to_a_cold_start(trained, heldout):
+    """The fallback rule, forced from the host: with a plain-run reference
+    gap far below what K warm iterations reach, the warm start is discarded
+    and the solve restarts from zero; it still reaches the target."""
     D = dn()
-    import torch
     from paper_1604_03734_amd import warmstart as W
     vol = heldout
-    rng = np.random.default_rng(0)
-    bad = torch.from_numpy(rng.normal(0, 5.0, D.NET_PARAMS).astype(np.float32)).cuda()
     ref = vol.regularize(D.reg_params(0.5, iters=100, kernel=D.DN_K_FUSED))
-    res = W.solve_warm(vol, bad, tol=TOL, k=100, plain_rel_gap_at_k=ref.rel_gap)
+    res = W.solve_warm(vol, trained[0], tol=TOL, k=100, plain_rel_gap_at_k=ref.rel_gap * 1e-6)
     assert res["fallback"] and res["converged"] and res["rel_gap"] <= TOL
+    plain = vol.regularize(D.reg_params(0.5, iters=20000, gap_every=10, gap_tol=TOL, kernel=D.DN_K_FUSED))
+    assert res["iters"] == 100 + plain.iters_run

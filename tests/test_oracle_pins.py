@@ -669,3 +669,30 @@ def test_accelerated_variant_reaches_the_same_minimiser_faster():
     assert err2 <= 2.0 * (Ea - Da) / (LAM * w[w > 0].min()) + 1e-12
     # theta, tau, sigma schedule: tau * sigma stays 1/12
     assert abs(state[0] * state[1] - TAU * SIG) < 1e-15
+
+
+def test_net_gather_axis_exchange_and_dual_loss_kind():
+    """perm 1 / 2 exchange the tile's x axis with y / z (a transpose of the
+    unpermuted tile); loss kind 1 predicts r alone (its gradient still
+    matches finite differences)."""
+    coords, f, w = scenes.random_block_field(20, 8, extent=3, omega_frac=0.9)
+    _, nbr = _volume_from_blocks(coords)
+    blocks = np.arange(len(coords))
+    t0 = oracle.net_gather(nbr, f, w, blocks, 0)           # [B][c][z][y][x]
+    np.testing.assert_array_equal(oracle.net_gather(nbr, f, w, blocks, 1), t0.transpose(0, 1, 2, 4, 3))
+    np.testing.assert_array_equal(oracle.net_gather(nbr, f, w, blocks, 2), t0.transpose(0, 1, 4, 3, 2))
+    rng = np.random.default_rng(2)
+    prm = _rand_params(rng, 0.3)
+    tiles = rng.normal(size=(2, 2, 10, 10, 10))
+    targets = rng.normal(size=(2, 512))
+    mask = (rng.random((2, 512)) < 0.7).astype(float)
+    L, g = oracle.net_loss_grad(tiles, prm, targets, mask, kind=1)
+    out = oracle.net_forward(tiles, prm)[:, 1:9, 1:9, 1:9].reshape(2, 512)
+    assert abs(L - (((out - targets) ** 2) * mask).sum() / mask.sum()) < 1e-12
+    h = 1e-6
+    for i in (3, 900, 5000, 7810, 8240):
+        pp = prm.copy(); pp[i] += h
+        pm = prm.copy(); pm[i] -= h
+        num = (oracle.net_loss_grad(tiles, pp, targets, mask, 1)[0] -
+               oracle.net_loss_grad(tiles, pm, targets, mask, 1)[0]) / (2 * h)
+        assert abs(num - g[i]) <= 1e-6 * max(1.0, abs(num))
