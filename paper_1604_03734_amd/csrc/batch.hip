@@ -8,6 +8,7 @@
 // and the item-to-workgroup mapping are picked by timing short trial runs
 // (autotuner), cached per problem size.
 #include <cstring>
+#include <cstdlib>
 
 #include <algorithm>
 #include <cmath>
@@ -81,7 +82,44 @@ __device__ __forceinline__ void grid_barrier(const BatchArgs &a, unsigned nwg)
     __syncthreads();
 }
 
-__global__ __launch_bounds__(512) void k_cp_persistent(BatchArgs a)
+// The item of a workgroup is the same for all its lanes: read it through
+// readfirstlane so the volume's pointers live in scalar registers.
+__device__ __forceinline__ int2 load_item(const BatchArgs &a, int64_t i)
+{
+    const int2 raw = a.items[i];
+    return make_int2(__builtin_amdgcn_readfirstlane(raw.x), __builtin_amdgcn_readfirstlane(raw.y));
+}
+
+// A value the whole wave shares, moved to scalar registers.
+template <class T> __device__ __forceinline__ T *uni(T *p)
+{
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+    return reinterpret_cast<T *>((uint64_t(hi) << 32) | lo);
+}
+
+__device__ __forceinline__ void item_args(const BatchArgs &a, int2 item, int it, float sigma, float tau,
+                                          float theta, CPArgs<SF32> &A)
+{
+    const VolDesc &d = a.vols[item.x];
+    const int c = (__builtin_amdgcn_readfirstlane(d.cur) + it) & 1;
+    const int64_t ps = int64_t(__builtin_amdgcn_readfirstlane(uint32_t(d.pstride))) |
+                       (int64_t(__builtin_amdgcn_readfirstlane(uint32_t(uint64_t(d.pstride) >> 32))) << 32);
+    A.nb = 0; A.pstride = ps; A.nbr = uni(d.nbr); A.emask = uni(d.emask); A.order = nullptr; A.xcd = 0;
+    A.f = uni(d.f); A.w = uni(d.w); A.u = uni(d.u);
+    A.ubar_in = uni(d.ubar[c]); A.ubar_out = uni(d.ubar[1 - c]);
+    A.p_in = uni(d.p[c]); A.p_out = uni(d.p[1 - c]); A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
+    A.sigma = sigma; A.tau = tau; A.lambda = a.lambda; A.theta = theta;
+}
+
+// All iterations of all sub-maps.  Each workgroup walks its items of an
+// iteration in a fixed order (with kPrefetch it issues the global loads of
+// the next item before computing the current one, two register sets, so
+// loads stay in flight while it works); a grid barrier closes every
+// iteration.
+template <int NT, bool kPrefetch>
+__device__ __forceinline__ void k_cp_persistent_body(const BatchArgs &a)
 {
     __shared__ CPShared sh;
     __shared__ int s_stop;
@@ -98,38 +136,60 @@ __global__ __launch_bounds__(512) void k_cp_persistent(BatchArgs a)
             acc_tau = th * acc_tau;
             acc_sigma = acc_sigma / th;
         }
+        int64_t i, hi, stride;
         if (a.xcd_chunks && G >= 8) {
             // workgroup g runs on XCD g % 8; XCD x owns items [x*chunk, (x+1)*chunk)
             // and has exactly (G - x + 7) / 8 workgroups to stride over them
             const int64_t x = blockIdx.x % 8, lane = blockIdx.x / 8;
-            const int64_t lanes = (G - x + 7) / 8;
             const int64_t chunk = (a.n_items + 7) / 8;
-            const int64_t lo = x * chunk, hi = min(a.n_items, lo + chunk);
-            for (int64_t i = lo + lane; i < hi; i += lanes) {
-                const int2 item = a.items[i];
-                const VolDesc d = a.vols[item.x];
-                const int c = (d.cur + it) & 1;
+            const int64_t lo = x * chunk;
+            hi = min(a.n_items, lo + chunk);
+            stride = (G - x + 7) / 8;
+            i = lo + lane;
+        } else {
+            i = blockIdx.x;
+            hi = a.n_items;
+            stride = G;
+        }
+        if constexpr (!kPrefetch) {
+            // one block after the other; the other workgroups on the CU overlap
+            for (; i < hi; i += stride) {
+                const int2 bi = load_item(a, i);
                 CPArgs<SF32> A;
-                A.nb = 0; A.pstride = d.pstride; A.nbr = d.nbr; A.emask = d.emask; A.order = nullptr; A.xcd = 0;
-                A.f = d.f; A.w = d.w; A.u = d.u; A.ubar_in = d.ubar[c]; A.ubar_out = d.ubar[1 - c];
-                A.p_in = d.p[c]; A.p_out = d.p[1 - c]; A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
-                A.sigma = sigma; A.tau = tau; A.lambda = a.lambda; A.theta = theta;
-                cp_block<SF32, false>(A, item.y, sh);
+                item_args(a, bi, it, sigma, tau, theta, A);
+                cp_block<SF32, false, NT>(A, bi.y, sh, opaque_tid());
                 __syncthreads();
             }
         } else {
-            for (int64_t i = blockIdx.x; i < a.n_items; i += G) {
-                const int2 item = a.items[i];
-                const VolDesc d = a.vols[item.x];
-                const int c = (d.cur + it) & 1;
-                CPArgs<SF32> A;
-                A.nb = 0; A.pstride = d.pstride; A.nbr = d.nbr; A.emask = d.emask; A.order = nullptr; A.xcd = 0;
-                A.f = d.f; A.w = d.w; A.u = d.u; A.ubar_in = d.ubar[c]; A.ubar_out = d.ubar[1 - c];
-                A.p_in = d.p[c]; A.p_out = d.p[1 - c]; A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
-                A.sigma = sigma; A.tau = tau; A.lambda = a.lambda; A.theta = theta;
-                cp_block<SF32, false>(A, item.y, sh);
-                __syncthreads();
+        CPRegs<NT> R0, R1;
+        CPArgs<SF32> A0, A1;
+        int2 b0 = make_int2(0, 0), b1 = make_int2(0, 0);
+        if (i < hi) {
+            b0 = load_item(a, i);
+            item_args(a, b0, it, sigma, tau, theta, A0);
+            cp_load<SF32, NT>(A0, b0.y, R0, opaque_tid());
+        }
+        while (i < hi) {
+            int64_t nx = i + stride;
+            if (nx < hi) {
+                b1 = load_item(a, nx);
+                item_args(a, b1, it, sigma, tau, theta, A1);
+                cp_load<SF32, NT>(A1, b1.y, R1, opaque_tid());
             }
+            cp_compute<SF32, false, NT>(A0, b0.y, R0, sh, opaque_tid());
+            __syncthreads();
+            i = nx;
+            if (i >= hi) break;
+            nx = i + stride;
+            if (nx < hi) {
+                b0 = load_item(a, nx);
+                item_args(a, b0, it, sigma, tau, theta, A0);
+                cp_load<SF32, NT>(A0, b0.y, R0, opaque_tid());
+            }
+            cp_compute<SF32, false, NT>(A1, b1.y, R1, sh, opaque_tid());
+            __syncthreads();
+            i = nx;
+        }
         }
         grid_barrier(a, nwg);
         if (threadIdx.x == 0)
@@ -139,10 +199,22 @@ __global__ __launch_bounds__(512) void k_cp_persistent(BatchArgs a)
     }
 }
 
+template <int NT, bool kPrefetch>
+__global__ __launch_bounds__(NT) void k_cp_persistent(BatchArgs a)
+{
+    k_cp_persistent_body<NT, kPrefetch>(a);
+}
+
+// The lean form: no prefetch, registers capped for 8 waves per SIMD.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_cp_persistent_lean(BatchArgs a)
+{
+    k_cp_persistent_body<256, false>(a);
+}
+
 __global__ void k_make_items(const int32_t *__restrict__ order, int64_t nb, int32_t vol, int2 *__restrict__ items)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < nb) items[i] = make_int2(vol, order[i]);
+    if (i < nb) items[i] = make_int2(vol, order ? order[i] : int32_t(i));
 }
 
 // Process-wide batch context (device buffers and the cached graph).
@@ -153,7 +225,7 @@ struct BatchCtx {
     // key of the captured graph
     const void *k_items = nullptr;
     int64_t k_n = -1;
-    int k_iters = -1, k_grid = -1, k_xcd = -1;
+    int k_iters = -1, k_grid = -1, k_xcd = -1, k_nt = -1;
     float k_prm[4] = {0, 0, 0, 0};
     double k_acc[3] = {0, 0, 0};
     const void *vols_ptr = nullptr;
@@ -163,7 +235,8 @@ struct BatchCtx {
 };
 static BatchCtx g_batch;
 
-struct TuneChoice { int wg_per_cu; int xcd; };
+// (threads per workgroup, workgroups per CU, XCD-chunked items, pool order)
+struct TuneChoice { int nt; int wg_per_cu; int xcd; int pool; };
 static std::map<int, TuneChoice> g_tuned;
 
 static int size_bucket(int64_t n)
@@ -173,10 +246,23 @@ static int size_bucket(int64_t n)
     return b;
 }
 
-static int launch_direct(hipStream_t st, const BatchArgs &a, int grid)
+// variant: 256 / 512 = threads per workgroup with prefetch of the next
+// block; 257 = 256 threads without prefetch (fewer registers, more
+// workgroups per CU)
+static void launch_kernel(hipStream_t st, const BatchArgs &a, int grid, int nt)
 {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, a.bar, a.err);
-    hipLaunchKernelGGL(k_cp_persistent, dim3(grid), dim3(512), 0, st, a);
+    if (nt == 256)
+        hipLaunchKernelGGL((k_cp_persistent<256, true>), dim3(grid), dim3(256), 0, st, a);
+    else if (nt == 257)
+        hipLaunchKernelGGL(k_cp_persistent_lean, dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_cp_persistent<512, true>), dim3(grid), dim3(512), 0, st, a);
+}
+
+static int launch_direct(hipStream_t st, const BatchArgs &a, int grid, int nt)
+{
+    launch_kernel(st, a, grid, nt);
     DN_HIP(hipGetLastError());
     return DN_OK;
 }
@@ -184,7 +270,7 @@ static int launch_direct(hipStream_t st, const BatchArgs &a, int grid)
 // Capture (once per configuration) and replay on a private stream that is
 // ordered after and before the caller's stream with events (the caller's
 // stream may be the null stream, which cannot be captured).
-static int launch_graph(hipStream_t st, const BatchArgs &a, int grid)
+static int launch_graph(hipStream_t st, const BatchArgs &a, int grid, int nt)
 {
     BatchCtx &c = g_batch;
     if (!c.cap) {
@@ -193,6 +279,7 @@ static int launch_graph(hipStream_t st, const BatchArgs &a, int grid)
         DN_HIP(hipEventCreateWithFlags(&c.ev_out, hipEventDisableTiming));
     }
     bool same = c.exec && c.k_items == a.items && c.k_n == a.n_items && c.k_iters == a.iters && c.k_grid == grid &&
+                c.k_nt == nt &&
                 c.k_xcd == a.xcd_chunks && c.k_prm[0] == a.sigma && c.k_prm[1] == a.tau &&
                 c.k_prm[2] == a.lambda && c.k_prm[3] == a.theta && c.vols_ptr == a.vols && c.bar_ptr == a.bar &&
                 c.k_acc[0] == a.gamma && c.k_acc[1] == a.tau0 && c.k_acc[2] == a.sigma0;
@@ -200,8 +287,7 @@ static int launch_graph(hipStream_t st, const BatchArgs &a, int grid)
         if (c.exec) { (void)hipGraphExecDestroy(c.exec); c.exec = nullptr; }
         if (c.graph) { (void)hipGraphDestroy(c.graph); c.graph = nullptr; }
         DN_HIP(hipStreamBeginCapture(c.cap, hipStreamCaptureModeThreadLocal));
-        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, c.cap, a.bar, a.err);
-        hipLaunchKernelGGL(k_cp_persistent, dim3(grid), dim3(512), 0, c.cap, a);
+        launch_kernel(c.cap, a, grid, nt);
         hipError_t le = hipGetLastError();
         hipError_t ce = hipStreamEndCapture(c.cap, &c.graph);
         if (le != hipSuccess || ce != hipSuccess) {
@@ -210,6 +296,7 @@ static int launch_graph(hipStream_t st, const BatchArgs &a, int grid)
         }
         DN_HIP(hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0));
         c.k_items = a.items; c.k_n = a.n_items; c.k_iters = a.iters; c.k_grid = grid; c.k_xcd = a.xcd_chunks;
+        c.k_nt = nt;
         c.k_prm[0] = a.sigma; c.k_prm[1] = a.tau; c.k_prm[2] = a.lambda; c.k_prm[3] = a.theta;
         c.k_acc[0] = a.gamma; c.k_acc[1] = a.tau0; c.k_acc[2] = a.sigma0;
         c.vols_ptr = a.vols; c.bar_ptr = a.bar;
@@ -274,7 +361,6 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     if ((rc = c.items.ensure(sizeof(int2) * size_t(total > 0 ? total : 1)))) return rc;
     if ((rc = c.state.ensure(64))) return rc;
     std::vector<VolDesc> hd(n);
-    int64_t ofs = 0;
     for (int i = 0; i < n; ++i) {
         dn_volume *v = vols[i];
         VolDesc &d = hd[i];
@@ -283,14 +369,22 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
         d.pstride = v->cap_blocks * kBlockVox;
         d.cur = v->cur;
         d.pad = 0;
-        if (v->nb > 0) {
-            hipLaunchKernelGGL(k_make_items, dim3(unsigned((v->nb + 255) / 256)), dim3(256), 0, st, v->order, v->nb,
-                               i, c.items.as<int2>() + ofs);
-            DN_HIP(hipGetLastError());
-        }
-        ofs += v->nb;
     }
     DN_HIP(hipMemcpyAsync(c.descs.ptr, hd.data(), sizeof(VolDesc) * size_t(n), hipMemcpyHostToDevice, st));
+    // work items (volume, block): volume after volume, blocks in Morton or pool order
+    auto build_items = [&](int pool) -> int {
+        int64_t ofs = 0;
+        for (int i = 0; i < n; ++i) {
+            dn_volume *v = vols[i];
+            if (v->nb > 0) {
+                hipLaunchKernelGGL(k_make_items, dim3(unsigned((v->nb + 255) / 256)), dim3(256), 0, st,
+                                   pool ? (const int32_t *)nullptr : v->order, v->nb, i, c.items.as<int2>() + ofs);
+                DN_HIP(hipGetLastError());
+            }
+            ofs += v->nb;
+        }
+        return DN_OK;
+    };
 
     BatchArgs a;
     a.vols = c.descs.as<VolDesc>();
@@ -305,14 +399,17 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     a.bar = c.state.as<unsigned>();
     a.err = reinterpret_cast<int32_t *>(c.state.as<unsigned>() + 4);
     a.spin_limit = 1LL << 22;
+    a.xcd_chunks = 1;
 
     // occupancy bound: every workgroup of the grid must be resident at once
-    int dev_cu = 0, per_cu = 0;
+    int dev_cu = 0, per_cu256 = 0, per_cu257 = 0, per_cu512 = 0;
     DN_HIP(hipDeviceGetAttribute(&dev_cu, hipDeviceAttributeMultiprocessorCount, v0->device));
-    DN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cp_persistent, 512, 0));
-    if (per_cu < 1) { set_error("persistent kernel does not fit on a compute unit"); return DN_E_DEVICE; }
+    DN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu256, k_cp_persistent<256, true>, 256, 0));
+    DN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu257, k_cp_persistent_lean, 256, 0));
+    DN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu512, k_cp_persistent<512, true>, 512, 0));
+    if (per_cu257 < 1) { set_error("persistent kernel does not fit on a compute unit"); return DN_E_DEVICE; }
 
-    TuneChoice ch{per_cu, 1};
+    TuneChoice ch = TuneChoice{257, per_cu257, 1, 0};
     const int key = size_bucket(total);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
@@ -324,21 +421,33 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
         DN_HIP(hipEventCreate(&e1));
         float best = 1e30f;
         const int trial = std::min(prm->iters, 6);
-        for (int wpc = 1; wpc <= per_cu; ++wpc)
-            for (int xcd = 0; xcd <= 1; ++xcd) {
-                BatchArgs t = a;
-                t.iters = trial;
-                t.xcd_chunks = xcd;
-                int grid = int(std::min<int64_t>(int64_t(wpc) * dev_cu, total));
-                DN_HIP(hipEventRecord(e0, st));
-                if ((rc = launch_direct(st, t, grid))) return rc;
-                DN_HIP(hipEventRecord(e1, st));
-                DN_HIP(hipEventSynchronize(e1));
-                if ((rc = check_err(st, t.err, v0->host))) return rc;
-                float ms = 0;
-                DN_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) { best = ms; ch = TuneChoice{wpc, xcd}; }
+        for (int pool = 0; pool <= 1; ++pool) {
+            if ((rc = build_items(pool))) return rc;
+            for (int nt : {257, 256, 512}) {
+                const int pc = nt == 256 ? per_cu256 : (nt == 257 ? per_cu257 : per_cu512);
+                if (pc < 1) continue;
+                for (int wpc : {pc, (pc + 1) / 2}) {
+                    if (wpc != pc && wpc == (pc + 1) / 2 && pc == 1) continue;
+                    for (int xcd = 0; xcd <= 1; ++xcd) {
+                        BatchArgs t = a;
+                        t.iters = trial;
+                        t.xcd_chunks = xcd;
+                        int grid = int(std::min<int64_t>(int64_t(wpc) * dev_cu, total));
+                        DN_HIP(hipEventRecord(e0, st));
+                        if ((rc = launch_direct(st, t, grid, nt))) return rc;
+                        DN_HIP(hipEventRecord(e1, st));
+                        DN_HIP(hipEventSynchronize(e1));
+                        if ((rc = check_err(st, t.err, v0->host))) return rc;
+                        float ms = 0;
+                        DN_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        if (getenv("DN_VERBOSE"))
+                            fprintf(stderr, "[denser] batch tune: nt %d wpc %d xcd %d pool %d: %.3f ms\n", nt, wpc,
+                                    xcd, pool, ms);
+                        if (ms < best) { best = ms; ch = TuneChoice{nt, wpc, xcd, pool}; }
+                    }
+                }
             }
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         g_tuned[key] = ch;
@@ -350,6 +459,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
             if (rc) return rc;
         }
     }
+    if ((rc = build_items(ch.pool))) return rc;
     a.iters = prm->iters;
     a.xcd_chunks = ch.xcd;
     const int grid = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(ch.wg_per_cu) * dev_cu, total)));
@@ -358,7 +468,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     DN_HIP(hipEventCreate(&e1));
     DN_HIP(hipEventRecord(e0, st));
     if (total > 0 && prm->iters > 0) {
-        if ((rc = launch_graph(st, a, grid))) return rc;
+        if ((rc = launch_graph(st, a, grid, ch.nt))) return rc;
     }
     DN_HIP(hipEventRecord(e1, st));
     DN_HIP(hipEventSynchronize(e1));
@@ -393,6 +503,8 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
             s.iters_run = prm->iters;
             s.converged = prm->gap_tol > 0 && s.gap <= prm->gap_tol * ed[0];
             s.ms_loop = ms;
+            s.kernel_used = ch.nt * 100 + ch.wg_per_cu;
+            s.layout_used = (ch.pool ? 1 : 0) | (ch.xcd ? 0 : 2);
         }
     }
     return DN_OK;

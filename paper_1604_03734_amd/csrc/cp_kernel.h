@@ -118,52 +118,89 @@ __device__ __forceinline__ void project(float &a, float &b, float &c)
     if (n > 1.0f) { a = a / n; b = b / n; c = c / n; }
 }
 
-// One fused Chambolle-Pock iteration on block b by NT threads (512: one
-// voxel per thread; 256: two voxels per thread, z layers l and l + 4).
-template <class S, bool kRefine, int NT = 512>
-__device__ __forceinline__ void cp_block(const CPArgs<S> &A, int64_t b, CPShared &sh)
+// Per-thread registers of one block's iteration: the thread's own voxels
+// (VPT = 512 / NT of them), its share of the ubar halo (432 voxels: six
+// faces and the six (-a, +b) edges) and, for t < 192, one voxel of the -1
+// faces (its edge mask and the three dual components).
+template <int NT> struct CPRegs {
+    static constexpr int VPT = kBlockVox / NT;
+    static constexpr int HPT = (432 + NT - 1) / NT;
+    float ub[VPT], p0[VPT], p1[VPT], p2[VPT], uo[VPT], fv[VPT], wv[VPT];
+    uint8_t m[VPT];
+    float hu[HPT];
+    float h0, h1, h2;
+    uint8_t hm;
+};
+
+// Global loads of one block's iteration (issued; used by cp_compute).
+template <class S, int NT>
+__device__ __forceinline__ void cp_load(const CPArgs<S> &A, int64_t b, CPRegs<NT> &R, int t)
 {
-    constexpr int VPT = kBlockVox / NT;
-    const int t = threadIdx.x;
+    constexpr int VPT = CPRegs<NT>::VPT, HPT = CPRegs<NT>::HPT;
     const int64_t g0i = b * kBlockVox;
     const int32_t *nb27 = A.nbr + b * kNbr;
     const int64_t ps = A.pstride;
-
-    float ub[VPT], p0[VPT], p1[VPT], p2[VPT], uo[VPT], fv[VPT], wv[VPT];
-    uint8_t m[VPT];
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
-        const int v = t + k * NT;
-        const int64_t gi = g0i + v;
-        ub[k] = S::ld(A.ubar_in[gi]);
-        m[k] = A.emask[gi];
-        p0[k] = S::ld(A.p_in[gi]); p1[k] = S::ld(A.p_in[gi + ps]); p2[k] = S::ld(A.p_in[gi + 2 * ps]);
-        uo[k] = S::ld(A.u[gi]);
-        fv[k] = A.f[gi]; wv[k] = A.w[gi];
+        const int64_t gi = g0i + t + k * NT;
+        R.ub[k] = S::ld(A.ubar_in[gi]);
+        R.m[k] = A.emask[gi];
+        R.p0[k] = S::ld(A.p_in[gi]); R.p1[k] = S::ld(A.p_in[gi + ps]); R.p2[k] = S::ld(A.p_in[gi + 2 * ps]);
+        R.uo[k] = S::ld(A.u[gi]);
+        R.fv[k] = A.f[gi]; R.wv[k] = A.w[gi];
     }
 #pragma unroll
-    for (int k = 0; k < VPT; ++k) {
-        const int v = t + k * NT, lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
-        sh.u[i10(lx, ly, lz)] = ub[k];
-        sh.m[i9(lx, ly, lz)] = m[k];
+    for (int k = 0; k < HPT; ++k) {
+        const int h = t + k * NT;
+        R.hu[k] = 0.0f;
+        if (h < 432) {
+            int hx, hy, hz;
+            halo_pos(h, hx, hy, hz);
+            int64_t j = halo_index(nb27, hx, hy, hz);
+            if (j >= 0) R.hu[k] = S::ld(A.ubar_in[j]);
+        }
     }
-    for (int h = t; h < 432; h += NT) {
-        int hx, hy, hz;
-        halo_pos(h, hx, hy, hz);
-        int64_t j = halo_index(nb27, hx, hy, hz);
-        sh.u[i10(hx, hy, hz)] = j >= 0 ? S::ld(A.ubar_in[j]) : 0.0f;
-    }
-    float h0 = 0.f, h1 = 0.f, h2 = 0.f;
-    uint8_t hm = 0;
-    int fx = 0, fy = 0, fz = 0;
+    R.h0 = R.h1 = R.h2 = 0.f;
+    R.hm = 0;
     if (t < 192) {
+        int fx, fy, fz;
         face_pos(t, fx, fy, fz);
         int64_t j = halo_index(nb27, fx, fy, fz);
         if (j >= 0) {
-            hm = A.emask[j];
-            h0 = S::ld(A.p_in[j]); h1 = S::ld(A.p_in[j + ps]); h2 = S::ld(A.p_in[j + 2 * ps]);
+            R.hm = A.emask[j];
+            R.h0 = S::ld(A.p_in[j]); R.h1 = S::ld(A.p_in[j + ps]); R.h2 = S::ld(A.p_in[j + 2 * ps]);
         }
-        sh.m[i9(fx, fy, fz)] = hm;
+    }
+}
+
+// The iteration of one block from its loaded registers (NT threads: 512 =
+// one voxel per thread; 256 = two voxels per thread, z layers l and l + 4).
+template <class S, bool kRefine, int NT>
+__device__ __forceinline__ void cp_compute(const CPArgs<S> &A, int64_t b, const CPRegs<NT> &R, CPShared &sh,
+                                           int t)
+{
+    constexpr int VPT = CPRegs<NT>::VPT, HPT = CPRegs<NT>::HPT;
+    const int64_t g0i = b * kBlockVox;
+    const int64_t ps = A.pstride;
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int v = t + k * NT, lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
+        sh.u[i10(lx, ly, lz)] = R.ub[k];
+        sh.m[i9(lx, ly, lz)] = R.m[k];
+    }
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+        const int h = t + k * NT;
+        if (h < 432) {
+            int hx, hy, hz;
+            halo_pos(h, hx, hy, hz);
+            sh.u[i10(hx, hy, hz)] = R.hu[k];
+        }
+    }
+    int fx = 0, fy = 0, fz = 0;
+    if (t < 192) {
+        face_pos(t, fx, fy, fz);
+        sh.m[i9(fx, fy, fz)] = R.hm;
     }
     __syncthreads();
 
@@ -172,10 +209,11 @@ __device__ __forceinline__ void cp_block(const CPArgs<S> &A, int64_t b, CPShared
     for (int k = 0; k < VPT; ++k) {
         const int v = t + k * NT, lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
         const int64_t gi = g0i + v;
-        float g0 = (m[k] & 2) ? sh.u[i10(lx + 1, ly, lz)] - ub[k] : 0.0f;
-        float g1 = (m[k] & 4) ? sh.u[i10(lx, ly + 1, lz)] - ub[k] : 0.0f;
-        float g2 = (m[k] & 8) ? sh.u[i10(lx, ly, lz + 1)] - ub[k] : 0.0f;
-        float a0 = p0[k] + A.sigma * g0, a1 = p1[k] + A.sigma * g1, a2 = p2[k] + A.sigma * g2;
+        const uint8_t m = R.m[k];
+        float g0 = (m & 2) ? sh.u[i10(lx + 1, ly, lz)] - R.ub[k] : 0.0f;
+        float g1 = (m & 4) ? sh.u[i10(lx, ly + 1, lz)] - R.ub[k] : 0.0f;
+        float g2 = (m & 8) ? sh.u[i10(lx, ly, lz + 1)] - R.ub[k] : 0.0f;
+        float a0 = R.p0[k] + A.sigma * g0, a1 = R.p1[k] + A.sigma * g1, a2 = R.p2[k] + A.sigma * g2;
         project(a0, a1, a2);
         const int q = i9(lx, ly, lz);
         sh.p[0][q] = a0; sh.p[1][q] = a1; sh.p[2][q] = a2;
@@ -184,11 +222,12 @@ __device__ __forceinline__ void cp_block(const CPArgs<S> &A, int64_t b, CPShared
     }
     // ... and on the -1 faces, which the divergence needs
     if (t < 192) {
+        const uint8_t hm = R.hm;
         float uh = sh.u[i10(fx, fy, fz)];
         float g0 = (hm & 2) ? sh.u[i10(fx + 1, fy, fz)] - uh : 0.0f;
         float g1 = (hm & 4) ? sh.u[i10(fx, fy + 1, fz)] - uh : 0.0f;
         float g2 = (hm & 8) ? sh.u[i10(fx, fy, fz + 1)] - uh : 0.0f;
-        h0 = h0 + A.sigma * g0; h1 = h1 + A.sigma * g1; h2 = h2 + A.sigma * g2;
+        float h0 = R.h0 + A.sigma * g0, h1 = R.h1 + A.sigma * g1, h2 = R.h2 + A.sigma * g2;
         project(h0, h1, h2);
         const int q = i9(fx, fy, fz);
         sh.p[0][q] = h0; sh.p[1][q] = h1; sh.p[2][q] = h2;
@@ -200,23 +239,44 @@ __device__ __forceinline__ void cp_block(const CPArgs<S> &A, int64_t b, CPShared
     for (int k = 0; k < VPT; ++k) {
         const int v = t + k * NT, lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
         const int64_t gi = g0i + v;
-        float un = uo[k];
-        if (m[k] & 1) {
+        const uint8_t m = R.m[k];
+        float un = R.uo[k];
+        if (m & 1) {
             const int q = i9(lx, ly, lz);
             const int qx = i9(lx - 1, ly, lz), qy = i9(lx, ly - 1, lz), qz = i9(lx, ly, lz - 1);
             float dv = 0.0f;
-            dv += ((m[k] & 2) ? sh.p[0][q] : 0.0f) - ((sh.m[qx] & 2) ? sh.p[0][qx] : 0.0f);
-            dv += ((m[k] & 4) ? sh.p[1][q] : 0.0f) - ((sh.m[qy] & 4) ? sh.p[1][qy] : 0.0f);
-            dv += ((m[k] & 8) ? sh.p[2][q] : 0.0f) - ((sh.m[qz] & 8) ? sh.p[2][qz] : 0.0f);
-            float ut = uo[k] + A.tau * dv;
-            float tlw = A.tau * A.lambda * wv[k];
-            un = (ut + tlw * fv[k]) / (1.0f + tlw);
+            dv += ((m & 2) ? sh.p[0][q] : 0.0f) - ((sh.m[qx] & 2) ? sh.p[0][qx] : 0.0f);
+            dv += ((m & 4) ? sh.p[1][q] : 0.0f) - ((sh.m[qy] & 4) ? sh.p[1][qy] : 0.0f);
+            dv += ((m & 8) ? sh.p[2][q] : 0.0f) - ((sh.m[qz] & 8) ? sh.p[2][qz] : 0.0f);
+            float ut = R.uo[k] + A.tau * dv;
+            float tlw = A.tau * A.lambda * R.wv[k];
+            un = (ut + tlw * R.fv[k]) / (1.0f + tlw);
         }
-        float ubn = un + A.theta * (un - uo[k]);
+        float ubn = un + A.theta * (un - R.uo[k]);
         A.u[gi] = S::rn(un);
         A.ubar_out[gi] = S::rn(ubn);
         if (kRefine) { A.u32[gi] = un; A.ubar32[gi] = ubn; }
     }
+}
+
+// One fused Chambolle-Pock iteration on block b by NT threads.  t is the
+// thread index (a loop that runs many blocks passes it through an opaque
+// copy so that the per-thread index arithmetic is redone per block instead
+// of being kept live across the loop).
+template <class S, bool kRefine, int NT = 512>
+__device__ __forceinline__ void cp_block(const CPArgs<S> &A, int64_t b, CPShared &sh, int t)
+{
+    CPRegs<NT> R;
+    cp_load<S, NT>(A, b, R, t);
+    cp_compute<S, kRefine, NT>(A, b, R, sh, t);
+}
+
+// threadIdx.x that the compiler cannot hoist out of an enclosing loop
+__device__ __forceinline__ int opaque_tid()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
 }
 
 // Workgroup -> block mapping.  Consecutive workgroups go round-robin to the

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(512) void k_cp_fused(CPArgs<S> A)
     int64_t slot = block_slot(blockIdx.x, A.nb, A.xcd);
     if (slot >= A.nb) return;
     int64_t b = A.order ? A.order[slot] : slot;
-    cp_block<S, kRefine, 512>(A, b, sh);
+    cp_block<S, kRefine, 512>(A, b, sh, threadIdx.x);
 }
 
 // The same iteration with 256 threads per block (two voxels per thread):
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_cp_fused256(CPArgs<S> A)
     int64_t slot = block_slot(blockIdx.x, A.nb, A.xcd);
     if (slot >= A.nb) return;
     int64_t b = A.order ? A.order[slot] : slot;
-    cp_block<S, kRefine, 256>(A, b, sh);
+    cp_block<S, kRefine, 256>(A, b, sh, threadIdx.x);
 }
 
 // ----------------------------------------------------- two-pass variant
