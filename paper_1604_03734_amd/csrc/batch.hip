@@ -41,43 +41,89 @@ struct BatchArgs {
     float sigma, tau, lambda, theta;
     double gamma;             // > 0: accelerated schedule from (tau, sigma)
     double tau0, sigma0;      // schedule state at the start of the launch
-    unsigned *bar;            // [0] arrivals, [1] generation
+    unsigned *bar;            // barrier state, kBarWords words (layout below)
     int32_t *err;             // set when a barrier wait exceeds its bound
     long long spin_limit;
 };
 
-__global__ void k_batch_reset(unsigned *bar, int32_t *err)
+// Barrier state: one 256-byte slot per word that is written concurrently,
+// so arrivals and polls of different groups never share a cache line.
+// slot 0: arrivals of group leaders, slot 1: generation, slot 2: error flag,
+// slots 3 .. 3+kBarMaxGroups-1: arrivals per group, then one release flag
+// per group.
+constexpr int kBarSlot = 64;
+constexpr int kBarGroup = 32;
+constexpr int kBarMaxGroups = 256;
+constexpr int kBarWords = (3 + 2 * kBarMaxGroups) * kBarSlot;
+constexpr int kBarMaxGrid = kBarGroup * kBarMaxGroups;
+
+__global__ void k_batch_reset(unsigned *bar)
 {
-    bar[0] = 0u;
-    bar[1] = 0u;
-    *err = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kBarWords; i += gridDim.x * blockDim.x)
+        bar[i] = 0u;
 }
 
-// Sense-free generation barrier over all workgroups.  Every wait is bounded:
-// after spin_limit polls the error flag is raised and every later barrier
-// returns at once, so the grid always drains.
-__device__ __forceinline__ void grid_barrier(const BatchArgs &a, unsigned nwg)
+// Bounded wait until *word >= target; false (and the error flag raised) if
+// the bound is exceeded or another workgroup already raised it.  The polls
+// are relaxed: an acquiring load invalidates the L2 of its XCD on every
+// poll, which would evict the data of the workgroups still computing; the
+// caller places one acquire fence after the wait instead.
+__device__ __forceinline__ bool wait_at_least(const BatchArgs &a, unsigned *word, unsigned target)
+{
+    long long spins = 0;
+    while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > a.spin_limit) {
+            __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    return true;
+}
+
+// Two-level grid barrier number `target` (1, 2, ... within a launch).
+// Workgroups arrive in groups of kBarGroup; the last arrival of a group
+// (its leader) arrives at the top counter and waits for the generation,
+// the last leader publishes it; each leader then releases its group
+// through the group's own flag.  Every poll and every atomic of one group
+// touches only that group's lines.  Ordering uses explicit agent-scope
+// fences around relaxed atomics: a release fence before each arrival, an
+// acquire fence after each observed arrival or release, so every
+// workgroup's writes of this iteration happen before every read of the
+// next.  Every wait is bounded: past spin_limit polls the error flag is
+// raised and every waiter returns, so the grid always drains.
+__device__ __forceinline__ void grid_barrier(const BatchArgs &a, unsigned nwg, unsigned target)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned g = __hip_atomic_load(&a.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        unsigned prev = __hip_atomic_fetch_add(&a.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == nwg - 1u) {
-            __hip_atomic_store(&a.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&a.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            long long spins = 0;
-            while (__hip_atomic_load(&a.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > a.spin_limit) {
-                    __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
+        const unsigned grp = blockIdx.x / kBarGroup;
+        const unsigned ngrp = (nwg + kBarGroup - 1) / kBarGroup;
+        const unsigned gsize = min(unsigned(kBarGroup), nwg - grp * kBarGroup);
+        unsigned *cnt = a.bar + (3 + grp) * kBarSlot;
+        unsigned *flag = a.bar + (3 + kBarMaxGroups + grp) * kBarSlot;
+        unsigned *top = a.bar;
+        unsigned *gen = a.bar + kBarSlot;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gsize - 1u) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned p2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (p2 == ngrp - 1u) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                (void)wait_at_least(a, gen, target);
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             }
+            __hip_atomic_store(flag, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            (void)wait_at_least(a, flag, target);
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
@@ -191,7 +237,7 @@ __device__ __forceinline__ void k_cp_persistent_body(const BatchArgs &a)
             i = nx;
         }
         }
-        grid_barrier(a, nwg);
+        grid_barrier(a, nwg, unsigned(it + 1));
         if (threadIdx.x == 0)
             s_stop = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
@@ -251,7 +297,7 @@ static int size_bucket(int64_t n)
 // workgroups per CU)
 static void launch_kernel(hipStream_t st, const BatchArgs &a, int grid, int nt)
 {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, a.bar, a.err);
+    hipLaunchKernelGGL(k_batch_reset, dim3(32), dim3(256), 0, st, a.bar);
     if (nt == 256)
         hipLaunchKernelGGL((k_cp_persistent<256, true>), dim3(grid), dim3(256), 0, st, a);
     else if (nt == 257)
@@ -359,7 +405,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     BatchCtx &c = g_batch;
     if ((rc = c.descs.ensure(sizeof(VolDesc) * size_t(n)))) return rc;
     if ((rc = c.items.ensure(sizeof(int2) * size_t(total > 0 ? total : 1)))) return rc;
-    if ((rc = c.state.ensure(64))) return rc;
+    if ((rc = c.state.ensure(sizeof(unsigned) * kBarWords))) return rc;
     std::vector<VolDesc> hd(n);
     for (int i = 0; i < n; ++i) {
         dn_volume *v = vols[i];
@@ -397,7 +443,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     a.tau0 = v0->acc_tau;
     a.sigma0 = v0->acc_sigma;
     a.bar = c.state.as<unsigned>();
-    a.err = reinterpret_cast<int32_t *>(c.state.as<unsigned>() + 4);
+    a.err = reinterpret_cast<int32_t *>(c.state.as<unsigned>() + 2 * kBarSlot);
     a.spin_limit = 1LL << 22;
     a.xcd_chunks = 1;
 
@@ -432,7 +478,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
                         BatchArgs t = a;
                         t.iters = trial;
                         t.xcd_chunks = xcd;
-                        int grid = int(std::min<int64_t>(int64_t(wpc) * dev_cu, total));
+                        int grid = int(std::min<int64_t>({int64_t(wpc) * dev_cu, total, int64_t(kBarMaxGrid)}));
                         DN_HIP(hipEventRecord(e0, st));
                         if ((rc = launch_direct(st, t, grid, nt))) return rc;
                         DN_HIP(hipEventRecord(e1, st));
@@ -462,7 +508,8 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     if ((rc = build_items(ch.pool))) return rc;
     a.iters = prm->iters;
     a.xcd_chunks = ch.xcd;
-    const int grid = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(ch.wg_per_cu) * dev_cu, total)));
+    const int grid = int(std::max<int64_t>(
+        1, std::min<int64_t>({int64_t(ch.wg_per_cu) * dev_cu, total, int64_t(kBarMaxGrid)})));
     hipEvent_t e0, e1;
     DN_HIP(hipEventCreate(&e0));
     DN_HIP(hipEventCreate(&e1));
