@@ -1,13 +1,21 @@
 // Learned warm start: a 3-layer 3x3x3 convolutional network on 10^3 tiles
 // (an 8^3 block plus a one-voxel halo), 2 -> 16 -> 16 -> 1 channels, ReLU,
-// "same" zero padding inside the tile.  Forward, input gradient and weight
-// gradient are implicit GEMMs on the gfx950 matrix cores
-// (v_mfma_f32_16x16x16_bf16: bfloat16 operands, float32 accumulation):
-//   one MFMA = 16 voxels x 16 output channels x 16 input channels of one tap.
-// Activations are stored channel-last in bfloat16, [tile][1000][16], with
-// unused channels zero (layer 1 has 2 inputs, layer 3 one output).
+// "same" zero padding inside the tile.
+//
+// Training path (forward, input gradient, weight gradient): one implicit
+// GEMM launch per layer on v_mfma_f32_16x16x16_bf16 (bfloat16 operands,
+// float32 accumulation; one MFMA = 16 voxels x 16 output channels x 16 input
+// channels of one tap), activations stored channel-last in bfloat16,
+// [tile][1000][16], unused channels zero.
+//
+// Inference path (warm start): one fused launch per axis, k_net_infer, on
+// v_mfma_f32_16x16x32_bf16 with all activations in LDS and the weights in
+// registers.  Its layer loops read one 1 KiB activation operand from LDS per
+// MFMA; at the measured ~140 B/clk of 16-byte LDS reads per CU that bounds
+// it near half the matrix peak.
 #include <cstring>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -331,21 +339,6 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
     p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
 }
 
-// u0 = clamp(f + r, -1, 1) on Omega, 0 elsewhere, for blocks [first, first+n)
-__global__ __launch_bounds__(512) void k_warm_u(const float *__restrict__ f, const uint8_t *__restrict__ emask,
-                                                const float *__restrict__ R, int64_t first, float *__restrict__ u0)
-{
-    const int64_t i = blockIdx.x;
-    const int v = threadIdx.x;
-    const int64_t g = (first + i) * kBlockVox + v;
-    float u = 0.f;
-    if (emask[g] & 1) {
-        u = f[g] + R[i * kT + centre_of(v)];
-        u = u < -1.f ? -1.f : (u > 1.f ? 1.f : u);
-    }
-    u0[g] = u;
-}
-
 // p0 = P(grad(u0) / delta) with the masked forward differences of Eq. (3)
 __global__ __launch_bounds__(512) void k_warm_p(int64_t nb, int64_t ps, const int32_t *__restrict__ nbr,
                                                 const uint8_t *__restrict__ emask, const float *__restrict__ u0,
@@ -366,21 +359,6 @@ __global__ __launch_bounds__(512) void k_warm_p(int64_t nb, int64_t ps, const in
     p0[gi] = g0; p0[gi + ps] = g1; p0[gi + 2 * ps] = g2;
 }
 
-// Dual warm start, axis a: the network ran on tiles whose x axis is the
-// volume's axis a (perm a); its centre output is p_a, kept where m_a = 1.
-__global__ __launch_bounds__(512) void k_warm_pdual(const uint8_t *__restrict__ emask, const float *__restrict__ R,
-                                                    int64_t first, int a, int64_t ps, float *__restrict__ p0)
-{
-    const int64_t i = blockIdx.x;
-    const int v = threadIdx.x;
-    int x = v & 7, y = (v >> 3) & 7, z = v >> 6;
-    if (a == 1) { int s = x; x = y; y = s; }
-    if (a == 2) { int s = x; x = z; z = s; }
-    const int64_t g = (first + i) * kBlockVox + v;
-    const float r = R[i * kT + ((z + 1) * 10 + (y + 1)) * 10 + (x + 1)];
-    p0[a * ps + g] = ((emask[g] >> (a + 1)) & 1) ? r : 0.0f;
-}
-
 // p0 onto the unit ball; u0 = f on Omega, 0 elsewhere
 __global__ void k_warm_finish(int64_t n, int64_t ps, const uint8_t *__restrict__ emask, const float *__restrict__ f,
                               float *__restrict__ p0, float *__restrict__ u0)
@@ -396,7 +374,7 @@ __global__ void k_warm_finish(int64_t n, int64_t ps, const uint8_t *__restrict__
 
 // Process-wide network scratch.
 struct NetCtx {
-    Buf wpack, x0, h1, h2, r, d3, d2, d1, parts, misc, tl;
+    Buf wpack, lanew, x0, h1, h2, r, d3, d2, d1, parts, misc, tl;
 };
 static NetCtx g_net;
 
@@ -405,6 +383,284 @@ static inline unsigned grid1(int64_t n, int bs = 256) { return unsigned((n + bs 
 // offsets of the layers in the canonical 8241-float parameter vector
 constexpr int kW1 = 0, kB1 = 16 * 2 * 27, kW2 = kB1 + 16, kB2 = kW2 + 16 * 16 * 27, kW3 = kB2 + 16,
               kB3 = kW3 + 16 * 27;
+
+// ---------------------------------------------------------------------------
+// Fused inference: gather, three layers and the warm-start epilogue of one
+// tile per iteration of a workgroup, activations in LDS only.  Every layer
+// is an implicit GEMM on v_mfma_f32_16x16x32_bf16 (16 voxels x 16 output
+// channels x 32 products of (tap, input channel)); the weights of all three
+// layers stay in registers for the whole launch.
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+constexpr int kL1M = 2;       // layer 1: 27 taps x 2 channels = 54 of 64 K slots
+constexpr int kL2M = 14;      // layer 2: 27 taps x 16 channels, two taps per MFMA
+constexpr int kL3M = 14;      // layer 3: as layer 2, output column 0 only
+constexpr int kLaneW = (kL1M + kL2M + kL3M) * 64 * 8;
+
+// Lane-ready weights [mfma][lane][8] (bfloat16).  The K slots of lane
+// group g = lane / 16, entry j, of MFMA m: layer 1 -> tap 16m + 4g + j/2,
+// channel j%2; layers 2 and 3 -> tap 2m + g/2, channel 8(g%2) + j.  The
+// output column is lane % 16.  The activation operand uses the same map, so
+// the products pair up whatever order the hardware sums them in.
+__global__ void k_pack_lanes(const float *__restrict__ params, uint16_t *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kLaneW) return;
+    const int j = k & 7, lane = (k >> 3) & 63, m = k >> 9;
+    const int g = lane >> 4, n = lane & 15;
+    float val = 0.f;
+    if (m < kL1M) {
+        const int t = 16 * m + 4 * g + (j >> 1), ci = j & 1;
+        if (t < kTaps) val = params[kW1 + (n * 2 + ci) * kTaps + t];
+    } else {
+        const bool l2 = m < kL1M + kL2M;
+        const int mm = l2 ? m - kL1M : m - kL1M - kL2M;
+        const int t = 2 * mm + (g >> 1), ci = 8 * (g & 1) + j;
+        if (t < kTaps) {
+            if (l2) val = params[kW2 + (n * 16 + ci) * kTaps + t];
+            else if (n == 0) val = params[kW3 + ci * kTaps + t];
+        }
+    }
+    out[k] = f2bf(val);
+}
+
+// LDS activation: two planes of 8 channels, [2][1001][8] bfloat16 (row
+// 1000 of each plane stays zero and stands for every neighbour outside the
+// tile).  The 16 lanes of a 16-byte read take consecutive voxels of one
+// plane, i.e. consecutive 16-byte chunks; the plane stride is 128 modulo
+// 256 bytes, so the same voxels of the two planes fall in opposite halves
+// of the banks.
+constexpr int kPlane = 16256;              // bytes per plane, >= 1001 * 16
+__device__ __forceinline__ int act_byte(int v, int half) { return half * kPlane + v * 16; }
+
+__device__ __forceinline__ v8bf as_v8bf(v4u q) { return __builtin_bit_cast(v8bf, q); }
+
+__host__ __device__ constexpr int tap_off(int t) { return (t % 3 - 1) + 10 * ((t / 3) % 3 - 1) + 100 * (t / 9 - 1); }
+
+// Bit t (tap t = 9 kz + 3 ky + kx) set when the neighbour of tile voxel
+// (x, y, z) through tap t lies inside the 10^3 tile.
+__device__ __forceinline__ uint32_t tap_mask(int x, int y, int z)
+{
+    const uint32_t mx = (x > 0 ? 1u : 0u) | 2u | (x < 9 ? 4u : 0u);
+    const uint32_t my = (y > 0 ? 1u : 0u) | 2u | (y < 9 ? 4u : 0u);
+    const uint32_t mz = (z > 0 ? 1u : 0u) | 2u | (z < 9 ? 4u : 0u);
+    const uint32_t X = mx * 0x01249249u;                       // kx pattern, 9 times
+    const uint32_t ys = ((my & 1u) ? 0x7u : 0u) | ((my & 2u) ? 0x38u : 0u) | ((my & 4u) ? 0x1C0u : 0u);
+    const uint32_t Y = ys * 0x00040201u;                       // 3 times, 9 bits apart
+    const uint32_t Z = ((mz & 1u) ? 0x1FFu : 0u) | ((mz & 2u) ? 0x3FE00u : 0u) | ((mz & 4u) ? 0x7FC0000u : 0u);
+    return X & Y & Z;
+}
+
+__device__ __forceinline__ v4u lds_row(const uint16_t *h, int byte)
+{
+    return *reinterpret_cast<const v4u *>(reinterpret_cast<const char *>(h) + byte);
+}
+
+// A K chain of NM MFMAs whose operands are loaded G at a time, one group
+// ahead of the products that use them, so LDS latency overlaps the matrix
+// work.  a_of(m) returns the activation operand of step m, b_of(m) the
+// weight operand (a register, or an LDS read when kLdsB).
+template <int NM, int G, bool kLdsB, class FA, class FB>
+__device__ __forceinline__ v4f mfma_chain(FA a_of, FB b_of)
+{
+    constexpr int NG = (NM + G - 1) / G;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    v8bf qa[2][G], qb[2][G];
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+        if (k < NM) {
+            qa[0][k] = a_of(k);
+            if constexpr (kLdsB) qb[0][k] = b_of(k);
+        }
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+        __builtin_amdgcn_sched_barrier(0);
+        const int cur = gi & 1;
+        if (gi + 1 < NG) {
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const int m = (gi + 1) * G + k;
+                if (m < NM) {
+                    qa[cur ^ 1][k] = a_of(m);
+                    if constexpr (kLdsB) qb[cur ^ 1][k] = b_of(m);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int m = gi * G + k;
+            if (m < NM) {
+                v8bf bb;
+                if constexpr (kLdsB) bb = qb[cur][k];
+                else bb = b_of(m);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bb, qa[cur][k], acc, 0, 0, 0);
+            }
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    return acc;
+}
+
+// Products are taken as W x A^T, so a lane holds 4 output channels
+// (4g .. 4g+3) of voxel i of the row tile: bias + ReLU, then one 8-byte
+// store per lane.
+__device__ __forceinline__ void store_act(uint16_t *h, int mt, int g, int i, v4f acc, const float *bias4)
+{
+    const int vo = mt * 16 + i;
+    if (vo < kT) {
+        uint16_t y[4];
+        for (int r = 0; r < 4; ++r) {
+            const float a = acc[r] + bias4[r];
+            y[r] = f2bf(a > 0.f ? a : 0.f);
+        }
+        const uint2 pk = make_uint2(uint32_t(y[0]) | (uint32_t(y[1]) << 16), uint32_t(y[2]) | (uint32_t(y[3]) << 16));
+        *reinterpret_cast<uint2 *>(reinterpret_cast<char *>(h) + act_byte(vo, g >> 1) + 8 * (g & 1)) = pk;
+    }
+}
+
+// Layer-1 input of blocks [0, nb): per tile voxel one 32-bit word, the
+// bfloat16 pair (f, log(1 + w) / log(101)), 0 for voxels of unallocated
+// neighbours; perm as in k_gather.
+__global__ void k_gather_pairs(const int32_t *__restrict__ nbr, const float *__restrict__ f,
+                               const float *__restrict__ w, int64_t nb, int perm, uint32_t *__restrict__ xp)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= nb * kT) return;
+    const int64_t b = k / kT;
+    const int v = int(k % kT);
+    int x = v % 10, y = (v / 10) % 10, z = v / 100;
+    if (perm == 1) { const int s = x; x = y; y = s; }
+    if (perm == 2) { const int s = x; x = z; z = s; }
+    const int64_t j = halo_vox(nbr + b * kNbr, x - 1, y - 1, z - 1);
+    float fv = 0.f, wv = 0.f;
+    if (j >= 0) {
+        fv = f[j];
+        wv = float(log(1.0 + double(w[j])) / log(101.0));
+    }
+    xp[k] = uint32_t(f2bf(fv)) | (uint32_t(f2bf(wv)) << 16);
+}
+
+// mode DN_WARM_DUAL: out = p0, component perm written on the centre (kept
+// where m_perm = 1); mode DN_WARM_PRIMAL (perm 0): out = u0 =
+// clamp(f + r, -1, 1) on Omega, 0 elsewhere.  Workgroups loop over tiles;
+// the layer-1 input of the next tile is loaded while the current one is
+// computed.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_net_infer(
+    const uint32_t *__restrict__ xp, const float *__restrict__ f, const uint8_t *__restrict__ emask, int64_t nb,
+    int perm, int mode, const uint16_t *__restrict__ lw, const float *__restrict__ params, int64_t ps,
+    float *__restrict__ out)
+{
+    __shared__ __align__(16) uint16_t h1[2 * kPlane / 2];
+    __shared__ __align__(16) uint16_t h2[2 * kPlane / 2];
+    __shared__ __align__(16) uint32_t x0[kT + 4];
+    __shared__ __align__(16) v4u w3s[kL3M * 4];   // layer-3 weights: column 0 only, per (MFMA, lane group)
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i = lane & 15, g = lane >> 4;
+    const int half = g & 1, par = g >> 1;      // channel half and tap parity of this lane's K slots
+    const v4u *lw4 = reinterpret_cast<const v4u *>(lw);
+    v8bf W1[kL1M], W2[kL2M];
+    for (int m = 0; m < kL1M; ++m) W1[m] = as_v8bf(lw4[m * 64 + lane]);
+    for (int m = 0; m < kL2M; ++m) W2[m] = as_v8bf(lw4[(kL1M + m) * 64 + lane]);
+    if (tid < kL3M * 4) w3s[tid] = lw4[(kL1M + kL2M + (tid >> 2)) * 64 + 16 * (tid & 3)];
+    float bias1[4], bias2[4];
+    for (int r = 0; r < 4; ++r) {
+        bias1[r] = params[kB1 + 4 * g + r];
+        bias2[r] = params[kB2 + 4 * g + r];
+    }
+    const float bias3 = params[kB3];
+    __builtin_amdgcn_s_waitcnt(0);
+    if (tid < 8) reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(h1) + (tid >> 2) * kPlane + kT * 16)[tid & 3] = 0u;
+    if (tid == 0) x0[kT] = 0u;
+
+    const v4u *xp4 = reinterpret_cast<const v4u *>(xp);
+    constexpr int kQ = kT / 4;
+    v4u nxt = {0u, 0u, 0u, 0u};
+    if (blockIdx.x < nb && tid < kQ) nxt = xp4[int64_t(blockIdx.x) * kQ + tid];
+
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        if (tid < kQ) reinterpret_cast<v4u *>(x0)[tid] = nxt;
+        __syncthreads();
+        const int64_t bn = b + gridDim.x;
+        if (bn < nb && tid < kQ) nxt = xp4[bn * kQ + tid];
+
+        // layer 1: 2 -> 16, ReLU
+        for (int mt = wave; mt < kMT; mt += 4) {
+            const int v = mt * 16 + i;
+            const uint32_t ok = v < kT ? tap_mask(v % 10, (v / 10) % 10, v / 100) : 0u;
+            v4u q[kL1M];
+            for (int m = 0; m < kL1M; ++m)
+                for (int e = 0; e < 4; ++e) {
+                    const int t = 16 * m + 4 * g + e;
+                    const int o = (t % 3 - 1) + 10 * ((t / 3) % 3 - 1) + 100 * (t / 9 - 1);
+                    q[m][e] = x0[t < kTaps && ((ok >> t) & 1u) ? v + o : kT];
+                }
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+            for (int m = 0; m < kL1M; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W1[m], as_v8bf(q[m]), acc, 0, 0, 0);
+            store_act(h1, mt, g, i, acc, bias1);
+        }
+        __syncthreads();
+
+        // layer 2: 16 -> 16, ReLU
+        for (int mt = wave; mt < kMT; mt += 4) {
+            const int v = mt * 16 + i;
+            const uint32_t ok = v < kT ? tap_mask(v % 10, (v / 10) % 10, v / 100) : 0u;
+            const v4f acc = mfma_chain<kL2M, 5, false>(
+                [&](int m) {
+                    const int o = par ? tap_off(2 * m + 1) : tap_off(2 * m);
+                    const int nv = ((ok >> (2 * m + par)) & 1u) ? v + o : kT;
+                    return as_v8bf(lds_row(h1, act_byte(nv, half)));
+                },
+                [&](int m) { return W2[m]; });
+            store_act(h2, mt, g, i, acc, bias2);
+        }
+        __syncthreads();
+
+        // layer 3: 16 -> 1 on the centre 8^3 only, then the epilogue
+        for (int mt = wave; mt < 32; mt += 4) {
+            const int c = mt * 16 + i;
+            const int v = ((c / 64 + 1) * 10 + ((c / 8) % 8 + 1)) * 10 + (c % 8 + 1);
+            // tap 27 (past the last) has zero weights: any row will do
+            const v4f acc = mfma_chain<kL3M, 4, true>(
+                [&](int m) {
+                    const int o = par ? (2 * m + 1 < kTaps ? tap_off(2 * m + 1) : 0) : tap_off(2 * m);
+                    return as_v8bf(lds_row(h2, act_byte(v + o, half)));
+                },
+                [&](int m) {
+                    // row 0 of the weight operand; the other rows are zero.
+                    // Only the 4 lanes that hold row 0 read (16 lanes reading
+                    // one 16-byte entry would serialise on its banks).
+                    v4u wb = {0u, 0u, 0u, 0u};
+                    if (i == 0) {
+                        asm volatile("" ::: "memory");
+                        wb = w3s[m * 4 + g];
+                    }
+                    return as_v8bf(wb);
+                });
+            if (g == 0) {
+                // output channel 0 of voxel i: row 0 of the product
+                int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+                if (perm == 1) { const int sw = x; x = y; y = sw; }
+                if (perm == 2) { const int sw = x; x = z; z = sw; }
+                const int64_t gi = b * kBlockVox + x + 8 * y + 64 * z;
+                const float rv = acc[0] + bias3;
+                const uint8_t em = emask[gi];
+                if (mode == DN_WARM_DUAL) {
+                    out[perm * ps + gi] = ((em >> (perm + 1)) & 1) ? rv : 0.f;
+                } else {
+                    float u = 0.f;
+                    if (em & 1) {
+                        u = f[gi] + rv;
+                        u = u < -1.f ? -1.f : (u > 1.f ? 1.f : u);
+                    }
+                    out[gi] = u;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
 
 static int pack_all(hipStream_t st, const float *params, bool with_flipped)
 {
@@ -556,26 +812,25 @@ int dn_net_warm_start(dn_volume *v, const float *params, int32_t mode, double de
     int rc;
     if ((rc = build_masks(v))) return rc;
     if (v->nb == 0) return DN_OK;
-    if ((rc = pack_all(st, params, false))) return rc;
-    const int64_t chunk = 16384;
-    if ((rc = ensure_acts(v->nb < chunk ? v->nb : chunk, false))) return rc;
+    if ((rc = g_net.lanew.ensure(size_t(kLaneW) * 2))) return rc;
+    hipLaunchKernelGGL(k_pack_lanes, dim3(grid1(kLaneW)), dim3(256), 0, st, params, g_net.lanew.as<uint16_t>());
+    DN_HIP(hipGetLastError());
+    int cus = 0;
+    DN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, v->device));
+    // two workgroups fit a compute unit (64 KiB of LDS each); each loops over tiles
+    const unsigned grid = unsigned(std::min<int64_t>(v->nb, int64_t(2) * (cus > 0 ? cus : 1)));
     const int64_t ps = v->nb * int64_t(kBlockVox);
     const int axes = mode == DN_WARM_DUAL ? 3 : 1;
-    for (int a = 0; a < axes; ++a)
-        for (int64_t first = 0; first < v->nb; first += chunk) {
-            const int64_t n = (v->nb - first) < chunk ? (v->nb - first) : chunk;
-            hipLaunchKernelGGL(k_gather, dim3(grid1(n * kT)), dim3(256), 0, st, v->nbr, v->f, v->w,
-                               (const int32_t *)nullptr, first, n, (float *)nullptr, g_net.x0.as<uint16_t>(), a);
-            DN_HIP(hipGetLastError());
-            if ((rc = forward_tiles(st, params, n))) return rc;
-            if (mode == DN_WARM_DUAL)
-                hipLaunchKernelGGL(k_warm_pdual, dim3(unsigned(n)), dim3(512), 0, st, v->emask, g_net.r.as<float>(),
-                                   first, a, ps, p0);
-            else
-                hipLaunchKernelGGL(k_warm_u, dim3(unsigned(n)), dim3(512), 0, st, v->f, v->emask, g_net.r.as<float>(),
-                                   first, u0);
-            DN_HIP(hipGetLastError());
-        }
+    if ((rc = g_net.x0.ensure(size_t(v->nb) * kT * 4))) return rc;
+    uint32_t *xp = g_net.x0.as<uint32_t>();
+    for (int a = 0; a < axes; ++a) {
+        hipLaunchKernelGGL(k_gather_pairs, dim3(grid1(v->nb * kT)), dim3(256), 0, st, v->nbr, v->f, v->w, v->nb, a,
+                           xp);
+        hipLaunchKernelGGL(k_net_infer, dim3(grid), dim3(256), 0, st, xp, v->f, v->emask, v->nb,
+                           mode == DN_WARM_DUAL ? a : 0, int(mode), g_net.lanew.as<uint16_t>(), params, ps,
+                           mode == DN_WARM_DUAL ? p0 : u0);
+        DN_HIP(hipGetLastError());
+    }
     if (mode == DN_WARM_DUAL) {
         hipLaunchKernelGGL(k_warm_finish, dim3(grid1(ps)), dim3(256), 0, st, ps, ps, v->emask, v->f, p0, u0);
         DN_HIP(hipGetLastError());
