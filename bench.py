@@ -286,6 +286,69 @@ def time_to_gap(wl, tol=1e-3, k=100):
     return out
 
 
+# dense matrix peak of the MI355X for bfloat16 operands (TFLOP/s)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+# useful multiply-adds x 2 of the network on one 10^3 tile: layers 1 and 2 on
+# all 1000 voxels, layer 3 on the 512 centre voxels (inference) or on all
+# 1000 (training forward)
+NET_INFER_FLOP_PER_TILE = 2.0 * (1000 * 16 * 54 + 1000 * 16 * 432 + 512 * 432)
+NET_FWD_FLOP_PER_TILE = 2.0 * (1000 * 16 * 54 + 1000 * 16 * 432 + 1000 * 432)
+# training step: forward + weight gradients of 3 layers + input gradients of
+# layers 3 and 2 (layer 1 needs none)
+NET_TRAIN_FLOP_PER_TILE = 2 * NET_FWD_FLOP_PER_TILE + 2.0 * (1000 * 16 * 432 + 1000 * 432)
+
+
+def net_rooflines(wl, reps=3, batch=256, train_steps=20):
+    """Matrix-core throughput of the network, timed with HIP events on the
+    stream the library launches on: the dual warm start of the street map
+    (gather pre-pass, one fused inference launch per axis, projection) and
+    training steps (loss gradient + Adam) on batches of synthetic tiles."""
+    D, torch = wl.D, wl.torch
+    from paper_1604_03734_amd import warmstart
+    w = warmstart.load_default_weights()
+    prm = torch.from_numpy(w if w is not None else warmstart.init_params(0)).cuda()
+    vol = wl.big
+    nb = vol.num_blocks
+    u0 = torch.empty((nb, 512), device="cuda")
+    p0 = torch.empty((3, nb, 512), device="cuda")
+    vol.net_warm_start(prm, u0, p0, mode=D.DN_WARM_DUAL)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        vol.net_warm_start(prm, u0, p0, mode=D.DN_WARM_DUAL)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    tf = NET_INFER_FLOP_PER_TILE * nb * 3 / (ms / 1000.0) / 1e12
+    out = {"inference": {"bound": "mfma", "what": f"dual warm start of the street map: {nb} tiles x 3 axes",
+                         "ms": ms, "achieved": tf, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / MFMA_BF16_PEAK_TFLOPS, "flop_per_tile": NET_INFER_FLOP_PER_TILE}}
+    del u0, p0
+    g = torch.Generator(device="cpu").manual_seed(0)
+    tiles = torch.randn((batch, 2, 10, 10, 10), generator=g).cuda()
+    tgt = torch.randn((batch, 512), generator=g).cuda()
+    msk = (torch.rand((batch, 512), generator=g) < 0.6).float().cuda()
+    p = prm.clone()
+    grad = torch.empty_like(p)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    D.net_loss_grad(tiles, p, tgt, msk, grad, kind=1)
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(train_steps):
+        D.net_loss_grad(tiles, p, tgt, msk, grad, kind=1, sync=False)
+        D.net_adam(p, grad, m, v, 1e-4, k + 1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / train_steps
+    tf = NET_TRAIN_FLOP_PER_TILE * batch / (ms / 1000.0) / 1e12
+    out["training"] = {"bound": "mfma", "what": f"loss gradient + Adam on {batch}-tile batches",
+                       "ms_per_step": ms, "achieved": tf, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": tf / MFMA_BF16_PEAK_TFLOPS, "flop_per_tile": NET_TRAIN_FLOP_PER_TILE}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -387,6 +450,9 @@ def main():
     if args.workload == "street" and not args.profile:
         log("accuracy against the analytic scene ...")
         line["accuracy"] = accuracy(wl)
+    if args.workload == "street" and not args.profile:
+        log("network throughput ...")
+        line["net_roofline"] = net_rooflines(wl)
     if not args.no_gap:
         log("time to gap ...")
         line["time_to_gap"] = time_to_gap(wl)

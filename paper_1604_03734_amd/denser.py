@@ -251,11 +251,13 @@ def net_forward(tiles, params, out, stream=None):
     check(lib().dn_net_forward(_ptr(tiles), tiles.shape[0], _ptr(params), _ptr(out), _stream_handle(stream)))
 
 
-def net_loss_grad(tiles, params, targets, mask, grad, kind=0, stream=None) -> float:
+def net_loss_grad(tiles, params, targets, mask, grad, kind=0, stream=None, sync=True):
+    """Loss (returned when sync, which waits for it) and gradient into grad."""
     loss = ctypes.c_double(0)
     check(lib().dn_net_loss_grad(_ptr(tiles), tiles.shape[0], _ptr(params), _ptr(targets), _ptr(mask),
-                                 int(kind), _ptr(grad), ctypes.byref(loss), _stream_handle(stream)))
-    return loss.value
+                                 int(kind), _ptr(grad), ctypes.byref(loss) if sync else None,
+                                 _stream_handle(stream)))
+    return loss.value if sync else None
 
 
 def net_adam(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
