@@ -548,6 +548,50 @@ static int autotune_single(dn_volume *v, const dn_reg_params *prm, int *choice)
     return zero_state(v);
 }
 
+// The same choice for 16-bit state storage, timed on the 16-bit kernels.
+// It runs only on a state just demoted from FP32 (the trials overwrite the
+// 16-bit buffers, which are then demoted again).
+static std::map<int, AutoChoice> g_auto_lowp;
+
+template <class S> static int autotune_lowp(dn_volume *v, const dn_reg_params *prm, int storage, int *choice)
+{
+    const int key = storage * 64 + size_bucket(v->nb);
+    auto it = g_auto_lowp.find(key);
+    if (it != g_auto_lowp.end()) {
+        *choice = it->second.kernel;
+        v->layout = it->second.layout;
+        return DN_OK;
+    }
+    hipEvent_t e0, e1;
+    DN_HIP(hipEventCreate(&e0));
+    DN_HIP(hipEventCreate(&e1));
+    const int cur = v->cur;
+    float best_ms = 1e30f;
+    AutoChoice best{DN_K_FUSED, 0};
+    const int trial = 6;
+    int rc = DN_OK;
+    for (int k : {DN_K_FUSED, DN_K_FUSED256})
+        for (int layout = 0; layout < 4 && !rc; ++layout) {
+            v->layout = layout;
+            if ((rc = step_lowp<S>(v, prm, false, k))) break;   // warm up
+            DN_HIP(hipEventRecord(e0, v->stream));
+            for (int i = 0; i < trial && !rc; ++i) rc = step_lowp<S>(v, prm, false, k);
+            DN_HIP(hipEventRecord(e1, v->stream));
+            DN_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            DN_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) { best_ms = ms; best = AutoChoice{k, layout}; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    v->cur = cur;
+    if (rc) return rc;
+    g_auto_lowp[key] = best;
+    *choice = best.kernel;
+    v->layout = best.layout;
+    return demote_state<S>(v);
+}
+
 }  // namespace dn
 
 using namespace dn;
@@ -607,6 +651,7 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
         v->acc_sigma = prm->sigma;
     }
     int kernel = prm->kernel;
+    bool fresh16 = false;     // the 16-bit state was just demoted from FP32
     if (storage != DN_F32) {
         if (kernel != DN_K_FUSED256) kernel = DN_K_FUSED;
         if ((rc = ensure_lowp(v))) return rc;
@@ -620,6 +665,20 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
             rc = storage == DN_F16 ? demote_state<SF16>(v) : demote_state<SBF16>(v);
             if (rc) return rc;
             v->state_storage = storage;
+            fresh16 = true;
+        }
+        if (prm->kernel == DN_K_AUTO && v->nb > 0) {
+            if (fresh16) {
+                rc = storage == DN_F16 ? autotune_lowp<SF16>(v, prm, storage, &kernel)
+                                       : autotune_lowp<SBF16>(v, prm, storage, &kernel);
+                if (rc) return rc;
+            } else {
+                auto it = g_auto_lowp.find(storage * 64 + size_bucket(v->nb));
+                if (it != g_auto_lowp.end()) {
+                    kernel = it->second.kernel;
+                    v->layout = it->second.layout;
+                }
+            }
         }
     } else {
         // a 16-bit run always ends with an FP32 sweep: continue from its output
