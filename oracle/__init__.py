@@ -59,6 +59,8 @@ def lib():
             "or_cp": (None, [P, i64, P, P, P, P, P, i32, f64, f64, f64, f64, i32]),
             "or_energy": (None, [P, i64, P, P, P, P, f64, P, i32]),
             "or_cp_accel": (None, [P, i64, P, P, P, P, P, i32, f64, f64, P, i32]),
+            "or_cp_l1": (None, [P, i64, P, P, P, P, P, i32, f64, f64, f64, f64, i32]),
+            "or_energy_l1": (None, [P, i64, P, P, P, P, f64, P, i32]),
             "or_extract": (i64, [P, P, i64, P, P, f64, P, i64]),
             "or_net_forward": (None, [P, i64, P, P, P]),
             "or_net_loss_grad": (f64, [P, i64, P, P, P, P, i32]),
@@ -175,6 +177,26 @@ def energy(nbr, f, w, u, p, lam, nthreads=None):
     lib().or_energy(_p(_c(nbr, np.int32)), nb, _p(_c(f, np.float64)), _p(_c(w, np.float64)),
                     _p(_c(u, np.float64)), _p(_c(p, np.float64)), lam, _p(out),
                     nthreads or nthreads_default())
+    return float(out[0]), float(out[1])
+
+
+def cp_l1(nbr, f, w, u, ubar, p, iters, lam, tau, sigma, theta=1.0, nthreads=None):
+    """In-place iterations of the TV-L1 variant on (u, ubar, p)."""
+    for a in (u, ubar, p):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    nb = len(nbr)
+    lib().or_cp_l1(_p(_c(nbr, np.int32)), nb, _p(_c(f, np.float64)), _p(_c(w, np.float64)),
+                   _p(u), _p(ubar), _p(p), int(iters), lam, tau, sigma, theta,
+                   nthreads or nthreads_default())
+
+
+def energy_l1(nbr, f, w, u, p, lam, nthreads=None):
+    """(E(u), D(p)) of the TV-L1 variant."""
+    out = np.zeros(2)
+    nb = len(nbr)
+    lib().or_energy_l1(_p(_c(nbr, np.int32)), nb, _p(_c(f, np.float64)), _p(_c(w, np.float64)),
+                       _p(_c(u, np.float64)), _p(_c(p, np.float64)), lam, _p(out),
+                       nthreads or nthreads_default())
     return float(out[0]), float(out[1])
 
 

@@ -445,6 +445,93 @@ void or_energy(const int32_t *nbr, int64_t nb, const double *f, const double *w,
 }
 
 /* ---------------------------------------------------------------------
+ * TV-L1 variant of the same framework (the paper names the L1 norm as the
+ * prior of its regulariser, Section III-B; this variant also takes the
+ * data term in L1):
+ *   E(u) = sum_Omega |grad u|_2 + lambda w |u - f|,   u in [-1, 1]
+ * The box is the range of a truncated signed distance; with f in [-1, 1]
+ * it does not change the minimiser (truncating u to [min f, max f] lowers
+ * neither term).  The iteration is or_cp's with the proximal map of
+ * tau lambda w |u - f| + box in place of the quadratic one: a soft
+ * threshold of u~ - f by tau lambda w, then the clamp to [-1, 1] (for a
+ * one-dimensional convex term plus an interval, the proximal map is the
+ * interval projection of the term's proximal map).
+ * ------------------------------------------------------------------- */
+static double shrink(double x, double t) { return x > t ? x - t : (x < -t ? x + t : 0.0); }
+static double clamp1(double x) { return x < -1.0 ? -1.0 : (x > 1.0 ? 1.0 : x); }
+
+void or_cp_l1(const int32_t *nbr, int64_t nb, const double *f, const double *w, double *u,
+              double *ubar, double *p, int32_t iters, double lambda, double tau, double sigma,
+              double theta, int32_t nthreads)
+{
+    int64_t nvox = nb * NVOX;
+    int nt = nthreads > 0 ? nthreads : 1;
+    for (int32_t it = 0; it < iters; ++it) {
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int64_t b = 0; b < nb; ++b)
+            for (int v = 0; v < NVOX; ++v) {
+                double g[3], pt[3];
+                grad_at(nbr, w, ubar, b, v, g);
+                int64_t i0 = b * NVOX + v;
+                for (int a = 0; a < 3; ++a) pt[a] = p[a * nvox + i0] + sigma * g[a];
+                double nrm = sqrt((pt[0] * pt[0] + pt[1] * pt[1]) + pt[2] * pt[2]);
+                double den = nrm > 1.0 ? nrm : 1.0;
+                for (int a = 0; a < 3; ++a) p[a * nvox + i0] = pt[a] / den;
+            }
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int64_t b = 0; b < nb; ++b)
+            for (int v = 0; v < NVOX; ++v) {
+                int64_t i0 = b * NVOX + v;
+                double uo = u[i0], un = uo;
+                if (in_omega(w, i0)) {
+                    double ut = uo + tau * div_at(nbr, w, p, nvox, b, v);
+                    un = clamp1(f[i0] + shrink(ut - f[i0], tau * lambda * w[i0]));
+                }
+                ubar[i0] = un + theta * (un - uo);
+                u[i0] = un;
+            }
+    }
+}
+
+/* Energies of the TV-L1 variant.  The dual is the minimum over u in the box
+ * of the Lagrangian -<u, div p> + lambda sum w |u - f|; per voxel the
+ * minimum of that piecewise linear function of u over [-1, 1] lies at -1,
+ * f or 1:
+ *   D(p) = sum_Omega min(-f d, -d + lambda w |1 - f|, d + lambda w |1 + f|),
+ * d = div p.  out[0] = E, out[1] = D. */
+void or_energy_l1(const int32_t *nbr, int64_t nb, const double *f, const double *w, const double *u,
+                  const double *p, double lambda, double *out, int32_t nthreads)
+{
+    int64_t nvox = nb * NVOX;
+    double *pe = (double *)malloc(sizeof(double) * (size_t)(nb > 0 ? nb : 1));
+    double *pd = (double *)malloc(sizeof(double) * (size_t)(nb > 0 ? nb : 1));
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int64_t b = 0; b < nb; ++b) {
+        double se = 0.0, sd = 0.0;
+        for (int v = 0; v < NVOX; ++v) {
+            int64_t i0 = b * NVOX + v;
+            if (!in_omega(w, i0)) continue;
+            double g[3];
+            grad_at(nbr, w, u, b, v, g);
+            se += sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]) + lambda * w[i0] * fabs(u[i0] - f[i0]);
+            double d = div_at(nbr, w, p, nvox, b, v);
+            double lw = lambda * w[i0];
+            double c0 = -f[i0] * d, c1 = -d + lw * fabs(1.0 - f[i0]), c2 = d + lw * fabs(1.0 + f[i0]);
+            double m = c0 < c1 ? c0 : c1;
+            sd += m < c2 ? m : c2;
+        }
+        pe[b] = se;
+        pd[b] = sd;
+    }
+    double E = 0.0, D = 0.0;
+    for (int64_t b = 0; b < nb; ++b) { E += pe[b]; D += pd[b]; }
+    out[0] = E;
+    out[1] = D;
+    free(pe);
+    free(pd);
+}
+
+/* ---------------------------------------------------------------------
  * Surface extraction (Section II: the zero-crossing level set of the TSDF).
  * For every voxel g and axis a with m_a(g) = 1 and a sign change between
  * u(g) and u(g + e_a) (sign = u < 0), the crossing point
