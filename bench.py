@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--copies", type=int, default=35)
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused256", "twopass"])
+    ap.add_argument("--data-term", default="l2", choices=["l2", "l1"],
+                    help="quadratic data term (the paper's) or the TV-L1 variant")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"],
                     help="storage of u, ubar, p (arithmetic is FP32 in every case)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
@@ -139,7 +141,8 @@ class Workload:
         self.build_map()
         storage = {"f32": D.DN_F32, "f16": D.DN_F16, "bf16": D.DN_BF16}[self.args.storage]
         st = self.big.regularize(D.reg_params(0.5, iters=self.args.iters, gap_every=0, kernel=self.kernel,
-                                              storage=storage, refine_every=50))
+                                              storage=storage, refine_every=50,
+                                              data_term=D.DN_DATA_L1 if getattr(self.args, "data_term", "l2") == "l1" else 0))
         pts = self.big.extract(D.DN_X_SURFACE)
         return st, pts.shape[0]
 
@@ -419,7 +422,8 @@ def main():
                               "synthetic street, 0.2 m voxels, mu 0.6 m, sigma 0.5 px, 5% invalid; "
                               f"map = {args.copies} translated copies of the fused street",
                   "blocks": nb, "voxels": nvox, "street_blocks": wl.street.num_blocks,
-                  "iters": args.iters, "lambda": 0.5, "kernel": args.kernel, "storage": args.storage}
+                  "iters": args.iters, "lambda": 0.5, "kernel": args.kernel, "storage": args.storage,
+                  "data_term": args.data_term}
         kname = "k_cp_fused (one CP iteration)"
     line = {
         "metric": metric,

@@ -112,7 +112,19 @@ typedef struct {
                                 sigma_{n+1} = sigma_n / theta_n, starting
                                 from (tau, sigma); the schedule continues
                                 across calls with DN_INIT_KEEP           */
+    int32_t data_term;       /* DN_DATA_L2: (lambda/2) w (u - f)^2 (Eq. 2 with
+                                the weight of Eq. 8).  DN_DATA_L1: lambda w
+                                |u - f| with u kept in [-1, 1] (the range of
+                                the TSDF); its primal step is a soft threshold
+                                of u~ - f by tau lambda w followed by the
+                                clamp, its dual D(p) = sum over Omega of
+                                min(-f d, -d + lambda w |1 - f|,
+                                d + lambda w |1 + f|), d = div p.  The L1 term
+                                is not uniformly convex: gamma must be 0.  */
 } dn_reg_params;
+
+#define DN_DATA_L2 0
+#define DN_DATA_L1 1
 
 typedef struct {
     double energy;           /* E(u), Eq. (2) with the weight of Eq. (8)      */
@@ -216,9 +228,10 @@ int dn_regularize(dn_volume *vol, const dn_reg_params *params, const float *u0_d
 int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_reg_params *params,
                         dn_reg_stats *out_host);
 
-/* Primal and dual energies of the current state: out_host[0] = E(u),
+/* Primal and dual energies of the current state for the data term
+ * data_term (DN_DATA_L2 or DN_DATA_L1): out_host[0] = E(u),
  * out_host[1] = D(p).  Synchronises. */
-int dn_energy(dn_volume *vol, double lambda, double out_host[2]);
+int dn_energy(dn_volume *vol, double lambda, int32_t data_term, double out_host[2]);
 
 /* -------------------------------------------------------------- extract */
 

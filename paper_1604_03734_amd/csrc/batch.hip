@@ -44,6 +44,7 @@ struct BatchArgs {
     unsigned *bar;            // barrier state, kBarWords words (layout below)
     int32_t *err;             // set when a barrier wait exceeds its bound
     long long spin_limit;
+    int32_t l1;               // L1 data term
 };
 
 // Barrier state: one 256-byte slot per word that is written concurrently,
@@ -157,6 +158,7 @@ __device__ __forceinline__ void item_args(const BatchArgs &a, int2 item, int it,
     A.ubar_in = uni(d.ubar[c]); A.ubar_out = uni(d.ubar[1 - c]);
     A.p_in = uni(d.p[c]); A.p_out = uni(d.p[1 - c]); A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
     A.sigma = sigma; A.tau = tau; A.lambda = a.lambda; A.theta = theta;
+    A.l1 = a.l1;
 }
 
 // All iterations of all sub-maps.  Each workgroup walks its items of an
@@ -271,7 +273,7 @@ struct BatchCtx {
     // key of the captured graph
     const void *k_items = nullptr;
     int64_t k_n = -1;
-    int k_iters = -1, k_grid = -1, k_xcd = -1, k_nt = -1;
+    int k_iters = -1, k_grid = -1, k_xcd = -1, k_nt = -1, k_l1 = -1;
     float k_prm[4] = {0, 0, 0, 0};
     double k_acc[3] = {0, 0, 0};
     const void *vols_ptr = nullptr;
@@ -325,7 +327,7 @@ static int launch_graph(hipStream_t st, const BatchArgs &a, int grid, int nt)
         DN_HIP(hipEventCreateWithFlags(&c.ev_out, hipEventDisableTiming));
     }
     bool same = c.exec && c.k_items == a.items && c.k_n == a.n_items && c.k_iters == a.iters && c.k_grid == grid &&
-                c.k_nt == nt &&
+                c.k_nt == nt && c.k_l1 == a.l1 &&
                 c.k_xcd == a.xcd_chunks && c.k_prm[0] == a.sigma && c.k_prm[1] == a.tau &&
                 c.k_prm[2] == a.lambda && c.k_prm[3] == a.theta && c.vols_ptr == a.vols && c.bar_ptr == a.bar &&
                 c.k_acc[0] == a.gamma && c.k_acc[1] == a.tau0 && c.k_acc[2] == a.sigma0;
@@ -343,6 +345,7 @@ static int launch_graph(hipStream_t st, const BatchArgs &a, int grid, int nt)
         DN_HIP(hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0));
         c.k_items = a.items; c.k_n = a.n_items; c.k_iters = a.iters; c.k_grid = grid; c.k_xcd = a.xcd_chunks;
         c.k_nt = nt;
+        c.k_l1 = a.l1;
         c.k_prm[0] = a.sigma; c.k_prm[1] = a.tau; c.k_prm[2] = a.lambda; c.k_prm[3] = a.theta;
         c.k_acc[0] = a.gamma; c.k_acc[1] = a.tau0; c.k_acc[2] = a.sigma0;
         c.vols_ptr = a.vols; c.bar_ptr = a.bar;
@@ -381,6 +384,9 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     DN_REQUIRE(prm->storage == DN_F32, "the batched solver stores its state in FP32");
     DN_REQUIRE(prm->init == DN_INIT_ZERO || prm->init == DN_INIT_KEEP, "init must be ZERO or KEEP");
     DN_REQUIRE(prm->gamma >= 0 && std::isfinite(prm->gamma), "gamma must be >= 0");
+    DN_REQUIRE(prm->data_term == DN_DATA_L2 || prm->data_term == DN_DATA_L1, "bad data_term");
+    DN_REQUIRE(prm->data_term == DN_DATA_L2 || prm->gamma == 0.0,
+               "the accelerated variant needs the uniformly convex (L2) data term");
     for (int i = 0; i < n; ++i) {
         DN_REQUIRE(vols[i], "null volume %d", i);
         DN_REQUIRE(vols[i]->device == vols[0]->device, "volumes on different devices");
@@ -446,6 +452,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     a.err = reinterpret_cast<int32_t *>(c.state.as<unsigned>() + 2 * kBarSlot);
     a.spin_limit = 1LL << 22;
     a.xcd_chunks = 1;
+    a.l1 = prm->data_term == DN_DATA_L1;
 
     // occupancy bound: every workgroup of the grid must be resident at once
     int dev_cu = 0, per_cu256 = 0, per_cu257 = 0, per_cu512 = 0;
@@ -536,7 +543,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
         hipStream_t keep = v->stream;
         v->stream = st;
         double ed[2] = {0, 0};
-        rc = energy_current(v, prm->lambda, true);
+        rc = energy_current(v, prm->lambda, true, prm->data_term);
         if (!rc) rc = read_energy(v, ed);
         v->stream = keep;
         if (rc) return rc;

@@ -53,6 +53,7 @@ template <class S> struct CPArgs {
     typename S::T *p_out;
     float *u32, *ubar32, *p32;  // FP32 copies written by a refinement sweep
     float sigma, tau, lambda, theta;
+    int32_t l1;                 // data term lambda w |u - f| (with u in [-1, 1]) instead of (lambda/2) w (u - f)^2
 };
 
 __device__ __forceinline__ int i10(int x, int y, int z) { return ((z + 1) * 10 + (y + 1)) * 10 + (x + 1); }
@@ -250,7 +251,14 @@ __device__ __forceinline__ void cp_compute(const CPArgs<S> &A, int64_t b, const 
             dv += ((m & 8) ? sh.p[2][q] : 0.0f) - ((sh.m[qz] & 8) ? sh.p[2][qz] : 0.0f);
             float ut = R.uo[k] + A.tau * dv;
             float tlw = A.tau * A.lambda * R.wv[k];
-            un = (ut + tlw * R.fv[k]) / (1.0f + tlw);
+            if (A.l1) {
+                // soft threshold of u~ - f by tau lambda w, then the [-1, 1] box
+                float r = ut - R.fv[k];
+                r = r > tlw ? r - tlw : (r < -tlw ? r + tlw : 0.0f);
+                un = fminf(fmaxf(R.fv[k] + r, -1.0f), 1.0f);
+            } else {
+                un = (ut + tlw * R.fv[k]) / (1.0f + tlw);
+            }
         }
         float ubn = un + A.theta * (un - R.uo[k]);
         A.u[gi] = S::rn(un);

@@ -110,7 +110,7 @@ namespace dn {
 int build_masks(dn_volume *v);
 int ensure_lowp(dn_volume *v);
 int zero_state(dn_volume *v);
-int energy_current(dn_volume *v, double lambda, bool use_f32);
+int energy_current(dn_volume *v, double lambda, bool use_f32, int data_term);
 int read_energy(dn_volume *v, double out[2]);
 // volume.hip
 int volume_sync(dn_volume *v);

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(512) void k_primal(int64_t nb, int64_t ps, const in
                                                 const uint8_t *__restrict__ emask, const float *__restrict__ p,
                                                 const float *__restrict__ f, const float *__restrict__ w,
                                                 float *__restrict__ u, float *__restrict__ ubar, float tau,
-                                                float lambda, float theta)
+                                                float lambda, float theta, int l1)
 {
     const int64_t b = blockIdx.x;
     if (b >= nb) return;
@@ -96,7 +96,13 @@ __global__ __launch_bounds__(512) void k_primal(int64_t nb, int64_t ps, const in
         }
         float ut = uo + tau * dv;
         float tlw = tau * lambda * w[gi];
-        un = (ut + tlw * f[gi]) / (1.0f + tlw);
+        if (l1) {
+            float r = ut - f[gi];
+            r = r > tlw ? r - tlw : (r < -tlw ? r + tlw : 0.0f);
+            un = fminf(fmaxf(f[gi] + r, -1.0f), 1.0f);
+        } else {
+            un = (ut + tlw * f[gi]) / (1.0f + tlw);
+        }
     }
     u[gi] = un;
     ubar[gi] = un + theta * (un - uo);
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(256) void k_energy_partial(int64_t nb, int64_t ps, 
                                                         const typename S::T *__restrict__ u,
                                                         const typename S::T *__restrict__ p,
                                                         const float *__restrict__ f, const float *__restrict__ w,
-                                                        double lambda, double *__restrict__ partials)
+                                                        double lambda, int l1, double *__restrict__ partials)
 {
     __shared__ float su[729];        // u on [0, 8]^3, index ((z*9)+y)*9+x
     __shared__ float sp[3][729];     // p on [-1, 7]^3, index i9
@@ -217,13 +223,20 @@ __global__ __launch_bounds__(256) void k_energy_partial(int64_t nb, int64_t ps, 
         const double g2 = (m & 8) ? double(su[iu(lx, ly, lz + 1)]) - u0 : 0.0;
         const double fv = f[gi], wv = w[gi];
         const double r = u0 - fv;
-        e += sqrt((g0 * g0 + g1 * g1) + g2 * g2) + 0.5 * lambda * wv * r * r;
+        e += sqrt((g0 * g0 + g1 * g1) + g2 * g2) + (l1 ? lambda * wv * fabs(r) : 0.5 * lambda * wv * r * r);
         const int qx = i9(lx - 1, ly, lz), qy = i9(lx, ly - 1, lz), qz = i9(lx, ly, lz - 1);
         double dv = 0.0;
         dv += ((m & 2) ? double(sp[0][q]) : 0.0) - ((sm[qx] & 2) ? double(sp[0][qx]) : 0.0);
         dv += ((m & 4) ? double(sp[1][q]) : 0.0) - ((sm[qy] & 4) ? double(sp[1][qy]) : 0.0);
         dv += ((m & 8) ? double(sp[2][q]) : 0.0) - ((sm[qz] & 8) ? double(sp[2][qz]) : 0.0);
-        d += -fv * dv - dv * dv / (2.0 * lambda * wv);
+        if (l1) {
+            // minimum over u in [-1, 1] of -u d + lambda w |u - f|: at -1, f or 1
+            const double lw = lambda * wv;
+            const double c0 = -fv * dv, c1 = -dv + lw * fabs(1.0 - fv), c2 = dv + lw * fabs(1.0 + fv);
+            d += fmin(fmin(c0, c1), c2);
+        } else {
+            d += -fv * dv - dv * dv / (2.0 * lambda * wv);
+        }
     }
     e = wave_sum(e);
     d = wave_sum(d);
@@ -319,7 +332,7 @@ int ensure_lowp(dn_volume *v)
 }
 
 template <class S>
-static int energy_launch(dn_volume *v, double lambda, const typename S::T *u, const typename S::T *p)
+static int energy_launch(dn_volume *v, double lambda, int l1, const typename S::T *u, const typename S::T *p)
 {
     hipStream_t st = v->stream;
     const int64_t ps = v->cap_blocks * kBlockVox;
@@ -329,7 +342,7 @@ static int energy_launch(dn_volume *v, double lambda, const typename S::T *u, co
         return DN_OK;
     }
     hipLaunchKernelGGL((k_energy_partial<S>), dim3(unsigned(v->nb)), dim3(256), 0, st, v->nb, ps, v->nbr,
-                       v->emask, u, p, v->f, v->w, lambda, v->partials);
+                       v->emask, u, p, v->f, v->w, lambda, l1, v->partials);
     DN_HIP(hipGetLastError());
     // reduce the per-block pairs level by level (ping-pong inside the scratch
     // that follows the per-block partials) until one pair is left
@@ -351,17 +364,18 @@ static int energy_launch(dn_volume *v, double lambda, const typename S::T *u, co
 }
 
 // Energies of the current state into v->energy2 (device).
-int energy_current(dn_volume *v, double lambda, bool use_f32)
+int energy_current(dn_volume *v, double lambda, bool use_f32, int data_term)
 {
+    const int l1 = data_term == DN_DATA_L1;
     int rc = build_masks(v);
     if (rc) return rc;
     switch (use_f32 ? DN_F32 : v->state_storage) {
     case DN_F16:
-        return energy_launch<SF16>(v, lambda, (const uint16_t *)v->u16, (const uint16_t *)v->p16[v->cur]);
+        return energy_launch<SF16>(v, lambda, l1, (const uint16_t *)v->u16, (const uint16_t *)v->p16[v->cur]);
     case DN_BF16:
-        return energy_launch<SBF16>(v, lambda, (const uint16_t *)v->u16, (const uint16_t *)v->p16[v->cur]);
+        return energy_launch<SBF16>(v, lambda, l1, (const uint16_t *)v->u16, (const uint16_t *)v->p16[v->cur]);
     default:
-        return energy_launch<SF32>(v, lambda, v->u, v->p[v->cur]);
+        return energy_launch<SF32>(v, lambda, l1, v->u, v->p[v->cur]);
     }
 }
 
@@ -392,6 +406,7 @@ static CPArgs<S> make_args(dn_volume *v, const dn_reg_params *prm, typename S::T
     A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
     A.sigma = float(prm->sigma); A.tau = float(prm->tau); A.lambda = float(prm->lambda);
     A.theta = float(prm->theta);
+    A.l1 = prm->data_term == DN_DATA_L1;
     return A;
 }
 
@@ -408,7 +423,7 @@ static int step_f32(dn_volume *v, const dn_reg_params *prm, int kernel)
         DN_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_primal, dim3(unsigned(v->nb)), dim3(512), 0, st, v->nb, ps, v->nbr, v->emask,
                            v->p[v->cur], v->f, v->w, v->u, v->ubar[v->cur], float(prm->tau), float(prm->lambda),
-                           float(prm->theta));
+                           float(prm->theta), int(prm->data_term == DN_DATA_L1));
         DN_HIP(hipGetLastError());
         return DN_OK;
     }
@@ -479,6 +494,9 @@ static int validate(const dn_reg_params *prm)
     DN_REQUIRE(prm->kernel >= DN_K_AUTO && prm->kernel <= DN_K_FUSED256, "bad kernel");
     DN_REQUIRE(prm->refine_every >= 0, "refine_every must be >= 0");
     DN_REQUIRE(prm->gamma >= 0 && std::isfinite(prm->gamma), "gamma must be >= 0");
+    DN_REQUIRE(prm->data_term == DN_DATA_L2 || prm->data_term == DN_DATA_L1, "bad data_term");
+    DN_REQUIRE(prm->data_term == DN_DATA_L2 || prm->gamma == 0.0,
+               "the accelerated variant needs the uniformly convex (L2) data term");
     return DN_OK;
 }
 
@@ -598,10 +616,11 @@ using namespace dn;
 
 extern "C" {
 
-int dn_energy(dn_volume *v, double lambda, double out[2])
+int dn_energy(dn_volume *v, double lambda, int32_t data_term, double out[2])
 {
     DN_REQUIRE(v && out && lambda > 0, "bad argument");
-    int rc = energy_current(v, lambda, false);
+    DN_REQUIRE(data_term == DN_DATA_L2 || data_term == DN_DATA_L1, "bad data_term");
+    int rc = energy_current(v, lambda, false, data_term);
     if (rc) return rc;
     return read_energy(v, out);
 }
@@ -720,7 +739,7 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
         }
         if (rc) return rc;
         if (prm->gap_every > 0 && (it + 1) % prm->gap_every == 0 && it + 1 < prm->iters) {
-            if ((rc = energy_current(v, prm->lambda, false))) return rc;
+            if ((rc = energy_current(v, prm->lambda, false, prm->data_term))) return rc;
             if ((rc = read_energy(v, ed))) return rc;
             double gap = ed[0] - ed[1];
             if (!std::isfinite(gap)) { set_error("non-finite gap at iteration %d", it + 1); return DN_E_NUMERIC; }
@@ -740,7 +759,7 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
     }
     // after a 16-bit run the result is the FP32 output of the last sweep
     const bool f32_result = storage == DN_F32 || (it > 0 && it == prm->iters);
-    if ((rc = energy_current(v, prm->lambda, f32_result))) return rc;
+    if ((rc = energy_current(v, prm->lambda, f32_result, prm->data_term))) return rc;
     if ((rc = read_energy(v, ed))) return rc;
     stats.energy = ed[0];
     stats.dual = ed[1];

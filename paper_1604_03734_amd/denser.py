@@ -25,6 +25,7 @@ DN_K_AUTO, DN_K_TWOPASS, DN_K_FUSED, DN_K_FUSED256 = 0, 1, 2, 3
  DN_X_CANDIDATES, DN_X_EMASK) = range(1, 12)
 NET_PARAMS = 8241
 DN_WARM_PRIMAL, DN_WARM_DUAL = 0, 1
+DN_DATA_L2, DN_DATA_L1 = 0, 1
 
 
 class DenserError(RuntimeError):
@@ -49,7 +50,7 @@ class RegParams(ctypes.Structure):
                 ("theta", ctypes.c_double), ("iters", ctypes.c_int32), ("gap_every", ctypes.c_int32),
                 ("gap_tol", ctypes.c_double), ("storage", ctypes.c_int32),
                 ("refine_every", ctypes.c_int32), ("init", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("gamma", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("data_term", ctypes.c_int32)]
 
 
 class RegStats(ctypes.Structure):
@@ -62,11 +63,12 @@ class RegStats(ctypes.Structure):
 
 
 def reg_params(lam=0.5, tau=None, sigma=None, theta=1.0, iters=200, gap_every=0, gap_tol=0.0,
-               storage=DN_F32, refine_every=50, init=DN_INIT_ZERO, kernel=DN_K_AUTO, gamma=0.0) -> RegParams:
+               storage=DN_F32, refine_every=50, init=DN_INIT_ZERO, kernel=DN_K_AUTO, gamma=0.0,
+               data_term=0) -> RegParams:
     tau = 1.0 / np.sqrt(12.0) if tau is None else tau
     sigma = 1.0 / np.sqrt(12.0) if sigma is None else sigma
     return RegParams(lam, tau, sigma, theta, iters, gap_every, gap_tol, storage, refine_every, init, kernel,
-                     gamma)
+                     gamma, data_term)
 
 
 _lib = None
@@ -94,7 +96,7 @@ def lib():
         "dn_load_fused": (i32, [P, P, P]),
         "dn_regularize": (i32, [P, P, P, P, P]),
         "dn_regularize_batch": (i32, [P, i32, P, P]),
-        "dn_energy": (i32, [P, f64, P]),
+        "dn_energy": (i32, [P, f64, i32, P]),
         "dn_extract": (i32, [P, i32, P, ctypes.c_size_t, P]),
         "dn_net_gather": (i32, [P, P, i64, i32, P]),
         "dn_net_forward": (i32, [P, i64, P, P, P]),
@@ -204,9 +206,9 @@ class Volume:
         check(lib().dn_regularize(self.handle, ctypes.byref(params), _ptr(u0), _ptr(p0), ctypes.byref(st)))
         return st
 
-    def energy(self, lam):
+    def energy(self, lam, data_term=DN_DATA_L2):
         out = (ctypes.c_double * 2)()
-        check(lib().dn_energy(self.handle, lam, out))
+        check(lib().dn_energy(self.handle, lam, int(data_term), out))
         return out[0], out[1]
 
     _SHAPES = {DN_X_COORDS: ("int32", (3,)), DN_X_HASH: ("int32", (4,)), DN_X_NBR: ("int32", (27,)),
