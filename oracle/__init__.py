@@ -62,6 +62,7 @@ def lib():
             "or_cp_l1": (None, [P, i64, P, P, P, P, P, i32, f64, f64, f64, f64, i32]),
             "or_energy_l1": (None, [P, i64, P, P, P, P, f64, P, i32]),
             "or_extract": (i64, [P, P, i64, P, P, f64, P, i64]),
+            "or_mesh": (i64, [P, P, i64, P, P, f64, P, i64, P]),
             "or_net_forward": (None, [P, i64, P, P, P]),
             "or_net_loss_grad": (f64, [P, i64, P, P, P, P, i32]),
             "or_net_gather": (None, [P, P, P, P, i64, P, i32]),
@@ -198,6 +199,22 @@ def energy_l1(nbr, f, w, u, p, lam, nthreads=None):
                        _p(_c(u, np.float64)), _p(_c(p, np.float64)), lam, _p(out),
                        nthreads or nthreads_default())
     return float(out[0]), float(out[1])
+
+
+def mesh(coords, nbr, w, u, s):
+    """Triangles [n][3][3] of the zero level set over fully observed cubes,
+    and their total area."""
+    coords = _c(coords, np.int32).reshape(-1, 3)
+    nb = len(coords)
+    area = np.zeros(1)
+    cap = 1024
+    while True:
+        out = np.zeros((cap, 9))
+        n = lib().or_mesh(_p(coords), _p(_c(nbr, np.int32)), nb, _p(_c(w, np.float64)), _p(_c(u, np.float64)),
+                          float(s), _p(out), cap, _p(area))
+        if n <= cap:
+            return out[:n].reshape(n, 3, 3), float(area[0])
+        cap = n
 
 
 def extract(coords, nbr, w, u, s) -> np.ndarray:

@@ -566,6 +566,119 @@ int64_t or_extract(const int32_t *coords, const int32_t *nbr, int64_t nb, const 
 }
 
 /* ---------------------------------------------------------------------
+ * Triangle mesh of the zero level set (Section II: the surface is the
+ * zero-crossing isosurface of the TSDF; the paper reports its area in
+ * Tables III and IV).  Reading: only cubes whose eight corner voxels are
+ * all observed (in Omega) are meshed.  Each cube (voxel g and g + {0,1}^3,
+ * corner k = x + 2y + 4z) is split into six tetrahedra along its main
+ * diagonal, one per axis order (a0, a1, a2):
+ *   corners 0, e_a0, e_a0 + e_a1, 7,
+ * in the order (0,1,2) (0,2,1) (1,0,2) (1,2,0) (2,0,1) (2,1,0); neighbouring
+ * cubes split their shared faces alike, so the mesh has no cracks.  In a
+ * tetrahedron with vertices q = 0..3 and signs u < 0:
+ *   one vertex alone on its side: one triangle on the edges from it to the
+ *     other three, in increasing q;
+ *   two and two (negative a < b, positive c < d): the triangles
+ *     (ac, ad, bd) and (ac, bd, bc).
+ * An edge point is P_i + t (P_j - P_i), t = u_i / (u_i - u_j), taken from
+ * the lower corner i (smaller k) so every cube computes a shared edge's
+ * point identically; corner positions are (g + offset + 0.5) s.  A triangle
+ * (A, B, C) is turned to (A, C, B) when its normal (B - A) x (C - A) points
+ * against r = n_neg sum(positive corner offsets) - n_pos sum(negative
+ * corner offsets), so normals point to u > 0.  Order: pool id, voxel index,
+ * tetrahedron, triangle.  Writes up to max_out triangles (9 values each),
+ * returns the total number, and the sum of the triangle areas (in that
+ * order) in *area.
+ * ------------------------------------------------------------------- */
+static const int TET_AXES[6][2] = {{0, 1}, {0, 2}, {1, 0}, {1, 2}, {2, 0}, {2, 1}};
+
+static void mesh_edge(const double P[8][3], const double uc[8], int ki, int kj, double out[3])
+{
+    if (ki > kj) { int x = ki; ki = kj; kj = x; }
+    double t = uc[ki] / (uc[ki] - uc[kj]);
+    for (int c = 0; c < 3; ++c) out[c] = P[ki][c] + t * (P[kj][c] - P[ki][c]);
+}
+
+static void mesh_tri(const double P[8][3], const double uc[8], const int kk[4], int e0a, int e0b, int e1a,
+                     int e1b, int e2a, int e2b, const double r[3], double *tris, int64_t *n, int64_t max_out,
+                     double *area)
+{
+    double A[3], B[3], C[3];
+    mesh_edge(P, uc, kk[e0a], kk[e0b], A);
+    mesh_edge(P, uc, kk[e1a], kk[e1b], B);
+    mesh_edge(P, uc, kk[e2a], kk[e2b], C);
+    double ab[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    double ac[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+    double nx = ab[1] * ac[2] - ab[2] * ac[1];
+    double ny = ab[2] * ac[0] - ab[0] * ac[2];
+    double nz = ab[0] * ac[1] - ab[1] * ac[0];
+    int flip = (nx * r[0] + ny * r[1]) + nz * r[2] < 0.0;
+    *area += 0.5 * sqrt((nx * nx + ny * ny) + nz * nz);
+    if (*n < max_out) {
+        double *o = tris + 9 * (*n);
+        for (int c = 0; c < 3; ++c) {
+            o[c] = A[c];
+            o[3 + c] = flip ? C[c] : B[c];
+            o[6 + c] = flip ? B[c] : C[c];
+        }
+    }
+    ++(*n);
+}
+
+int64_t or_mesh(const int32_t *coords, const int32_t *nbr, int64_t nb, const double *w, const double *u,
+                double s, double *tris, int64_t max_out, double *area)
+{
+    int64_t n = 0;
+    double ar = 0.0;
+    for (int64_t b = 0; b < nb; ++b)
+        for (int v = 0; v < NVOX; ++v) {
+            int l[3] = {v % 8, (v / 8) % 8, v / 64};
+            double uc[8], P[8][3];
+            int ok = 1;
+            for (int k = 0; k < 8 && ok; ++k) {
+                int o[3] = {k & 1, (k >> 1) & 1, (k >> 2) & 1};
+                int64_t idx = vox_at(nbr, b, l[0] + o[0], l[1] + o[1], l[2] + o[2]);
+                if (!in_omega(w, idx)) { ok = 0; break; }
+                uc[k] = u[idx];
+                for (int c = 0; c < 3; ++c) P[k][c] = ((double)(8 * coords[3 * b + c] + l[c] + o[c]) + 0.5) * s;
+            }
+            if (!ok) continue;
+            for (int tt = 0; tt < 6; ++tt) {
+                int a0 = TET_AXES[tt][0], a1 = TET_AXES[tt][1];
+                int kk[4] = {0, 1 << a0, (1 << a0) | (1 << a1), 7};
+                int neg[4], nneg = 0;
+                for (int q = 0; q < 4; ++q) { neg[q] = uc[kk[q]] < 0.0; nneg += neg[q]; }
+                if (nneg == 0 || nneg == 4) continue;
+                double r[3] = {0.0, 0.0, 0.0};
+                for (int q = 0; q < 4; ++q)
+                    for (int c = 0; c < 3; ++c) {
+                        double oc = (double)((kk[q] >> c) & 1);
+                        r[c] += neg[q] ? -(double)(4 - nneg) * oc : (double)nneg * oc;
+                    }
+                if (nneg == 1 || nneg == 3) {
+                    int odd = -1, j[3], m = 0;
+                    for (int q = 0; q < 4; ++q)
+                        if (neg[q] == (nneg == 1)) odd = q;
+                    for (int q = 0; q < 4; ++q)
+                        if (q != odd) j[m++] = q;
+                    mesh_tri(P, uc, kk, odd, j[0], odd, j[1], odd, j[2], r, tris, &n, max_out, &ar);
+                } else {
+                    int ng[2], ps[2], mn = 0, mp = 0;
+                    for (int q = 0; q < 4; ++q) {
+                        if (neg[q]) ng[mn++] = q;
+                        else ps[mp++] = q;
+                    }
+                    int a = ng[0], bb = ng[1], c = ps[0], d = ps[1];
+                    mesh_tri(P, uc, kk, a, c, a, d, bb, d, r, tris, &n, max_out, &ar);
+                    mesh_tri(P, uc, kk, a, c, bb, d, bb, c, r, tris, &n, max_out, &ar);
+                }
+            }
+        }
+    *area = ar;
+    return n;
+}
+
+/* ---------------------------------------------------------------------
  * Learned warm start: a 3-layer 3x3x3 convolutional network on a 10^3 tile
  * (an 8^3 block plus a one-voxel halo) with two input channels (fused f and
  * the normalised weight), 16 hidden channels with ReLU, one output channel.
