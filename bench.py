@@ -232,8 +232,9 @@ def cpu_baseline(wl):
 
 def accuracy(wl, iters=500):
     """Synthetic analogue of the paper's error statistics (Section V,
-    Table III): distance of the zero-crossing surface of the street to the
-    analytic scene, before (u = f) and after regularisation."""
+    Tables III and IV): distance of the zero-crossing surface of the street
+    to the analytic scene and area of its mesh, before (u = f) and after
+    regularisation."""
     import scenes
     D, torch = wl.D, wl.torch
     vol = wl.street
@@ -245,11 +246,15 @@ def accuracy(wl, iters=500):
         vol.regularize(prm, u0=u0)
         pts = vol.extract(D.DN_X_SURFACE).cpu().numpy()
         d = scenes.distance_to_scene(pts, boxes) * 100.0
+        area, ntri = vol.mesh_area()
         out[name] = {"points": int(len(pts)), "median_cm": float(np.median(d)),
-                     "p75_cm": float(np.percentile(d, 75)), "mean_cm": float(d.mean())}
+                     "p75_cm": float(np.percentile(d, 75)), "mean_cm": float(d.mean()),
+                     "mesh_area_m2": area, "mesh_triangles": ntri}
     r, g = out["raw"], out["regularised"]
     out["median_change"] = g["median_cm"] / r["median_cm"] - 1.0
+    out["p75_change"] = g["p75_cm"] / r["p75_cm"] - 1.0
     out["points_change"] = g["points"] / r["points"] - 1.0
+    out["area_change"] = g["mesh_area_m2"] / r["mesh_area_m2"] - 1.0
     return out
 
 

@@ -76,6 +76,8 @@ extern "C" {
 #define DN_X_CANDIDATES 10 /* int32 [n][3] distinct block keys the last
                               dn_alloc_blocks frame touched, ascending          */
 #define DN_X_EMASK 11     /* uint8 [n_blocks][512] bit0 Omega, bit1+a m_a     */
+#define DN_X_MESH 12      /* float [n][3][3] triangles of the zero level set of
+                             u (world metres), see dn_extract                */
 
 typedef struct dn_volume dn_volume;
 
@@ -243,8 +245,23 @@ int dn_energy(dn_volume *vol, double lambda, int32_t data_term, double out_host[
  * DN_X_SURFACE: for every voxel g and axis a with both g and g + e_a
  * observed and a sign change (u < 0 differs), the point
  * (g + 0.5) s + t s e_a with t = u(g) / (u(g) - u(g + e_a)), in the order
- * (pool id, voxel index, axis). */
+ * (pool id, voxel index, axis).
+ * DN_X_MESH (Section II: the surface model is the zero-crossing
+ * isosurface; Tables III-IV report its area): triangles over every cube of
+ * voxels g + {0,1}^3 whose eight corners are observed.  The cube (corner
+ * k = x + 2y + 4z) is cut into six tetrahedra along its main diagonal,
+ * corners 0, e_a0, e_a0 + e_a1, 7 for the axis orders (0,1) (0,2) (1,0)
+ * (1,2) (2,0) (2,1); a vertex alone on its side of zero gives one triangle
+ * on its three edges, two and two (negative a < b, positive c < d) give
+ * (ac, ad, bd) and (ac, bd, bc); an edge point is P_i + t (P_j - P_i),
+ * t = u_i / (u_i - u_j), from the corner with the smaller k; normals point
+ * to u > 0.  Order (pool id, voxel, tetrahedron, triangle); float64
+ * arithmetic rounded to float. */
 int dn_extract(dn_volume *vol, int32_t what, void *out_dev, size_t out_bytes, int64_t *n_out);
+
+/* Total area (float64, square metres) of the DN_X_MESH triangles and their
+ * number (n_tris_host may be NULL).  Synchronises. */
+int dn_mesh_area(dn_volume *vol, double *area_host, int64_t *n_tris_host);
 
 /* ---------------------------------------------------- learned warm start */
 /* The network: three 3x3x3 convolutions with "same" zero padding on a

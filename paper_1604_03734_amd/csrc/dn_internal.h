@@ -112,6 +112,7 @@ int ensure_lowp(dn_volume *v);
 int zero_state(dn_volume *v);
 int energy_current(dn_volume *v, double lambda, bool use_f32, int data_term);
 int read_energy(dn_volume *v, double out[2]);
+int reduce_pairs(dn_volume *v, int64_t n);
 // volume.hip
 int volume_sync(dn_volume *v);
 }  // namespace dn

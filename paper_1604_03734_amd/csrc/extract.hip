@@ -94,6 +94,199 @@ __global__ __launch_bounds__(512) void k_surface_write(int64_t nb, const int32_t
     }
 }
 
+// ------------------------------------------------------------------ mesh
+// Zero level set of u as triangles (Section II; Tables III and IV report
+// the area of this surface).  Cubes are voxel g and g + {0,1}^3 (corner
+// k = x + 2y + 4z), meshed only when all eight corners are observed (bit 0
+// of the edge mask).  Each cube is cut into six tetrahedra along its main
+// diagonal, corners 0, e_a0, e_a0 + e_a1, 7 for the axis orders below, so
+// neighbouring cubes cut their shared faces alike.  One vertex alone on
+// its side of zero gives the triangle on its three edges (increasing
+// tetrahedron order); two and two (negative a < b, positive c < d) give
+// (ac, ad, bd) and (ac, bd, bc).  Edge points are taken from the corner
+// with the smaller k, so a shared edge is computed identically everywhere;
+// a triangle is turned when its normal points against r = n_neg *
+// sum(positive offsets) - n_pos * sum(negative offsets).  Double precision
+// throughout; the output rounds to float.  Order: pool id, voxel,
+// tetrahedron, triangle.
+__constant__ int kTetAxes[6][2] = {{0, 1}, {0, 2}, {1, 0}, {1, 2}, {2, 0}, {2, 1}};
+
+struct Cube {
+    double u[8];
+};
+
+__device__ __forceinline__ bool cube_load(const int32_t *nb27, const float *u, const uint8_t *emask, int lx, int ly,
+                                          int lz, Cube &c)
+{
+    for (int k = 0; k < 8; ++k) {
+        const int64_t j = nb_index(nb27, lx + (k & 1), ly + ((k >> 1) & 1), lz + ((k >> 2) & 1));
+        if (j < 0 || !(emask[j] & 1)) return false;
+        c.u[k] = double(u[j]);
+    }
+    return true;
+}
+
+__device__ __forceinline__ int cube_count(const Cube &c)
+{
+    int n = 0;
+    for (int tt = 0; tt < 6; ++tt) {
+        const int a0 = kTetAxes[tt][0], a1 = kTetAxes[tt][1];
+        const int kk[4] = {0, 1 << a0, (1 << a0) | (1 << a1), 7};
+        int nneg = 0;
+        for (int q = 0; q < 4; ++q) nneg += c.u[kk[q]] < 0.0;
+        n += (nneg == 1 || nneg == 3) ? 1 : (nneg == 2 ? 2 : 0);
+    }
+    return n;
+}
+
+// Visit the cube's triangles in order: fn(A, B, C) with the oriented
+// vertices (world metres).
+template <class F>
+__device__ __forceinline__ void cube_triangles(const Cube &c, const int32_t *c4, int lx, int ly, int lz, double s,
+                                               F fn)
+{
+    const int l[3] = {lx, ly, lz};
+    auto pos = [&](int k, int comp) {
+        return (double(8 * c4[comp] + l[comp] + ((k >> comp) & 1)) + 0.5) * s;
+    };
+    auto edge = [&](int ki, int kj, double out[3]) {
+        if (ki > kj) { const int x = ki; ki = kj; kj = x; }
+        const double t = c.u[ki] / (c.u[ki] - c.u[kj]);
+        for (int comp = 0; comp < 3; ++comp) {
+            const double pi = pos(ki, comp), pj = pos(kj, comp);
+            out[comp] = pi + t * (pj - pi);
+        }
+    };
+    for (int tt = 0; tt < 6; ++tt) {
+        const int a0 = kTetAxes[tt][0], a1 = kTetAxes[tt][1];
+        const int kk[4] = {0, 1 << a0, (1 << a0) | (1 << a1), 7};
+        int neg[4], nneg = 0;
+        for (int q = 0; q < 4; ++q) { neg[q] = c.u[kk[q]] < 0.0; nneg += neg[q]; }
+        if (nneg == 0 || nneg == 4) continue;
+        double r[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < 4; ++q)
+            for (int comp = 0; comp < 3; ++comp) {
+                const double oc = double((kk[q] >> comp) & 1);
+                r[comp] += neg[q] ? -double(4 - nneg) * oc : double(nneg) * oc;
+            }
+        auto tri = [&](int e0a, int e0b, int e1a, int e1b, int e2a, int e2b) {
+            double A[3], B[3], C[3];
+            edge(kk[e0a], kk[e0b], A);
+            edge(kk[e1a], kk[e1b], B);
+            edge(kk[e2a], kk[e2b], C);
+            const double ab[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+            const double ac[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+            const double nx = ab[1] * ac[2] - ab[2] * ac[1];
+            const double ny = ab[2] * ac[0] - ab[0] * ac[2];
+            const double nz = ab[0] * ac[1] - ab[1] * ac[0];
+            const bool flip = (nx * r[0] + ny * r[1]) + nz * r[2] < 0.0;
+            const double area = 0.5 * sqrt((nx * nx + ny * ny) + nz * nz);
+            if (flip) fn(A, C, B, area);
+            else fn(A, B, C, area);
+        };
+        if (nneg == 1 || nneg == 3) {
+            int odd = 0, j[3], m = 0;
+            for (int q = 0; q < 4; ++q)
+                if (neg[q] == (nneg == 1)) odd = q;
+            for (int q = 0; q < 4; ++q)
+                if (q != odd) j[m++] = q;
+            tri(odd, j[0], odd, j[1], odd, j[2]);
+        } else {
+            int ng[2], ps[2], mn = 0, mp = 0;
+            for (int q = 0; q < 4; ++q) {
+                if (neg[q]) ng[mn++] = q;
+                else ps[mp++] = q;
+            }
+            tri(ng[0], ps[0], ng[0], ps[1], ng[1], ps[1]);
+            tri(ng[0], ps[0], ng[1], ps[1], ng[1], ps[0]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(512) void k_mesh_count(int64_t nb, const int32_t *__restrict__ nbr,
+                                                    const uint8_t *__restrict__ emask, const float *__restrict__ u,
+                                                    int64_t *__restrict__ counts)
+{
+    __shared__ int wsum[8];
+    const int64_t b = blockIdx.x;
+    const int t = threadIdx.x;
+    Cube c;
+    int n = cube_load(nbr + b * kNbr, u, emask, t & 7, (t >> 3) & 7, t >> 6, c) ? cube_count(c) : 0;
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+    if ((t & 63) == 0) wsum[t >> 6] = n;
+    __syncthreads();
+    if (t == 0) {
+        int sum = 0;
+        for (int i = 0; i < 8; ++i) sum += wsum[i];
+        counts[b] = sum;
+    }
+}
+
+__global__ __launch_bounds__(512) void k_mesh_write(int64_t nb, const int32_t *__restrict__ coords,
+                                                    const int32_t *__restrict__ nbr,
+                                                    const uint8_t *__restrict__ emask, const float *__restrict__ u,
+                                                    const int64_t *__restrict__ offsets, double s,
+                                                    float *__restrict__ out)
+{
+    __shared__ int scan[512];
+    const int64_t b = blockIdx.x;
+    const int t = threadIdx.x, lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+    Cube c;
+    const bool ok = cube_load(nbr + b * kNbr, u, emask, lx, ly, lz, c);
+    const int n = ok ? cube_count(c) : 0;
+    scan[t] = n;
+    __syncthreads();
+    for (int d = 1; d < 512; d <<= 1) {
+        const int v = t >= d ? scan[t - d] : 0;
+        __syncthreads();
+        scan[t] += v;
+        __syncthreads();
+    }
+    if (!ok || n == 0) return;
+    int64_t pos = offsets[b] + scan[t] - n;
+    cube_triangles(c, coords + 4 * b, lx, ly, lz, s, [&](const double *A, const double *B, const double *C, double) {
+        float *o = out + 9 * pos;
+        for (int i = 0; i < 3; ++i) {
+            o[i] = float(A[i]);
+            o[3 + i] = float(B[i]);
+            o[6 + i] = float(C[i]);
+        }
+        ++pos;
+    });
+}
+
+// Per-block (area, triangle count) pairs, float64, fixed order: lanes by
+// xor butterflies, then the 8 wave sums in wave order.
+__global__ __launch_bounds__(512) void k_mesh_area(int64_t nb, const int32_t *__restrict__ coords,
+                                                   const int32_t *__restrict__ nbr,
+                                                   const uint8_t *__restrict__ emask, const float *__restrict__ u,
+                                                   double s, double *__restrict__ partials)
+{
+    __shared__ double wa[8], wn[8];
+    const int64_t b = blockIdx.x;
+    const int t = threadIdx.x, lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+    Cube c;
+    double a = 0.0, n = 0.0;
+    if (cube_load(nbr + b * kNbr, u, emask, lx, ly, lz, c))
+        cube_triangles(c, coords + 4 * b, lx, ly, lz, s, [&](const double *, const double *, const double *,
+                                                             double ar) {
+            a += ar;
+            n += 1.0;
+        });
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        n += __shfl_xor(n, o, 64);
+    }
+    if ((t & 63) == 0) { wa[t >> 6] = a; wn[t >> 6] = n; }
+    __syncthreads();
+    if (t == 0) {
+        double sa = 0.0, sn = 0.0;
+        for (int i = 0; i < 8; ++i) { sa += wa[i]; sn += wn[i]; }
+        partials[2 * b] = sa;
+        partials[2 * b + 1] = sn;
+    }
+}
+
 __global__ void k_fill_zero_i64(int64_t *a) { *a = 0; }
 
 __global__ void k_copy_coords(const int32_t *__restrict__ c4, int64_t nb, int32_t *__restrict__ out)
@@ -164,6 +357,37 @@ extern "C" int dn_extract(dn_volume *v, int32_t what, void *out, size_t out_byte
         DN_HIP(hipStreamSynchronize(st));
         return DN_OK;
     }
+    case DN_X_MESH: {
+        if ((rc = build_masks(v))) return rc;
+        if ((rc = v->s_counts.ensure((nb + 1) * 8))) return rc;
+        if ((rc = v->s_offsets.ensure((nb + 1) * 8))) return rc;
+        int64_t *cnt = v->s_counts.as<int64_t>(), *ofs = v->s_offsets.as<int64_t>();
+        if (nb > 0) {
+            hipLaunchKernelGGL(k_mesh_count, dim3(unsigned(nb)), dim3(512), 0, st, nb, v->nbr, v->emask, v->u, cnt);
+            DN_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_fill_zero_i64, dim3(1), dim3(1), 0, st, cnt + nb);
+        DN_HIP(hipGetLastError());
+        size_t tb = 0;
+        DN_HIP(rocprim::exclusive_scan(nullptr, tb, cnt, ofs, int64_t(0), size_t(nb + 1), rocprim::plus<int64_t>(), st));
+        if ((rc = v->s_tmp.ensure(tb))) return rc;
+        size_t tbytes = v->s_tmp.bytes;
+        DN_HIP(rocprim::exclusive_scan(v->s_tmp.ptr, tbytes, cnt, ofs, int64_t(0), size_t(nb + 1),
+                                       rocprim::plus<int64_t>(), st));
+        if ((rc = v->host.ensure(64))) return rc;
+        DN_HIP(hipMemcpyAsync(v->host.ptr, ofs + nb, 8, hipMemcpyDeviceToHost, st));
+        DN_HIP(hipStreamSynchronize(st));
+        items = v->host.as<int64_t>()[0];
+        need = size_t(items) * 36;
+        *n_out = items;
+        if (items == 0) return DN_OK;
+        if (!out || out_bytes < need) { set_error("output too small: need %zu bytes", need); return DN_E_CAPACITY; }
+        hipLaunchKernelGGL(k_mesh_write, dim3(unsigned(nb)), dim3(512), 0, st, nb, v->coords, v->nbr, v->emask,
+                           v->u, ofs, v->prm.voxel_size, static_cast<float *>(out));
+        DN_HIP(hipGetLastError());
+        DN_HIP(hipStreamSynchronize(st));
+        return DN_OK;
+    }
     default:
         set_error("unknown extract target %d", what);
         return DN_E_INVALID;
@@ -198,5 +422,24 @@ extern "C" int dn_extract(dn_volume *v, int32_t what, void *out, size_t out_byte
         break;
     }
     DN_HIP(hipStreamSynchronize(st));
+    return DN_OK;
+}
+
+// Total area (float64) and number of the mesh's triangles.
+extern "C" int dn_mesh_area(dn_volume *v, double *area, int64_t *n_tris)
+{
+    DN_REQUIRE(v && area, "null argument");
+    int rc;
+    if ((rc = build_masks(v))) return rc;
+    double ed[2] = {0.0, 0.0};
+    if (v->nb > 0) {
+        hipLaunchKernelGGL(k_mesh_area, dim3(unsigned(v->nb)), dim3(512), 0, v->stream, v->nb, v->coords, v->nbr,
+                           v->emask, v->u, v->prm.voxel_size, v->partials);
+        DN_HIP(hipGetLastError());
+        if ((rc = reduce_pairs(v, v->nb))) return rc;
+        if ((rc = read_energy(v, ed))) return rc;
+    }
+    *area = ed[0];
+    if (n_tris) *n_tris = int64_t(ed[1]);
     return DN_OK;
 }

@@ -344,9 +344,15 @@ static int energy_launch(dn_volume *v, double lambda, int l1, const typename S::
     hipLaunchKernelGGL((k_energy_partial<S>), dim3(unsigned(v->nb)), dim3(256), 0, st, v->nb, ps, v->nbr,
                        v->emask, u, p, v->f, v->w, lambda, l1, v->partials);
     DN_HIP(hipGetLastError());
-    // reduce the per-block pairs level by level (ping-pong inside the scratch
-    // that follows the per-block partials) until one pair is left
-    int64_t n = v->nb;
+    return reduce_pairs(v, v->nb);
+}
+
+// Fixed-order sum of the n per-block pairs in v->partials into
+// v->energy2: level by level (ping-pong inside the scratch that follows the
+// per-block partials) until one pair is left.
+int reduce_pairs(dn_volume *v, int64_t n)
+{
+    hipStream_t st = v->stream;
     double *src = v->partials;
     double *bufs[2] = {v->partials + 2 * v->cap_blocks, v->partials + 2 * v->cap_blocks + 2 * ((v->cap_blocks + 1023) / 1024 + 1)};
     int which = 0;

@@ -22,7 +22,7 @@ DN_F32, DN_F16, DN_BF16 = 0, 1, 2
 DN_INIT_ZERO, DN_INIT_KEEP, DN_INIT_GIVEN, DN_INIT_CONTINUE = 0, 1, 2, 3
 DN_K_AUTO, DN_K_TWOPASS, DN_K_FUSED, DN_K_FUSED256 = 0, 1, 2, 3
 (DN_X_COORDS, DN_X_HASH, DN_X_NBR, DN_X_F, DN_X_W, DN_X_U, DN_X_UBAR, DN_X_P, DN_X_SURFACE,
- DN_X_CANDIDATES, DN_X_EMASK) = range(1, 12)
+ DN_X_CANDIDATES, DN_X_EMASK, DN_X_MESH) = range(1, 13)
 NET_PARAMS = 8241
 DN_WARM_PRIMAL, DN_WARM_DUAL = 0, 1
 DN_DATA_L2, DN_DATA_L1 = 0, 1
@@ -97,6 +97,7 @@ def lib():
         "dn_regularize": (i32, [P, P, P, P, P]),
         "dn_regularize_batch": (i32, [P, i32, P, P]),
         "dn_energy": (i32, [P, f64, i32, P]),
+        "dn_mesh_area": (i32, [P, P, P]),
         "dn_extract": (i32, [P, i32, P, ctypes.c_size_t, P]),
         "dn_net_gather": (i32, [P, P, i64, i32, P]),
         "dn_net_forward": (i32, [P, i64, P, P, P]),
@@ -214,7 +215,8 @@ class Volume:
     _SHAPES = {DN_X_COORDS: ("int32", (3,)), DN_X_HASH: ("int32", (4,)), DN_X_NBR: ("int32", (27,)),
                DN_X_F: ("float32", (512,)), DN_X_W: ("float32", (512,)), DN_X_U: ("float32", (512,)),
                DN_X_UBAR: ("float32", (512,)), DN_X_SURFACE: ("float32", (3,)),
-               DN_X_CANDIDATES: ("int32", (3,)), DN_X_EMASK: ("uint8", (512,))}
+               DN_X_CANDIDATES: ("int32", (3,)), DN_X_EMASK: ("uint8", (512,)),
+               DN_X_MESH: ("float32", (3, 3))}
 
     def extract(self, what):
         """Return the requested part as a device tensor."""
@@ -233,6 +235,13 @@ class Volume:
             return out
         check(lib().dn_extract(self.handle, what, _ptr(out), out.numel() * out.element_size(), ctypes.byref(n)))
         return out
+
+    def mesh_area(self):
+        """(area in square metres, number of triangles) of the DN_X_MESH surface."""
+        a = ctypes.c_double(0)
+        n = ctypes.c_int64(0)
+        check(lib().dn_mesh_area(self.handle, ctypes.byref(a), ctypes.byref(n)))
+        return a.value, n.value
 
     # ------------------------------------------------------- warm start
     def net_gather(self, blocks, tiles, perm=0):
