@@ -63,6 +63,8 @@ def lib():
             "or_energy_l1": (None, [P, i64, P, P, P, P, f64, P, i32]),
             "or_extract": (i64, [P, P, i64, P, P, f64, P, i64]),
             "or_mesh": (i64, [P, P, i64, P, P, f64, P, i64, P]),
+            "or_candidates_laser": (i64, [P, i64, P, f64, f64, f64, P, i64]),
+            "or_fuse_laser": (None, [P, i32, i32, i64, P, P, P, i64, P, f64, f64, f64]),
             "or_net_forward": (None, [P, i64, P, P, P]),
             "or_net_loss_grad": (f64, [P, i64, P, P, P, P, i32]),
             "or_net_gather": (None, [P, P, P, P, i64, P, i32]),
@@ -99,6 +101,19 @@ def candidates(depth, K4, T, s, mu, max_depth) -> np.ndarray:
     while True:
         out = np.empty((cap, 3), np.int32)
         n = lib().or_candidates(_p(depth), W, H, _p(K4), _p(T), s, mu, max_depth, _p(out), cap)
+        if n <= cap:
+            return out[:n]
+        cap = int(n)
+
+
+def candidates_laser(pts, T, s, mu, max_depth) -> np.ndarray:
+    """Every block key visited by every valid return's band (with repeats)."""
+    pts = _c(pts, np.float32).reshape(-1, 3)
+    T = _c(T, np.float64)
+    cap = max(1024, len(pts) * 16)
+    while True:
+        out = np.empty((cap, 3), np.int32)
+        n = lib().or_candidates_laser(_p(pts), len(pts), _p(T), s, mu, max_depth, _p(out), cap)
         if n <= cap:
             return out[:n]
         cap = int(n)
@@ -328,6 +343,18 @@ class OracleVolume:
     def fuse(self, depth, K4, T, nthreads=None):
         fuse(self.coords, self.f, self.w, depth, K4, T, self.voxel_size, self.mu,
              self.max_depth, nthreads)
+
+    def alloc_laser(self, pts, T) -> int:
+        c = candidates_laser(pts, T, self.voxel_size, self.mu, self.max_depth)
+        self.last_candidates = _unique_rows(c)
+        return self.insert(self.last_candidates)
+
+    def fuse_laser(self, pts, T):
+        assert self.f.flags["C_CONTIGUOUS"] and self.w.flags["C_CONTIGUOUS"]
+        pts = _c(pts, np.float32).reshape(-1, 3)
+        lib().or_fuse_laser(_p(_c(self.slots, np.int32)), self.cap, self.hash_tail, self.nb, _p(self.f),
+                            _p(self.w), _p(pts), len(pts), _p(_c(T, np.float64)), self.voxel_size, self.mu,
+                            self.max_depth)
 
     def integrate(self, depth, K4, T):
         n = self.alloc(depth, K4, T)

@@ -126,6 +126,174 @@ int64_t or_candidates(const float *depth, int32_t W, int32_t H, const double *K4
 }
 
 /* ---------------------------------------------------------------------
+ * Laser range data, Section III-A: the projective update extends to laser
+ * sensors by updating only the voxels along each ray from the sensor to mu
+ * behind the observed surface.  Readings: a return is a point p in the
+ * sensor frame (T maps sensor to world); its range is r = |p|, valid iff
+ * finite, r > 0 and r <= max_depth; the ray direction is p / r.  Points at
+ * range rho along the ray are computed like the depth path's camera points,
+ * world_i = ((T_i0 (rho d_x) + T_i1 (rho d_y)) + T_i2 (rho d_z)) + T_i3.
+ *   Allocation: the blocks the band segment rho in [max(r - mu, 1e-3),
+ *     r + mu] passes through (the depth path's rule), by the same traversal.
+ *   Fusion: the voxel-grid traversal of rho in [0, r + mu]; a visited voxel
+ *     of an allocated block with centre c gets eta = r - (c - o) . D (o the
+ *     sensor origin, D the world direction) and, if eta >= -mu, the
+ *     observation psi = min(1, eta / mu).  All observations of one scan are
+ *     applied together: with k of them and S their sum (double, in ray
+ *     order), f <- (w f + S) / (w + k), w <- w + k.
+ * ------------------------------------------------------------------- */
+typedef void (*cell_fn)(int64_t x, int64_t y, int64_t z, void *ctx);
+
+/* Amanatides-Woo traversal of the segment a -> b on the unit grid, ties
+ * x before y before z, only axes with steps left stepped (the traversal of
+ * or_candidates).  Returns the number of cells. */
+static int64_t walk_segment(const double a[3], const double b[3], cell_fn fn, void *ctx)
+{
+    for (int i = 0; i < 3; ++i)
+        if (!(fabs(a[i]) < 1e9 && fabs(b[i]) < 1e9)) return 0;
+    int64_t k[3], left[3];
+    int step[3];
+    double tmax[3], tdel[3];
+    for (int i = 0; i < 3; ++i) {
+        k[i] = (int64_t)floor(a[i]);
+        int64_t e = (int64_t)floor(b[i]);
+        double dir = b[i] - a[i];
+        if (e > k[i]) {
+            step[i] = 1; left[i] = e - k[i];
+            tmax[i] = ((double)(k[i] + 1) - a[i]) / dir;
+            tdel[i] = 1.0 / dir;
+        } else if (e < k[i]) {
+            step[i] = -1; left[i] = k[i] - e;
+            tmax[i] = ((double)k[i] - a[i]) / dir;
+            tdel[i] = -1.0 / dir;
+        } else {
+            step[i] = 0; left[i] = 0; tmax[i] = 0.0; tdel[i] = 0.0;
+        }
+    }
+    int64_t n = 0;
+    for (;;) {
+        fn(k[0], k[1], k[2], ctx);
+        ++n;
+        int c = -1;
+        for (int i = 0; i < 3; ++i) {
+            if (left[i] == 0) continue;
+            if (c < 0 || tmax[i] < tmax[c]) c = i;
+        }
+        if (c < 0) break;
+        k[c] += step[c];
+        tmax[c] += tdel[c];
+        left[c] -= 1;
+    }
+    return n;
+}
+
+/* range and unit direction of a return; 0 if invalid */
+static int laser_ray(const float *p, double max_depth, double *r, double d[3])
+{
+    if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) return 0;
+    double x = p[0], y = p[1], z = p[2];
+    double rr = sqrt((x * x + y * y) + z * z);
+    if (!(rr > 0.0 && rr <= max_depth)) return 0;
+    *r = rr;
+    d[0] = x / rr; d[1] = y / rr; d[2] = z / rr;
+    return 1;
+}
+
+static void ray_point(const double *T, const double d[3], double rho, double out[3])
+{
+    for (int i = 0; i < 3; ++i)
+        out[i] = ((T[4 * i + 0] * (rho * d[0]) + T[4 * i + 1] * (rho * d[1])) + T[4 * i + 2] * (rho * d[2])) + T[4 * i + 3];
+}
+
+typedef struct { int32_t *out; int64_t n, max_out; } cand_ctx;
+
+static void cand_cell(int64_t x, int64_t y, int64_t z, void *vc)
+{
+    cand_ctx *c = (cand_ctx *)vc;
+    if (c->n < c->max_out) {
+        c->out[3 * c->n + 0] = (int32_t)x;
+        c->out[3 * c->n + 1] = (int32_t)y;
+        c->out[3 * c->n + 2] = (int32_t)z;
+    }
+    c->n++;
+}
+
+int64_t or_candidates_laser(const float *pts, int64_t n, const double *T, double s, double mu, double max_depth,
+                            int32_t *out, int64_t max_out)
+{
+    cand_ctx c = {out, 0, max_out};
+    const double bs = 8.0 * s;
+    for (int64_t i = 0; i < n; ++i) {
+        double r, d[3], pa[3], pb[3], a[3], b[3];
+        if (!laser_ray(pts + 3 * i, max_depth, &r, d)) continue;
+        double r0 = r - mu;
+        if (r0 < 1e-3) r0 = 1e-3;
+        ray_point(T, d, r0, pa);
+        ray_point(T, d, r + mu, pb);
+        for (int k = 0; k < 3; ++k) { a[k] = pa[k] / bs; b[k] = pb[k] / bs; }
+        walk_segment(a, b, cand_cell, &c);
+    }
+    return c.n;
+}
+
+typedef struct {
+    const int32_t *slots; int32_t cap, tail;
+    double s, mu, r, o[3], D[3];
+    double *sum; int64_t *cnt;
+} fuse_ctx;
+
+int32_t or_hash_find(const int32_t *slots, int32_t cap, int32_t tail, int32_t x, int32_t y, int32_t z);
+
+static void fuse_cell(int64_t x, int64_t y, int64_t z, void *vc)
+{
+    fuse_ctx *c = (fuse_ctx *)vc;
+    int32_t bx = fdiv8((int32_t)x), by = fdiv8((int32_t)y), bz = fdiv8((int32_t)z);
+    int32_t id = or_hash_find(c->slots, c->cap, c->tail, bx, by, bz);
+    if (id < 0) return;
+    double rho = 0.0;
+    double g[3] = {(double)x, (double)y, (double)z};
+    for (int i = 0; i < 3; ++i) rho += ((g[i] + 0.5) * c->s - c->o[i]) * c->D[i];
+    double eta = c->r - rho;
+    if (eta < -c->mu) return;
+    double psi = eta / c->mu;
+    if (psi > 1.0) psi = 1.0;
+    int64_t v = (int64_t)id * NVOX + lin((int)(x - 8 * (int64_t)bx), (int)(y - 8 * (int64_t)by), (int)(z - 8 * (int64_t)bz));
+    c->sum[v] += psi;
+    c->cnt[v] += 1;
+}
+
+void or_fuse_laser(const int32_t *slots, int32_t cap, int32_t tail, int64_t nb, double *f, double *w,
+                   const float *pts, int64_t n, const double *T, double s, double mu, double max_depth)
+{
+    int64_t nv = nb * NVOX;
+    double *sum = (double *)calloc((size_t)(nv > 0 ? nv : 1), sizeof(double));
+    int64_t *cnt = (int64_t *)calloc((size_t)(nv > 0 ? nv : 1), sizeof(int64_t));
+    fuse_ctx c;
+    c.slots = slots; c.cap = cap; c.tail = tail; c.s = s; c.mu = mu; c.sum = sum; c.cnt = cnt;
+    for (int i = 0; i < 3; ++i) {
+        c.o[i] = T[4 * i + 3];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double r, d[3], pa[3], pb[3], a[3], b[3];
+        if (!laser_ray(pts + 3 * i, max_depth, &r, d)) continue;
+        c.r = r;
+        for (int k = 0; k < 3; ++k) c.D[k] = (T[4 * k + 0] * d[0] + T[4 * k + 1] * d[1]) + T[4 * k + 2] * d[2];
+        ray_point(T, d, 0.0, pa);
+        ray_point(T, d, r + mu, pb);
+        for (int k = 0; k < 3; ++k) { a[k] = pa[k] / s; b[k] = pb[k] / s; }
+        walk_segment(a, b, fuse_cell, &c);
+    }
+    for (int64_t v = 0; v < nv; ++v) {
+        if (cnt[v] == 0) continue;
+        double wn = w[v] + (double)cnt[v];
+        f[v] = (w[v] * f[v] + sum[v]) / wn;
+        w[v] = wn;
+    }
+    free(sum);
+    free(cnt);
+}
+
+/* ---------------------------------------------------------------------
  * Spatial hash (the paper cites Teschner et al. and Niessner et al. for
  * the hashing voxel grid without giving a function).  Reading: the
  * Teschner primes XOR-ed over the two's-complement coordinates, masked to
