@@ -294,6 +294,35 @@ def time_to_gap(wl, tol=1e-3, k=100):
     return out
 
 
+def laser_throughput(wl, n_scans=10, rings=64, azimuth=1024):
+    """Laser range fusion on the street (Section III-A's extension to laser
+    sensors): synthetic 64 x 1024 scans every 10 m along the street, each
+    allocated and fused into a fresh volume; returns per second of
+    allocation + fusion (HIP events), inputs resident in HBM."""
+    import scenes
+    D, torch = wl.D, wl.torch
+    boxes = scenes.scene_street(100.0, 0, 2)
+    poses = [scenes.pose_translation(0.0, 0.0, 10.0 * k) for k in range(n_scans)]
+    scans = [torch.from_numpy(scenes.laser_scan(boxes, T, k, n_rings=rings, n_azimuth=azimuth,
+                                                 elev_deg=(-25.0, 3.0), max_range=50.0)).cuda()
+             for k, T in enumerate(poses)]
+    vol = D.Volume(wl.fr.voxel_size, wl.fr.mu, wl.fr.max_depth, 1 << 16, 18, 4096)
+    for pts, T in zip(scans[:2], poses[:2]):
+        vol.integrate_laser(pts, T)
+    vol.clear()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for pts, T in zip(scans, poses):
+        vol.integrate_laser(pts, T)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    n = sum(int(torch.isfinite(p[:, 0]).sum()) for p in scans)
+    return {"scans": n_scans, "returns": n, "blocks": vol.num_blocks, "ms": ms,
+            "returns_per_s": n / (ms / 1000.0)}
+
+
 # dense matrix peak of the MI355X for bfloat16 operands (TFLOP/s)
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 # useful multiply-adds x 2 of the network on one 10^3 tile: layers 1 and 2 on
@@ -460,6 +489,8 @@ def main():
         log("accuracy against the analytic scene ...")
         line["accuracy"] = accuracy(wl)
     if args.workload == "street" and not args.profile:
+        log("laser fusion ...")
+        line["laser_fusion"] = laser_throughput(wl)
         log("network throughput ...")
         line["net_roofline"] = net_rooflines(wl)
     if not args.no_gap:

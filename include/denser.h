@@ -200,6 +200,23 @@ int dn_insert_blocks(dn_volume *vol, const int32_t *coords_dev, int64_t n, int32
 int dn_fuse_depth(dn_volume *vol, const float *depth_dev, const dn_intrinsics *K,
                   const double T_gc[16]);
 
+/* Laser range data (Section III-A: the update extends to laser sensors by
+ * updating only the voxels along each ray from the sensor to mu behind the
+ * observed surface).  pts_dev: float [n][3] returns in the sensor frame,
+ * T_gs row-major sensor-to-world (host).  A return's range is r = |p|,
+ * valid iff finite and 0 < r <= max_depth, its direction p / r.
+ * dn_alloc_laser: allocates the blocks that the band of range
+ * [max(r - mu, 1e-3), r + mu] along each ray passes through (the same
+ * traversal, append order and errors as dn_alloc_blocks).
+ * dn_fuse_laser: every voxel of an allocated block that the ray meets
+ * between the sensor and r + mu, with eta = r - (c - o) . D >= -mu (c the
+ * voxel centre, o the sensor, D the world direction), observes
+ * psi = min(1, eta / mu); one call applies all of its observations
+ * together: f <- (w f + sum psi) / (w + k), w <- w + k (the sum in float64,
+ * in the order of the returns).  Both synchronise. */
+int dn_alloc_laser(dn_volume *vol, const float *pts_dev, int64_t n, const double T_gs[16], int32_t *n_new_out);
+int dn_fuse_laser(dn_volume *vol, const float *pts_dev, int64_t n, const double T_gs[16]);
+
 /* Overwrite f and w of all allocated blocks (device float [n_blocks][512]
  * each); w > 0 marks the voxel as observed (in Omega).  Enqueue only. */
 int dn_load_fused(dn_volume *vol, const float *f_dev, const float *w_dev);

@@ -100,7 +100,7 @@ struct dn_volume {
 
     // scratch for allocation and extraction
     dn::Buf s_cand, s_cand2, s_counts, s_offsets, s_tmp, s_uniq, s_flags, s_new, s_sorted,
-        s_vals, s_vals2, s_home, s_home2, s_pos, s_misc;
+        s_vals, s_vals2, s_home, s_home2, s_pos, s_misc, s_laser;
     int64_t last_nuniq = 0;             // distinct candidates of the last frame
     dn::HostBuf host;
 };

@@ -475,6 +475,212 @@ static int make_geo(const dn_volume *v, const dn_intrinsics *K, const double *T,
     return DN_OK;
 }
 
+// ------------------------------------------------------------------ laser
+// Laser range data (Section III-A: the projective update extends to laser
+// sensors by updating only the voxels along each ray from the sensor to mu
+// behind the observed surface).  A return is a point p in the sensor frame
+// (T: sensor -> world), range r = |p|, valid iff finite, 0 < r <= max_depth,
+// direction d = p / r; the point at range rho is
+// ((T_i0 (rho d_x) + T_i1 (rho d_y)) + T_i2 (rho d_z)) + T_i3.
+//   Allocation: the blocks met by the band rho in [max(r - mu, 1e-3), r + mu].
+//   Fusion: the voxels met by rho in [0, r + mu] in allocated blocks with
+//   eta = r - (c - o) . D >= -mu give psi = min(1, eta / mu); one scan's
+//   observations are applied together, f <- (w f + sum psi) / (w + k),
+//   w <- w + k, the sum in float64 in ray order.
+struct LGeo {
+    double T[16];
+    double s, mu, maxd;
+};
+
+__device__ inline bool laser_ray(const float *p, double maxd, double &r, double d[3])
+{
+    if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) return false;
+    const double x = p[0], y = p[1], z = p[2];
+    const double rr = sqrt((x * x + y * y) + z * z);
+    if (!(rr > 0.0 && rr <= maxd)) return false;
+    r = rr;
+    d[0] = x / rr; d[1] = y / rr; d[2] = z / rr;
+    return true;
+}
+
+__device__ inline void ray_point(const double *T, const double d[3], double rho, double out[3])
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        out[i] = ((T[4 * i + 0] * (rho * d[0]) + T[4 * i + 1] * (rho * d[1])) + T[4 * i + 2] * (rho * d[2])) +
+                 T[4 * i + 3];
+}
+
+// Amanatides-Woo traversal of a -> b on the unit grid (the allocation
+// traversal: ties x before y before z, only axes with steps left).
+template <class Emit>
+__device__ int64_t walk_segment(const double a[3], const double b[3], Emit emit)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (!(fabs(a[i]) < 1e9 && fabs(b[i]) < 1e9)) return 0;
+    int64_t k[3], left[3];
+    int step[3];
+    double tmax[3], tdel[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        k[i] = int64_t(floor(a[i]));
+        const int64_t e = int64_t(floor(b[i]));
+        const double dir = b[i] - a[i];
+        if (e > k[i]) {
+            step[i] = 1; left[i] = e - k[i];
+            tmax[i] = (double(k[i] + 1) - a[i]) / dir;
+            tdel[i] = 1.0 / dir;
+        } else if (e < k[i]) {
+            step[i] = -1; left[i] = k[i] - e;
+            tmax[i] = (double(k[i]) - a[i]) / dir;
+            tdel[i] = -1.0 / dir;
+        } else {
+            step[i] = 0; left[i] = 0; tmax[i] = 0.0; tdel[i] = 0.0;
+        }
+    }
+    int64_t n = 0;
+    for (;;) {
+        emit(n, k[0], k[1], k[2]);
+        ++n;
+        int c = -1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (left[i] == 0) continue;
+            if (c < 0 || tmax[i] < tmax[c]) c = i;
+        }
+        if (c < 0) break;
+        k[c] += step[c];
+        tmax[c] += tdel[c];
+        left[c] -= 1;
+    }
+    return n;
+}
+
+template <class Emit>
+__device__ int64_t laser_band(const LGeo &g, const float *p, Emit emit)
+{
+    double r, d[3], pa[3], pb[3], a[3], b[3];
+    if (!laser_ray(p, g.maxd, r, d)) return 0;
+    double r0 = r - g.mu;
+    if (r0 < 1e-3) r0 = 1e-3;
+    ray_point(g.T, d, r0, pa);
+    ray_point(g.T, d, r + g.mu, pb);
+    const double bs = 8.0 * g.s;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { a[i] = pa[i] / bs; b[i] = pb[i] / bs; }
+    return walk_segment(a, b, emit);
+}
+
+__global__ void k_laser_cand_count(LGeo g, const float *__restrict__ pts, int64_t n, int32_t *__restrict__ counts)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    counts[i] = int32_t(laser_band(g, pts + 3 * i, [](int64_t, int64_t, int64_t, int64_t) {}));
+}
+
+__global__ void k_laser_cand_emit(LGeo g, const float *__restrict__ pts, int64_t n, const int32_t *__restrict__ offsets,
+                                  uint64_t *__restrict__ out, int64_t total)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t base = offsets[i];
+    laser_band(g, pts + 3 * i, [&](int64_t j, int64_t x, int64_t y, int64_t z) {
+        if (base + j < total) out[base + j] = pack_key(int32_t(x), int32_t(y), int32_t(z));
+    });
+}
+
+// The observations of one return: emit(j, voxel index, psi) for each visited
+// voxel of an allocated block with eta >= -mu; returns their number.
+template <class Emit>
+__device__ int64_t laser_obs(const LGeo &g, const float *p, const int4 *slots, int64_t nslots, uint32_t cap,
+                             Emit emit)
+{
+    double r, d[3], pa[3], pb[3], a[3], b[3], D[3];
+    if (!laser_ray(p, g.maxd, r, d)) return 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) D[i] = (g.T[4 * i + 0] * d[0] + g.T[4 * i + 1] * d[1]) + g.T[4 * i + 2] * d[2];
+    ray_point(g.T, d, 0.0, pa);
+    ray_point(g.T, d, r + g.mu, pb);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { a[i] = pa[i] / g.s; b[i] = pb[i] / g.s; }
+    int64_t m = 0;
+    int64_t kb[3] = {INT64_MIN, 0, 0};
+    int32_t id = -1;
+    walk_segment(a, b, [&](int64_t, int64_t x, int64_t y, int64_t z) {
+        const int64_t bx = x >> 3, by = y >> 3, bz = z >> 3;   // floor division
+        if (bx != kb[0] || by != kb[1] || bz != kb[2]) {
+            kb[0] = bx; kb[1] = by; kb[2] = bz;
+            id = hash_lookup(slots, nslots, cap, int32_t(bx), int32_t(by), int32_t(bz));
+        }
+        if (id < 0) return;
+        const double gg[3] = {double(x), double(y), double(z)};
+        double rho = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) rho += ((gg[i] + 0.5) * g.s - g.T[4 * i + 3]) * D[i];
+        const double eta = r - rho;
+        if (eta < -g.mu) return;
+        double psi = eta / g.mu;
+        if (psi > 1.0) psi = 1.0;
+        const int64_t v = int64_t(id) * kBlockVox + ((x - 8 * bx) + 8 * (y - 8 * by) + 64 * (z - 8 * bz));
+        emit(m, v, psi);
+        ++m;
+    });
+    return m;
+}
+
+__global__ void k_laser_obs_count(LGeo g, const float *__restrict__ pts, int64_t n, const int4 *__restrict__ slots,
+                                  int64_t nslots, uint32_t cap, int64_t *__restrict__ counts)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    counts[i] = laser_obs(g, pts + 3 * i, slots, nslots, cap, [](int64_t, int64_t, double) {});
+}
+
+__global__ void k_laser_obs_emit(LGeo g, const float *__restrict__ pts, int64_t n, const int4 *__restrict__ slots,
+                                 int64_t nslots, uint32_t cap, const int64_t *__restrict__ offsets,
+                                 uint32_t *__restrict__ keys, double *__restrict__ vals, int64_t total)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t base = offsets[i];
+    laser_obs(g, pts + 3 * i, slots, nslots, cap, [&](int64_t j, int64_t v, double psi) {
+        if (base + j < total) {
+            keys[base + j] = uint32_t(v);
+            vals[base + j] = psi;
+        }
+    });
+}
+
+// After the stable sort by voxel: the first observation of each voxel sums
+// its run in order and applies the scan's update.
+__global__ void k_laser_apply(const uint32_t *__restrict__ keys, const double *__restrict__ vals, int64_t m,
+                              float *__restrict__ f, float *__restrict__ w)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= m || (i > 0 && keys[i] == keys[i - 1])) return;
+    const uint32_t v = keys[i];
+    double sum = 0.0;
+    int64_t k = 0;
+    for (int64_t j = i; j < m && keys[j] == v; ++j) {
+        sum += vals[j];
+        ++k;
+    }
+    const double w0 = w[v];
+    const double wn = w0 + double(k);
+    f[v] = float((w0 * double(f[v]) + sum) / wn);
+    w[v] = float(wn);
+}
+
+static int make_lgeo(const dn_volume *v, const double *T, LGeo &g)
+{
+    DN_REQUIRE(T, "null pose");
+    for (int i = 0; i < 16; ++i) DN_REQUIRE(std::isfinite(T[i]), "non-finite pose");
+    for (int i = 0; i < 16; ++i) g.T[i] = T[i];
+    g.s = v->prm.voxel_size; g.mu = v->prm.mu; g.maxd = v->prm.max_depth;
+    return DN_OK;
+}
+
 }  // namespace dn
 
 using namespace dn;
@@ -658,6 +864,91 @@ int dn_load_fused(dn_volume *v, const float *f, const float *w)
     size_t bytes = size_t(v->nb) * kBlockVox * 4;
     DN_HIP(hipMemcpyAsync(v->f, f, bytes, hipMemcpyDeviceToDevice, v->stream));
     DN_HIP(hipMemcpyAsync(v->w, w, bytes, hipMemcpyDeviceToDevice, v->stream));
+    v->emask_nb = -1;
+    return DN_OK;
+}
+
+int dn_alloc_laser(dn_volume *v, const float *pts, int64_t n, const double T[16], int32_t *n_new_out)
+{
+    DN_REQUIRE(v && (pts || n == 0) && n >= 0, "bad argument");
+    LGeo g;
+    int rc = make_lgeo(v, T, g);
+    if (rc) return rc;
+    if (n_new_out) *n_new_out = 0;
+    if (n == 0) { v->last_nuniq = 0; return DN_OK; }
+    DN_REQUIRE(n < (int64_t(1) << 31), "too many returns in one scan");
+    hipStream_t st = v->stream;
+    if ((rc = v->s_counts.ensure(n * 4))) return rc;
+    if ((rc = v->s_offsets.ensure(n * 4 + 8))) return rc;
+    int32_t *counts = v->s_counts.as<int32_t>();
+    int32_t *offs = v->s_offsets.as<int32_t>();
+    hipLaunchKernelGGL(k_laser_cand_count, dim3(grid1(n)), dim3(256), 0, st, g, pts, n, counts);
+    DN_HIP(hipGetLastError());
+    size_t tb = 0;
+    DN_HIP(rocprim::exclusive_scan(nullptr, tb, counts, offs, 0, size_t(n), rocprim::plus<int32_t>(), st));
+    if ((rc = v->s_tmp.ensure(tb))) return rc;
+    size_t tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::exclusive_scan(v->s_tmp.ptr, tbytes, counts, offs, 0, size_t(n), rocprim::plus<int32_t>(), st));
+    if ((rc = v->host.ensure(64))) return rc;
+    DN_HIP(hipMemcpyAsync(v->host.as<int32_t>(), offs + n - 1, 4, hipMemcpyDeviceToHost, st));
+    DN_HIP(hipMemcpyAsync(v->host.as<int32_t>() + 1, counts + n - 1, 4, hipMemcpyDeviceToHost, st));
+    DN_HIP(hipStreamSynchronize(st));
+    const int64_t total = int64_t(v->host.as<int32_t>()[0]) + v->host.as<int32_t>()[1];
+    if (total == 0) { v->last_nuniq = 0; return DN_OK; }
+    if ((rc = v->s_cand.ensure(total * 8))) return rc;
+    hipLaunchKernelGGL(k_laser_cand_emit, dim3(grid1(n)), dim3(256), 0, st, g, pts, n, offs,
+                       v->s_cand.as<uint64_t>(), total);
+    DN_HIP(hipGetLastError());
+    return insert_packed(v, v->s_cand.as<uint64_t>(), total, n_new_out);
+}
+
+int dn_fuse_laser(dn_volume *v, const float *pts, int64_t n, const double T[16])
+{
+    DN_REQUIRE(v && (pts || n == 0) && n >= 0, "bad argument");
+    LGeo g;
+    int rc = make_lgeo(v, T, g);
+    if (rc) return rc;
+    if (n == 0 || v->nb == 0) return DN_OK;
+    DN_REQUIRE(v->nb * int64_t(kBlockVox) < (int64_t(1) << 32), "volume too large for 32-bit voxel keys");
+    hipStream_t st = v->stream;
+    const int4 *slots = reinterpret_cast<const int4 *>(v->hash[v->cur_hash]);
+    if ((rc = v->s_counts.ensure(n * 8))) return rc;
+    if ((rc = v->s_offsets.ensure(n * 8 + 8))) return rc;
+    int64_t *counts = v->s_counts.as<int64_t>();
+    int64_t *offs = v->s_offsets.as<int64_t>();
+    hipLaunchKernelGGL(k_laser_obs_count, dim3(grid1(n)), dim3(256), 0, st, g, pts, n, slots, v->hash_slots,
+                       v->hash_cap, counts);
+    DN_HIP(hipGetLastError());
+    size_t tb = 0;
+    DN_HIP(rocprim::exclusive_scan(nullptr, tb, counts, offs, int64_t(0), size_t(n), rocprim::plus<int64_t>(), st));
+    if ((rc = v->s_tmp.ensure(tb))) return rc;
+    size_t tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::exclusive_scan(v->s_tmp.ptr, tbytes, counts, offs, int64_t(0), size_t(n),
+                                   rocprim::plus<int64_t>(), st));
+    if ((rc = v->host.ensure(64))) return rc;
+    DN_HIP(hipMemcpyAsync(v->host.as<int64_t>(), offs + n - 1, 8, hipMemcpyDeviceToHost, st));
+    DN_HIP(hipMemcpyAsync(v->host.as<int64_t>() + 1, counts + n - 1, 8, hipMemcpyDeviceToHost, st));
+    DN_HIP(hipStreamSynchronize(st));
+    const int64_t m = v->host.as<int64_t>()[0] + v->host.as<int64_t>()[1];
+    if (m == 0) return DN_OK;
+    // keys and values, then their sorted copies
+    if ((rc = v->s_laser.ensure(size_t(m) * 24 * 2 + 256))) return rc;
+    uint32_t *k_in = reinterpret_cast<uint32_t *>(v->s_laser.ptr);
+    uint32_t *k_out = k_in + m;
+    double *v_in = reinterpret_cast<double *>(static_cast<char *>(v->s_laser.ptr) + ((size_t(m) * 8 + 255) / 256) * 256);
+    double *v_out = v_in + m;
+    hipLaunchKernelGGL(k_laser_obs_emit, dim3(grid1(n)), dim3(256), 0, st, g, pts, n, slots, v->hash_slots,
+                       v->hash_cap, offs, k_in, v_in, m);
+    DN_HIP(hipGetLastError());
+    int bits = 1;
+    while ((int64_t(1) << bits) < v->nb * int64_t(kBlockVox)) ++bits;
+    tb = 0;
+    DN_HIP(rocprim::radix_sort_pairs(nullptr, tb, k_in, k_out, v_in, v_out, size_t(m), 0, bits, st));
+    if ((rc = v->s_tmp.ensure(tb))) return rc;
+    tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::radix_sort_pairs(v->s_tmp.ptr, tbytes, k_in, k_out, v_in, v_out, size_t(m), 0, bits, st));
+    hipLaunchKernelGGL(k_laser_apply, dim3(grid1(m)), dim3(256), 0, st, k_out, v_out, m, v->f, v->w);
+    DN_HIP(hipGetLastError());
     v->emask_nb = -1;
     return DN_OK;
 }

@@ -93,6 +93,8 @@ def lib():
         "dn_alloc_blocks": (i32, [P, P, P, P, P]),
         "dn_insert_blocks": (i32, [P, P, i64, P]),
         "dn_fuse_depth": (i32, [P, P, P, P]),
+        "dn_alloc_laser": (i32, [P, P, i64, P, P]),
+        "dn_fuse_laser": (i32, [P, P, i64, P]),
         "dn_load_fused": (i32, [P, P, P]),
         "dn_regularize": (i32, [P, P, P, P, P]),
         "dn_regularize_batch": (i32, [P, i32, P, P]),
@@ -197,6 +199,22 @@ class Volume:
     def integrate(self, depth, K: Intrinsics, T) -> int:
         n = self.alloc_blocks(depth, K, T)
         self.fuse_depth(depth, K, T)
+        return n
+
+    def alloc_laser(self, pts, T) -> int:
+        """pts: device float [n][3] returns in the sensor frame; T: sensor -> world."""
+        n = ctypes.c_int32(0)
+        _, tp = _pose(T)
+        check(lib().dn_alloc_laser(self.handle, _ptr(pts), pts.shape[0], tp, ctypes.byref(n)))
+        return n.value
+
+    def fuse_laser(self, pts, T):
+        _, tp = _pose(T)
+        check(lib().dn_fuse_laser(self.handle, _ptr(pts), pts.shape[0], tp))
+
+    def integrate_laser(self, pts, T) -> int:
+        n = self.alloc_laser(pts, T)
+        self.fuse_laser(pts, T)
         return n
 
     def load_fused(self, f, w):

@@ -136,6 +136,36 @@ def render_depth(boxes, cam: Camera, pose, rng: np.random.Generator,
     return np.where(ok, Zn, 0.0).astype(np.float32)
 
 
+def laser_scan(boxes: np.ndarray, pose: np.ndarray, seed: int, n_rings: int = 16, n_azimuth: int = 360,
+               elev_deg=(-15.0, 15.0), sigma_m: float = 0.01, max_range: float = 50.0) -> np.ndarray:
+    """A spinning range scanner at `pose` (sensor -> world; the sensor looks
+    along +z, rings spread in elevation about the sensor x axis, azimuth
+    about its y axis): float32 [n_rings * n_azimuth][3] returns in the
+    sensor frame, range noise N(0, sigma_m) along the ray; returns with no
+    hit or beyond max_range are NaN."""
+    rng = np.random.default_rng(np.random.SeedSequence([11, seed]))
+    el = np.deg2rad(np.linspace(elev_deg[0], elev_deg[1], n_rings))
+    az = np.linspace(-np.pi, np.pi, n_azimuth, endpoint=False)
+    E, A = np.meshgrid(el, az, indexing="ij")
+    ds = np.stack([np.cos(E) * np.sin(A), -np.sin(E), np.cos(E) * np.cos(A)], -1).reshape(-1, 3)
+    dw = ds @ pose[:3, :3].T
+    o = pose[:3, 3]
+    best = np.full(len(ds), np.inf)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / dw
+        for lo, hi in boxes:
+            t0 = (lo - o) * inv
+            t1 = (hi - o) * inv
+            tn = np.nanmax(np.minimum(t0, t1), axis=-1)
+            tf = np.nanmin(np.maximum(t0, t1), axis=-1)
+            hit = (tn <= tf) & (tn > 1e-6) & (tn < best)
+            best = np.where(hit, tn, best)
+    r = best + rng.normal(0.0, sigma_m, size=best.shape)
+    ok = np.isfinite(best) & (r > 0) & (r <= max_range)
+    pts = np.where(ok[:, None], ds * np.where(ok, r, 0.0)[:, None], np.nan)
+    return pts.astype(np.float32)
+
+
 def _box(lo, hi):
     return np.array([lo, hi], dtype=np.float64)
 
