@@ -162,6 +162,19 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, c
     }
 }
 
+// First level of the partial reduction: chunk c of the partials (parts
+// [c*per, (c+1)*per)) summed in order, per entry, into out[c][...].
+__global__ void k_sum_parts(const float *__restrict__ partials, int nparts, int per, float *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (k >= kWPack + kC) return;
+    float s = 0.f;
+    const int p1 = min(nparts, (c + 1) * per);
+    for (int p = c * per; p < p1; ++p) s += partials[int64_t(p) * (kWPack + kC) + k];
+    out[int64_t(c) * (kWPack + kC) + k] = s;
+}
+
 // Sum the per-workgroup partials (fixed order) into the canonical parameter
 // layout W[co][ci][tap], b[co] of a layer with cout x cin real channels.
 __global__ void k_grad_reduce(const float *__restrict__ partials, int nparts, int cout, int cin,
@@ -266,11 +279,30 @@ __global__ void k_gather(const int32_t *__restrict__ nbr, const float *__restric
 
 __device__ __forceinline__ int centre_of(int v) { return ((v / 64 + 1) * 10 + ((v / 8) % 8 + 1)) * 10 + (v % 8 + 1); }
 
-__global__ void k_mask_count(const float *__restrict__ mask, int64_t n, double *__restrict__ out)
+// Number of mask entries set: workgroup g sums its 4096-entry chunk in a
+// fixed order (thread-strided, then a tree) into part[g]; then one
+// workgroup sums the parts in order.
+__global__ void k_mask_part(const float *__restrict__ mask, int64_t n, double *__restrict__ part)
+{
+    __shared__ double s[256];
+    const int64_t base = int64_t(blockIdx.x) * 4096;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < 4096; k += 256)
+        if (base + k < n) acc += mask[base + k];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void k_mask_count(const double *__restrict__ part, int64_t nparts, double *__restrict__ out)
 {
     __shared__ double s[256];
     double acc = 0.0;
-    for (int64_t k = threadIdx.x; k < n; k += 256) acc += mask[k];
+    for (int64_t k = threadIdx.x; k < nparts; k += 256) acc += part[k];
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -374,7 +406,7 @@ __global__ void k_warm_finish(int64_t n, int64_t ps, const uint8_t *__restrict__
 
 // Process-wide network scratch.
 struct NetCtx {
-    Buf wpack, lanew, x0, h1, h2, r, d3, d2, d1, parts, misc, tl;
+    Buf wpack, lanew, x0, h1, h2, r, d3, d2, d1, parts, chunks, mparts, misc, tl;
 };
 static NetCtx g_net;
 
@@ -752,6 +784,11 @@ int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const f
     if ((rc = pack_all(st, params, true))) return rc;
     const int nparts = int(n < 512 ? n : 512);
     if ((rc = g_net.parts.ensure(size_t(nparts) * (kWPack + kC) * 4))) return rc;
+    // the partials are summed in chunks of `per`, then the chunk sums
+    const int per = 16, nchunks = (nparts + per - 1) / per;
+    if ((rc = g_net.chunks.ensure(size_t(nchunks) * (kWPack + kC) * 4))) return rc;
+    float *chunks = g_net.chunks.as<float>();
+    const dim3 cgrid(grid1(kWPack + kC), unsigned(nchunks));
     if ((rc = g_net.misc.ensure(64))) return rc;
     if ((rc = g_net.tl.ensure(size_t(n) * 8))) return rc;
     uint16_t *x0 = g_net.x0.as<uint16_t>(), *h1 = g_net.h1.as<uint16_t>(), *h2 = g_net.h2.as<uint16_t>();
@@ -762,26 +799,32 @@ int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const f
     hipLaunchKernelGGL(k_tiles_to_bf16, dim3(grid1(n * kT)), dim3(256), 0, st, tiles, n, x0);
     DN_HIP(hipGetLastError());
     if ((rc = forward_tiles(st, params, n))) return rc;
-    hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(256), 0, st, mask, n * 512, cnt);
+    const int64_t nmask = (n * 512 + 4095) / 4096;
+    if ((rc = g_net.mparts.ensure(size_t(nmask) * 8))) return rc;
+    hipLaunchKernelGGL(k_mask_part, dim3(unsigned(nmask)), dim3(256), 0, st, mask, n * 512, g_net.mparts.as<double>());
+    hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(256), 0, st, g_net.mparts.as<double>(), nmask, cnt);
     hipLaunchKernelGGL(k_loss, dim3(unsigned(n)), dim3(512), 0, st, tiles, g_net.r.as<float>(), targets, mask, cnt, n,
                        int(kind), d3, g_net.tl.as<double>());
     hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, st, g_net.tl.as<double>(), n, lsum);
     DN_HIP(hipGetLastError());
     // layer 3: weights from (h2, d3); input gradient d2 = conv(d3, W3 flipped) * [h2 > 0]
     hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, st, h2, d3, n, parts);
-    hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 27 + 1)), dim3(256), 0, st, parts, nparts, 1, 16,
+    hipLaunchKernelGGL(k_sum_parts, cgrid, dim3(256), 0, st, parts, nparts, per, chunks);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 27 + 1)), dim3(256), 0, st, chunks, nchunks, 1, 16,
                        grad + kW3, grad + kB3);
     hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, d3, n, wp + 4 * kWPack, (const float *)nullptr, 0,
                        h2, d2, (float *)nullptr);
     // layer 2
     hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, st, h1, d2, n, parts);
-    hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 16 * 27 + 16)), dim3(256), 0, st, parts, nparts, 16, 16,
+    hipLaunchKernelGGL(k_sum_parts, cgrid, dim3(256), 0, st, parts, nparts, per, chunks);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 16 * 27 + 16)), dim3(256), 0, st, chunks, nchunks, 16, 16,
                        grad + kW2, grad + kB2);
     hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, d2, n, wp + 3 * kWPack, (const float *)nullptr, 0,
                        h1, d1, (float *)nullptr);
     // layer 1
     hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, st, x0, d1, n, parts);
-    hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 2 * 27 + 16)), dim3(256), 0, st, parts, nparts, 16, 2,
+    hipLaunchKernelGGL(k_sum_parts, cgrid, dim3(256), 0, st, parts, nparts, per, chunks);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 2 * 27 + 16)), dim3(256), 0, st, chunks, nchunks, 16, 2,
                        grad + kW1, grad + kB1);
     DN_HIP(hipGetLastError());
     if (loss_host) {
