@@ -28,13 +28,16 @@ def _oracle_l1(ov, iters, lam=LAM1):
     return u, p
 
 
-@pytest.mark.parametrize("kernel", ["twopass", "fused", "fused256"])
-def test_l1_parity_every_kernel(c1, kernel):
+@pytest.mark.parametrize("kernel,lam", [("twopass", 0.8), ("fused", 0.8), ("fused256", 0.8), ("fused256", 0.5),
+                                        ("twopass", 0.5)])
+def test_l1_parity_every_kernel(c1, kernel, lam):
+    """Config 1 (200 iterations; lambda 0.5 is the configuration's) with
+    each kernel."""
     D = dn()
     fr, ov, gv = c1
     k = {"twopass": D.DN_K_TWOPASS, "fused": D.DN_K_FUSED, "fused256": D.DN_K_FUSED256}[kernel]
-    st = gv.regularize(D.reg_params(LAM1, TAU, SIG, 1.0, iters=200, kernel=k, data_term=D.DN_DATA_L1))
-    u, p = _oracle_l1(ov, 200)
+    st = gv.regularize(D.reg_params(lam, TAU, SIG, 1.0, iters=200, kernel=k, data_term=D.DN_DATA_L1))
+    u, p = _oracle_l1(ov, 200, lam)
     gu, gub, gp = state_of(D, gv)
     print(f"{kernel}: max |du| {np.abs(gu - u).max():.2e}")
     assert np.abs(gu - u).max() <= 1e-4
@@ -43,14 +46,14 @@ def test_l1_parity_every_kernel(c1, kernel):
     # energies of the GPU state, with the fused field the library holds (the
     # L1 term is first-order sensitive to the 1e-4 fusion differences)
     gf = host(gv.extract(D.DN_X_F)).astype(np.float64)
-    E, Dd = oracle.energy_l1(ov.nbr, gf, ov.w, gu, gp, LAM1)
+    E, Dd = oracle.energy_l1(ov.nbr, gf, ov.w, gu, gp, lam)
     assert abs(st.energy - E) <= 1e-9 * abs(E) and abs(st.dual - Dd) <= 1e-9 * abs(E)
     assert st.gap >= 0
     # dn_energy with the L1 term gives the same pair; the L2 pair differs
-    e1 = gv.energy(LAM1, D.DN_DATA_L1)
+    e1 = gv.energy(lam, D.DN_DATA_L1)
     assert abs(e1[0] - st.energy) <= 1e-12 * abs(E) and abs(e1[1] - st.dual) <= 1e-12 * abs(E)
-    E2, D2 = oracle.energy(ov.nbr, gf, ov.w, gu, gp, LAM1)
-    e2 = gv.energy(LAM1, D.DN_DATA_L2)
+    E2, D2 = oracle.energy(ov.nbr, gf, ov.w, gu, gp, lam)
+    e2 = gv.energy(lam, D.DN_DATA_L2)
     assert abs(e2[0] - E2) <= 1e-9 * abs(E2) and abs(e2[1] - D2) <= 1e-9 * abs(E2)
 
 
