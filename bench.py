@@ -482,6 +482,17 @@ def main():
         line["config"]["kernel_used"] = names.get(st.kernel_used, str(st.kernel_used))
         line["config"]["layout_used"] = {"order": "pool" if st.layout_used & 1 else "morton",
                                          "xcd_chunks": not (st.layout_used & 2)}
+    if args.workload == "street":
+        # the boundary takes device buffers; a caller with host depth maps
+        # also pays their upload (pageable host memory here)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        up = [torch.from_numpy(d).cuda() for d in wl.fr.depths]
+        torch.cuda.synchronize()
+        h2d_ms = 1000.0 * (time.time() - t0)
+        del up
+        line["pcie_inclusive"] = {"h2d_ms_per_step": h2d_ms,
+                                  "value": nvox * args.iters / ((ms_step + h2d_ms) / 1000.0)}
     if not args.no_cpu:
         log("timing the CPU oracle ...")
         line["cpu_baseline"] = cpu_baseline(wl)
