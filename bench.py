@@ -262,8 +262,9 @@ def time_to_gap(wl, tol=1e-3, k=100):
     """Wall time to relative gap <= tol on the street map, from zero (plain)
     and from the learned warm start (network inference + iterations, with
     the fallback to a cold start), both with their gap checks (every 10
-    iterations).  For the configured fixed steps (tau = sigma = 1/sqrt(12))
-    and for the accelerated variant (gamma = lambda)."""
+    iterations).  For the configured fixed steps (tau = sigma = 1/sqrt(12)),
+    for the accelerated variant (gamma = lambda), and with each solver at its
+    fastest step ratio among the same candidates."""
     D = wl.D
     torch = wl.torch
     from paper_1604_03734_amd import warmstart
@@ -291,6 +292,30 @@ def time_to_gap(wl, tol=1e-3, k=100):
             r["warm_fallback"] = res["fallback"]
             r["speedup"] = r["plain_s"] / r["warm_s"]
         out[name] = r
+    # each solver at its best step ratio: tau from the same candidates,
+    # sigma = 1 / (12 tau), both with the fixed schedule
+    if wt is not None:
+        cand = (0.02, 0.03, 0.05, 0.1, 1.0 / np.sqrt(12.0))
+        ref = wl.big.regularize(D.reg_params(0.5, iters=k))
+        plain, warm = {}, {}
+        for tau in cand:
+            torch.cuda.synchronize()
+            t0 = time.time()
+            st = wl.big.regularize(D.reg_params(0.5, tau, 1.0 / (12.0 * tau), iters=20000, gap_every=10,
+                                                gap_tol=tol))
+            torch.cuda.synchronize()
+            plain[tau] = (time.time() - t0, st.iters_run, bool(st.converged))
+            torch.cuda.synchronize()
+            t0 = time.time()
+            res = warmstart.solve_warm(wl.big, wt, tol=tol, k=k, plain_rel_gap_at_k=ref.rel_gap, tau0=tau)
+            torch.cuda.synchronize()
+            warm[tau] = (time.time() - t0, res["iters"], bool(res["converged"]), bool(res["fallback"]))
+        bp = min((v[0], t) for t, v in plain.items() if v[2])[1]
+        bw = min((v[0], t) for t, v in warm.items() if v[2])[1]
+        out["best_steps"] = {"tau_candidates": list(cand),
+                             "plain_tau": bp, "plain_s": plain[bp][0], "plain_iters": plain[bp][1],
+                             "warm_tau": bw, "warm_s": warm[bw][0], "warm_iters": warm[bw][1],
+                             "warm_fallback": warm[bw][3], "speedup": plain[bp][0] / warm[bw][0]}
     return out
 
 
