@@ -69,25 +69,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def src_digest():
+def src_digest(names=("cp_kernel.h", "regularize.hip")):
     """Digest of the sources of the iteration kernels."""
     h = hashlib.sha256()
-    for name in ("cp_kernel.h", "regularize.hip"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_1604_03734_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(nvox):
-    """HBM bytes per launch of the fused kernel from the committed counter
-    summary, if it was taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "cp_fused_street35_traffic.json")
+TRAFFIC_FILES = {"street": ("cp_fused_street35_traffic.json", ("cp_kernel.h", "regularize.hip")),
+                 "batched": ("cp_persistent_batched64_traffic.json", ("cp_kernel.h", "batch.hip"))}
+
+
+def load_traffic(nvox, workload="street"):
+    """Bytes leaving L2 per launch of the iteration kernel, from the
+    committed counter summary, if it was taken on the current kernel
+    source (else None)."""
+    name, srcs = TRAFFIC_FILES[workload]
+    p = os.path.join(ROOT, "profiles", name)
     try:
         with open(p) as f:
             t = json.load(f)
     except OSError:
         return None
-    if t.get("source_digest") != src_digest():
+    if t.get("source_digest") != src_digest(srcs):
         return None
     return t["bytes_per_voxel_iter"] * nvox
 
@@ -467,14 +473,16 @@ def main():
     kern_ms = float(np.mean(loops))
     alg_bytes = ALG_BYTES_PER_VOXEL_ITER if args.storage == "f32" else ALG_BYTES_PER_VOXEL_ITER_16
     achieved = alg_bytes * nvox / (kern_ms / 1000.0) / 1e9
-    traffic = load_traffic(nvox)
+    traffic = load_traffic(nvox, args.workload)
     if args.workload == "batched":
         metric = f"voxel-iterations/s ({args.submaps} sub-maps, {args.iters} CP iterations, one persistent launch)"
         config = {"workload": f"batched sub-maps: {args.submaps} street segments with block counts "
                               "log-uniform in [1e3, 5e4] (0.2 m voxels), one persistent launch in a HIP "
                               "graph, autotuned grid", "blocks": nb, "voxels": nvox,
                   "iters": args.iters, "lambda": 0.5}
-        kname = "k_cp_persistent (one CP iteration of every sub-map)"
+        kname = {257: "k_cp_persistent_lean", 256: "k_cp_persistent<256>",
+                 512: "k_cp_persistent<512>"}.get(st.kernel_used // 100, "k_cp_persistent")
+        kname += " (one CP iteration of every sub-map)"
     else:
         metric = "voxel-iterations/s (fusion + 500 CP iterations + gap + surface, street map)"
         config = {"workload": "street-scale plain method, FP32: 100 depth maps 1242x375 of a 100 m "
@@ -483,7 +491,8 @@ def main():
                   "blocks": nb, "voxels": nvox, "street_blocks": wl.street.num_blocks,
                   "iters": args.iters, "lambda": 0.5, "kernel": args.kernel, "storage": args.storage,
                   "data_term": args.data_term}
-        kname = "k_cp_fused (one CP iteration)"
+        kname = {1: "k_dual + k_primal", 2: "k_cp_fused", 3: "k_cp_fused256"}.get(st.kernel_used, "k_cp_fused")
+        kname += " (one CP iteration)"
     line = {
         "metric": metric,
         "value": value,
@@ -497,11 +506,17 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic if (args.workload == "street" and args.storage == "f32") else None,
+                     "traffic": traffic if args.storage == "f32" else None,
                      "alg_bytes_per_launch": alg_bytes * nvox,
                      "avg_launch_ms": kern_ms},
         "cp_voxel_iters_per_s": nvox / (kern_ms / 1000.0),
     }
+    if args.workload == "batched":
+        line["config"]["kernel_used"] = {"threads": 256 if st.kernel_used // 100 == 257 else st.kernel_used // 100,
+                                         "lean": st.kernel_used // 100 == 257,
+                                         "wg_per_cu": st.kernel_used % 100}
+        line["config"]["layout_used"] = {"order": "pool" if st.layout_used & 1 else "morton",
+                                         "xcd_chunks": not (st.layout_used & 2)}
     if args.workload == "street":
         names = {1: "twopass", 2: "fused512", 3: "fused256x2"}
         line["config"]["kernel_used"] = names.get(st.kernel_used, str(st.kernel_used))
