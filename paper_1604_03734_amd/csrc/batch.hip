@@ -131,9 +131,9 @@ __device__ __forceinline__ void grid_barrier(const BatchArgs &a, unsigned nwg, u
 
 // The item of a workgroup is the same for all its lanes: read it through
 // readfirstlane so the volume's pointers live in scalar registers.
-__device__ __forceinline__ int2 load_item(const BatchArgs &a, int64_t i)
+__device__ __forceinline__ int2 load_item(const int2 *__restrict__ items, int64_t i)
 {
-    const int2 raw = a.items[i];
+    const int2 raw = items[i];
     return make_int2(__builtin_amdgcn_readfirstlane(raw.x), __builtin_amdgcn_readfirstlane(raw.y));
 }
 
@@ -146,10 +146,10 @@ template <class T> __device__ __forceinline__ T *uni(T *p)
     return reinterpret_cast<T *>((uint64_t(hi) << 32) | lo);
 }
 
-__device__ __forceinline__ void item_args(const BatchArgs &a, int2 item, int it, float sigma, float tau,
-                                          float theta, CPArgs<SF32> &A)
+__device__ __forceinline__ void item_args(const BatchArgs &a, const VolDesc *__restrict__ vols, int2 item, int it,
+                                          float sigma, float tau, float theta, CPArgs<SF32> &A)
 {
-    const VolDesc &d = a.vols[item.x];
+    const VolDesc &d = vols[item.x];
     const int c = (__builtin_amdgcn_readfirstlane(d.cur) + it) & 1;
     const int64_t ps = int64_t(__builtin_amdgcn_readfirstlane(uint32_t(d.pstride))) |
                        (int64_t(__builtin_amdgcn_readfirstlane(uint32_t(uint64_t(d.pstride) >> 32))) << 32);
@@ -167,7 +167,8 @@ __device__ __forceinline__ void item_args(const BatchArgs &a, int2 item, int it,
 // loads stay in flight while it works); a grid barrier closes every
 // iteration.
 template <int NT, bool kPrefetch>
-__device__ __forceinline__ void k_cp_persistent_body(const BatchArgs &a)
+__device__ __forceinline__ void k_cp_persistent_body(const BatchArgs &a, const VolDesc *__restrict__ vols,
+                                                     const int2 *__restrict__ items)
 {
     __shared__ CPShared sh;
     __shared__ int s_stop;
@@ -202,9 +203,9 @@ __device__ __forceinline__ void k_cp_persistent_body(const BatchArgs &a)
         if constexpr (!kPrefetch) {
             // one block after the other; the other workgroups on the CU overlap
             for (; i < hi; i += stride) {
-                const int2 bi = load_item(a, i);
+                const int2 bi = load_item(items, i);
                 CPArgs<SF32> A;
-                item_args(a, bi, it, sigma, tau, theta, A);
+                item_args(a, vols, bi, it, sigma, tau, theta, A);
                 cp_block<SF32, false, NT>(A, bi.y, sh, opaque_tid());
                 __syncthreads();
             }
@@ -213,15 +214,15 @@ __device__ __forceinline__ void k_cp_persistent_body(const BatchArgs &a)
         CPArgs<SF32> A0, A1;
         int2 b0 = make_int2(0, 0), b1 = make_int2(0, 0);
         if (i < hi) {
-            b0 = load_item(a, i);
-            item_args(a, b0, it, sigma, tau, theta, A0);
+            b0 = load_item(items, i);
+            item_args(a, vols, b0, it, sigma, tau, theta, A0);
             cp_load<SF32, NT>(A0, b0.y, R0, opaque_tid());
         }
         while (i < hi) {
             int64_t nx = i + stride;
             if (nx < hi) {
-                b1 = load_item(a, nx);
-                item_args(a, b1, it, sigma, tau, theta, A1);
+                b1 = load_item(items, nx);
+                item_args(a, vols, b1, it, sigma, tau, theta, A1);
                 cp_load<SF32, NT>(A1, b1.y, R1, opaque_tid());
             }
             cp_compute<SF32, false, NT>(A0, b0.y, R0, sh, opaque_tid());
@@ -230,8 +231,8 @@ __device__ __forceinline__ void k_cp_persistent_body(const BatchArgs &a)
             if (i >= hi) break;
             nx = i + stride;
             if (nx < hi) {
-                b0 = load_item(a, nx);
-                item_args(a, b0, it, sigma, tau, theta, A0);
+                b0 = load_item(items, nx);
+                item_args(a, vols, b0, it, sigma, tau, theta, A0);
                 cp_load<SF32, NT>(A0, b0.y, R0, opaque_tid());
             }
             cp_compute<SF32, false, NT>(A1, b1.y, R1, sh, opaque_tid());
@@ -247,16 +248,22 @@ __device__ __forceinline__ void k_cp_persistent_body(const BatchArgs &a)
     }
 }
 
+// The descriptors and the item list (read-only during the launch) are also
+// passed as restrict-qualified kernel arguments: no store of the loop can
+// then alias them, so the compiler reads them with scalar loads, which
+// shortens the chain of dependent loads in front of each block.
 template <int NT, bool kPrefetch>
-__global__ __launch_bounds__(NT) void k_cp_persistent(BatchArgs a)
+__global__ __launch_bounds__(NT) void k_cp_persistent(BatchArgs a, const VolDesc *__restrict__ vols,
+                                                     const int2 *__restrict__ items)
 {
-    k_cp_persistent_body<NT, kPrefetch>(a);
+    k_cp_persistent_body<NT, kPrefetch>(a, vols, items);
 }
 
 // The lean form: no prefetch, registers capped for 8 waves per SIMD.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_cp_persistent_lean(BatchArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_cp_persistent_lean(
+    BatchArgs a, const VolDesc *__restrict__ vols, const int2 *__restrict__ items)
 {
-    k_cp_persistent_body<256, false>(a);
+    k_cp_persistent_body<256, false>(a, vols, items);
 }
 
 __global__ void k_make_items(const int32_t *__restrict__ order, int64_t nb, int32_t vol, int2 *__restrict__ items)
@@ -301,11 +308,11 @@ static void launch_kernel(hipStream_t st, const BatchArgs &a, int grid, int nt)
 {
     hipLaunchKernelGGL(k_batch_reset, dim3(32), dim3(256), 0, st, a.bar);
     if (nt == 256)
-        hipLaunchKernelGGL((k_cp_persistent<256, true>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_cp_persistent<256, true>), dim3(grid), dim3(256), 0, st, a, a.vols, a.items);
     else if (nt == 257)
-        hipLaunchKernelGGL(k_cp_persistent_lean, dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_cp_persistent_lean, dim3(grid), dim3(256), 0, st, a, a.vols, a.items);
     else
-        hipLaunchKernelGGL((k_cp_persistent<512, true>), dim3(grid), dim3(512), 0, st, a);
+        hipLaunchKernelGGL((k_cp_persistent<512, true>), dim3(grid), dim3(512), 0, st, a, a.vols, a.items);
 }
 
 static int launch_direct(hipStream_t st, const BatchArgs &a, int grid, int nt)
