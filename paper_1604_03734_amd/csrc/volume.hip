@@ -757,7 +757,7 @@ void dn_volume_destroy(dn_volume *v)
         if (p) (void)hipFree(p);
     dn::Buf *bufs[] = {&v->s_cand, &v->s_cand2, &v->s_counts, &v->s_offsets, &v->s_tmp, &v->s_uniq,
                        &v->s_flags, &v->s_new, &v->s_sorted, &v->s_vals, &v->s_vals2, &v->s_home,
-                       &v->s_home2, &v->s_pos, &v->s_misc};
+                       &v->s_home2, &v->s_pos, &v->s_misc, &v->s_laser};
     for (auto *b : bufs) b->release();
     v->host.release();
     delete v;
