@@ -78,22 +78,29 @@ def src_digest(names=("cp_kernel.h", "regularize.hip")):
     return h.hexdigest()[:16]
 
 
-TRAFFIC_FILES = {"street": ("cp_fused_street35_traffic.json", ("cp_kernel.h", "regularize.hip")),
-                 "batched": ("cp_persistent_batched64_traffic.json", ("cp_kernel.h", "batch.hip"))}
+TRAFFIC_FILES = {
+    ("street", "f32"): ("cp_fused_street35_traffic.json", ("cp_kernel.h", "regularize.hip")),
+    ("street", "f16"): ("cp_fused_street35_f16_traffic.json", ("cp_kernel.h", "regularize.hip")),
+    ("street", "bf16"): ("cp_fused_street35_bf16_traffic.json", ("cp_kernel.h", "regularize.hip")),
+    ("batched", "f32"): ("cp_persistent_batched64_traffic.json", ("cp_kernel.h", "batch.hip")),
+}
 
 
-def load_traffic(nvox, workload="street"):
+def load_traffic(nvox, workload, storage, kernel_id):
     """Bytes leaving L2 per launch of the iteration kernel, from the
-    committed counter summary, if it was taken on the current kernel
-    source (else None)."""
-    name, srcs = TRAFFIC_FILES[workload]
+    committed counter summary, if it was taken on the current kernel source
+    and on the kernel variant that ran (else None)."""
+    entry = TRAFFIC_FILES.get((workload, storage))
+    if entry is None:
+        return None
+    name, srcs = entry
     p = os.path.join(ROOT, "profiles", name)
     try:
         with open(p) as f:
             t = json.load(f)
     except OSError:
         return None
-    if t.get("source_digest") != src_digest(srcs):
+    if t.get("source_digest") != src_digest(srcs) or t.get("kernel_id") != kernel_id:
         return None
     return t["bytes_per_voxel_iter"] * nvox
 
@@ -473,7 +480,8 @@ def main():
     kern_ms = float(np.mean(loops))
     alg_bytes = ALG_BYTES_PER_VOXEL_ITER if args.storage == "f32" else ALG_BYTES_PER_VOXEL_ITER_16
     achieved = alg_bytes * nvox / (kern_ms / 1000.0) / 1e9
-    traffic = load_traffic(nvox, args.workload)
+    kernel_id = st.kernel_used // 100 if args.workload == "batched" else st.kernel_used
+    traffic = load_traffic(nvox, args.workload, args.storage, kernel_id)
     if args.workload == "batched":
         metric = f"voxel-iterations/s ({args.submaps} sub-maps, {args.iters} CP iterations, one persistent launch)"
         config = {"workload": f"batched sub-maps: {args.submaps} street segments with block counts "
@@ -484,7 +492,7 @@ def main():
                  512: "k_cp_persistent<512>"}.get(st.kernel_used // 100, "k_cp_persistent")
         kname += " (one CP iteration of every sub-map)"
     else:
-        metric = "voxel-iterations/s (fusion + 500 CP iterations + gap + surface, street map)"
+        metric = f"voxel-iterations/s (fusion + {args.iters} CP iterations + gap + surface, street map)"
         config = {"workload": "street-scale plain method, FP32: 100 depth maps 1242x375 of a 100 m "
                               "synthetic street, 0.2 m voxels, mu 0.6 m, sigma 0.5 px, 5% invalid; "
                               f"map = {args.copies} translated copies of the fused street",
@@ -506,7 +514,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic if args.storage == "f32" else None,
+                     "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes * nvox,
                      "avg_launch_ms": kern_ms},
         "cp_voxel_iters_per_s": nvox / (kern_ms / 1000.0),
