@@ -51,11 +51,13 @@ struct BatchArgs {
 // so arrivals and polls of different groups never share a cache line.
 // slot 0: arrivals of group leaders, slot 1: generation, slot 2: error flag,
 // slots 3 .. 3+kBarMaxGroups-1: arrivals per group, then one release flag
-// per group.
+// per group, then the item counters of the eight XCD chunks.  All zeroed
+// before every launch.
 constexpr int kBarSlot = 64;
 constexpr int kBarGroup = 32;
 constexpr int kBarMaxGroups = 256;
-constexpr int kBarWords = (3 + 2 * kBarMaxGroups) * kBarSlot;
+constexpr int kBarCtr = (3 + 2 * kBarMaxGroups) * kBarSlot;   // then 8 item counters, one slot each
+constexpr int kBarWords = kBarCtr + 8 * kBarSlot;
 constexpr int kBarMaxGrid = kBarGroup * kBarMaxGroups;
 
 __global__ void k_batch_reset(unsigned *bar)
@@ -161,10 +163,11 @@ __device__ __forceinline__ void item_args(const BatchArgs &a, const VolDesc *__r
     A.l1 = a.l1;
 }
 
-// All iterations of all sub-maps.  Each workgroup walks its items of an
-// iteration in a fixed order (with kPrefetch it issues the global loads of
-// the next item before computing the current one, two register sets, so
-// loads stay in flight while it works); a grid barrier closes every
+// All iterations of all sub-maps.  Without kPrefetch the workgroups take
+// the items of an iteration from a shared counter (per XCD chunk); with
+// kPrefetch each walks a fixed stride of them and issues the global loads
+// of the next item before computing the current one (two register sets, so
+// loads stay in flight while it works).  A grid barrier closes every
 // iteration.
 template <int NT, bool kPrefetch>
 __device__ __forceinline__ void k_cp_persistent_body(const BatchArgs &a, const VolDesc *__restrict__ vols,
@@ -172,6 +175,7 @@ __device__ __forceinline__ void k_cp_persistent_body(const BatchArgs &a, const V
 {
     __shared__ CPShared sh;
     __shared__ int s_stop;
+    __shared__ unsigned s_next;
     const unsigned nwg = gridDim.x;
     const int64_t G = nwg;
     double acc_tau = a.tau0, acc_sigma = a.sigma0;
@@ -185,29 +189,51 @@ __device__ __forceinline__ void k_cp_persistent_body(const BatchArgs &a, const V
             acc_tau = th * acc_tau;
             acc_sigma = acc_sigma / th;
         }
-        int64_t i, hi, stride;
+        int64_t i, hi, stride, lo = 0, cx = 0;
         if (a.xcd_chunks && G >= 8) {
             // workgroup g runs on XCD g % 8; XCD x owns items [x*chunk, (x+1)*chunk)
             // and has exactly (G - x + 7) / 8 workgroups to stride over them
             const int64_t x = blockIdx.x % 8, lane = blockIdx.x / 8;
             const int64_t chunk = (a.n_items + 7) / 8;
-            const int64_t lo = x * chunk;
+            lo = x * chunk;
             hi = min(a.n_items, lo + chunk);
             stride = (G - x + 7) / 8;
             i = lo + lane;
+            cx = x;
         } else {
             i = blockIdx.x;
             hi = a.n_items;
             stride = G;
         }
         if constexpr (!kPrefetch) {
-            // one block after the other; the other workgroups on the CU overlap
-            for (; i < hi; i += stride) {
-                const int2 bi = load_item(items, i);
+            // One block after the other (the other workgroups on the CU
+            // overlap), each taken in order from the items [lo, hi) through
+            // the chunk's counter, so that the items in flight stay one
+            // contiguous window however unevenly the workgroups progress.
+            // The next index is taken while the current block is processed.
+            // Every workgroup of the chunk ends an iteration with exactly one
+            // index past the end, so the counter advances by len + stride per
+            // iteration and the index is its value less that base (modulo
+            // 2^32, which keeps differences exact).
+            unsigned *ctr = a.bar + kBarCtr + cx * kBarSlot;
+            const unsigned len = unsigned(hi > lo ? hi - lo : 0);
+            const unsigned base = unsigned(it) * (len + unsigned(stride));
+            if (threadIdx.x == 0)
+                s_next = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base;
+            __syncthreads();
+            unsigned rel = s_next;
+            while (rel < len) {
+                unsigned nraw = 0;
+                __syncthreads();   // every thread has read s_next
+                if (threadIdx.x == 0)
+                    nraw = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int2 bi = load_item(items, lo + rel);
                 CPArgs<SF32> A;
                 item_args(a, vols, bi, it, sigma, tau, theta, A);
                 cp_block<SF32, false, NT>(A, bi.y, sh, opaque_tid());
+                if (threadIdx.x == 0) s_next = nraw - base;
                 __syncthreads();
+                rel = s_next;
             }
         } else {
         CPRegs<NT> R0, R1;
