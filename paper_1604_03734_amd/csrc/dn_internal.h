@@ -101,13 +101,19 @@ struct dn_volume {
     // scratch for allocation and extraction
     dn::Buf s_cand, s_cand2, s_counts, s_offsets, s_tmp, s_uniq, s_flags, s_new, s_sorted,
         s_vals, s_vals2, s_home, s_home2, s_pos, s_misc, s_laser;
-    int64_t last_nuniq = 0;             // distinct candidates of the last frame
+    dn::Buf s_newk;                     // distinct new keys of an insertion
+    int64_t last_nuniq = 0;             // distinct candidates of the last frame (once built)
+    const uint64_t *cand_src = nullptr; // raw candidate list of the last frame
+    int64_t cand_n = 0;
+    bool cand_pending = false;          // its distinct list is not built yet
     dn::HostBuf host;
 };
 
 namespace dn {
 // regularize.hip
 int build_masks(dn_volume *v);
+// volume.hip
+int ensure_candidates(dn_volume *v);
 int ensure_lowp(dn_volume *v);
 int zero_state(dn_volume *v);
 int energy_current(dn_volume *v, double lambda, bool use_f32, int data_term);

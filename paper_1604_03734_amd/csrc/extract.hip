@@ -325,7 +325,11 @@ extern "C" int dn_extract(dn_volume *v, int32_t what, void *out, size_t out_byte
     case DN_X_F: case DN_X_W: case DN_X_U: case DN_X_UBAR: items = nb; need = size_t(nv) * 4; break;
     case DN_X_P: items = nb; need = size_t(nv) * 12; break;
     case DN_X_EMASK: items = nb; need = size_t(nv); break;
-    case DN_X_CANDIDATES: items = v->last_nuniq; need = size_t(items) * 12; break;
+    case DN_X_CANDIDATES:
+        if ((rc = ensure_candidates(v))) return rc;
+        items = v->last_nuniq;
+        need = size_t(items) * 12;
+        break;
     case DN_X_SURFACE: {
         if ((rc = build_masks(v))) return rc;
         if ((rc = v->s_counts.ensure((nb + 1) * 8))) return rc;

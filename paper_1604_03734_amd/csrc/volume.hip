@@ -215,6 +215,17 @@ __global__ void k_flag_new(const uint64_t *__restrict__ uniq, const int64_t *__r
     flag[i] = hash_lookup(slots, nslots, cap, x, y, z) < 0 ? 1 : 0;
 }
 
+// flag[i] = 1 when raw candidate i (repeats allowed) is not in the table.
+__global__ void k_flag_unknown(const uint64_t *__restrict__ cand, int64_t n, const int4 *__restrict__ slots,
+                               int64_t nslots, uint32_t cap, uint8_t *__restrict__ flag)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t x, y, z;
+    unpack_key(cand[i], x, y, z);
+    flag[i] = hash_lookup(slots, nslots, cap, x, y, z) < 0 ? 1 : 0;
+}
+
 // Append the sorted new keys after the existing pool; clear their fields.
 __global__ void k_append(const uint64_t *__restrict__ newk, int64_t n_new, int64_t nb_old,
                          int32_t *__restrict__ coords, uint64_t *__restrict__ keys)
@@ -300,52 +311,63 @@ static int bits_for(uint64_t v)
 }
 
 // Insert a packed candidate list (device, n_cand entries, repeats allowed).
-// Dedupes, appends new keys in ascending order, rebuilds hash + neighbours.
+// Appends the keys not yet present in ascending order, rebuilds hash +
+// neighbours.  The raw list is first filtered against the table, so only
+// candidates of new blocks are sorted (after the first frames of a sequence
+// almost every candidate is a block that exists); the ascending list of all
+// distinct candidates is built from the same raw list only when it is
+// extracted (ensure_candidates).
 static int insert_packed(dn_volume *v, uint64_t *cand, int64_t n_cand, int32_t *n_new_out)
 {
     hipStream_t st = v->stream;
     if (n_new_out) *n_new_out = 0;
-    if (n_cand == 0) { v->last_nuniq = 0; return DN_OK; }
+    v->last_nuniq = 0;
+    v->cand_src = cand;
+    v->cand_n = n_cand;
+    v->cand_pending = n_cand > 0;
+    if (n_cand == 0) return DN_OK;
     int rc;
-    // 1) sort + unique
-    if ((rc = v->s_sorted.ensure(n_cand * sizeof(uint64_t)))) return rc;
-    if ((rc = v->s_uniq.ensure(n_cand * sizeof(uint64_t)))) return rc;
+    // 1) the candidates of blocks not in the table (repeats kept)
     if ((rc = v->s_flags.ensure(n_cand))) return rc;
     if ((rc = v->s_new.ensure(n_cand * sizeof(uint64_t)))) return rc;
     if ((rc = v->s_misc.ensure(64))) return rc;
-    int64_t *d_nuniq = v->s_misc.as<int64_t>();
-    int64_t *d_nnew = d_nuniq + 1;
-    uint64_t *sorted = v->s_sorted.as<uint64_t>();
-    uint64_t *uniq = v->s_uniq.as<uint64_t>();
-    size_t tb = 0, t2 = 0;
-    DN_HIP(rocprim::radix_sort_keys(nullptr, tb, cand, sorted, size_t(n_cand), 0, 63, st));
-    DN_HIP(rocprim::unique(nullptr, t2, sorted, uniq, d_nuniq, size_t(n_cand), rocprim::equal_to<uint64_t>(), st));
-    tb = tb > t2 ? tb : t2;
-    t2 = 0;
-    DN_HIP(rocprim::select(nullptr, t2, uniq, v->s_flags.as<uint8_t>(), v->s_new.as<uint64_t>(), d_nnew,
+    int64_t *d_nraw = v->s_misc.as<int64_t>();
+    int64_t *d_nnew = d_nraw + 1;
+    const int4 *slots = reinterpret_cast<const int4 *>(v->hash[v->cur_hash]);
+    hipLaunchKernelGGL(k_flag_unknown, dim3(grid1(n_cand)), dim3(256), 0, st, cand, n_cand, slots,
+                       v->hash_slots, v->hash_cap, v->s_flags.as<uint8_t>());
+    DN_HIP(hipGetLastError());
+    size_t tb = 0;
+    DN_HIP(rocprim::select(nullptr, tb, cand, v->s_flags.as<uint8_t>(), v->s_new.as<uint64_t>(), d_nraw,
                            size_t(n_cand), st));
-    tb = tb > t2 ? tb : t2;
     if ((rc = v->s_tmp.ensure(tb))) return rc;
     size_t tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::radix_sort_keys(v->s_tmp.ptr, tbytes, cand, sorted, size_t(n_cand), 0, 63, st));
-    tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::unique(v->s_tmp.ptr, tbytes, sorted, uniq, d_nuniq, size_t(n_cand),
-                           rocprim::equal_to<uint64_t>(), st));
-    // 2) which distinct keys are new
-    const int4 *slots = reinterpret_cast<const int4 *>(v->hash[v->cur_hash]);
-    hipLaunchKernelGGL(k_flag_new, dim3(grid1(n_cand)), dim3(256), 0, st, uniq, d_nuniq, slots,
-                       v->hash_slots, v->hash_cap, v->s_flags.as<uint8_t>(), n_cand);
-    DN_HIP(hipGetLastError());
-    tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::select(v->s_tmp.ptr, tbytes, uniq, v->s_flags.as<uint8_t>(), v->s_new.as<uint64_t>(),
-                           d_nnew, size_t(n_cand), st));
+    DN_HIP(rocprim::select(v->s_tmp.ptr, tbytes, cand, v->s_flags.as<uint8_t>(), v->s_new.as<uint64_t>(),
+                           d_nraw, size_t(n_cand), st));
     if ((rc = v->host.ensure(64))) return rc;
-    DN_HIP(hipMemcpyAsync(v->host.ptr, d_nuniq, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    DN_HIP(hipMemcpyAsync(v->host.ptr, d_nraw, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     DN_HIP(hipStreamSynchronize(st));
-    int64_t nuniq = v->host.as<int64_t>()[0];
-    int64_t n_new = v->host.as<int64_t>()[1];
-    v->last_nuniq = nuniq;
-    if (n_new == 0) return DN_OK;
+    const int64_t n_raw = v->host.as<int64_t>()[0];
+    if (n_raw == 0) return DN_OK;
+    // 2) the distinct new keys, ascending
+    if ((rc = v->s_sorted.ensure(n_raw * sizeof(uint64_t)))) return rc;
+    if ((rc = v->s_newk.ensure(n_raw * sizeof(uint64_t)))) return rc;
+    uint64_t *sorted = v->s_sorted.as<uint64_t>();
+    uint64_t *newk = v->s_newk.as<uint64_t>();
+    size_t t2 = 0;
+    tb = 0;
+    DN_HIP(rocprim::radix_sort_keys(nullptr, tb, v->s_new.as<uint64_t>(), sorted, size_t(n_raw), 0, 63, st));
+    DN_HIP(rocprim::unique(nullptr, t2, sorted, newk, d_nnew, size_t(n_raw), rocprim::equal_to<uint64_t>(), st));
+    if ((rc = v->s_tmp.ensure(tb > t2 ? tb : t2))) return rc;
+    tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::radix_sort_keys(v->s_tmp.ptr, tbytes, v->s_new.as<uint64_t>(), sorted, size_t(n_raw), 0, 63,
+                                    st));
+    tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::unique(v->s_tmp.ptr, tbytes, sorted, newk, d_nnew, size_t(n_raw), rocprim::equal_to<uint64_t>(),
+                           st));
+    DN_HIP(hipMemcpyAsync(v->host.ptr, d_nnew, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    DN_HIP(hipStreamSynchronize(st));
+    const int64_t n_new = v->host.as<int64_t>()[0];
     if (v->nb + n_new > v->cap_blocks) {
         set_error("block pool full: %lld + %lld new blocks > max_blocks %lld", (long long)v->nb,
                   (long long)n_new, (long long)v->cap_blocks);
@@ -353,8 +375,7 @@ static int insert_packed(dn_volume *v, uint64_t *cand, int64_t n_cand, int32_t *
     }
     // 3) tentatively append (beyond nb; not committed until the hash fits)
     const int64_t nb_old = v->nb, nb_new = v->nb + n_new;
-    hipLaunchKernelGGL(k_append, dim3(grid1(n_new)), dim3(256), 0, st, v->s_new.as<uint64_t>(), n_new,
-                       nb_old, v->coords, v->keys);
+    hipLaunchKernelGGL(k_append, dim3(grid1(n_new)), dim3(256), 0, st, newk, n_new, nb_old, v->coords, v->keys);
     DN_HIP(hipGetLastError());
     // 4) canonical table: sort (key -> id), then stable sort by bucket
     if ((rc = v->s_vals.ensure(nb_new * sizeof(int32_t)))) return rc;
@@ -394,7 +415,7 @@ static int insert_packed(dn_volume *v, uint64_t *cand, int64_t n_cand, int32_t *
     DN_HIP(rocprim::inclusive_scan(v->s_tmp.ptr, tbytes, dm, runmax, size_t(nb_new), rocprim::maximum<int64_t>(), st));
     int other = 1 - v->cur_hash;
     int4 *dst = reinterpret_cast<int4 *>(v->hash[other]);
-    int32_t *d_ovf = reinterpret_cast<int32_t *>(d_nuniq + 2);
+    int32_t *d_ovf = reinterpret_cast<int32_t *>(d_nraw + 2);
     DN_HIP(hipMemsetAsync(d_ovf, 0, sizeof(int32_t), st));
     hipLaunchKernelGGL(k_fill_empty, dim3(grid1(v->hash_slots)), dim3(256), 0, st, dst, v->hash_slots);
     DN_HIP(hipGetLastError());
@@ -681,6 +702,37 @@ static int make_lgeo(const dn_volume *v, const double *T, LGeo &g)
     return DN_OK;
 }
 
+// The ascending distinct keys of the last candidate list, in s_uniq
+// (last_nuniq of them), built on first request.
+int ensure_candidates(dn_volume *v)
+{
+    if (!v->cand_pending) return DN_OK;
+    hipStream_t st = v->stream;
+    const int64_t n = v->cand_n;
+    int rc;
+    if ((rc = v->s_sorted.ensure(n * sizeof(uint64_t)))) return rc;
+    if ((rc = v->s_uniq.ensure(n * sizeof(uint64_t)))) return rc;
+    if ((rc = v->s_misc.ensure(64))) return rc;
+    int64_t *d_n = v->s_misc.as<int64_t>() + 3;
+    uint64_t *sorted = v->s_sorted.as<uint64_t>();
+    size_t tb = 0, t2 = 0;
+    DN_HIP(rocprim::radix_sort_keys(nullptr, tb, v->cand_src, sorted, size_t(n), 0, 63, st));
+    DN_HIP(rocprim::unique(nullptr, t2, sorted, v->s_uniq.as<uint64_t>(), d_n, size_t(n),
+                           rocprim::equal_to<uint64_t>(), st));
+    if ((rc = v->s_tmp.ensure(tb > t2 ? tb : t2))) return rc;
+    size_t tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::radix_sort_keys(v->s_tmp.ptr, tbytes, v->cand_src, sorted, size_t(n), 0, 63, st));
+    tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::unique(v->s_tmp.ptr, tbytes, sorted, v->s_uniq.as<uint64_t>(), d_n, size_t(n),
+                           rocprim::equal_to<uint64_t>(), st));
+    if ((rc = v->host.ensure(64))) return rc;
+    DN_HIP(hipMemcpyAsync(v->host.ptr, d_n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    DN_HIP(hipStreamSynchronize(st));
+    v->last_nuniq = v->host.as<int64_t>()[0];
+    v->cand_pending = false;
+    return DN_OK;
+}
+
 }  // namespace dn
 
 using namespace dn;
@@ -757,7 +809,7 @@ void dn_volume_destroy(dn_volume *v)
         if (p) (void)hipFree(p);
     dn::Buf *bufs[] = {&v->s_cand, &v->s_cand2, &v->s_counts, &v->s_offsets, &v->s_tmp, &v->s_uniq,
                        &v->s_flags, &v->s_new, &v->s_sorted, &v->s_vals, &v->s_vals2, &v->s_home,
-                       &v->s_home2, &v->s_pos, &v->s_misc, &v->s_laser};
+                       &v->s_home2, &v->s_pos, &v->s_misc, &v->s_laser, &v->s_newk};
     for (auto *b : bufs) b->release();
     v->host.release();
     delete v;
@@ -779,6 +831,7 @@ int dn_volume_clear(dn_volume *v)
     v->nb_state = 0;
     v->emask_nb = -1;
     v->last_nuniq = 0;
+    v->cand_pending = false;
     v->state_storage = DN_F32;
     return DN_OK;
 }
@@ -824,7 +877,9 @@ int dn_alloc_blocks(dn_volume *v, const float *depth, const dn_intrinsics *K, co
     DN_HIP(hipMemcpyAsync(v->host.as<int32_t>() + 1, counts + npx - 1, 4, hipMemcpyDeviceToHost, st));
     DN_HIP(hipStreamSynchronize(st));
     int64_t total = int64_t(v->host.as<int32_t>()[0]) + v->host.as<int32_t>()[1];
-    if (total == 0) { v->last_nuniq = 0; return DN_OK; }
+    if (total == 0) { v->last_nuniq = 0; v->cand_pending = false; return DN_OK; }
+    v->cand_pending = false;
+    v->last_nuniq = 0;
     if ((rc = v->s_cand.ensure(total * 8))) return rc;
     hipLaunchKernelGGL(k_dda_emit, dim3(grid1(npx)), dim3(256), 0, st, g, depth, offs, v->s_cand.as<uint64_t>(), total);
     DN_HIP(hipGetLastError());
@@ -837,6 +892,8 @@ int dn_insert_blocks(dn_volume *v, const int32_t *coords, int64_t n, int32_t *n_
     if (n_new_out) *n_new_out = 0;
     if (n == 0) return DN_OK;
     int rc;
+    v->cand_pending = false;
+    v->last_nuniq = 0;
     if ((rc = v->s_cand.ensure(n * 8))) return rc;
     hipLaunchKernelGGL(k_pack_coords, dim3(grid1(n)), dim3(256), 0, v->stream, coords, n, v->s_cand.as<uint64_t>());
     DN_HIP(hipGetLastError());
@@ -875,7 +932,7 @@ int dn_alloc_laser(dn_volume *v, const float *pts, int64_t n, const double T[16]
     int rc = make_lgeo(v, T, g);
     if (rc) return rc;
     if (n_new_out) *n_new_out = 0;
-    if (n == 0) { v->last_nuniq = 0; return DN_OK; }
+    if (n == 0) { v->last_nuniq = 0; v->cand_pending = false; return DN_OK; }
     DN_REQUIRE(n < (int64_t(1) << 31), "too many returns in one scan");
     hipStream_t st = v->stream;
     if ((rc = v->s_counts.ensure(n * 4))) return rc;
@@ -894,7 +951,9 @@ int dn_alloc_laser(dn_volume *v, const float *pts, int64_t n, const double T[16]
     DN_HIP(hipMemcpyAsync(v->host.as<int32_t>() + 1, counts + n - 1, 4, hipMemcpyDeviceToHost, st));
     DN_HIP(hipStreamSynchronize(st));
     const int64_t total = int64_t(v->host.as<int32_t>()[0]) + v->host.as<int32_t>()[1];
-    if (total == 0) { v->last_nuniq = 0; return DN_OK; }
+    if (total == 0) { v->last_nuniq = 0; v->cand_pending = false; return DN_OK; }
+    v->cand_pending = false;
+    v->last_nuniq = 0;
     if ((rc = v->s_cand.ensure(total * 8))) return rc;
     hipLaunchKernelGGL(k_laser_cand_emit, dim3(grid1(n)), dim3(256), 0, st, g, pts, n, offs,
                        v->s_cand.as<uint64_t>(), total);
