@@ -428,14 +428,17 @@ typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
 constexpr int kL1M = 2;       // layer 1: 27 taps x 2 channels = 54 of 64 K slots
 constexpr int kL2M = 14;      // layer 2: 27 taps x 16 channels, two taps per MFMA
-constexpr int kL3M = 14;      // layer 3: as layer 2, output column 0 only
+constexpr int kL3M = 2;       // layer 3: rows = the 9 (y, z) tap pairs, K = 3 x taps x 16 channels
 constexpr int kLaneW = (kL1M + kL2M + kL3M) * 64 * 8;
 
 // Lane-ready weights [mfma][lane][8] (bfloat16).  The K slots of lane
 // group g = lane / 16, entry j, of MFMA m: layer 1 -> tap 16m + 4g + j/2,
-// channel j%2; layers 2 and 3 -> tap 2m + g/2, channel 8(g%2) + j.  The
-// output column is lane % 16.  The activation operand uses the same map, so
-// the products pair up whatever order the hardware sums them in.
+// channel j%2; layer 2 -> tap 2m + g/2, channel 8(g%2) + j; the output
+// column (output channel) is lane % 16.  Layer 3 has one output channel, so
+// its rows are taps instead: row n = 3 kz + ky (n < 9) is the (y, z) tap
+// pair, and the K slots of MFMA m, group g are x tap kx = 2m + g/2 (kx < 3),
+// channel 8(g%2) + j.  The activation operand uses the same map, so the
+// products pair up whatever order the hardware sums them in.
 __global__ void k_pack_lanes(const float *__restrict__ params, uint16_t *__restrict__ out)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -446,14 +449,12 @@ __global__ void k_pack_lanes(const float *__restrict__ params, uint16_t *__restr
     if (m < kL1M) {
         const int t = 16 * m + 4 * g + (j >> 1), ci = j & 1;
         if (t < kTaps) val = params[kW1 + (n * 2 + ci) * kTaps + t];
+    } else if (m < kL1M + kL2M) {
+        const int t = 2 * (m - kL1M) + (g >> 1), ci = 8 * (g & 1) + j;
+        if (t < kTaps) val = params[kW2 + (n * 16 + ci) * kTaps + t];
     } else {
-        const bool l2 = m < kL1M + kL2M;
-        const int mm = l2 ? m - kL1M : m - kL1M - kL2M;
-        const int t = 2 * mm + (g >> 1), ci = 8 * (g & 1) + j;
-        if (t < kTaps) {
-            if (l2) val = params[kW2 + (n * 16 + ci) * kTaps + t];
-            else if (n == 0) val = params[kW3 + ci * kTaps + t];
-        }
+        const int kx = 2 * (m - kL1M - kL2M) + (g >> 1), ci = 8 * (g & 1) + j;
+        if (kx < 3 && n < 9) val = params[kW3 + ci * kTaps + 3 * n + kx];
     }
     out[k] = f2bf(val);
 }
@@ -587,15 +588,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     __shared__ __align__(16) uint16_t h1[2 * kPlane / 2];
     __shared__ __align__(16) uint16_t h2[2 * kPlane / 2];
     __shared__ __align__(16) uint32_t x0[kT + 4];
-    __shared__ __align__(16) v4u w3s[kL3M * 4];   // layer-3 weights: column 0 only, per (MFMA, lane group)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int i = lane & 15, g = lane >> 4;
     const int half = g & 1, par = g >> 1;      // channel half and tap parity of this lane's K slots
     const v4u *lw4 = reinterpret_cast<const v4u *>(lw);
-    v8bf W1[kL1M], W2[kL2M];
+    v8bf W1[kL1M], W2[kL2M], W3[kL3M];
     for (int m = 0; m < kL1M; ++m) W1[m] = as_v8bf(lw4[m * 64 + lane]);
     for (int m = 0; m < kL2M; ++m) W2[m] = as_v8bf(lw4[(kL1M + m) * 64 + lane]);
-    if (tid < kL3M * 4) w3s[tid] = lw4[(kL1M + kL2M + (tid >> 2)) * 64 + 16 * (tid & 3)];
+    for (int m = 0; m < kL3M; ++m) W3[m] = as_v8bf(lw4[(kL1M + kL2M + m) * 64 + lane]);
     float bias1[4], bias2[4];
     for (int r = 0; r < 4; ++r) {
         bias1[r] = params[kB1 + 4 * g + r];
@@ -649,47 +649,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
         __syncthreads();
 
-        // layer 3: 16 -> 1 on the centre 8^3 only, then the epilogue
-        for (int mt = wave; mt < 32; mt += 4) {
-            const int c = mt * 16 + i;
-            const int v = ((c / 64 + 1) * 10 + ((c / 8) % 8 + 1)) * 10 + (c % 8 + 1);
-            // tap 27 (past the last) has zero weights: any row will do
-            const v4f acc = mfma_chain<kL3M, 4, true>(
-                [&](int m) {
-                    const int o = par ? (2 * m + 1 < kTaps ? tap_off(2 * m + 1) : 0) : tap_off(2 * m);
-                    return as_v8bf(lds_row(h2, act_byte(v + o, half)));
-                },
-                [&](int m) {
-                    // row 0 of the weight operand; the other rows are zero.
-                    // Only the 4 lanes that hold row 0 read (16 lanes reading
-                    // one 16-byte entry would serialise on its banks).
-                    v4u wb = {0u, 0u, 0u, 0u};
-                    if (i == 0) {
-                        asm volatile("" ::: "memory");
-                        wb = w3s[m * 4 + g];
-                    }
-                    return as_v8bf(wb);
-                });
-            if (g == 0) {
-                // output channel 0 of voxel i: row 0 of the product
-                int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
-                if (perm == 1) { const int sw = x; x = y; y = sw; }
-                if (perm == 2) { const int sw = x; x = z; z = sw; }
-                const int64_t gi = b * kBlockVox + x + 8 * y + 64 * z;
-                const float rv = acc[0] + bias3;
-                const uint8_t em = emask[gi];
-                if (mode == DN_WARM_DUAL) {
-                    out[perm * ps + gi] = ((em >> (perm + 1)) & 1) ? rv : 0.f;
-                } else {
-                    float u = 0.f;
-                    if (em & 1) {
-                        u = f[gi] + rv;
-                        u = u < -1.f ? -1.f : (u > 1.f ? 1.f : u);
-                    }
-                    out[gi] = u;
+        // layer 3: 16 -> 1 on the centre 8^3, as partial sums over the x taps.
+        // P[n][u] = sum over kx, ci of W3[ci][3n + kx] h2[u + kx - 1][ci] for
+        // the 9 (y, z) tap pairs n and the 800 voxels u with x in 1..8 (rows
+        // r = 10 z + y, 8 voxels each), one 16-voxel tile (two rows) per pair
+        // of MFMAs; P goes to h1, which layer 2 has finished reading.
+        float *P = reinterpret_cast<float *>(h1);
+        for (int mt = wave; mt < 50; mt += 4) {
+            const int r = 2 * mt + (i >> 3), u = 10 * r + (i & 7) + 1;
+            const v4u z4 = {0u, 0u, 0u, 0u};
+            const v4u q0 = lds_row(h2, act_byte(u - 1 + par, half));       // kx = par
+            const v4u q1 = par ? z4 : lds_row(h2, act_byte(u + 1, half));  // kx = 2
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W3[0], as_v8bf(q0), acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W3[1], as_v8bf(q1), acc, 0, 0, 0);
+            // lane: rows (tap pairs) 4g .. 4g+3 of column i
+            for (int e = 0; e < 4; ++e)
+                if (4 * g + e < 9) P[(4 * g + e) * 800 + 8 * r + (i & 7)] = acc[e];
+        }
+        __syncthreads();
+
+        // the 9 pair sums of each centre voxel, then the epilogue
+        for (int c = tid; c < kBlockVox; c += 256) {
+            const int cx = c & 7, cy = (c >> 3) & 7, cz = c >> 6;
+            float acc = 0.f;
+            for (int n = 0; n < 9; ++n) {
+                const int row = (cz + n / 3) * 10 + (cy + n % 3);   // (z + kz - 1 + 1, y + ky - 1 + 1)
+                acc += P[n * 800 + 8 * row + cx];
+            }
+            int x = cx, y = cy, z = cz;
+            if (perm == 1) { const int sw = x; x = y; y = sw; }
+            if (perm == 2) { const int sw = x; x = z; z = sw; }
+            const int64_t gi = b * kBlockVox + x + 8 * y + 64 * z;
+            const float rv = acc + bias3;
+            const uint8_t em = emask[gi];
+            if (mode == DN_WARM_DUAL) {
+                out[perm * ps + gi] = ((em >> (perm + 1)) & 1) ? rv : 0.f;
+            } else {
+                float uu = 0.f;
+                if (em & 1) {
+                    uu = f[gi] + rv;
+                    uu = uu < -1.f ? -1.f : (uu > 1.f ? 1.f : uu);
                 }
+                out[gi] = uu;
             }
         }
+        // P overwrote the zero row of h1's first plane
+        if (tid < 4) reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(h1) + kT * 16)[tid] = 0u;
         __syncthreads();
     }
 }

@@ -176,6 +176,42 @@ def test_given_initial_state_and_ragged_capacity():
     assert gv.num_blocks == 20
 
 
+def test_candidates_survive_other_work_and_known_frames():
+    """The distinct candidate keys of the last frame are built when they are
+    extracted, from the frame's raw candidate list: a regularisation in
+    between (which reuses the sort scratch) must not change them, and a
+    frame whose blocks all exist allocates nothing but still reports its
+    candidates."""
+    D = dn()
+    fr = scenes.frames_c1(0)
+    cam = fr.camera
+    ov = oracle.OracleVolume(fr.voxel_size, fr.mu, fr.max_depth, 8192, 12, 256)
+    gv = D.Volume(fr.voxel_size, fr.mu, fr.max_depth, 8192, 12, 256)
+    K = intr(D, cam)
+    d0, T0 = fr.depths[0], fr.poses[0]
+    n_o = ov.alloc(d0, K4(cam), T0)
+    dd = to_dev(d0)
+    assert gv.alloc_blocks(dd, K, T0) == n_o > 0
+    gv.fuse_depth(dd, K, T0)
+    gv.regularize(D.reg_params(LAM, iters=5, kernel=D.DN_K_FUSED))
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_CANDIDATES)), ov.last_candidates)
+    # the same frame again: every candidate is known
+    assert ov.alloc(d0, K4(cam), T0) == 0
+    assert gv.alloc_blocks(dd, K, T0) == 0
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_CANDIDATES)), ov.last_candidates)
+    # a second extraction returns the same list
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_CANDIDATES)), ov.last_candidates)
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_COORDS)), ov.coords)
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_HASH)), ov.slots)
+    # a frame with new and known blocks, then a clear
+    d1, T1 = fr.depths[1], fr.poses[1]
+    assert gv.alloc_blocks(to_dev(d1), K, T1) == ov.alloc(d1, K4(cam), T1)
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_CANDIDATES)), ov.last_candidates)
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_NBR)), ov.nbr)
+    gv.clear()
+    assert host(gv.extract(D.DN_X_CANDIDATES)).shape == (0, 3)
+
+
 def test_error_paths_and_degenerate_inputs():
     D = dn()
     import torch
