@@ -406,7 +406,7 @@ __global__ void k_warm_finish(int64_t n, int64_t ps, const uint8_t *__restrict__
 
 // Process-wide network scratch.
 struct NetCtx {
-    Buf wpack, lanew, x0, h1, h2, r, d3, d2, d1, parts, chunks, mparts, misc, tl;
+    Buf wpack, lanew, x0, h1, h2, r, d3, d2, d1, parts, chunks, mparts, misc, tl, vpair;
 };
 static NetCtx g_net;
 
@@ -553,11 +553,21 @@ __device__ __forceinline__ void store_act(uint16_t *h, int mt, int g, int i, v4f
     }
 }
 
-// Layer-1 input of blocks [0, nb): per tile voxel one 32-bit word, the
-// bfloat16 pair (f, log(1 + w) / log(101)), 0 for voxels of unallocated
-// neighbours; perm as in k_gather.
-__global__ void k_gather_pairs(const int32_t *__restrict__ nbr, const float *__restrict__ f,
-                               const float *__restrict__ w, int64_t nb, int perm, uint32_t *__restrict__ xp)
+// Layer-1 input word of every voxel of the pool: the bfloat16 pair
+// (f, log(1 + w) / log(101)), computed once for the three axes.
+__global__ void k_voxel_pairs(const float *__restrict__ f, const float *__restrict__ w, int64_t n,
+                              uint32_t *__restrict__ pair)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float wv = float(log(1.0 + double(w[i])) / log(101.0));
+    pair[i] = uint32_t(f2bf(f[i])) | (uint32_t(f2bf(wv)) << 16);
+}
+
+// Layer-1 input of blocks [0, nb): per tile voxel its pair word, 0 (the
+// pair (0, 0)) for voxels of unallocated neighbours; perm as in k_gather.
+__global__ void k_gather_pairs(const int32_t *__restrict__ nbr, const uint32_t *__restrict__ pair, int64_t nb,
+                               int perm, uint32_t *__restrict__ xp)
 {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= nb * kT) return;
@@ -567,12 +577,7 @@ __global__ void k_gather_pairs(const int32_t *__restrict__ nbr, const float *__r
     if (perm == 1) { const int s = x; x = y; y = s; }
     if (perm == 2) { const int s = x; x = z; z = s; }
     const int64_t j = halo_vox(nbr + b * kNbr, x - 1, y - 1, z - 1);
-    float fv = 0.f, wv = 0.f;
-    if (j >= 0) {
-        fv = f[j];
-        wv = float(log(1.0 + double(w[j])) / log(101.0));
-    }
-    xp[k] = uint32_t(f2bf(fv)) | (uint32_t(f2bf(wv)) << 16);
+    xp[k] = j >= 0 ? pair[j] : 0u;
 }
 
 // mode DN_WARM_DUAL: out = p0, component perm written on the centre (kept
@@ -871,10 +876,12 @@ int dn_net_warm_start(dn_volume *v, const float *params, int32_t mode, double de
     const int64_t ps = v->nb * int64_t(kBlockVox);
     const int axes = mode == DN_WARM_DUAL ? 3 : 1;
     if ((rc = g_net.x0.ensure(size_t(v->nb) * kT * 4))) return rc;
+    if ((rc = g_net.vpair.ensure(size_t(ps) * 4))) return rc;
     uint32_t *xp = g_net.x0.as<uint32_t>();
+    uint32_t *vp = g_net.vpair.as<uint32_t>();
+    hipLaunchKernelGGL(k_voxel_pairs, dim3(grid1(ps)), dim3(256), 0, st, v->f, v->w, ps, vp);
     for (int a = 0; a < axes; ++a) {
-        hipLaunchKernelGGL(k_gather_pairs, dim3(grid1(v->nb * kT)), dim3(256), 0, st, v->nbr, v->f, v->w, v->nb, a,
-                           xp);
+        hipLaunchKernelGGL(k_gather_pairs, dim3(grid1(v->nb * kT)), dim3(256), 0, st, v->nbr, vp, v->nb, a, xp);
         hipLaunchKernelGGL(k_net_infer, dim3(grid), dim3(256), 0, st, xp, v->f, v->emask, v->nb,
                            mode == DN_WARM_DUAL ? a : 0, int(mode), g_net.lanew.as<uint16_t>(), params, ps,
                            mode == DN_WARM_DUAL ? p0 : u0);
