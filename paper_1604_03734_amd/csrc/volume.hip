@@ -674,18 +674,37 @@ __global__ void k_laser_obs_emit(LGeo g, const float *__restrict__ pts, int64_t 
 }
 
 // After the stable sort by voxel: the first observation of each voxel sums
-// its run in order and applies the scan's update.
+// its run in order and applies the scan's update.  Voxels near the sensor
+// are crossed by thousands of rays, so the run is read 16 observations at a
+// time (independent loads) and summed one after the other as before.
 __global__ void k_laser_apply(const uint32_t *__restrict__ keys, const double *__restrict__ vals, int64_t m,
                               float *__restrict__ f, float *__restrict__ w)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= m || (i > 0 && keys[i] == keys[i - 1])) return;
     const uint32_t v = keys[i];
+    constexpr int kChunk = 16;
     double sum = 0.0;
     int64_t k = 0;
-    for (int64_t j = i; j < m && keys[j] == v; ++j) {
-        sum += vals[j];
-        ++k;
+    bool more = true;
+    for (int64_t j = i; more; j += kChunk) {
+        uint32_t kk[kChunk];
+        double vv[kChunk];
+#pragma unroll
+        for (int e = 0; e < kChunk; ++e) {
+            const bool in = j + e < m;
+            kk[e] = in ? keys[j + e] : 0u;
+            vv[e] = in ? vals[j + e] : 0.0;
+            if (!in) kk[e] = v + 1u;   // ends the run (keys are voxel indices below 2^32 - 1)
+        }
+#pragma unroll
+        for (int e = 0; e < kChunk; ++e) {
+            more = more && kk[e] == v;
+            if (more) {
+                sum += vv[e];
+                ++k;
+            }
+        }
     }
     const double w0 = w[v];
     const double wn = w0 + double(k);
