@@ -212,8 +212,8 @@ int dn_fuse_depth(dn_volume *vol, const float *depth_dev, const dn_intrinsics *K
  * between the sensor and r + mu, with eta = r - (c - o) . D >= -mu (c the
  * voxel centre, o the sensor, D the world direction), observes
  * psi = min(1, eta / mu); one call applies all of its observations
- * together: f <- (w f + sum psi) / (w + k), w <- w + k (the sum in float64,
- * in the order of the returns).  Both synchronise. */
+ * together: f <- (w f + sum psi) / (w + k), w <- w + k (the sum in
+ * float64).  Both synchronise. */
 int dn_alloc_laser(dn_volume *vol, const float *pts_dev, int64_t n, const double T_gs[16], int32_t *n_new_out);
 int dn_fuse_laser(dn_volume *vol, const float *pts_dev, int64_t n, const double T_gs[16]);
 

@@ -8,6 +8,7 @@
 #include <rocprim/rocprim.hpp>
 
 #include <cstdarg>
+#include <algorithm>
 #include <cmath>
 
 #include "dn_internal.h"
@@ -507,7 +508,8 @@ static int make_geo(const dn_volume *v, const dn_intrinsics *K, const double *T,
 //   Fusion: the voxels met by rho in [0, r + mu] in allocated blocks with
 //   eta = r - (c - o) . D >= -mu give psi = min(1, eta / mu); one scan's
 //   observations are applied together, f <- (w f + sum psi) / (w + k),
-//   w <- w + k, the sum in float64 in ray order.
+//   w <- w + k, the sum in float64 (a segmented reduction over the
+//   observations sorted by voxel).
 struct LGeo {
     double T[16];
     double s, mu, maxd;
@@ -673,42 +675,18 @@ __global__ void k_laser_obs_emit(LGeo g, const float *__restrict__ pts, int64_t 
     });
 }
 
-// After the stable sort by voxel: the first observation of each voxel sums
-// its run in order and applies the scan's update.  Voxels near the sensor
-// are crossed by thousands of rays, so the run is read 16 observations at a
-// time (independent loads) and summed one after the other as before.
-__global__ void k_laser_apply(const uint32_t *__restrict__ keys, const double *__restrict__ vals, int64_t m,
+// One scan's update of each observed voxel, from the per-voxel sums and
+// counts of its observations (a segmented reduction of the sorted list).
+__global__ void k_laser_apply(const uint32_t *__restrict__ uniq, const double *__restrict__ sums,
+                              const uint32_t *__restrict__ counts, const uint32_t *__restrict__ nruns, int64_t m,
                               float *__restrict__ f, float *__restrict__ w)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= m || (i > 0 && keys[i] == keys[i - 1])) return;
-    const uint32_t v = keys[i];
-    constexpr int kChunk = 16;
-    double sum = 0.0;
-    int64_t k = 0;
-    bool more = true;
-    for (int64_t j = i; more; j += kChunk) {
-        uint32_t kk[kChunk];
-        double vv[kChunk];
-#pragma unroll
-        for (int e = 0; e < kChunk; ++e) {
-            const bool in = j + e < m;
-            kk[e] = in ? keys[j + e] : 0u;
-            vv[e] = in ? vals[j + e] : 0.0;
-            if (!in) kk[e] = v + 1u;   // ends the run (keys are voxel indices below 2^32 - 1)
-        }
-#pragma unroll
-        for (int e = 0; e < kChunk; ++e) {
-            more = more && kk[e] == v;
-            if (more) {
-                sum += vv[e];
-                ++k;
-            }
-        }
-    }
+    if (i >= m || i >= int64_t(*nruns)) return;
+    const uint32_t v = uniq[i];
     const double w0 = w[v];
-    const double wn = w0 + double(k);
-    f[v] = float((w0 * double(f[v]) + sum) / wn);
+    const double wn = w0 + double(counts[i]);
+    f[v] = float((w0 * double(f[v]) + sums[i]) / wn);
     w[v] = float(wn);
 }
 
@@ -1009,8 +987,9 @@ int dn_fuse_laser(dn_volume *v, const float *pts, int64_t n, const double T[16])
     DN_HIP(hipStreamSynchronize(st));
     const int64_t m = v->host.as<int64_t>()[0] + v->host.as<int64_t>()[1];
     if (m == 0) return DN_OK;
-    // keys and values, then their sorted copies
-    if ((rc = v->s_laser.ensure(size_t(m) * 24 * 2 + 256))) return rc;
+    DN_REQUIRE(m < (int64_t(1) << 32), "too many observations in one scan");
+    // keys, values, their sorted copies, the counts and the run count
+    if ((rc = v->s_laser.ensure(size_t(m) * 48 + 1024))) return rc;
     uint32_t *k_in = reinterpret_cast<uint32_t *>(v->s_laser.ptr);
     uint32_t *k_out = k_in + m;
     double *v_in = reinterpret_cast<double *>(static_cast<char *>(v->s_laser.ptr) + ((size_t(m) * 8 + 255) / 256) * 256);
@@ -1020,12 +999,24 @@ int dn_fuse_laser(dn_volume *v, const float *pts, int64_t n, const double T[16])
     DN_HIP(hipGetLastError());
     int bits = 1;
     while ((int64_t(1) << bits) < v->nb * int64_t(kBlockVox)) ++bits;
-    tb = 0;
-    DN_HIP(rocprim::radix_sort_pairs(nullptr, tb, k_in, k_out, v_in, v_out, size_t(m), 0, bits, st));
-    if ((rc = v->s_tmp.ensure(tb))) return rc;
+    // sort by voxel, then the sum and the count of each voxel's observations
+    // (distinct voxels into k_in / v_in, counts after the sorted values)
+    uint32_t *counts32 = reinterpret_cast<uint32_t *>(v_out + m);
+    uint32_t *nruns = counts32 + ((m + 63) / 64) * 64;
+    size_t t1 = 0, t2 = 0, t3 = 0;
+    DN_HIP(rocprim::radix_sort_pairs(nullptr, t1, k_in, k_out, v_in, v_out, size_t(m), 0, bits, st));
+    DN_HIP(rocprim::reduce_by_key(nullptr, t2, k_out, v_out, size_t(m), k_in, v_in, nruns, rocprim::plus<double>(),
+                                  rocprim::equal_to<uint32_t>(), st));
+    DN_HIP(rocprim::run_length_encode(nullptr, t3, k_out, size_t(m), k_in, counts32, nruns, st));
+    if ((rc = v->s_tmp.ensure(std::max(t1, std::max(t2, t3))))) return rc;
     tbytes = v->s_tmp.bytes;
     DN_HIP(rocprim::radix_sort_pairs(v->s_tmp.ptr, tbytes, k_in, k_out, v_in, v_out, size_t(m), 0, bits, st));
-    hipLaunchKernelGGL(k_laser_apply, dim3(grid1(m)), dim3(256), 0, st, k_out, v_out, m, v->f, v->w);
+    tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::reduce_by_key(v->s_tmp.ptr, tbytes, k_out, v_out, size_t(m), k_in, v_in, nruns,
+                                  rocprim::plus<double>(), rocprim::equal_to<uint32_t>(), st));
+    tbytes = v->s_tmp.bytes;
+    DN_HIP(rocprim::run_length_encode(v->s_tmp.ptr, tbytes, k_out, size_t(m), k_in, counts32, nruns, st));
+    hipLaunchKernelGGL(k_laser_apply, dim3(grid1(m)), dim3(256), 0, st, k_in, v_in, counts32, nruns, m, v->f, v->w);
     DN_HIP(hipGetLastError());
     v->emask_nb = -1;
     return DN_OK;
