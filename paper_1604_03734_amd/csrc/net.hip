@@ -539,16 +539,21 @@ __device__ __forceinline__ v4f mfma_chain(FA a_of, FB b_of)
 // Products are taken as W x A^T, so a lane holds 4 output channels
 // (4g .. 4g+3) of voxel i of the row tile: bias + ReLU, then one 8-byte
 // store per lane.
+// (bias + ReLU rounded to bfloat16 by the hardware's round-to-nearest-even
+// pair conversion, the same rounding as f2bf for these finite values)
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void store_act(uint16_t *h, int mt, int g, int i, v4f acc, const float *bias4)
 {
     const int vo = mt * 16 + i;
     if (vo < kT) {
-        uint16_t y[4];
+        float y[4];
         for (int r = 0; r < 4; ++r) {
             const float a = acc[r] + bias4[r];
-            y[r] = f2bf(a > 0.f ? a : 0.f);
+            y[r] = a > 0.f ? a : 0.f;
         }
-        const uint2 pk = make_uint2(uint32_t(y[0]) | (uint32_t(y[1]) << 16), uint32_t(y[2]) | (uint32_t(y[3]) << 16));
+        const uint2 pk = make_uint2(__builtin_bit_cast(uint32_t, __builtin_convertvector(v2f_t{y[0], y[1]}, v2bf_t)),
+                                    __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f_t{y[2], y[3]}, v2bf_t)));
         *reinterpret_cast<uint2 *>(reinterpret_cast<char *>(h) + act_byte(vo, g >> 1) + 8 * (g & 1)) = pk;
     }
 }
@@ -593,7 +598,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     __shared__ __align__(16) uint16_t h1[2 * kPlane / 2];
     __shared__ __align__(16) uint16_t h2[2 * kPlane / 2];
     __shared__ __align__(16) uint32_t x0[kT + 4];
+    __shared__ uint32_t okt[kMT * 16];   // tap masks of the tile voxels (0 past the tile)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int v = tid; v < kMT * 16; v += 256) okt[v] = v < kT ? tap_mask(v % 10, (v / 10) % 10, v / 100) : 0u;
     const int i = lane & 15, g = lane >> 4;
     const int half = g & 1, par = g >> 1;      // channel half and tap parity of this lane's K slots
     const v4u *lw4 = reinterpret_cast<const v4u *>(lw);
@@ -625,7 +632,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         // layer 1: 2 -> 16, ReLU
         for (int mt = wave; mt < kMT; mt += 4) {
             const int v = mt * 16 + i;
-            const uint32_t ok = v < kT ? tap_mask(v % 10, (v / 10) % 10, v / 100) : 0u;
+            const uint32_t ok = okt[v];
             v4u q[kL1M];
             for (int m = 0; m < kL1M; ++m)
                 for (int e = 0; e < 4; ++e) {
@@ -642,7 +649,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         // layer 2: 16 -> 16, ReLU
         for (int mt = wave; mt < kMT; mt += 4) {
             const int v = mt * 16 + i;
-            const uint32_t ok = v < kT ? tap_mask(v % 10, (v / 10) % 10, v / 100) : 0u;
+            const uint32_t ok = okt[v];
             const v4f acc = mfma_chain<kL2M, 5, false>(
                 [&](int m) {
                     const int o = par ? tap_off(2 * m + 1) : tap_off(2 * m);
