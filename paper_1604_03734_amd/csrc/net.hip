@@ -543,9 +543,8 @@ __device__ __forceinline__ v4f mfma_chain(FA a_of, FB b_of)
 // pair conversion, the same rounding as f2bf for these finite values)
 typedef float v2f_t __attribute__((ext_vector_type(2)));
 typedef __bf16 v2bf_t __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void store_act(uint16_t *h, int mt, int g, int i, v4f acc, const float *bias4)
+__device__ __forceinline__ void store_act(uint16_t *h, int vo, int g, v4f acc, const float *bias4)
 {
-    const int vo = mt * 16 + i;
     if (vo < kT) {
         float y[4];
         for (int r = 0; r < 4; ++r) {
@@ -599,8 +598,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     __shared__ __align__(16) uint16_t h2[2 * kPlane / 2];
     __shared__ __align__(16) uint32_t x0[kT + 4];
     __shared__ uint32_t okt[kMT * 16];   // tap masks of the tile voxels (0 past the tile)
+    __shared__ uint16_t vt[kMT * 16];    // voxel of each (row tile, lane column)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int v = tid; v < kMT * 16; v += 256) okt[v] = v < kT ? tap_mask(v % 10, (v / 10) % 10, v / 100) : 0u;
+    // Row tiles 0..31 hold the 512 voxels with x, y, z in 1..8 (two x-rows
+    // of 8 each), whose taps all stay in the tile; tiles 32..62 hold the
+    // other 488 voxels in linear order and 8 empty columns (kT).
+    for (int v = tid; v < kMT * 16; v += 256) {
+        okt[v] = v < kT ? tap_mask(v % 10, (v / 10) % 10, v / 100) : 0u;
+        if (v >= kT) {
+            vt[v] = uint16_t(kT);
+            continue;
+        }
+        const int x = v % 10, y = (v / 10) % 10, z = v / 100;
+        const bool iz = z >= 1 && z <= 8, iy = y >= 1 && y <= 8, ix = x >= 1 && x <= 8;
+        int before = 64 * min(max(z - 1, 0), 8);                  // interior voxels before v
+        if (iz) before += 8 * min(max(y - 1, 0), 8);
+        if (iz && iy) before += min(max(x - 1, 0), 8);
+        vt[(iz && iy && ix) ? before : 512 + (v - before)] = uint16_t(v);
+    }
     const int i = lane & 15, g = lane >> 4;
     const int half = g & 1, par = g >> 1;      // channel half and tap parity of this lane's K slots
     const v4u *lw4 = reinterpret_cast<const v4u *>(lw);
@@ -631,8 +646,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
         // layer 1: 2 -> 16, ReLU
         for (int mt = wave; mt < kMT; mt += 4) {
-            const int v = mt * 16 + i;
-            const uint32_t ok = okt[v];
+            const int v = vt[mt * 16 + i];
+            const uint32_t ok = mt < 32 ? 0x7FFFFFFu : okt[v];
             v4u q[kL1M];
             for (int m = 0; m < kL1M; ++m)
                 for (int e = 0; e < 4; ++e) {
@@ -642,22 +657,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 }
             v4f acc = {0.f, 0.f, 0.f, 0.f};
             for (int m = 0; m < kL1M; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W1[m], as_v8bf(q[m]), acc, 0, 0, 0);
-            store_act(h1, mt, g, i, acc, bias1);
+            store_act(h1, v, g, acc, bias1);
         }
         __syncthreads();
 
-        // layer 2: 16 -> 16, ReLU
+        // layer 2: 16 -> 16, ReLU; interior tiles read every tap at a fixed
+        // offset from the voxel (the past-the-end tap 27 reads the zero row)
         for (int mt = wave; mt < kMT; mt += 4) {
-            const int v = mt * 16 + i;
-            const uint32_t ok = okt[v];
-            const v4f acc = mfma_chain<kL2M, 5, false>(
-                [&](int m) {
-                    const int o = par ? tap_off(2 * m + 1) : tap_off(2 * m);
-                    const int nv = ((ok >> (2 * m + par)) & 1u) ? v + o : kT;
-                    return as_v8bf(lds_row(h1, act_byte(nv, half)));
-                },
-                [&](int m) { return W2[m]; });
-            store_act(h2, mt, g, i, acc, bias2);
+            const int v = vt[mt * 16 + i];
+            v4f acc;
+            if (mt < 32) {
+                const int base = act_byte(v, half), zero = act_byte(kT, half);
+                acc = mfma_chain<kL2M, 5, false>(
+                    [&](int m) {
+                        const int addr = par ? (2 * m + 1 < kTaps ? base + 16 * tap_off(2 * m + 1) : zero)
+                                             : base + 16 * tap_off(2 * m);
+                        return as_v8bf(lds_row(h1, addr));
+                    },
+                    [&](int m) { return W2[m]; });
+            } else {
+                const uint32_t ok = okt[v];
+                acc = mfma_chain<kL2M, 5, false>(
+                    [&](int m) {
+                        const int o = par ? tap_off(2 * m + 1) : tap_off(2 * m);
+                        const int nv = ((ok >> (2 * m + par)) & 1u) ? v + o : kT;
+                        return as_v8bf(lds_row(h1, act_byte(nv, half)));
+                    },
+                    [&](int m) { return W2[m]; });
+            }
+            store_act(h2, v, g, acc, bias2);
         }
         __syncthreads();
 
