@@ -81,3 +81,19 @@ def test_invalid_and_empty_scans_change_nothing():
     assert gv.num_blocks == nb
     np.testing.assert_array_equal(host(gv.extract(D.DN_X_F)), f0)
     np.testing.assert_array_equal(host(gv.extract(D.DN_X_W)), w0)
+
+
+def test_scans_of_one_and_three_returns():
+    """The smallest scans: a handful of observations (the scan's scratch
+    holds them, their sorted copies, the per-voxel counts and the count)."""
+    D = dn()
+    ov = oracle.OracleVolume(0.1, 0.3, 20.0, 1024, 10, 128)
+    gv = D.Volume(0.1, 0.3, 20.0, 1024, 10, 128)
+    T = _poses()[0]
+    for pts in (np.array([[2.0, 0.1, 0.05]], np.float32),
+                np.array([[1.5, 0.0, 0.0], [0.3, 1.1, 0.2], [-0.7, 0.2, 2.5]], np.float32)):
+        assert ov.alloc_laser(pts, T) == gv.alloc_laser(to_dev(pts), T)
+        ov.fuse_laser(pts, T)
+        gv.fuse_laser(to_dev(pts), T)
+        _check(D, ov, gv)
+    assert (ov.w > 0).sum() > 0
