@@ -600,9 +600,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     __shared__ uint32_t okt[kMT * 16];   // tap masks of the tile voxels (0 past the tile)
     __shared__ uint16_t vt[kMT * 16];    // voxel of each (row tile, lane column)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    // Row tiles 0..31 hold the 512 voxels with x, y, z in 1..8 (two x-rows
-    // of 8 each), whose taps all stay in the tile; tiles 32..62 hold the
-    // other 488 voxels in linear order and 8 empty columns (kT).
+    // Row tiles 0..31 hold the 512 voxels with x, y, z in 1..8, whose taps
+    // all stay in the tile: x = 1..8 of rows y and y + 4 of one z plane
+    // (640 bytes apart, so the 16 lanes' 16-byte reads cover the 64 LDS
+    // banks once); tiles 32..62 hold the other 488 voxels in linear order
+    // and 8 empty columns (kT).
     for (int v = tid; v < kMT * 16; v += 256) {
         okt[v] = v < kT ? tap_mask(v % 10, (v / 10) % 10, v / 100) : 0u;
         if (v >= kT) {
@@ -614,7 +616,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         int before = 64 * min(max(z - 1, 0), 8);                  // interior voxels before v
         if (iz) before += 8 * min(max(y - 1, 0), 8);
         if (iz && iy) before += min(max(x - 1, 0), 8);
-        vt[(iz && iy && ix) ? before : 512 + (v - before)] = uint16_t(v);
+        const int inner = 64 * (z - 1) + 16 * ((y - 1) % 4) + 8 * ((y - 1) / 4) + (x - 1);
+        vt[(iz && iy && ix) ? inner : 512 + (v - before)] = uint16_t(v);
     }
     const int i = lane & 15, g = lane >> 4;
     const int half = g & 1, par = g >> 1;      // channel half and tap parity of this lane's K slots
