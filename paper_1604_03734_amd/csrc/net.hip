@@ -558,7 +558,8 @@ __device__ __forceinline__ void store_act(uint16_t *h, int vo, int g, v4f acc, c
 }
 
 // Layer-1 input word of every voxel of the pool: the bfloat16 pair
-// (f, log(1 + w) / log(101)), computed once for the three axes.
+// (f, log(1 + w) / log(101)), computed once for the three axes; the
+// inference kernel reads its tiles from it through the neighbour table.
 __global__ void k_voxel_pairs(const float *__restrict__ f, const float *__restrict__ w, int64_t n,
                               uint32_t *__restrict__ pair)
 {
@@ -568,31 +569,15 @@ __global__ void k_voxel_pairs(const float *__restrict__ f, const float *__restri
     pair[i] = uint32_t(f2bf(f[i])) | (uint32_t(f2bf(wv)) << 16);
 }
 
-// Layer-1 input of blocks [0, nb): per tile voxel its pair word, 0 (the
-// pair (0, 0)) for voxels of unallocated neighbours; perm as in k_gather.
-__global__ void k_gather_pairs(const int32_t *__restrict__ nbr, const uint32_t *__restrict__ pair, int64_t nb,
-                               int perm, uint32_t *__restrict__ xp)
-{
-    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= nb * kT) return;
-    const int64_t b = k / kT;
-    const int v = int(k % kT);
-    int x = v % 10, y = (v / 10) % 10, z = v / 100;
-    if (perm == 1) { const int s = x; x = y; y = s; }
-    if (perm == 2) { const int s = x; x = z; z = s; }
-    const int64_t j = halo_vox(nbr + b * kNbr, x - 1, y - 1, z - 1);
-    xp[k] = j >= 0 ? pair[j] : 0u;
-}
-
 // mode DN_WARM_DUAL: out = p0, component perm written on the centre (kept
 // where m_perm = 1); mode DN_WARM_PRIMAL (perm 0): out = u0 =
 // clamp(f + r, -1, 1) on Omega, 0 elsewhere.  Workgroups loop over tiles;
 // the layer-1 input of the next tile is loaded while the current one is
 // computed.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_net_infer(
-    const uint32_t *__restrict__ xp, const float *__restrict__ f, const uint8_t *__restrict__ emask, int64_t nb,
-    int perm, int mode, const uint16_t *__restrict__ lw, const float *__restrict__ params, int64_t ps,
-    float *__restrict__ out)
+    const int32_t *__restrict__ nbr, const uint32_t *__restrict__ pair, const float *__restrict__ f,
+    const uint8_t *__restrict__ emask, int64_t nb, int perm, int mode, const uint16_t *__restrict__ lw,
+    const float *__restrict__ params, int64_t ps, float *__restrict__ out)
 {
     __shared__ __align__(16) uint16_t h1[2 * kPlane / 2];
     __shared__ __align__(16) uint16_t h2[2 * kPlane / 2];
@@ -636,16 +621,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     if (tid < 8) reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(h1) + (tid >> 2) * kPlane + kT * 16)[tid & 3] = 0u;
     if (tid == 0) x0[kT] = 0u;
 
-    const v4u *xp4 = reinterpret_cast<const v4u *>(xp);
-    constexpr int kQ = kT / 4;
-    v4u nxt = {0u, 0u, 0u, 0u};
-    if (blockIdx.x < nb && tid < kQ) nxt = xp4[int64_t(blockIdx.x) * kQ + tid];
+    // the layer-1 input of a tile, read from the pool's pair words through
+    // the neighbour table (tile voxels of unallocated blocks give 0), the
+    // next tile's while this one is computed
+    constexpr int kGet = (kT + 255) / 256;
+    uint32_t nxt[kGet];
+    auto fetch = [&](int64_t bb) {
+        const int32_t *nb27 = nbr + bb * kNbr;
+        for (int e = 0; e < kGet; ++e) {
+            const int k = tid + 256 * e;
+            nxt[e] = 0u;
+            if (k < kT) {
+                int x = k % 10, y = (k / 10) % 10, z = k / 100;
+                if (perm == 1) { const int sw = x; x = y; y = sw; }
+                if (perm == 2) { const int sw = x; x = z; z = sw; }
+                const int64_t j = halo_vox(nb27, x - 1, y - 1, z - 1);
+                if (j >= 0) nxt[e] = pair[j];
+            }
+        }
+    };
+    if (blockIdx.x < nb) fetch(blockIdx.x);
 
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        if (tid < kQ) reinterpret_cast<v4u *>(x0)[tid] = nxt;
+        for (int e = 0; e < kGet; ++e)
+            if (tid + 256 * e < kT) x0[tid + 256 * e] = nxt[e];
         __syncthreads();
         const int64_t bn = b + gridDim.x;
-        if (bn < nb && tid < kQ) nxt = xp4[bn * kQ + tid];
+        if (bn < nb) fetch(bn);
 
         // layer 1: 2 -> 16, ReLU
         for (int mt = wave; mt < kMT; mt += 4) {
@@ -913,14 +915,11 @@ int dn_net_warm_start(dn_volume *v, const float *params, int32_t mode, double de
     const unsigned grid = unsigned(std::min<int64_t>(v->nb, int64_t(2) * (cus > 0 ? cus : 1)));
     const int64_t ps = v->nb * int64_t(kBlockVox);
     const int axes = mode == DN_WARM_DUAL ? 3 : 1;
-    if ((rc = g_net.x0.ensure(size_t(v->nb) * kT * 4))) return rc;
     if ((rc = g_net.vpair.ensure(size_t(ps) * 4))) return rc;
-    uint32_t *xp = g_net.x0.as<uint32_t>();
     uint32_t *vp = g_net.vpair.as<uint32_t>();
     hipLaunchKernelGGL(k_voxel_pairs, dim3(grid1(ps)), dim3(256), 0, st, v->f, v->w, ps, vp);
     for (int a = 0; a < axes; ++a) {
-        hipLaunchKernelGGL(k_gather_pairs, dim3(grid1(v->nb * kT)), dim3(256), 0, st, v->nbr, vp, v->nb, a, xp);
-        hipLaunchKernelGGL(k_net_infer, dim3(grid), dim3(256), 0, st, xp, v->f, v->emask, v->nb,
+        hipLaunchKernelGGL(k_net_infer, dim3(grid), dim3(256), 0, st, v->nbr, vp, v->f, v->emask, v->nb,
                            mode == DN_WARM_DUAL ? a : 0, int(mode), g_net.lanew.as<uint16_t>(), params, ps,
                            mode == DN_WARM_DUAL ? p0 : u0);
         DN_HIP(hipGetLastError());
