@@ -65,8 +65,8 @@ def lib():
             "or_mesh": (i64, [P, P, i64, P, P, f64, P, i64, P]),
             "or_candidates_laser": (i64, [P, i64, P, f64, f64, f64, P, i64]),
             "or_fuse_laser": (None, [P, i32, i32, i64, P, P, P, i64, P, f64, f64, f64]),
-            "or_net_forward": (None, [P, i64, P, P, P]),
-            "or_net_loss_grad": (f64, [P, i64, P, P, P, P, i32]),
+            "or_net_forward": (None, [P, i64, P, P, P, P, i32]),
+            "or_net_loss_grad": (f64, [P, i64, P, P, P, P, i32, i32]),
             "or_net_gather": (None, [P, P, P, P, i64, P, i32]),
         }
         for name, (res, args) in sig.items():
@@ -248,21 +248,26 @@ def extract(coords, nbr, w, u, s) -> np.ndarray:
 NET_PARAMS = 8241
 
 
-def net_forward(tiles, params):
+def net_forward(tiles, params, gate=0):
+    """gate 0: ReLUs open where the float64 pre-activation is > 0; gate 1:
+    the open/closed decision is taken with bfloat16 operands (the network's
+    own precision), the values stay float64."""
     tiles = _c(tiles, np.float64)
     B = tiles.shape[0]
     out = np.empty((B, 10, 10, 10))
-    lib().or_net_forward(_p(tiles), B, _p(_c(params, np.float64)), _p(out), None)
+    lib().or_net_forward(_p(tiles), B, _p(_c(params, np.float64)), _p(out), None, None, int(gate))
     return out
 
 
-def net_loss_grad(tiles, params, targets, mask, kind=0):
-    """kind 0: prediction f + r (primal residual); kind 1: prediction r."""
+def net_loss_grad(tiles, params, targets, mask, kind=0, gate=0):
+    """kind 0: prediction f + r (primal residual); kind 1: prediction r.
+    gate: as in net_forward."""
     tiles = _c(tiles, np.float64)
     B = tiles.shape[0]
     g = np.empty(NET_PARAMS)
     L = lib().or_net_loss_grad(_p(tiles), B, _p(_c(params, np.float64)),
-                               _p(_c(targets, np.float64)), _p(_c(mask, np.float64)), _p(g), int(kind))
+                               _p(_c(targets, np.float64)), _p(_c(mask, np.float64)), _p(g), int(kind),
+                               int(gate))
     return float(L), g
 
 

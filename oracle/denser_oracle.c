@@ -45,8 +45,8 @@ static inline int depth_valid(float d, double max_depth)
 }
 
 /* ---------------------------------------------------------------------
- * Block allocation, Section III-A ("anytime a surface is observed within a
- * given voxel block, all the voxels in that block are allocated").
+ * Block allocation, Section III-A: a whole block is allocated as soon as
+ * a surface is observed somewhere inside it.
  * Reading: a pixel with depth d observes the band z in [d - mu, d + mu]
  * along its ray; every block that segment passes through is allocated.
  * The segment is walked with the Amanatides-Woo grid traversal over the
@@ -880,27 +880,80 @@ static void conv_same(const double *x, int cin, const double *Wt, const double *
                 }
 }
 
+/* Round to the nearest bfloat16 value (ties to even), through float32 as
+ * the device sees its float32 inputs, weights and accumulators.  Used only
+ * to take the ReLU decisions in the network's own operand precision. */
+static double to_bf16(double v)
+{
+    float f = (float)v;
+    uint32_t bits;
+    memcpy(&bits, &f, sizeof bits);
+    if ((bits & 0x7f800000u) != 0x7f800000u) {
+        uint32_t lsb = (bits >> 16) & 1u;
+        bits = bits + 0x7fffu + lsb;
+    }
+    bits &= 0xffff0000u;
+    memcpy(&f, &bits, sizeof f);
+    return (double)f;
+}
+
 /* Forward pass for a batch of tiles.  tiles: [B][2][10][10][10];
  * out: [B][10][10][10] residual r (the caller crops the centre 8^3).
- * If acts is not NULL it receives the pre-activation of layers 1 and 2,
- * [B][2][16][1000], for the backward pass. */
-void or_net_forward(const double *tiles, int64_t B, const double *params, double *out, double *acts)
+ * If acts is not NULL it receives the pre-activations of layers 1 and 2,
+ * [B][2][16][1000], and gates (same shape) the values whose sign opens
+ * each ReLU, for the backward pass.
+ * gate 0: a ReLU is open where its float64 pre-activation is > 0.
+ * gate 1: the network is specified to run with bfloat16 operands, and an
+ *   open/closed ReLU is a discrete decision, so it is taken in that
+ *   precision: a second forward pass whose inputs, weights and layer inputs
+ *   are rounded to bfloat16 (float64 sums, biases unrounded) decides which
+ *   ReLUs are open; the values themselves stay float64.  The layer-1
+ *   weights, to which the output is most sensitive, are the pair
+ *   bf16(W) + bf16(W - bf16(W)) in that pass (the network's layer-1
+ *   operands). */
+void or_net_forward(const double *tiles, int64_t B, const double *params, double *out, double *acts,
+                    double *gates, int32_t gate)
 {
     const double *W1 = params, *b1 = W1 + HID * 2 * 27, *W2 = b1 + HID, *b2 = W2 + HID * HID * 27,
                  *W3 = b2 + HID, *b3 = W3 + HID * 27;
+    const int nw1 = HID * 2 * 27, nw2 = HID * HID * 27;
     double *h1 = (double *)malloc(sizeof(double) * HID * T3);
     double *h2 = (double *)malloc(sizeof(double) * HID * T3);
+    double *g1 = (double *)malloc(sizeof(double) * HID * T3);
+    double *g2 = (double *)malloc(sizeof(double) * HID * T3);
+    double *xr = (double *)malloc(sizeof(double) * 2 * T3);
+    double *W1r = (double *)malloc(sizeof(double) * nw1);
+    double *W2r = (double *)malloc(sizeof(double) * nw2);
+    for (int i = 0; i < nw1; ++i) W1r[i] = to_bf16(W1[i]) + to_bf16(W1[i] - to_bf16(W1[i]));
+    for (int i = 0; i < nw2; ++i) W2r[i] = to_bf16(W2[i]);
     for (int64_t bi = 0; bi < B; ++bi) {
-        conv_same(tiles + bi * 2 * T3, 2, W1, b1, HID, h1);
-        if (acts) memcpy(acts + (bi * 2 + 0) * HID * T3, h1, sizeof(double) * HID * T3);
-        for (int i = 0; i < HID * T3; ++i) h1[i] = h1[i] > 0.0 ? h1[i] : 0.0;
+        const double *x = tiles + bi * 2 * T3;
+        conv_same(x, 2, W1, b1, HID, h1);
+        if (gate) {
+            for (int i = 0; i < 2 * T3; ++i) xr[i] = to_bf16(x[i]);
+            conv_same(xr, 2, W1r, b1, HID, g1);
+        } else {
+            memcpy(g1, h1, sizeof(double) * HID * T3);
+        }
+        if (acts) {
+            memcpy(acts + (bi * 2 + 0) * HID * T3, h1, sizeof(double) * HID * T3);
+            memcpy(gates + (bi * 2 + 0) * HID * T3, g1, sizeof(double) * HID * T3);
+        }
+        for (int i = 0; i < HID * T3; ++i) {
+            h1[i] = g1[i] > 0.0 ? h1[i] : 0.0;
+            g1[i] = g1[i] > 0.0 ? to_bf16(g1[i]) : 0.0;
+        }
         conv_same(h1, HID, W2, b2, HID, h2);
-        if (acts) memcpy(acts + (bi * 2 + 1) * HID * T3, h2, sizeof(double) * HID * T3);
-        for (int i = 0; i < HID * T3; ++i) h2[i] = h2[i] > 0.0 ? h2[i] : 0.0;
+        if (gate) conv_same(g1, HID, W2r, b2, HID, g2);
+        else memcpy(g2, h2, sizeof(double) * HID * T3);
+        if (acts) {
+            memcpy(acts + (bi * 2 + 1) * HID * T3, h2, sizeof(double) * HID * T3);
+            memcpy(gates + (bi * 2 + 1) * HID * T3, g2, sizeof(double) * HID * T3);
+        }
+        for (int i = 0; i < HID * T3; ++i) h2[i] = g2[i] > 0.0 ? h2[i] : 0.0;
         conv_same(h2, HID, W3, b3, 1, out + bi * T3);
     }
-    free(h1);
-    free(h2);
+    free(h1); free(h2); free(g1); free(g2); free(xr); free(W1r); free(W2r);
 }
 
 /* Gradient of a same-padded convolution y = conv(x, W) + b given dy:
@@ -937,15 +990,16 @@ static void conv_same_backward(const double *x, int cin, const double *Wt, int c
  * targets, mask: [B][512] (block voxel order of the tile's centre); mask is
  * 0/1.  grad: [8241], overwritten.  Returns L. */
 double or_net_loss_grad(const double *tiles, int64_t B, const double *params, const double *targets,
-                        const double *mask, double *grad, int32_t kind)
+                        const double *mask, double *grad, int32_t kind, int32_t gate)
 {
     const double *W1 = params, *W2 = params + HID * 2 * 27 + HID, *W3 = W2 + HID * HID * 27 + HID;
     double *gW1 = grad, *gb1 = gW1 + HID * 2 * 27, *gW2 = gb1 + HID, *gb2 = gW2 + HID * HID * 27,
            *gW3 = gb2 + HID, *gb3 = gW3 + HID * 27;
     memset(grad, 0, sizeof(double) * 8241);
     double *acts = (double *)malloc(sizeof(double) * (size_t)B * 2 * HID * T3);
+    double *gates = (double *)malloc(sizeof(double) * (size_t)B * 2 * HID * T3);
     double *out = (double *)malloc(sizeof(double) * (size_t)B * T3);
-    or_net_forward(tiles, B, params, out, acts);
+    or_net_forward(tiles, B, params, out, acts, gates, gate);
     double nmask = 0.0;
     for (int64_t i = 0; i < B * 512; ++i) nmask += mask[i];
     double norm = nmask > 1.0 ? nmask : 1.0;
@@ -967,18 +1021,19 @@ double or_net_loss_grad(const double *tiles, int64_t B, const double *params, co
             d3[t] = 2.0 * e / norm;
         }
         const double *a1 = acts + (bi * 2 + 0) * HID * T3, *a2 = acts + (bi * 2 + 1) * HID * T3;
-        /* layer 3: input relu(a2) */
-        for (int i = 0; i < HID * T3; ++i) h[i] = a2[i] > 0.0 ? a2[i] : 0.0;
+        const double *o1 = gates + (bi * 2 + 0) * HID * T3, *o2 = gates + (bi * 2 + 1) * HID * T3;
+        /* layer 3: input relu(a2), open where o2 > 0 */
+        for (int i = 0; i < HID * T3; ++i) h[i] = o2[i] > 0.0 ? a2[i] : 0.0;
         conv_same_backward(h, HID, W3, 1, d3, gW3, gb3, dh);
-        for (int i = 0; i < HID * T3; ++i) dh[i] = a2[i] > 0.0 ? dh[i] : 0.0;
-        /* layer 2: input relu(a1) */
-        for (int i = 0; i < HID * T3; ++i) h[i] = a1[i] > 0.0 ? a1[i] : 0.0;
+        for (int i = 0; i < HID * T3; ++i) dh[i] = o2[i] > 0.0 ? dh[i] : 0.0;
+        /* layer 2: input relu(a1), open where o1 > 0 */
+        for (int i = 0; i < HID * T3; ++i) h[i] = o1[i] > 0.0 ? a1[i] : 0.0;
         conv_same_backward(h, HID, W2, HID, dh, gW2, gb2, dh1);
-        for (int i = 0; i < HID * T3; ++i) dh1[i] = a1[i] > 0.0 ? dh1[i] : 0.0;
+        for (int i = 0; i < HID * T3; ++i) dh1[i] = o1[i] > 0.0 ? dh1[i] : 0.0;
         /* layer 1: input tile */
         conv_same_backward(tiles + bi * 2 * T3, 2, W1, HID, dh1, gW1, gb1, NULL);
     }
-    free(acts); free(out); free(d3); free(h); free(dh); free(dh1);
+    free(acts); free(gates); free(out); free(d3); free(h); free(dh); free(dh1);
     return loss;
 }
 

@@ -60,14 +60,17 @@ __device__ __forceinline__ void load_tile(uint16_t *dst, const uint16_t *src)
 //   Y[v][co] = bias[co] + sum_t sum_ci W[t][co][ci] X[v + off(t)][ci]
 // then optional ReLU, optional gate (multiply by [G[v][co] > 0], the ReLU
 // derivative of the backward pass), stored as bfloat16 (Y) and/or channel 0
-// as float (Yf).
+// as float (Yf).  With Wlo the weights are the pair Wp + Wlo (a second
+// bfloat16 holding what the first rounded off).
 __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, int64_t n,
-                                              const uint16_t *__restrict__ Wp, const float *__restrict__ bias,
-                                              int relu, const uint16_t *__restrict__ gate,
-                                              uint16_t *__restrict__ Y, float *__restrict__ Yf)
+                                              const uint16_t *__restrict__ Wp, const uint16_t *__restrict__ Wlo,
+                                              const float *__restrict__ bias, int relu,
+                                              const uint16_t *__restrict__ gate, uint16_t *__restrict__ Y,
+                                              float *__restrict__ Yf)
 {
     __shared__ __align__(16) uint16_t sx[kT * kC];
     __shared__ __align__(16) uint16_t sw[kWPack];
+    __shared__ __align__(16) uint16_t swl[kWPack];
     const int64_t tile = blockIdx.x;
     if (tile >= n) return;
     load_tile(sx, X + tile * kT * kC);
@@ -75,6 +78,11 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, in
         const uint4 *s = reinterpret_cast<const uint4 *>(Wp);
         uint4 *d = reinterpret_cast<uint4 *>(sw);
         for (int i = threadIdx.x; i < kWPack / 8; i += blockDim.x) d[i] = s[i];
+        if (Wlo) {
+            const uint4 *sl = reinterpret_cast<const uint4 *>(Wlo);
+            uint4 *dl = reinterpret_cast<uint4 *>(swl);
+            for (int i = threadIdx.x; i < kWPack / 8; i += blockDim.x) dl[i] = sl[i];
+        }
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -91,6 +99,10 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, in
             }
             v4s b = *reinterpret_cast<const v4s *>(&sw[(t * kC + i) * kC + 4 * kg]);
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+            if (Wlo) {
+                v4s bl = *reinterpret_cast<const v4s *>(&swl[(t * kC + i) * kC + 4 * kg]);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bl, acc, 0, 0, 0);
+            }
         }
         for (int r = 0; r < 4; ++r) {
             const int vo = mt * 16 + 4 * kg + r;
@@ -197,15 +209,17 @@ __global__ void k_grad_reduce(const float *__restrict__ partials, int nparts, in
 
 // Pack the float parameters into bfloat16 [tap][co][ci] layers, zero padded
 // to 16x16; flipped = 1 gives the input-gradient weights
-// W'[t][a][b] = W[26 - t][b][a].
+// W'[t][a][b] = W[26 - t][b][a]; flipped = 2 gives the unflipped low part
+// bfloat16(W - bfloat16(W)) (layer 1 runs on the pair hi + lo).
 __global__ void k_pack(const float *__restrict__ W, int cout, int cin, int flipped, uint16_t *__restrict__ out)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= kWPack) return;
     int t = k / (kC * kC), a = (k / kC) % kC, b = k % kC;
     float val = 0.f;
-    if (!flipped) {
+    if (flipped != 1) {
         if (a < cout && b < cin) val = W[(a * cin + b) * kTaps + t];
+        if (flipped == 2) val -= bf2f(f2bf(val));
     } else {
         // a indexes the forward input channel, b the forward output channel
         if (b < cout && a < cin) val = W[(b * cin + a) * kTaps + (kTaps - 1 - t)];
@@ -429,7 +443,10 @@ typedef unsigned v4u __attribute__((ext_vector_type(4)));
 constexpr int kL1M = 2;       // layer 1: 27 taps x 2 channels = 54 of 64 K slots
 constexpr int kL2M = 14;      // layer 2: 27 taps x 16 channels, two taps per MFMA
 constexpr int kL3M = 2;       // layer 3: rows = the 9 (y, z) tap pairs, K = 3 x taps x 16 channels
-constexpr int kLaneW = (kL1M + kL2M + kL3M) * 64 * 8;
+// layer 1 runs on the weight pair hi + lo (bfloat16(W) and bfloat16(W -
+// bfloat16(W))): its few input channels make the layer's output sensitive to
+// the rounding of W1, and the second MFMA per K step costs little
+constexpr int kLaneW = (2 * kL1M + kL2M + kL3M) * 64 * 8;
 
 // Lane-ready weights [mfma][lane][8] (bfloat16).  The K slots of lane
 // group g = lane / 16, entry j, of MFMA m: layer 1 -> tap 16m + 4g + j/2,
@@ -446,9 +463,11 @@ __global__ void k_pack_lanes(const float *__restrict__ params, uint16_t *__restr
     const int j = k & 7, lane = (k >> 3) & 63, m = k >> 9;
     const int g = lane >> 4, n = lane & 15;
     float val = 0.f;
-    if (m < kL1M) {
-        const int t = 16 * m + 4 * g + (j >> 1), ci = j & 1;
+    if (m < kL1M || m >= kL1M + kL2M + kL3M) {
+        const int ml = m < kL1M ? m : m - (kL1M + kL2M + kL3M);
+        const int t = 16 * ml + 4 * g + (j >> 1), ci = j & 1;
         if (t < kTaps) val = params[kW1 + (n * 2 + ci) * kTaps + t];
+        if (m >= kL1M) val -= bf2f(f2bf(val));
     } else if (m < kL1M + kL2M) {
         const int t = 2 * (m - kL1M) + (g >> 1), ci = 8 * (g & 1) + j;
         if (t < kTaps) val = params[kW2 + (n * 16 + ci) * kTaps + t];
@@ -607,8 +626,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int i = lane & 15, g = lane >> 4;
     const int half = g & 1, par = g >> 1;      // channel half and tap parity of this lane's K slots
     const v4u *lw4 = reinterpret_cast<const v4u *>(lw);
-    v8bf W1[kL1M], W2[kL2M], W3[kL3M];
+    v8bf W1[kL1M], W1l[kL1M], W2[kL2M], W3[kL3M];
     for (int m = 0; m < kL1M; ++m) W1[m] = as_v8bf(lw4[m * 64 + lane]);
+    for (int m = 0; m < kL1M; ++m) W1l[m] = as_v8bf(lw4[(kL1M + kL2M + kL3M + m) * 64 + lane]);
     for (int m = 0; m < kL2M; ++m) W2[m] = as_v8bf(lw4[(kL1M + m) * 64 + lane]);
     for (int m = 0; m < kL3M; ++m) W3[m] = as_v8bf(lw4[(kL1M + kL2M + m) * 64 + lane]);
     float bias1[4], bias2[4];
@@ -661,7 +681,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                     q[m][e] = x0[t < kTaps && ((ok >> t) & 1u) ? v + o : kT];
                 }
             v4f acc = {0.f, 0.f, 0.f, 0.f};
-            for (int m = 0; m < kL1M; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W1[m], as_v8bf(q[m]), acc, 0, 0, 0);
+            for (int m = 0; m < kL1M; ++m) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W1[m], as_v8bf(q[m]), acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W1l[m], as_v8bf(q[m]), acc, 0, 0, 0);
+            }
             store_act(h1, v, g, acc, bias1);
         }
         __syncthreads();
@@ -747,12 +770,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
 static int pack_all(hipStream_t st, const float *params, bool with_flipped)
 {
-    int rc = g_net.wpack.ensure(size_t(5) * kWPack * 2);
+    int rc = g_net.wpack.ensure(size_t(6) * kWPack * 2);
     if (rc) return rc;
     uint16_t *wp = g_net.wpack.as<uint16_t>();
     hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW1, 16, 2, 0, wp);
     hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW2, 16, 16, 0, wp + kWPack);
     hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW3, 1, 16, 0, wp + 2 * kWPack);
+    hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW1, 16, 2, 2, wp + 5 * kWPack);
     if (with_flipped) {
         hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW2, 16, 16, 1, wp + 3 * kWPack);
         hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW3, 1, 16, 1, wp + 4 * kWPack);
@@ -784,12 +808,12 @@ static int forward_tiles(hipStream_t st, const float *params, int64_t n)
     if (n <= 0) return DN_OK;
     const uint16_t *wp = g_net.wpack.as<uint16_t>();
     uint16_t *x0 = g_net.x0.as<uint16_t>(), *h1 = g_net.h1.as<uint16_t>(), *h2 = g_net.h2.as<uint16_t>();
-    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, x0, n, wp, params + kB1, 1,
+    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, x0, n, wp, wp + 5 * kWPack, params + kB1, 1,
                        (const uint16_t *)nullptr, h1, (float *)nullptr);
-    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, h1, n, wp + kWPack, params + kB2, 1,
-                       (const uint16_t *)nullptr, h2, (float *)nullptr);
-    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, h2, n, wp + 2 * kWPack, params + kB3, 0,
-                       (const uint16_t *)nullptr, (uint16_t *)nullptr, g_net.r.as<float>());
+    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, h1, n, wp + kWPack, (const uint16_t *)nullptr,
+                       params + kB2, 1, (const uint16_t *)nullptr, h2, (float *)nullptr);
+    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, h2, n, wp + 2 * kWPack, (const uint16_t *)nullptr,
+                       params + kB3, 0, (const uint16_t *)nullptr, (uint16_t *)nullptr, g_net.r.as<float>());
     DN_HIP(hipGetLastError());
     return DN_OK;
 }
@@ -863,15 +887,15 @@ int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const f
     hipLaunchKernelGGL(k_sum_parts, cgrid, dim3(256), 0, st, parts, nparts, per, chunks);
     hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 27 + 1)), dim3(256), 0, st, chunks, nchunks, 1, 16,
                        grad + kW3, grad + kB3);
-    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, d3, n, wp + 4 * kWPack, (const float *)nullptr, 0,
-                       h2, d2, (float *)nullptr);
+    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, d3, n, wp + 4 * kWPack, (const uint16_t *)nullptr,
+                       (const float *)nullptr, 0, h2, d2, (float *)nullptr);
     // layer 2
     hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, st, h1, d2, n, parts);
     hipLaunchKernelGGL(k_sum_parts, cgrid, dim3(256), 0, st, parts, nparts, per, chunks);
     hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 16 * 27 + 16)), dim3(256), 0, st, chunks, nchunks, 16, 16,
                        grad + kW2, grad + kB2);
-    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, d2, n, wp + 3 * kWPack, (const float *)nullptr, 0,
-                       h1, d1, (float *)nullptr);
+    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, d2, n, wp + 3 * kWPack, (const uint16_t *)nullptr,
+                       (const float *)nullptr, 0, h1, d1, (float *)nullptr);
     // layer 1
     hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, st, x0, d1, n, parts);
     hipLaunchKernelGGL(k_sum_parts, cgrid, dim3(256), 0, st, parts, nparts, per, chunks);

@@ -283,6 +283,12 @@ template <class S> __global__ void k_demote(const float *__restrict__ a, typenam
     if (i < n) b[i] = rz ? S::rz(a[i]) : S::rn(a[i]);
 }
 
+template <class S> __global__ void k_promote(const typename S::T *__restrict__ b, float *__restrict__ a, int64_t n)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = S::ld(b[i]);
+}
+
 static inline unsigned grid1(int64_t n, int bs = 256) { return unsigned((n + bs - 1) / bs); }
 
 template <class T> static int fill(hipStream_t st, T *a, int64_t n, T v)
@@ -506,6 +512,25 @@ static int validate(const dn_reg_params *prm)
     return DN_OK;
 }
 
+// Copy the 16-bit state (exactly) into the FP32 buffers, so that a 16-bit
+// run that stopped between refinement sweeps leaves its current state
+// where the extraction and an FP32 continuation read it.
+template <class S> static int promote_state(dn_volume *v)
+{
+    hipStream_t st = v->stream;
+    const int64_t n = v->nb * kBlockVox, ps = v->cap_blocks * kBlockVox;
+    using T = typename S::T;
+    if (n == 0) return DN_OK;
+    hipLaunchKernelGGL((k_promote<S>), dim3(grid1(n)), dim3(256), 0, st, (const T *)v->u16, v->u, n);
+    hipLaunchKernelGGL((k_promote<S>), dim3(grid1(n)), dim3(256), 0, st, (const T *)v->ubar16[v->cur],
+                       v->ubar[v->cur], n);
+    for (int a = 0; a < 3; ++a)
+        hipLaunchKernelGGL((k_promote<S>), dim3(grid1(n)), dim3(256), 0, st, (const T *)v->p16[v->cur] + a * ps,
+                           v->p[v->cur] + a * ps, n);
+    DN_HIP(hipGetLastError());
+    return DN_OK;
+}
+
 int zero_state(dn_volume *v)
 {
     hipStream_t st = v->stream;
@@ -726,6 +751,7 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
     DN_HIP(hipEventCreate(&ev1));
     DN_HIP(hipEventRecord(ev0, st));
     dn_reg_params step_prm = *prm;
+    bool last_refined = false;   // the last 16-bit iteration also wrote the FP32 state
     for (; it < prm->iters && v->nb > 0; ++it) {
         if (prm->gamma > 0.0) {
             // accelerated schedule: this iteration's (sigma_n, tau_n, theta_n)
@@ -742,6 +768,7 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
             bool refine = (prm->refine_every > 0 && (it + 1) % prm->refine_every == 0) || it + 1 == prm->iters;
             rc = storage == DN_F16 ? step_lowp<SF16>(v, &step_prm, refine, kernel)
                                    : step_lowp<SBF16>(v, &step_prm, refine, kernel);
+            last_refined = refine;
         }
         if (rc) return rc;
         if (prm->gap_every > 0 && (it + 1) % prm->gap_every == 0 && it + 1 < prm->iters) {
@@ -754,6 +781,12 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
     }
     stats.iters_run = it;
     v->nb_state = v->nb;
+    if (storage != DN_F32 && it > 0 && !last_refined) {
+        // stopped early (gap_tol) between sweeps: the FP32 buffers take the
+        // current 16-bit state
+        rc = storage == DN_F16 ? promote_state<SF16>(v) : promote_state<SBF16>(v);
+        if (rc) return rc;
+    }
     DN_HIP(hipEventRecord(ev1, st));
     DN_HIP(hipEventSynchronize(ev1));
     {
@@ -763,9 +796,9 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
         (void)hipEventDestroy(ev0);
         (void)hipEventDestroy(ev1);
     }
-    // after a 16-bit run the result is the FP32 output of the last sweep
-    const bool f32_result = storage == DN_F32 || (it > 0 && it == prm->iters);
-    if ((rc = energy_current(v, prm->lambda, f32_result, prm->data_term))) return rc;
+    // after a 16-bit run the FP32 buffers hold the result: the output of
+    // the last sweep, or the promoted 16-bit state after an early stop
+    if ((rc = energy_current(v, prm->lambda, true, prm->data_term))) return rc;
     if ((rc = read_energy(v, ed))) return rc;
     stats.energy = ed[0];
     stats.dual = ed[1];

@@ -1,5 +1,13 @@
 """Network kernels (BF16 MFMA, FP32 accumulation) against the FP64 oracle:
-gather, forward, loss gradient (all three layers), Adam, warm start."""
+gather, forward, loss gradient (all three layers), Adam, warm start.
+
+Bar: relative L2 error <= 1e-2 against the float64 oracle for the forward
+output, the gradient of every layer and the warm-start fields.  Whether a
+ReLU is open is a discrete decision that floating point takes; it is taken
+in the network's own precision on both sides (the oracle's gate 1: the sign
+of a pre-activation computed from bfloat16-rounded operands), the values
+are compared in float64.  The errors against the oracle with float64
+decisions (gate 0) are printed beside them."""
 import numpy as np
 import pytest
 
@@ -16,6 +24,9 @@ def _rel_l2(a, b):
 
 def _cos(a, b):
     return float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+BAR = 1e-2
 
 
 def _params(seed, scale=0.15):
@@ -46,9 +57,12 @@ def test_forward_matches_oracle(seed, B):
     out = torch.empty((B, 10, 10, 10), device="cuda")
     D.net_forward(to_dev(tiles, torch.float32), to_dev(prm, torch.float32), out)
     torch.cuda.synchronize()
-    ref = oracle.net_forward(tiles, prm)
+    ref = oracle.net_forward(tiles, prm, gate=1)
+    ref0 = oracle.net_forward(tiles, prm)
     g = host(out).astype(np.float64)
-    assert _rel_l2(g, ref) <= 2e-2 and _cos(g, ref) >= 0.999
+    print(f"forward B={B}: rel-L2 {_rel_l2(g, ref):.3e} max-abs {np.abs(g - ref).max():.3e} "
+          f"(float64 decisions: rel-L2 {_rel_l2(g, ref0):.3e})")
+    assert _rel_l2(g, ref) <= BAR and _cos(g, ref) >= 0.999
 
 
 def test_loss_gradient_matches_oracle():
@@ -63,13 +77,16 @@ def test_loss_gradient_matches_oracle():
     grad = torch.empty(oracle.NET_PARAMS, device="cuda")
     loss = D.net_loss_grad(to_dev(tiles, torch.float32), to_dev(prm, torch.float32),
                            to_dev(targets, torch.float32), to_dev(mask, torch.float32), grad)
-    L, g_ref = oracle.net_loss_grad(tiles, prm, targets, mask)
+    L, g_ref = oracle.net_loss_grad(tiles, prm, targets, mask, gate=1)
+    _, g_ref0 = oracle.net_loss_grad(tiles, prm, targets, mask)
     g = host(grad).astype(np.float64)
-    assert abs(loss - L) <= 2e-2 * abs(L)
+    print(f"loss {loss:.6e} oracle {L:.6e}")
+    assert abs(loss - L) <= BAR * abs(L)
     for lo, hi, name in [(0, 880, "layer1"), (880, 7808, "layer2"), (7808, 8241, "layer3")]:
         rel, cos = _rel_l2(g[lo:hi], g_ref[lo:hi]), _cos(g[lo:hi], g_ref[lo:hi])
-        print(f"{name}: rel-L2 {rel:.3e} cos {cos:.6f}")
-        assert rel <= 5e-2 and cos >= 0.998, name
+        print(f"{name}: rel-L2 {rel:.3e} cos {cos:.6f} (float64 decisions: rel-L2 "
+              f"{_rel_l2(g[lo:hi], g_ref0[lo:hi]):.3e})")
+        assert rel <= BAR and cos >= 0.999, name
 
 
 def test_adam_step():
@@ -102,10 +119,12 @@ def test_warm_start_fields():
     f = host(gv.extract(D.DN_X_F)).astype(np.float64)
     w = ov.w
     tiles = oracle.net_gather(ov.nbr, f, w, np.arange(nb, dtype=np.int32))
-    r = oracle.net_forward(tiles, prm)[:, 1:9, 1:9, 1:9].reshape(nb, 512)
+    r = oracle.net_forward(tiles, prm, gate=1)[:, 1:9, 1:9, 1:9].reshape(nb, 512)
     ref = np.where(w > 0, np.clip(f + r, -1, 1), 0.0)
     gu = host(u0).astype(np.float64)
-    assert np.abs(gu - ref).max() <= 3e-2
+    om = w > 0
+    print(f"primal warm start: rel-L2 {_rel_l2(gu[om], ref[om]):.3e} max-abs {np.abs(gu - ref).max():.3e}")
+    assert _rel_l2(gu[om], ref[om]) <= BAR
     assert (gu[w == 0] == 0).all()
     g = oracle.grad(ov.nbr, w, gu) / 0.1
     nrm = np.maximum(1.0, np.sqrt((g ** 2).sum(0)))
@@ -137,10 +156,15 @@ def test_dual_kind_loss_gradient_matches_oracle():
     grad = torch.empty(oracle.NET_PARAMS, device="cuda")
     loss = D.net_loss_grad(to_dev(tiles, torch.float32), to_dev(prm, torch.float32),
                            to_dev(targets, torch.float32), to_dev(mask, torch.float32), grad, kind=1)
-    L, g_ref = oracle.net_loss_grad(tiles, prm, targets, mask, kind=1)
+    L, g_ref = oracle.net_loss_grad(tiles, prm, targets, mask, kind=1, gate=1)
+    _, g_ref0 = oracle.net_loss_grad(tiles, prm, targets, mask, kind=1)
     g = host(grad).astype(np.float64)
-    assert abs(loss - L) <= 2e-2 * abs(L)
-    assert _rel_l2(g, g_ref) <= 5e-2 and _cos(g, g_ref) >= 0.998
+    print(f"dual kind loss {loss:.6e} oracle {L:.6e}")
+    assert abs(loss - L) <= BAR * abs(L)
+    for lo, hi, name in [(0, 880, "layer1"), (880, 7808, "layer2"), (7808, 8241, "layer3")]:
+        rel = _rel_l2(g[lo:hi], g_ref[lo:hi])
+        print(f"dual kind {name}: rel-L2 {rel:.3e} (float64 decisions: {_rel_l2(g[lo:hi], g_ref0[lo:hi]):.3e})")
+        assert rel <= BAR and _cos(g[lo:hi], g_ref[lo:hi]) >= 0.999, name
 
 
 def test_dual_warm_start_matches_oracle():
@@ -160,7 +184,8 @@ def test_dual_warm_start_matches_oracle():
     em = host(gv.extract(D.DN_X_EMASK))
     ref = np.zeros((3, nb, 512))
     for a in range(3):
-        r = oracle.net_forward(oracle.net_gather(ov.nbr, f, ov.w, np.arange(nb, dtype=np.int32), a), prm)
+        r = oracle.net_forward(oracle.net_gather(ov.nbr, f, ov.w, np.arange(nb, dtype=np.int32), a), prm,
+                               gate=1)
         c = r[:, 1:9, 1:9, 1:9]                     # tile centre [z'][y'][x']
         if a == 1:
             c = c.transpose(0, 1, 3, 2)
@@ -168,5 +193,10 @@ def test_dual_warm_start_matches_oracle():
             c = c.transpose(0, 3, 2, 1)
         ref[a] = np.where((em >> (a + 1)) & 1, c.reshape(nb, 512), 0.0)
     ref = ref / np.maximum(1.0, np.sqrt((ref ** 2).sum(0)))
-    assert np.abs(host(p0) - ref).max() <= 3e-2
+    gp = host(p0).astype(np.float64)
+    for a in range(3):
+        ma = ((em >> (a + 1)) & 1).astype(bool)
+        rel = _rel_l2(gp[a][ma], ref[a][ma])
+        print(f"dual warm start axis {a}: rel-L2 {rel:.3e} max-abs {np.abs(gp[a] - ref[a]).max():.3e}")
+        assert rel <= BAR, a
     assert np.array_equal(host(u0), np.where(ov.w > 0, f, 0.0).astype(np.float32))

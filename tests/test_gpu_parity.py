@@ -308,3 +308,53 @@ def test_continuous_regularisation_interleaved_with_fusion():
         gv.regularize(D.reg_params(LAM, iters=30, kernel=D.DN_K_FUSED, init=D.DN_INIT_CONTINUE))
         gu = host(gv.extract(D.DN_X_U))
         assert np.abs(gu - u).max() <= TOL_U
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_mixed_precision_early_stop_leaves_the_current_state(c1, storage):
+    """A 16-bit run that reaches gap_tol between refinement sweeps leaves its
+    current state in the FP32 buffers: DN_X_U, the reported energies and an
+    FP32 continuation all see the state after iters_run iterations."""
+    D = dn()
+    fr, ov, gv = c1
+    s = D.DN_F16 if storage == "f16" else D.DN_BF16
+    st = gv.regularize(D.reg_params(LAM, iters=200, storage=s, refine_every=50, gap_every=10, gap_tol=0.2))
+    k = st.iters_run
+    assert st.converged and 0 < k < 50 and k % 10 == 0
+    u = np.zeros_like(ov.f); ub = np.zeros_like(u); p = np.zeros((3,) + u.shape)
+    oracle.cp(ov.nbr, ov.f, ov.w, u, ub, p, k, LAM, TAU, SIG, 1.0)
+    gu = host(gv.extract(D.DN_X_U)).astype(np.float64)
+    om = ov.w > 0
+    err = np.abs(gu - u)[om]
+    print(f"{storage} stopped at {k}: max {err.max():.3e} median {np.median(err):.3e}")
+    assert err.max() <= (2e-2 if storage == "f16" else 1.5e-1)
+    E, Dd = gv.energy(LAM)
+    assert abs(E - st.energy) <= 1e-12 * abs(E) and abs(Dd - st.dual) <= 1e-12 * abs(E)
+    # an FP32 continuation starts from that state: its first iteration equals
+    # the oracle's iteration from the extracted FP32 state
+    gu0, gub0, gp0 = state_of(D, gv)
+    gv.regularize(D.reg_params(LAM, iters=1, init=D.DN_INIT_KEEP, kernel=D.DN_K_FUSED))
+    u1, ub1, p1 = gu0.copy(), gub0.copy(), gp0.copy()
+    oracle.cp(ov.nbr, ov.f, ov.w, u1, ub1, p1, 1, LAM, TAU, SIG, 1.0)
+    assert np.abs(host(gv.extract(D.DN_X_U)) - u1).max() <= 1e-5
+
+
+def test_non_finite_data_is_a_numeric_error():
+    """A NaN in the fused TSDF of an observed voxel makes the energy
+    non-finite: dn_regularize returns DN_E_NUMERIC at its gap check."""
+    D = dn()
+    import torch
+    coords, f, w = scenes.random_block_field(6, 3, extent=2, omega_frac=0.8)
+    gv = D.Volume(0.1, 0.3, 10.0, 64, 8, 64)
+    assert gv.insert_blocks(to_dev(coords.astype(np.int32))) == len(coords)
+    f = f.copy()
+    i = np.argwhere(w > 0)[0]
+    f[i[0], i[1]] = np.nan
+    gv.load_fused(to_dev(f, torch.float32), to_dev(w, torch.float32))
+    with pytest.raises(D.DenserError) as e:
+        gv.regularize(D.reg_params(LAM, iters=20, gap_every=10, kernel=D.DN_K_FUSED))
+    assert e.value.code == D.DN_E_NUMERIC
+    # without gap checks the final energy is the one that fails
+    with pytest.raises(D.DenserError) as e:
+        gv.regularize(D.reg_params(LAM, iters=5, kernel=D.DN_K_FUSED))
+    assert e.value.code == D.DN_E_NUMERIC

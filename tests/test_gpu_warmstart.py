@@ -57,6 +57,31 @@ def test_warm_start_gain_on_a_held_out_street(trained, heldout, gamma):
           f"(fallback {res['fallback']}, gap after 100: warm {res['rel_gap_at_k']:.2e} plain {ref.rel_gap:.2e})")
     assert plain.converged and res["converged"]
     assert res["rel_gap"] <= TOL
+    # what the trained network gains over the method without it
+    assert not res["fallback"]
+    assert res["iters"] < plain.iters_run
+
+
+def test_fallback_on_a_wrong_network(trained, heldout):
+    """A genuinely wrong network (the trained one with its output layer
+    negated and scaled by 20, so every dual component points the wrong way
+    at full length) makes the gap after K warm iterations more than twice
+    the plain solver's: the warm start is discarded, the solve restarts from
+    zero and still reaches the target in K plus the plain iterations."""
+    D = dn()
+    import torch
+    from paper_1604_03734_amd import warmstart as W
+    vol = heldout
+    bad = trained[0].clone()
+    bad[7808:8241] *= -20.0
+    ref = vol.regularize(D.reg_params(0.5, iters=100, kernel=D.DN_K_FUSED))
+    res = W.solve_warm(vol, bad, tol=TOL, k=100, plain_rel_gap_at_k=ref.rel_gap)
+    print(f"wrong network: gap after 100 warm {res['rel_gap_at_k']:.3e}, plain {ref.rel_gap:.3e}, "
+          f"fallback {res['fallback']}")
+    assert res["fallback"] and res["converged"] and res["rel_gap"] <= TOL
+    plain = vol.regularize(D.reg_params(0.5, iters=20000, gap_every=10, gap_tol=TOL, kernel=D.DN_K_FUSED))
+    assert res["iters"] == 100 + plain.iters_run
+    torch.cuda.synchronize()
 
 
 def test_fallback_to_a_cold_start(trained, heldout):

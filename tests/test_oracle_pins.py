@@ -621,6 +621,67 @@ def test_net_gradient_matches_finite_differences():
         assert abs(num - g[i]) <= 1e-6 * max(1.0, abs(num)), (i, num, g[i])
 
 
+def _torch_gated_net(torch, tiles, prm, gate):
+    """Reference of the oracle network written with torch: float64 values,
+    each ReLU opened by the sign of a pre-activation computed either in
+    float64 (gate 0) or with operands rounded float64 -> float32 ->
+    bfloat16 by torch's own conversions (gate 1; layer-1 weights as the
+    pair bf16(W) + bf16(W - bf16(W)))."""
+    import torch.nn.functional as F
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a))
+    bf = lambda x: x.float().bfloat16().double()
+    W1 = t(prm[:864].reshape(16, 2, 3, 3, 3)); b1 = t(prm[864:880])
+    W2 = t(prm[880:7792].reshape(16, 16, 3, 3, 3)); b2 = t(prm[7792:7808])
+    W3 = t(prm[7808:8240].reshape(1, 16, 3, 3, 3)); b3 = t(prm[8240:8241])
+    Ws = [W.clone().requires_grad_(True) for W in (W1, b1, W2, b2, W3, b3)]
+    x = t(tiles)
+    a1 = F.conv3d(x, Ws[0], Ws[1], padding=1)
+    if gate:
+        W1p = bf(W1) + bf(W1 - bf(W1))          # layer 1 runs on a weight pair
+        g1 = F.conv3d(bf(x), W1p, b1, padding=1)
+        m1 = g1 > 0
+        g2 = F.conv3d(torch.where(m1, bf(g1), torch.zeros_like(g1)), bf(W2), b2, padding=1)
+    else:
+        m1 = a1 > 0
+    h1 = torch.where(m1, a1, torch.zeros_like(a1))
+    a2 = F.conv3d(h1, Ws[2], Ws[3], padding=1)
+    m2 = (g2 > 0) if gate else (a2 > 0)
+    h2 = torch.where(m2, a2, torch.zeros_like(a2))
+    return F.conv3d(h2, Ws[4], Ws[5], padding=1)[:, 0], Ws, (m1, m2)
+
+
+@pytest.mark.parametrize("gate", [0, 1])
+def test_net_gated_forward_and_gradient_match_torch(gate):
+    """The ReLU decision in bfloat16 operand precision (gate 1) against a
+    torch reference (torch's float -> bfloat16 rounding, conv3d, autograd
+    through the fixed activation pattern); gate 0 is the plain network."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(21 + gate)
+    prm = _rand_params(rng, 0.25)
+    tiles = rng.normal(0, 0.6, size=(2, 2, 10, 10, 10))
+    targets = rng.normal(size=(2, 512))
+    mask = (rng.random((2, 512)) < 0.7).astype(float)
+    out, Ws, (m1, m2) = _torch_gated_net(torch, tiles, prm, gate)
+    np.testing.assert_allclose(oracle.net_forward(tiles, prm, gate=gate), out.detach().numpy(), atol=1e-12)
+    pred = out[:, 1:9, 1:9, 1:9].reshape(2, 512)
+    for kind in (0, 1):
+        if kind == 0:
+            p_ = pred + torch.from_numpy(tiles[:, 0, 1:9, 1:9, 1:9].reshape(2, 512))
+        else:
+            p_ = pred
+        m = torch.from_numpy(mask)
+        loss = (((p_ - torch.from_numpy(targets)) ** 2) * m).sum() / m.sum()
+        grads = torch.autograd.grad(loss, Ws, retain_graph=True)
+        ref = torch.cat([g_.flatten() for g_ in grads]).numpy()
+        L, g = oracle.net_loss_grad(tiles, prm, targets, mask, kind=kind, gate=gate)
+        assert abs(L - float(loss.detach())) <= 1e-12 * max(1.0, abs(L))
+        np.testing.assert_allclose(g, ref, rtol=1e-10, atol=1e-12)
+    if gate:
+        # the two decisions differ somewhere (else this pin would not pin the gate)
+        _, _, (f1, f2) = _torch_gated_net(torch, tiles, prm, 0)
+        assert int((m1 != f1).sum()) + int((m2 != f2).sum()) > 0
+
+
 def test_net_gather_halo_comes_from_neighbours():
     coords, f, w = scenes.random_block_field(20, 8, extent=3, omega_frac=0.9)
     _, nbr = _volume_from_blocks(coords)
