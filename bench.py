@@ -117,8 +117,11 @@ class Workload:
         cam = self.fr.camera
         self.K = D.intrinsics(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height)
         self.depths = [torch.from_numpy(d).cuda() for d in self.fr.depths]
-        self.street = D.Volume(self.fr.voxel_size, self.fr.mu, self.fr.max_depth, 16384, 16, 1024)
-        self.big = D.Volume(self.fr.voxel_size, self.fr.mu, self.fr.max_depth, 1 << 18, 19, 8192)
+        self.street = D.Volume(self.fr.voxel_size, self.fr.mu, self.fr.max_depth, 16384, 16, 1024,
+                               max_points=cam.width * cam.height)
+        # the map is built from keys (no sensor input)
+        self.big = D.Volume(self.fr.voxel_size, self.fr.mu, self.fr.max_depth, 1 << 18, 19, 8192,
+                            max_points=0, max_candidates=1 << 18)
         self.kernel = {"auto": D.DN_K_AUTO, "fused": D.DN_K_FUSED, "fused256": D.DN_K_FUSED256,
                        "twopass": D.DN_K_TWOPASS}[args.kernel]
         torch.cuda.synchronize()
@@ -174,7 +177,8 @@ class BatchedWorkload(Workload):
         cap = int(self.counts.max())
         for n in self.counts:
             self.subs.append(self.D.Volume(self.fr.voxel_size, self.fr.mu, self.fr.max_depth, int(n),
-                                           max(10, int(np.ceil(np.log2(n))) + 1), 4096))
+                                           max(10, int(np.ceil(np.log2(n))) + 1), 4096, max_points=0,
+                                           state16=False))
         self.fuse_street()
         self._layout()
 
@@ -344,7 +348,10 @@ def laser_throughput(wl, n_scans=10, rings=64, azimuth=1024):
     scans = [torch.from_numpy(scenes.laser_scan(boxes, T, k, n_rings=rings, n_azimuth=azimuth,
                                                  elev_deg=(-25.0, 3.0), max_range=50.0)).cuda()
              for k, T in enumerate(poses)]
-    vol = D.Volume(wl.fr.voxel_size, wl.fr.mu, wl.fr.max_depth, 1 << 16, 18, 4096)
+    n_ret = rings * azimuth
+    vol = D.Volume(wl.fr.voxel_size, wl.fr.mu, wl.fr.max_depth, 1 << 16, 18, 4096, max_points=n_ret,
+                   max_observations=D.laser_observations_bound(n_ret, wl.fr.voxel_size, wl.fr.mu,
+                                                              wl.fr.max_depth))
     for pts, T in zip(scans[:2], poses[:2]):
         vol.integrate_laser(pts, T)
     vol.clear()

@@ -12,9 +12,18 @@
  *  - All device work is ordered on the HIP stream given to dn_volume_create
  *    (or dn_set_stream).  Calls that must return a count or a status to the
  *    host synchronise that stream before returning; the others only enqueue.
- *  - The library allocates the volume's own device storage at creation
- *    (sized by max_blocks) and grows internal scratch on demand; it frees
- *    everything in dn_volume_destroy.
+ *  - The library never allocates device memory.  A volume lives in one
+ *    arena of dn_volume_bytes(params) bytes that the caller allocates and
+ *    passes to dn_volume_create (pool, hash table, fields, solver state and
+ *    the scratch every later call needs, sized there from the params'
+ *    limits); the batched solver and the network calls take a workspace of
+ *    the size their *_bytes function gives.  Calls whose input exceeds a
+ *    limit return DN_E_CAPACITY and change nothing.  The caller frees the
+ *    arena after dn_volume_destroy.
+ *  - The library keeps no device state between calls outside the arenas
+ *    and workspaces; host-side caches (kernel choices of the tuners, one
+ *    captured batch graph per device) are guarded by a mutex.  Calls on
+ *    one volume must not overlap.
  *  - Return value: DN_OK (0) or a negative DN_E_* code; dn_last_error()
  *    gives a thread-local message for the last failure.  A failed call
  *    leaves the volume unchanged unless its comment says otherwise.
@@ -93,6 +102,19 @@ typedef struct {
     int32_t max_blocks;      /* capacity of the block pool                   */
     int32_t hash_cap_log2;   /* the table has 2^hash_cap_log2 buckets ...    */
     int32_t hash_tail;       /* ... plus this many overflow slots            */
+    int32_t state16;         /* 1: room for FP16/BF16 solver state (DN_F16,
+                                DN_BF16 storage), 18 more bytes per voxel   */
+    int64_t max_points;      /* most pixels of one depth map (width x height)
+                                or returns of one laser scan a call takes
+                                (0: the volume takes no sensor data)        */
+    int64_t max_candidates;  /* most band cells (repeats counted) one
+                                dn_alloc_blocks / dn_alloc_laser call may
+                                list, and most keys of one dn_insert_blocks
+                                call; a pixel's band crosses at most
+                                4 + sqrt(3) 2 mu |r| / (8 s) blocks, r its
+                                ray direction with unit depth              */
+    int64_t max_observations; /* most voxel observations one dn_fuse_laser
+                                call may make (0: no laser fusion)          */
 } dn_volume_params;
 
 typedef struct {
@@ -144,12 +166,24 @@ typedef struct {
 
 /* ------------------------------------------------------------ lifecycle */
 
-/* Create an empty volume.  hash_cap_log2 in [4, 30], hash_tail >= 0,
- * max_blocks >= 1, voxel_size > 0, mu > 0, max_depth > 0.  hip_stream is a
- * hipStream_t (NULL: the default stream).  *out receives the handle. */
-int dn_volume_create(const dn_volume_params *params, void *hip_stream, dn_volume **out);
+/* Bytes of device memory a volume with these parameters needs (its arena),
+ * or 0 if the parameters are invalid.  Pure arithmetic: no device call. */
+size_t dn_volume_bytes(const dn_volume_params *params);
 
-/* Release all device storage of the volume (synchronises its stream). */
+/* Create an empty volume in the caller's arena.  hash_cap_log2 in [4, 30],
+ * hash_tail >= 0, max_blocks >= 1, voxel_size > 0, mu > 0, max_depth > 0,
+ * max_points, max_candidates, max_observations >= 0.  arena_dev: device
+ * memory of arena_bytes >= dn_volume_bytes(params) bytes, 256-byte aligned,
+ * owned by the caller and used by the volume until dn_volume_destroy.
+ * hip_stream is a hipStream_t (NULL: the default stream).  *out receives
+ * the handle.  DN_E_INVALID for bad parameters or a null or misaligned
+ * arena, DN_E_CAPACITY for a short arena (both checked before any device
+ * call). */
+int dn_volume_create(const dn_volume_params *params, void *arena_dev, size_t arena_bytes, void *hip_stream,
+                     dn_volume **out);
+
+/* Release the handle (synchronises the volume's stream first).  The arena
+ * is the caller's to free afterwards. */
 void dn_volume_destroy(dn_volume *vol);
 
 /* Remove every block (the volume becomes empty; its capacity is kept).
@@ -180,14 +214,16 @@ const char *dn_last_error(void);
  * (bucket, key) order) and the 27-neighbour table are rebuilt.
  * depth_dev: float32 [height][width].  T_gc: host float64[16].
  * *n_new_out (host, may be NULL) receives the number of new blocks.
- * DN_E_CAPACITY if the pool or the table would overflow (volume unchanged).
- * Synchronises the stream. */
+ * DN_E_CAPACITY if width x height exceeds max_points, the band cells
+ * exceed max_candidates, or the pool or the table would overflow (volume
+ * unchanged).  Synchronises the stream. */
 int dn_alloc_blocks(dn_volume *vol, const float *depth_dev, const dn_intrinsics *K,
                     const double T_gc[16], int32_t *n_new_out);
 
 /* Append explicit block keys (int32 [n][3], device) with the same rules as
  * dn_alloc_blocks (duplicates and existing keys are ignored; new keys are
- * appended in ascending order).  Synchronises the stream. */
+ * appended in ascending order).  n <= max_candidates (else DN_E_CAPACITY).
+ * Synchronises the stream. */
 int dn_insert_blocks(dn_volume *vol, const int32_t *coords_dev, int64_t n, int32_t *n_new_out);
 
 /* --------------------------------------------------------------- fusion */
@@ -213,7 +249,9 @@ int dn_fuse_depth(dn_volume *vol, const float *depth_dev, const dn_intrinsics *K
  * voxel centre, o the sensor, D the world direction), observes
  * psi = min(1, eta / mu); one call applies all of its observations
  * together: f <- (w f + sum psi) / (w + k), w <- w + k (the sum in
- * float64).  Both synchronise. */
+ * float64).  Both synchronise.  DN_E_CAPACITY (volume unchanged) if n
+ * exceeds max_points, the band cells max_candidates or the observations
+ * max_observations. */
 int dn_alloc_laser(dn_volume *vol, const float *pts_dev, int64_t n, const double T_gs[16], int32_t *n_new_out);
 int dn_fuse_laser(dn_volume *vol, const float *pts_dev, int64_t n, const double T_gs[16]);
 
@@ -232,10 +270,18 @@ int dn_load_fused(dn_volume *vol, const float *f_dev, const float *w_dev);
  * div = -grad^T (Eq. 4).  Voxels outside Omega keep their u.
  * u0_dev (float [n_blocks][512]) and p0_dev (float [3][n_blocks][512]) are
  * read only with init == DN_INIT_GIVEN.  out_host (may be NULL) receives the
- * final energies.  DN_E_NUMERIC if the gap becomes non-finite.  Synchronises
- * the stream (at every gap check and at the end). */
+ * final energies.  DN_E_NUMERIC if the gap becomes non-finite.  16-bit
+ * storage needs a volume created with state16 (else DN_E_INVALID).  A
+ * 16-bit run leaves its result in the FP32 state as well (the output of its
+ * last refinement sweep, or, when gap_tol stops it between sweeps, its
+ * current state).  Synchronises the stream (at every gap check and at the
+ * end). */
 int dn_regularize(dn_volume *vol, const dn_reg_params *params, const float *u0_dev,
                   const float *p0_dev, dn_reg_stats *out_host);
+
+/* Workspace bytes of dn_regularize_batch for n volumes holding
+ * total_blocks blocks together (0 for bad arguments). */
+size_t dn_regularize_batch_bytes(int32_t n, int64_t total_blocks);
 
 /* Regularise n independent volumes with the same parameters in ONE
  * persistent kernel launch (a grid-wide barrier separates iterations),
@@ -243,9 +289,13 @@ int dn_regularize(dn_volume *vol, const dn_reg_params *params, const float *u0_d
  * pairs balanced over the grid.  All volumes must share one device; the
  * first volume's stream is used.  gap_every / gap_tol are ignored (the
  * gaps are computed once at the end); init must be ZERO or KEEP; storage
- * must be DN_F32.  out_host: n stats (may be NULL). */
-int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_reg_params *params,
-                        dn_reg_stats *out_host);
+ * must be DN_F32.  workspace_dev: caller device memory of at least
+ * dn_regularize_batch_bytes(n, sum of the volumes' blocks) bytes, 256-byte
+ * aligned (else DN_E_CAPACITY / DN_E_INVALID); the captured graph refers to
+ * it and is replayed while the same workspace, volumes and parameters come
+ * back.  out_host: n stats (may be NULL). */
+int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_reg_params *params, void *workspace_dev,
+                        size_t workspace_bytes, dn_reg_stats *out_host);
 
 /* Primal and dual energies of the current state for the data term
  * data_term (DN_DATA_L2 or DN_DATA_L1): out_host[0] = E(u),
@@ -296,18 +346,25 @@ int dn_mesh_area(dn_volume *vol, double *area_host, int64_t *n_tris_host);
  * energy unchanged, so one network serves every axis. */
 int dn_net_gather(dn_volume *vol, const int32_t *blocks_dev, int64_t n, int32_t perm, float *tiles_dev);
 
-/* Forward pass: out_dev float [n][10][10][10] (the residual r). */
+/* Workspace bytes of dn_net_forward (training 0) or dn_net_loss_grad
+ * (training 1) on n tiles (0 for bad arguments). */
+size_t dn_net_bytes(int64_t n_tiles, int32_t training);
+
+/* Forward pass: out_dev float [n][10][10][10] (the residual r).
+ * workspace_dev: device memory of dn_net_bytes(n, 0) bytes, 256-byte
+ * aligned (else DN_E_CAPACITY / DN_E_INVALID). */
 int dn_net_forward(const float *tiles_dev, int64_t n, const float *params_dev, float *out_dev,
-                   void *hip_stream);
+                   void *workspace_dev, size_t workspace_bytes, void *hip_stream);
 
 /* Masked mean-squared loss on the centre 8^3 and its gradient: the
  * prediction is f + r (kind 0, a primal residual) or r (kind 1, a dual
  * component); targets_dev, mask_dev float [n][512] in the tile's centre
  * order (mask 0/1); grad_dev float [8241] (overwritten).  *loss_host
- * receives the loss (synchronises). */
+ * receives the loss (synchronises).  workspace_dev: dn_net_bytes(n, 1)
+ * bytes. */
 int dn_net_loss_grad(const float *tiles_dev, int64_t n, const float *params_dev,
                      const float *targets_dev, const float *mask_dev, int32_t kind, float *grad_dev,
-                     double *loss_host, void *hip_stream);
+                     void *workspace_dev, size_t workspace_bytes, double *loss_host, void *hip_stream);
 
 /* One Adam step on n float32 parameters (m, v: moments, step >= 1). */
 int dn_net_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, int64_t n,
@@ -321,11 +378,13 @@ int dn_net_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v
  *    the volume's axis a and its output is taken as the dual component p_a
  *    (kept where m_a = 1); p0 is projected onto the unit ball and u0 = f on
  *    Omega.  delta is unused.
- * Enqueue only. */
+ * workspace_dev: device memory of dn_warm_start_bytes(number of blocks)
+ * bytes, 256-byte aligned.  Enqueue only. */
 #define DN_WARM_PRIMAL 0
 #define DN_WARM_DUAL 1
+size_t dn_warm_start_bytes(int64_t n_blocks);
 int dn_net_warm_start(dn_volume *vol, const float *params_dev, int32_t mode, double delta,
-                      float *u0_dev, float *p0_dev);
+                      float *u0_dev, float *p0_dev, void *workspace_dev, size_t workspace_bytes);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "cp_kernel.h"
@@ -298,9 +299,9 @@ __global__ void k_make_items(const int32_t *__restrict__ order, int64_t nb, int3
     if (i < nb) items[i] = make_int2(vol, order ? order[i] : int32_t(i));
 }
 
-// Process-wide batch context (device buffers and the cached graph).
+// Per-device batch context: the cached graph and the private stream it is
+// captured on and replayed on (the device buffers are the caller's workspace).
 struct BatchCtx {
-    Buf descs, items, state;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     // key of the captured graph
@@ -314,11 +315,28 @@ struct BatchCtx {
     hipStream_t cap = nullptr;        // private stream for capture and replay
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
-static BatchCtx g_batch;
+static std::map<int, BatchCtx> g_batch;     // by device
+static std::mutex g_batch_mutex;             // held for a whole batched call
 
 // (threads per workgroup, workgroups per CU, XCD-chunked items, pool order)
 struct TuneChoice { int nt; int wg_per_cu; int xcd; int pool; };
-static std::map<int, TuneChoice> g_tuned;
+static std::map<int64_t, TuneChoice> g_tuned;   // by (device, size bucket)
+
+// The workspace of one batched call: volume descriptors, work items and
+// the barrier state.
+struct BatchWS {
+    VolDesc *descs;
+    int2 *items;
+    unsigned *state;
+};
+static BatchWS carve_batch(Bump &b, int32_t n, int64_t total)
+{
+    BatchWS x;
+    x.descs = b.take<VolDesc>(size_t(n));
+    x.items = b.take<int2>(size_t(total > 0 ? total : 1));
+    x.state = b.take<unsigned>(size_t(kBarWords));
+    return x;
+}
 
 static int size_bucket(int64_t n)
 {
@@ -351,9 +369,8 @@ static int launch_direct(hipStream_t st, const BatchArgs &a, int grid, int nt)
 // Capture (once per configuration) and replay on a private stream that is
 // ordered after and before the caller's stream with events (the caller's
 // stream may be the null stream, which cannot be captured).
-static int launch_graph(hipStream_t st, const BatchArgs &a, int grid, int nt)
+static int launch_graph(BatchCtx &c, hipStream_t st, const BatchArgs &a, int grid, int nt)
 {
-    BatchCtx &c = g_batch;
     if (!c.cap) {
         DN_HIP(hipStreamCreateWithFlags(&c.cap, hipStreamNonBlocking));
         DN_HIP(hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming));
@@ -391,13 +408,16 @@ static int launch_graph(hipStream_t st, const BatchArgs &a, int grid, int nt)
     return DN_OK;
 }
 
-static int check_err(hipStream_t st, int32_t *err_dev, HostBuf &host)
+static int check_err(dn_volume *v0, hipStream_t st, int32_t *err_dev)
 {
-    int rc = host.ensure(64);
+    hipStream_t keep = v0->stream;
+    v0->stream = st;
+    int rc = read_back(v0, err_dev, 4);
+    v0->stream = keep;
     if (rc) return rc;
-    DN_HIP(hipMemcpyAsync(host.ptr, err_dev, 4, hipMemcpyDeviceToHost, st));
-    DN_HIP(hipStreamSynchronize(st));
-    if (*host.as<int32_t>() != 0) {
+    int32_t err = 0;
+    memcpy(&err, v0->host_stage, 4);
+    if (err != 0) {
         set_error("persistent kernel: a grid barrier wait exceeded its bound (workgroups not co-resident)");
         return DN_E_DEVICE;
     }
@@ -408,9 +428,20 @@ static int check_err(hipStream_t st, int32_t *err_dev, HostBuf &host)
 
 using namespace dn;
 
-extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_reg_params *prm, dn_reg_stats *out)
+extern "C" size_t dn_regularize_batch_bytes(int32_t n, int64_t total_blocks)
+{
+    if (n <= 0 || total_blocks < 0) return 0;
+    Bump b(nullptr, 0);
+    carve_batch(b, n, total_blocks);
+    return (b.off + 255) & ~size_t(255);
+}
+
+extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_reg_params *prm, void *workspace,
+                                   size_t workspace_bytes, dn_reg_stats *out)
 {
     DN_REQUIRE(vols && n > 0 && prm, "bad argument");
+    DN_REQUIRE(workspace && (reinterpret_cast<uintptr_t>(workspace) & 255) == 0,
+               "the workspace must be non-null and 256-byte aligned");
     DN_REQUIRE(prm->lambda > 0 && prm->tau > 0 && prm->sigma > 0 && prm->tau * prm->sigma * 12.0 <= 1.0 + 1e-9,
                "bad step sizes");
     DN_REQUIRE(prm->theta >= 0 && prm->theta <= 1 && prm->iters >= 0, "bad theta or iters");
@@ -428,6 +459,17 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     hipStream_t st = v0->stream;
     int rc;
     int64_t total = 0;
+    for (int i = 0; i < n; ++i) total += vols[i]->nb;
+    if (workspace_bytes < dn_regularize_batch_bytes(n, total)) {
+        set_error("workspace of %zu bytes is short: %zu needed (dn_regularize_batch_bytes)", workspace_bytes,
+                  dn_regularize_batch_bytes(n, total));
+        return DN_E_CAPACITY;
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mutex);
+    BatchCtx &c = g_batch[v0->device];
+    Bump bump(workspace, workspace_bytes);
+    const BatchWS ws = carve_batch(bump, n, total);
+    total = 0;
     for (int i = 0; i < n; ++i) {
         dn_volume *v = vols[i];
         // each volume's own work must be ordered before ours
@@ -441,10 +483,6 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
         if (rc) return rc;
         total += v->nb;
     }
-    BatchCtx &c = g_batch;
-    if ((rc = c.descs.ensure(sizeof(VolDesc) * size_t(n)))) return rc;
-    if ((rc = c.items.ensure(sizeof(int2) * size_t(total > 0 ? total : 1)))) return rc;
-    if ((rc = c.state.ensure(sizeof(unsigned) * kBarWords))) return rc;
     std::vector<VolDesc> hd(n);
     for (int i = 0; i < n; ++i) {
         dn_volume *v = vols[i];
@@ -455,7 +493,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
         d.cur = v->cur;
         d.pad = 0;
     }
-    DN_HIP(hipMemcpyAsync(c.descs.ptr, hd.data(), sizeof(VolDesc) * size_t(n), hipMemcpyHostToDevice, st));
+    DN_HIP(hipMemcpyAsync(ws.descs, hd.data(), sizeof(VolDesc) * size_t(n), hipMemcpyHostToDevice, st));
     // work items (volume, block): volume after volume, blocks in Morton or pool order
     auto build_items = [&](int pool) -> int {
         int64_t ofs = 0;
@@ -463,7 +501,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
             dn_volume *v = vols[i];
             if (v->nb > 0) {
                 hipLaunchKernelGGL(k_make_items, dim3(unsigned((v->nb + 255) / 256)), dim3(256), 0, st,
-                                   pool ? (const int32_t *)nullptr : v->order, v->nb, i, c.items.as<int2>() + ofs);
+                                   pool ? (const int32_t *)nullptr : v->order, v->nb, i, ws.items + ofs);
                 DN_HIP(hipGetLastError());
             }
             ofs += v->nb;
@@ -472,8 +510,8 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     };
 
     BatchArgs a;
-    a.vols = c.descs.as<VolDesc>();
-    a.items = c.items.as<int2>();
+    a.vols = ws.descs;
+    a.items = ws.items;
     a.n_items = total;
     a.sigma = float(prm->sigma); a.tau = float(prm->tau); a.lambda = float(prm->lambda); a.theta = float(prm->theta);
     // the accelerated schedule of the batch lives in the first volume
@@ -481,8 +519,8 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     a.gamma = prm->gamma;
     a.tau0 = v0->acc_tau;
     a.sigma0 = v0->acc_sigma;
-    a.bar = c.state.as<unsigned>();
-    a.err = reinterpret_cast<int32_t *>(c.state.as<unsigned>() + 2 * kBarSlot);
+    a.bar = ws.state;
+    a.err = reinterpret_cast<int32_t *>(ws.state + 2 * kBarSlot);
     a.spin_limit = 1LL << 22;
     a.xcd_chunks = 1;
     a.l1 = prm->data_term == DN_DATA_L1;
@@ -496,7 +534,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     if (per_cu257 < 1) { set_error("persistent kernel does not fit on a compute unit"); return DN_E_DEVICE; }
 
     TuneChoice ch = TuneChoice{257, per_cu257, 1, 0};
-    const int key = size_bucket(total);
+    const int64_t key = (int64_t(v0->device) << 32) | size_bucket(total);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
         ch = it->second;
@@ -523,7 +561,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
                         if ((rc = launch_direct(st, t, grid, nt))) return rc;
                         DN_HIP(hipEventRecord(e1, st));
                         DN_HIP(hipEventSynchronize(e1));
-                        if ((rc = check_err(st, t.err, v0->host))) return rc;
+                        if ((rc = check_err(v0, st, t.err))) return rc;
                         float ms = 0;
                         DN_HIP(hipEventElapsedTime(&ms, e0, e1));
                         if (getenv("DN_VERBOSE"))
@@ -555,7 +593,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     DN_HIP(hipEventCreate(&e1));
     DN_HIP(hipEventRecord(e0, st));
     if (total > 0 && prm->iters > 0) {
-        if ((rc = launch_graph(st, a, grid, ch.nt))) return rc;
+        if ((rc = launch_graph(c, st, a, grid, ch.nt))) return rc;
     }
     DN_HIP(hipEventRecord(e1, st));
     DN_HIP(hipEventSynchronize(e1));
@@ -563,7 +601,7 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     DN_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if ((rc = check_err(st, a.err, v0->host))) return rc;
+    if ((rc = check_err(v0, st, a.err))) return rc;
     if (prm->gamma > 0.0)
         for (int k = 0; k < prm->iters; ++k) {
             const double th = 1.0 / std::sqrt(1.0 + 2.0 * prm->gamma * v0->acc_tau);

@@ -38,23 +38,47 @@ void set_error(const char *fmt, ...);
         }                                                                      \
     } while (0)
 
-// A device buffer that only grows.
-struct Buf {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-    int ensure(size_t need);   // DN_OK or DN_E_DEVICE
-    void release();
-    template <class T> T *as() const { return static_cast<T *>(ptr); }
+// Bump allocator over caller-owned device memory.  With a null base it
+// only measures (the same sequence of take() calls sizes a region and later
+// carves it, so sizing and use cannot disagree).  Every piece starts on a
+// 256-byte boundary.
+struct Bump {
+    char *base;
+    size_t cap;
+    size_t off = 0;
+    Bump(void *b, size_t c) : base(static_cast<char *>(b)), cap(c) {}
+    template <class T> T *take(size_t n)
+    {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+    bool fits() const { return off <= cap; }
 };
 
-// Pinned host staging for small read-backs.
-struct HostBuf {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-    int ensure(size_t need);
-    void release();
-    template <class T> T *as() const { return static_cast<T *>(ptr); }
+// Temporary storage handed to the rocprim calls: a bound on what they ask
+// for (a radix sort needs one copy of its keys and values plus small
+// tables, the scans, selections and reductions a few bytes per thousand
+// items), so every scratch region is sized before the first call.  rocprim
+// checks the size it is given and fails (no write) if it needed more; the
+// library also compares the bounds with rocprim's own figures once per
+// volume.
+inline size_t tmp_sort(size_t n, size_t key_value_bytes) { return n * key_value_bytes + n / 2 + (size_t(2) << 20); }
+inline size_t tmp_light(size_t n) { return n / 16 + (size_t(1) << 20); }
+
+// The scratch buffers of one insertion of n_cand candidate keys into a
+// pool that will hold at most n_blocks blocks (volume.hip).
+struct InsertScratch {
+    uint8_t *flags;
+    uint64_t *newraw, *sorted, *newk, *ksorted;
+    int32_t *ids0, *ids1;
+    uint32_t *home, *home2;
+    int64_t *dm, *runmax;
+    void *tmp;
+    size_t tmp_bytes;
 };
+InsertScratch carve_insert(Bump &b, int64_t n_cand, int64_t n_blocks);
 
 }  // namespace dn
 
@@ -83,7 +107,7 @@ struct dn_volume {
     float *ubar[2] = {nullptr, nullptr};
     float *p[2] = {nullptr, nullptr};   // each [3][max][512]
     int cur = 0;                        // index of the current ubar/p buffers
-    // 16-bit solver state (allocated on first use)
+    // 16-bit solver state (in the arena when the volume has state16)
     void *u16 = nullptr;
     void *ubar16[2] = {nullptr, nullptr};
     void *p16[2] = {nullptr, nullptr};
@@ -98,27 +122,31 @@ struct dn_volume {
     double *partials = nullptr;         // [max][2]
     double *energy2 = nullptr;          // [2] device
 
-    // scratch for allocation and extraction
-    dn::Buf s_cand, s_cand2, s_counts, s_offsets, s_tmp, s_uniq, s_flags, s_new, s_sorted,
-        s_vals, s_vals2, s_home, s_home2, s_pos, s_misc, s_laser;
-    dn::Buf s_newk;                     // distinct new keys of an insertion
-    int64_t last_nuniq = 0;             // distinct candidates of the last frame (once built)
-    const uint64_t *cand_src = nullptr; // raw candidate list of the last frame
-    int64_t cand_n = 0;
-    bool cand_pending = false;          // its distinct list is not built yet
-    dn::HostBuf host;
+    // caller-owned arena: everything above lives in it, then
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    uint64_t *cand = nullptr;           // [max_candidates] raw candidate keys of the last frame
+    int64_t cand_n = 0;                 // how many the last allocation call listed
+    int64_t *misc = nullptr;            // small device counters (256 bytes)
+    char *scratch = nullptr;            // per-call scratch, reused by every call
+    size_t scratch_bytes = 0;
+    int64_t host_stage[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // host side of small read-backs
 };
 
 namespace dn {
 // regularize.hip
 int build_masks(dn_volume *v);
+size_t masks_scratch(int64_t n_blocks);
 // volume.hip
-int ensure_candidates(dn_volume *v);
-int ensure_lowp(dn_volume *v);
+int build_candidates(dn_volume *v, uint64_t **uniq, int64_t *n_uniq);
+size_t candidates_scratch(int64_t n_cand);
 int zero_state(dn_volume *v);
 int energy_current(dn_volume *v, double lambda, bool use_f32, int data_term);
 int read_energy(dn_volume *v, double out[2]);
 int reduce_pairs(dn_volume *v, int64_t n);
 // volume.hip
 int volume_sync(dn_volume *v);
+int read_back(dn_volume *v, const void *dev, size_t bytes);   // into v->host_stage, synchronises
+// extract.hip
+size_t extract_scratch(int64_t n_blocks);
 }  // namespace dn

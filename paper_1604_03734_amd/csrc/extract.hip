@@ -306,6 +306,52 @@ __global__ void k_unpack_keys(const uint64_t *__restrict__ k, int64_t n, int32_t
     out[3 * i + 2] = int32_t(int64_t(k[i] & m) - off);
 }
 
+struct ScanScratch {
+    int64_t *cnt, *ofs;
+    void *tmp;
+    size_t tmp_bytes;
+};
+static ScanScratch carve_scan(Bump &b, int64_t nb)
+{
+    ScanScratch x;
+    x.cnt = b.take<int64_t>(size_t(nb) + 1);
+    x.ofs = b.take<int64_t>(size_t(nb) + 1);
+    x.tmp_bytes = tmp_light(size_t(nb) + 1);
+    x.tmp = b.take<char>(x.tmp_bytes);
+    return x;
+}
+
+size_t extract_scratch(int64_t n_blocks)
+{
+    Bump b(nullptr, 0);
+    carve_scan(b, n_blocks);
+    return b.off;
+}
+
+// Per-block counts (count_kernel) -> offsets -> total, in the scratch.
+template <class CountK>
+static int count_and_scan(dn_volume *v, CountK count_kernel, ScanScratch &x, int64_t *total)
+{
+    hipStream_t st = v->stream;
+    const int64_t nb = v->nb;
+    Bump bump(v->scratch, v->scratch_bytes);
+    x = carve_scan(bump, nb);
+    if (!bump.fits()) { set_error("scratch too small for the extraction"); return DN_E_CAPACITY; }
+    if (nb > 0) {
+        hipLaunchKernelGGL(count_kernel, dim3(unsigned(nb)), dim3(512), 0, st, nb, v->nbr, v->emask, v->u, x.cnt);
+        DN_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_fill_zero_i64, dim3(1), dim3(1), 0, st, x.cnt + nb);
+    DN_HIP(hipGetLastError());
+    size_t tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::exclusive_scan(x.tmp, tbytes, x.cnt, x.ofs, int64_t(0), size_t(nb + 1), rocprim::plus<int64_t>(),
+                                   st));
+    int rc = read_back(v, x.ofs + nb, 8);
+    if (rc) return rc;
+    *total = v->host_stage[0];
+    return DN_OK;
+}
+
 }  // namespace dn
 
 using namespace dn;
@@ -318,6 +364,7 @@ extern "C" int dn_extract(dn_volume *v, int32_t what, void *out, size_t out_byte
     int64_t items = 0;
     size_t need = 0;
     int rc;
+    uint64_t *uniq = nullptr;
     switch (what) {
     case DN_X_COORDS: items = nb; need = size_t(nb) * 12; break;
     case DN_X_HASH: items = v->hash_slots; need = size_t(items) * 16; break;
@@ -326,68 +373,33 @@ extern "C" int dn_extract(dn_volume *v, int32_t what, void *out, size_t out_byte
     case DN_X_P: items = nb; need = size_t(nv) * 12; break;
     case DN_X_EMASK: items = nb; need = size_t(nv); break;
     case DN_X_CANDIDATES:
-        if ((rc = ensure_candidates(v))) return rc;
-        items = v->last_nuniq;
+        if ((rc = build_candidates(v, &uniq, &items))) return rc;
         need = size_t(items) * 12;
         break;
     case DN_X_SURFACE: {
         if ((rc = build_masks(v))) return rc;
-        if ((rc = v->s_counts.ensure((nb + 1) * 8))) return rc;
-        if ((rc = v->s_offsets.ensure((nb + 1) * 8))) return rc;
-        int64_t *cnt = v->s_counts.as<int64_t>(), *ofs = v->s_offsets.as<int64_t>();
-        if (nb > 0) {
-            hipLaunchKernelGGL(k_surface_count, dim3(unsigned(nb)), dim3(512), 0, st, nb, v->nbr, v->emask, v->u, cnt);
-            DN_HIP(hipGetLastError());
-        }
-        hipLaunchKernelGGL(k_fill_zero_i64, dim3(1), dim3(1), 0, st, cnt + nb);
-        DN_HIP(hipGetLastError());
-        size_t tb = 0;
-        DN_HIP(rocprim::exclusive_scan(nullptr, tb, cnt, ofs, int64_t(0), size_t(nb + 1), rocprim::plus<int64_t>(), st));
-        if ((rc = v->s_tmp.ensure(tb))) return rc;
-        size_t tbytes = v->s_tmp.bytes;
-        DN_HIP(rocprim::exclusive_scan(v->s_tmp.ptr, tbytes, cnt, ofs, int64_t(0), size_t(nb + 1),
-                                       rocprim::plus<int64_t>(), st));
-        if ((rc = v->host.ensure(64))) return rc;
-        DN_HIP(hipMemcpyAsync(v->host.ptr, ofs + nb, 8, hipMemcpyDeviceToHost, st));
-        DN_HIP(hipStreamSynchronize(st));
-        items = v->host.as<int64_t>()[0];
+        ScanScratch x;
+        if ((rc = count_and_scan(v, k_surface_count, x, &items))) return rc;
         need = size_t(items) * 12;
         *n_out = items;
         if (items == 0) return DN_OK;
         if (!out || out_bytes < need) { set_error("output too small: need %zu bytes", need); return DN_E_CAPACITY; }
         hipLaunchKernelGGL(k_surface_write, dim3(unsigned(nb)), dim3(512), 0, st, nb, v->coords, v->nbr, v->emask,
-                           v->u, ofs, v->prm.voxel_size, static_cast<float *>(out));
+                           v->u, x.ofs, v->prm.voxel_size, static_cast<float *>(out));
         DN_HIP(hipGetLastError());
         DN_HIP(hipStreamSynchronize(st));
         return DN_OK;
     }
     case DN_X_MESH: {
         if ((rc = build_masks(v))) return rc;
-        if ((rc = v->s_counts.ensure((nb + 1) * 8))) return rc;
-        if ((rc = v->s_offsets.ensure((nb + 1) * 8))) return rc;
-        int64_t *cnt = v->s_counts.as<int64_t>(), *ofs = v->s_offsets.as<int64_t>();
-        if (nb > 0) {
-            hipLaunchKernelGGL(k_mesh_count, dim3(unsigned(nb)), dim3(512), 0, st, nb, v->nbr, v->emask, v->u, cnt);
-            DN_HIP(hipGetLastError());
-        }
-        hipLaunchKernelGGL(k_fill_zero_i64, dim3(1), dim3(1), 0, st, cnt + nb);
-        DN_HIP(hipGetLastError());
-        size_t tb = 0;
-        DN_HIP(rocprim::exclusive_scan(nullptr, tb, cnt, ofs, int64_t(0), size_t(nb + 1), rocprim::plus<int64_t>(), st));
-        if ((rc = v->s_tmp.ensure(tb))) return rc;
-        size_t tbytes = v->s_tmp.bytes;
-        DN_HIP(rocprim::exclusive_scan(v->s_tmp.ptr, tbytes, cnt, ofs, int64_t(0), size_t(nb + 1),
-                                       rocprim::plus<int64_t>(), st));
-        if ((rc = v->host.ensure(64))) return rc;
-        DN_HIP(hipMemcpyAsync(v->host.ptr, ofs + nb, 8, hipMemcpyDeviceToHost, st));
-        DN_HIP(hipStreamSynchronize(st));
-        items = v->host.as<int64_t>()[0];
+        ScanScratch x;
+        if ((rc = count_and_scan(v, k_mesh_count, x, &items))) return rc;
         need = size_t(items) * 36;
         *n_out = items;
         if (items == 0) return DN_OK;
         if (!out || out_bytes < need) { set_error("output too small: need %zu bytes", need); return DN_E_CAPACITY; }
         hipLaunchKernelGGL(k_mesh_write, dim3(unsigned(nb)), dim3(512), 0, st, nb, v->coords, v->nbr, v->emask,
-                           v->u, ofs, v->prm.voxel_size, static_cast<float *>(out));
+                           v->u, x.ofs, v->prm.voxel_size, static_cast<float *>(out));
         DN_HIP(hipGetLastError());
         DN_HIP(hipStreamSynchronize(st));
         return DN_OK;
@@ -420,7 +432,7 @@ extern "C" int dn_extract(dn_volume *v, int32_t what, void *out, size_t out_byte
         DN_HIP(hipMemcpyAsync(out, v->emask, need, hipMemcpyDeviceToDevice, st));
         break;
     case DN_X_CANDIDATES:
-        hipLaunchKernelGGL(k_unpack_keys, dim3(grid1(items)), dim3(256), 0, st, v->s_uniq.as<uint64_t>(), items,
+        hipLaunchKernelGGL(k_unpack_keys, dim3(grid1(items)), dim3(256), 0, st, uniq, items,
                            static_cast<int32_t *>(out));
         DN_HIP(hipGetLastError());
         break;

@@ -418,11 +418,43 @@ __global__ void k_warm_finish(int64_t n, int64_t ps, const uint8_t *__restrict__
     u0[g] = (emask[g] & 1) ? f[g] : 0.f;
 }
 
-// Process-wide network scratch.
-struct NetCtx {
-    Buf wpack, lanew, x0, h1, h2, r, d3, d2, d1, parts, chunks, mparts, misc, tl, vpair;
+// The workspace of one network call (caller device memory): packed
+// weights, activations of n tiles and, for training, their gradients and
+// the weight-gradient partial sums.
+struct NetWS {
+    uint16_t *wpack, *x0, *h1, *h2, *d3, *d2, *d1;
+    float *r, *parts, *chunks;
+    double *misc, *tl, *mparts;
+    int nparts, nchunks;
+    int64_t nmask;
 };
-static NetCtx g_net;
+constexpr int kPartsPer = 16;   // partials summed per chunk
+static NetWS carve_net(Bump &b, int64_t n, bool training)
+{
+    NetWS x{};
+    const size_t act = size_t(n) * kT * kC;
+    x.wpack = b.take<uint16_t>(size_t(6) * kWPack);
+    x.x0 = b.take<uint16_t>(act);
+    x.h1 = b.take<uint16_t>(act);
+    x.h2 = b.take<uint16_t>(act);
+    x.r = b.take<float>(size_t(n) * kT);
+    if (training) {
+        x.d3 = b.take<uint16_t>(act);
+        x.d2 = b.take<uint16_t>(act);
+        x.d1 = b.take<uint16_t>(act);
+        x.nparts = int(n < 512 ? n : 512);
+        x.nchunks = (x.nparts + kPartsPer - 1) / kPartsPer;
+        x.parts = b.take<float>(size_t(x.nparts) * (kWPack + kC));
+        x.chunks = b.take<float>(size_t(x.nchunks) * (kWPack + kC));
+        x.misc = b.take<double>(8);
+        x.tl = b.take<double>(size_t(n));
+        x.nmask = (n * 512 + 4095) / 4096;
+        x.mparts = b.take<double>(size_t(x.nmask));
+    }
+    return x;
+}
+
+static bool ws_ok(const void *ws) { return ws && (reinterpret_cast<uintptr_t>(ws) & 255) == 0; }
 
 static inline unsigned grid1(int64_t n, int bs = 256) { return unsigned((n + bs - 1) / bs); }
 
@@ -768,11 +800,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 }
 
-static int pack_all(hipStream_t st, const float *params, bool with_flipped)
+static int pack_all(hipStream_t st, const float *params, bool with_flipped, uint16_t *wp)
 {
-    int rc = g_net.wpack.ensure(size_t(6) * kWPack * 2);
-    if (rc) return rc;
-    uint16_t *wp = g_net.wpack.as<uint16_t>();
     hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW1, 16, 2, 0, wp);
     hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW2, 16, 16, 0, wp + kWPack);
     hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW3, 1, 16, 0, wp + 2 * kWPack);
@@ -785,35 +814,19 @@ static int pack_all(hipStream_t st, const float *params, bool with_flipped)
     return DN_OK;
 }
 
-static int ensure_acts(int64_t n, bool training)
-{
-    int rc;
-    size_t act = size_t(n) * kT * kC * 2;
-    if ((rc = g_net.x0.ensure(act))) return rc;
-    if ((rc = g_net.h1.ensure(act))) return rc;
-    if ((rc = g_net.h2.ensure(act))) return rc;
-    if ((rc = g_net.r.ensure(size_t(n) * kT * 4))) return rc;
-    if (training) {
-        if ((rc = g_net.d3.ensure(act))) return rc;
-        if ((rc = g_net.d2.ensure(act))) return rc;
-        if ((rc = g_net.d1.ensure(act))) return rc;
-    }
-    return DN_OK;
-}
-
-// Forward of n tiles already in g_net.x0 (packed weights in g_net.wpack):
-// h1, h2 (bfloat16) and the residual r (float) of every tile voxel.
-static int forward_tiles(hipStream_t st, const float *params, int64_t n)
+// Forward of n tiles already in ws.x0 (packed weights in ws.wpack): h1, h2
+// (bfloat16) and the residual r (float) of every tile voxel.
+static int forward_tiles(hipStream_t st, const float *params, int64_t n, const NetWS &ws)
 {
     if (n <= 0) return DN_OK;
-    const uint16_t *wp = g_net.wpack.as<uint16_t>();
-    uint16_t *x0 = g_net.x0.as<uint16_t>(), *h1 = g_net.h1.as<uint16_t>(), *h2 = g_net.h2.as<uint16_t>();
+    const uint16_t *wp = ws.wpack;
+    uint16_t *x0 = ws.x0, *h1 = ws.h1, *h2 = ws.h2;
     hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, x0, n, wp, wp + 5 * kWPack, params + kB1, 1,
                        (const uint16_t *)nullptr, h1, (float *)nullptr);
     hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, h1, n, wp + kWPack, (const uint16_t *)nullptr,
                        params + kB2, 1, (const uint16_t *)nullptr, h2, (float *)nullptr);
     hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, h2, n, wp + 2 * kWPack, (const uint16_t *)nullptr,
-                       params + kB3, 0, (const uint16_t *)nullptr, (uint16_t *)nullptr, g_net.r.as<float>());
+                       params + kB3, 0, (const uint16_t *)nullptr, (uint16_t *)nullptr, ws.r);
     DN_HIP(hipGetLastError());
     return DN_OK;
 }
@@ -834,53 +847,68 @@ int dn_net_gather(dn_volume *v, const int32_t *blocks, int64_t n, int32_t perm, 
     return DN_OK;
 }
 
-int dn_net_forward(const float *tiles, int64_t n, const float *params, float *out, void *stream)
+size_t dn_net_bytes(int64_t n_tiles, int32_t training)
+{
+    if (n_tiles < 0 || (training != 0 && training != 1)) return 0;
+    Bump b(nullptr, 0);
+    carve_net(b, n_tiles, training != 0);
+    return (b.off + 255) & ~size_t(255);
+}
+
+int dn_net_forward(const float *tiles, int64_t n, const float *params, float *out, void *workspace,
+                   size_t workspace_bytes, void *stream)
 {
     DN_REQUIRE(tiles && params && out && n >= 0, "bad argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (n == 0) return DN_OK;
+    DN_REQUIRE(ws_ok(workspace), "the workspace must be non-null and 256-byte aligned");
+    if (workspace_bytes < dn_net_bytes(n, 0)) {
+        set_error("workspace of %zu bytes is short: %zu needed (dn_net_bytes)", workspace_bytes, dn_net_bytes(n, 0));
+        return DN_E_CAPACITY;
+    }
+    Bump bump(workspace, workspace_bytes);
+    const NetWS ws = carve_net(bump, n, false);
     int rc;
-    if ((rc = ensure_acts(n, false))) return rc;
-    if ((rc = pack_all(st, params, false))) return rc;
-    hipLaunchKernelGGL(k_tiles_to_bf16, dim3(grid1(n * kT)), dim3(256), 0, st, tiles, n, g_net.x0.as<uint16_t>());
+    if ((rc = pack_all(st, params, false, ws.wpack))) return rc;
+    hipLaunchKernelGGL(k_tiles_to_bf16, dim3(grid1(n * kT)), dim3(256), 0, st, tiles, n, ws.x0);
     DN_HIP(hipGetLastError());
-    if ((rc = forward_tiles(st, params, n))) return rc;
-    DN_HIP(hipMemcpyAsync(out, g_net.r.ptr, size_t(n) * kT * 4, hipMemcpyDeviceToDevice, st));
+    if ((rc = forward_tiles(st, params, n, ws))) return rc;
+    DN_HIP(hipMemcpyAsync(out, ws.r, size_t(n) * kT * 4, hipMemcpyDeviceToDevice, st));
     return DN_OK;
 }
 
 int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const float *targets, const float *mask,
-                     int32_t kind, float *grad, double *loss_host, void *stream)
+                     int32_t kind, float *grad, void *workspace, size_t workspace_bytes, double *loss_host,
+                     void *stream)
 {
     DN_REQUIRE(tiles && params && targets && mask && grad && n > 0 && (kind == 0 || kind == 1), "bad argument");
+    DN_REQUIRE(ws_ok(workspace), "the workspace must be non-null and 256-byte aligned");
+    if (workspace_bytes < dn_net_bytes(n, 1)) {
+        set_error("workspace of %zu bytes is short: %zu needed (dn_net_bytes)", workspace_bytes, dn_net_bytes(n, 1));
+        return DN_E_CAPACITY;
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
+    Bump bump(workspace, workspace_bytes);
+    const NetWS ws = carve_net(bump, n, true);
     int rc;
-    if ((rc = ensure_acts(n, true))) return rc;
-    if ((rc = pack_all(st, params, true))) return rc;
-    const int nparts = int(n < 512 ? n : 512);
-    if ((rc = g_net.parts.ensure(size_t(nparts) * (kWPack + kC) * 4))) return rc;
-    // the partials are summed in chunks of `per`, then the chunk sums
-    const int per = 16, nchunks = (nparts + per - 1) / per;
-    if ((rc = g_net.chunks.ensure(size_t(nchunks) * (kWPack + kC) * 4))) return rc;
-    float *chunks = g_net.chunks.as<float>();
+    if ((rc = pack_all(st, params, true, ws.wpack))) return rc;
+    const int nparts = ws.nparts, per = kPartsPer, nchunks = ws.nchunks;
+    float *chunks = ws.chunks;
     const dim3 cgrid(grid1(kWPack + kC), unsigned(nchunks));
-    if ((rc = g_net.misc.ensure(64))) return rc;
-    if ((rc = g_net.tl.ensure(size_t(n) * 8))) return rc;
-    uint16_t *x0 = g_net.x0.as<uint16_t>(), *h1 = g_net.h1.as<uint16_t>(), *h2 = g_net.h2.as<uint16_t>();
-    uint16_t *d3 = g_net.d3.as<uint16_t>(), *d2 = g_net.d2.as<uint16_t>(), *d1 = g_net.d1.as<uint16_t>();
-    const uint16_t *wp = g_net.wpack.as<uint16_t>();
-    double *cnt = g_net.misc.as<double>(), *lsum = cnt + 1;
-    float *parts = g_net.parts.as<float>();
+    uint16_t *x0 = ws.x0, *h1 = ws.h1, *h2 = ws.h2;
+    uint16_t *d3 = ws.d3, *d2 = ws.d2, *d1 = ws.d1;
+    const uint16_t *wp = ws.wpack;
+    double *cnt = ws.misc, *lsum = cnt + 1;
+    float *parts = ws.parts;
     hipLaunchKernelGGL(k_tiles_to_bf16, dim3(grid1(n * kT)), dim3(256), 0, st, tiles, n, x0);
     DN_HIP(hipGetLastError());
-    if ((rc = forward_tiles(st, params, n))) return rc;
-    const int64_t nmask = (n * 512 + 4095) / 4096;
-    if ((rc = g_net.mparts.ensure(size_t(nmask) * 8))) return rc;
-    hipLaunchKernelGGL(k_mask_part, dim3(unsigned(nmask)), dim3(256), 0, st, mask, n * 512, g_net.mparts.as<double>());
-    hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(256), 0, st, g_net.mparts.as<double>(), nmask, cnt);
-    hipLaunchKernelGGL(k_loss, dim3(unsigned(n)), dim3(512), 0, st, tiles, g_net.r.as<float>(), targets, mask, cnt, n,
-                       int(kind), d3, g_net.tl.as<double>());
-    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, st, g_net.tl.as<double>(), n, lsum);
+    if ((rc = forward_tiles(st, params, n, ws))) return rc;
+    const int64_t nmask = ws.nmask;
+    hipLaunchKernelGGL(k_mask_part, dim3(unsigned(nmask)), dim3(256), 0, st, mask, n * 512, ws.mparts);
+    hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(256), 0, st, ws.mparts, nmask, cnt);
+    hipLaunchKernelGGL(k_loss, dim3(unsigned(n)), dim3(512), 0, st, tiles, ws.r, targets, mask, cnt, n,
+                       int(kind), d3, ws.tl);
+    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, st, ws.tl, n, lsum);
     DN_HIP(hipGetLastError());
     // layer 3: weights from (h2, d3); input gradient d2 = conv(d3, W3 flipped) * [h2 > 0]
     hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, st, h2, d3, n, parts);
@@ -922,7 +950,17 @@ int dn_net_adam(float *params, const float *grad, float *m, float *v, int64_t n,
     return DN_OK;
 }
 
-int dn_net_warm_start(dn_volume *v, const float *params, int32_t mode, double delta, float *u0, float *p0)
+size_t dn_warm_start_bytes(int64_t n_blocks)
+{
+    if (n_blocks < 0) return 0;
+    Bump b(nullptr, 0);
+    b.take<uint16_t>(size_t(kLaneW));
+    b.take<uint32_t>(size_t(n_blocks) * kBlockVox);
+    return (b.off + 255) & ~size_t(255);
+}
+
+int dn_net_warm_start(dn_volume *v, const float *params, int32_t mode, double delta, float *u0, float *p0,
+                      void *workspace, size_t workspace_bytes)
 {
     DN_REQUIRE(v && params && u0 && (mode == DN_WARM_PRIMAL || mode == DN_WARM_DUAL), "bad argument");
     DN_REQUIRE(mode == DN_WARM_DUAL ? p0 != nullptr : delta > 0, "dual mode needs p0; primal mode needs delta > 0");
@@ -930,8 +968,16 @@ int dn_net_warm_start(dn_volume *v, const float *params, int32_t mode, double de
     int rc;
     if ((rc = build_masks(v))) return rc;
     if (v->nb == 0) return DN_OK;
-    if ((rc = g_net.lanew.ensure(size_t(kLaneW) * 2))) return rc;
-    hipLaunchKernelGGL(k_pack_lanes, dim3(grid1(kLaneW)), dim3(256), 0, st, params, g_net.lanew.as<uint16_t>());
+    DN_REQUIRE(ws_ok(workspace), "the workspace must be non-null and 256-byte aligned");
+    if (workspace_bytes < dn_warm_start_bytes(v->nb)) {
+        set_error("workspace of %zu bytes is short: %zu needed (dn_warm_start_bytes)", workspace_bytes,
+                  dn_warm_start_bytes(v->nb));
+        return DN_E_CAPACITY;
+    }
+    Bump bump(workspace, workspace_bytes);
+    uint16_t *lanew = bump.take<uint16_t>(size_t(kLaneW));
+    uint32_t *vp = bump.take<uint32_t>(size_t(v->nb) * kBlockVox);
+    hipLaunchKernelGGL(k_pack_lanes, dim3(grid1(kLaneW)), dim3(256), 0, st, params, lanew);
     DN_HIP(hipGetLastError());
     int cus = 0;
     DN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, v->device));
@@ -939,12 +985,10 @@ int dn_net_warm_start(dn_volume *v, const float *params, int32_t mode, double de
     const unsigned grid = unsigned(std::min<int64_t>(v->nb, int64_t(2) * (cus > 0 ? cus : 1)));
     const int64_t ps = v->nb * int64_t(kBlockVox);
     const int axes = mode == DN_WARM_DUAL ? 3 : 1;
-    if ((rc = g_net.vpair.ensure(size_t(ps) * 4))) return rc;
-    uint32_t *vp = g_net.vpair.as<uint32_t>();
     hipLaunchKernelGGL(k_voxel_pairs, dim3(grid1(ps)), dim3(256), 0, st, v->f, v->w, ps, vp);
     for (int a = 0; a < axes; ++a) {
         hipLaunchKernelGGL(k_net_infer, dim3(grid), dim3(256), 0, st, v->nbr, vp, v->f, v->emask, v->nb,
-                           mode == DN_WARM_DUAL ? a : 0, int(mode), g_net.lanew.as<uint16_t>(), params, ps,
+                           mode == DN_WARM_DUAL ? a : 0, int(mode), lanew, params, ps,
                            mode == DN_WARM_DUAL ? p0 : u0);
         DN_HIP(hipGetLastError());
     }

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "cp_kernel.h"
@@ -299,6 +300,30 @@ template <class T> static int fill(hipStream_t st, T *a, int64_t n, T v)
     return DN_OK;
 }
 
+struct MaskScratch {
+    uint64_t *code, *code2;
+    int32_t *ids;
+    void *tmp;
+    size_t tmp_bytes;
+};
+static MaskScratch carve_masks(Bump &b, int64_t nb)
+{
+    MaskScratch x;
+    x.code = b.take<uint64_t>(size_t(nb));
+    x.code2 = b.take<uint64_t>(size_t(nb));
+    x.ids = b.take<int32_t>(size_t(nb));
+    x.tmp_bytes = tmp_sort(size_t(nb), 12);
+    x.tmp = b.take<char>(x.tmp_bytes);
+    return x;
+}
+
+size_t masks_scratch(int64_t n_blocks)
+{
+    Bump b(nullptr, 0);
+    carve_masks(b, n_blocks);
+    return b.off;
+}
+
 int build_masks(dn_volume *v)
 {
     if (v->emask_nb == v->nb) return DN_OK;
@@ -307,33 +332,15 @@ int build_masks(dn_volume *v)
         hipLaunchKernelGGL(k_masks, dim3(unsigned(v->nb)), dim3(512), 0, st, v->nb, v->nbr, v->w, v->emask);
         DN_HIP(hipGetLastError());
         // Morton processing order of the blocks
-        int rc;
-        if ((rc = v->s_sorted.ensure(v->nb * 8 * 2))) return rc;
-        if ((rc = v->s_vals.ensure(v->nb * 4))) return rc;
-        uint64_t *code = v->s_sorted.as<uint64_t>();
-        uint64_t *code2 = code + v->nb;
-        int32_t *ids = v->s_vals.as<int32_t>();
-        hipLaunchKernelGGL(k_morton, dim3(grid1(v->nb)), dim3(256), 0, st, v->coords, v->nb, code, ids);
+        Bump bump(v->scratch, v->scratch_bytes);
+        MaskScratch x = carve_masks(bump, v->nb);
+        if (!bump.fits()) { set_error("scratch too small for the block order"); return DN_E_CAPACITY; }
+        hipLaunchKernelGGL(k_morton, dim3(grid1(v->nb)), dim3(256), 0, st, v->coords, v->nb, x.code, x.ids);
         DN_HIP(hipGetLastError());
-        size_t tb = 0;
-        DN_HIP(rocprim::radix_sort_pairs(nullptr, tb, code, code2, ids, v->order, size_t(v->nb), 0, 63, st));
-        if ((rc = v->s_tmp.ensure(tb))) return rc;
-        size_t tbytes = v->s_tmp.bytes;
-        DN_HIP(rocprim::radix_sort_pairs(v->s_tmp.ptr, tbytes, code, code2, ids, v->order, size_t(v->nb), 0, 63, st));
+        size_t tbytes = x.tmp_bytes;
+        DN_HIP(rocprim::radix_sort_pairs(x.tmp, tbytes, x.code, x.code2, x.ids, v->order, size_t(v->nb), 0, 63, st));
     }
     v->emask_nb = v->nb;
-    return DN_OK;
-}
-
-int ensure_lowp(dn_volume *v)
-{
-    if (v->u16) return DN_OK;
-    const size_t vox = size_t(v->cap_blocks) * kBlockVox;
-    DN_HIP(hipMalloc(&v->u16, vox * 2));
-    DN_HIP(hipMalloc(&v->ubar16[0], vox * 2));
-    DN_HIP(hipMalloc(&v->ubar16[1], vox * 2));
-    DN_HIP(hipMalloc(&v->p16[0], vox * 6));
-    DN_HIP(hipMalloc(&v->p16[1], vox * 6));
     return DN_OK;
 }
 
@@ -393,12 +400,9 @@ int energy_current(dn_volume *v, double lambda, bool use_f32, int data_term)
 
 int read_energy(dn_volume *v, double out[2])
 {
-    int rc = v->host.ensure(64);
+    int rc = read_back(v, v->energy2, 16);
     if (rc) return rc;
-    DN_HIP(hipMemcpyAsync(v->host.ptr, v->energy2, 16, hipMemcpyDeviceToHost, v->stream));
-    DN_HIP(hipStreamSynchronize(v->stream));
-    out[0] = v->host.as<double>()[0];
-    out[1] = v->host.as<double>()[1];
+    memcpy(out, v->host_stage, 16);
     return DN_OK;
 }
 
@@ -548,7 +552,9 @@ int zero_state(dn_volume *v)
 // (kernel variant, layout) with layout bit 0 = pool order instead of Morton
 // order, bit 1 = plain workgroup -> block map instead of XCD chunks.
 struct AutoChoice { int kernel; int layout; };
-static std::map<int, AutoChoice> g_auto_kernel;
+// Keyed by (device, size bucket); the tuners of all threads share them.
+static std::map<int64_t, AutoChoice> g_auto_kernel;
+static std::mutex g_auto_mutex;
 
 static int size_bucket(int64_t nb)
 {
@@ -557,13 +563,30 @@ static int size_bucket(int64_t nb)
     return b;
 }
 
+static int64_t tune_key(const dn_volume *v, int64_t sub) { return (int64_t(v->device) << 32) | sub; }
+
+static bool find_choice(std::map<int64_t, AutoChoice> &m, int64_t key, AutoChoice *out)
+{
+    std::lock_guard<std::mutex> lk(g_auto_mutex);
+    auto it = m.find(key);
+    if (it == m.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+static void store_choice(std::map<int64_t, AutoChoice> &m, int64_t key, AutoChoice c)
+{
+    std::lock_guard<std::mutex> lk(g_auto_mutex);
+    m[key] = c;
+}
+
 static int autotune_single(dn_volume *v, const dn_reg_params *prm, int *choice)
 {
-    int key = size_bucket(v->nb);
-    auto it = g_auto_kernel.find(key);
-    if (it != g_auto_kernel.end()) {
-        *choice = it->second.kernel;
-        v->layout = it->second.layout;
+    const int64_t key = tune_key(v, size_bucket(v->nb));
+    AutoChoice found;
+    if (find_choice(g_auto_kernel, key, &found)) {
+        *choice = found.kernel;
+        v->layout = found.layout;
         return DN_OK;
     }
     // time a few iterations of each candidate from the zero state
@@ -591,7 +614,7 @@ static int autotune_single(dn_volume *v, const dn_reg_params *prm, int *choice)
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    g_auto_kernel[key] = best;
+    store_choice(g_auto_kernel, key, best);
     *choice = best.kernel;
     v->layout = best.layout;
     return zero_state(v);
@@ -600,15 +623,15 @@ static int autotune_single(dn_volume *v, const dn_reg_params *prm, int *choice)
 // The same choice for 16-bit state storage, timed on the 16-bit kernels.
 // It runs only on a state just demoted from FP32 (the trials overwrite the
 // 16-bit buffers, which are then demoted again).
-static std::map<int, AutoChoice> g_auto_lowp;
+static std::map<int64_t, AutoChoice> g_auto_lowp;
 
 template <class S> static int autotune_lowp(dn_volume *v, const dn_reg_params *prm, int storage, int *choice)
 {
-    const int key = storage * 64 + size_bucket(v->nb);
-    auto it = g_auto_lowp.find(key);
-    if (it != g_auto_lowp.end()) {
-        *choice = it->second.kernel;
-        v->layout = it->second.layout;
+    const int64_t key = tune_key(v, storage * 64 + size_bucket(v->nb));
+    AutoChoice found;
+    if (find_choice(g_auto_lowp, key, &found)) {
+        *choice = found.kernel;
+        v->layout = found.layout;
         return DN_OK;
     }
     hipEvent_t e0, e1;
@@ -635,7 +658,7 @@ template <class S> static int autotune_lowp(dn_volume *v, const dn_reg_params *p
     (void)hipEventDestroy(e1);
     v->cur = cur;
     if (rc) return rc;
-    g_auto_lowp[key] = best;
+    store_choice(g_auto_lowp, key, best);
     *choice = best.kernel;
     v->layout = best.layout;
     return demote_state<S>(v);
@@ -662,6 +685,7 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
     int rc = validate(prm);
     if (rc) return rc;
     DN_REQUIRE(prm->init != DN_INIT_GIVEN || u0, "init GIVEN needs u0");
+    DN_REQUIRE(prm->storage == DN_F32 || v->prm.state16, "16-bit storage needs a volume created with state16");
     hipStream_t st = v->stream;
     if ((rc = build_masks(v))) return rc;
     const int64_t n = v->nb * kBlockVox, ps = v->cap_blocks * kBlockVox;
@@ -704,7 +728,6 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
     bool fresh16 = false;     // the 16-bit state was just demoted from FP32
     if (storage != DN_F32) {
         if (kernel != DN_K_FUSED256) kernel = DN_K_FUSED;
-        if ((rc = ensure_lowp(v))) return rc;
         if (v->state_storage != storage) {
             // the FP32 state (zero, given or an earlier FP32 run) is demoted
             if (v->state_storage != DN_F32) {
@@ -723,10 +746,10 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
                                        : autotune_lowp<SBF16>(v, prm, storage, &kernel);
                 if (rc) return rc;
             } else {
-                auto it = g_auto_lowp.find(storage * 64 + size_bucket(v->nb));
-                if (it != g_auto_lowp.end()) {
-                    kernel = it->second.kernel;
-                    v->layout = it->second.layout;
+                AutoChoice found;
+                if (find_choice(g_auto_lowp, tune_key(v, storage * 64 + size_bucket(v->nb)), &found)) {
+                    kernel = found.kernel;
+                    v->layout = found.layout;
                 }
             }
         }
@@ -737,9 +760,13 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
             if (prm->init == DN_INIT_ZERO) {
                 if ((rc = autotune_single(v, prm, &kernel))) return rc;
             } else {
-                auto it = g_auto_kernel.find(size_bucket(v->nb));
-                kernel = it != g_auto_kernel.end() ? it->second.kernel : DN_K_FUSED;
-                if (it != g_auto_kernel.end()) v->layout = it->second.layout;
+                AutoChoice found;
+                if (find_choice(g_auto_kernel, tune_key(v, size_bucket(v->nb)), &found)) {
+                    kernel = found.kernel;
+                    v->layout = found.layout;
+                } else {
+                    kernel = DN_K_FUSED;
+                }
             }
         }
     }

@@ -25,37 +25,12 @@ void set_error(const char *fmt, ...)
     va_end(ap);
 }
 
-int Buf::ensure(size_t need)
+int read_back(dn_volume *v, const void *dev, size_t bytes)
 {
-    if (need <= bytes) return DN_OK;
-    if (ptr) { (void)hipFree(ptr); ptr = nullptr; bytes = 0; }
-    size_t nb = need + need / 4 + 256;
-    DN_HIP(hipMalloc(&ptr, nb));
-    bytes = nb;
+    if (bytes > sizeof(v->host_stage)) { set_error("read-back too large"); return DN_E_INVALID; }
+    DN_HIP(hipMemcpyAsync(v->host_stage, dev, bytes, hipMemcpyDeviceToHost, v->stream));
+    DN_HIP(hipStreamSynchronize(v->stream));
     return DN_OK;
-}
-
-void Buf::release()
-{
-    if (ptr) (void)hipFree(ptr);
-    ptr = nullptr;
-    bytes = 0;
-}
-
-int HostBuf::ensure(size_t need)
-{
-    if (need <= bytes) return DN_OK;
-    if (ptr) { (void)hipHostFree(ptr); ptr = nullptr; bytes = 0; }
-    DN_HIP(hipHostMalloc(&ptr, need < 4096 ? 4096 : need, hipHostMallocDefault));
-    bytes = need < 4096 ? 4096 : need;
-    return DN_OK;
-}
-
-void HostBuf::release()
-{
-    if (ptr) (void)hipHostFree(ptr);
-    ptr = nullptr;
-    bytes = 0;
 }
 
 int volume_sync(dn_volume *v)
@@ -269,6 +244,8 @@ __global__ void k_home_minus_rank(const uint32_t *__restrict__ home, int64_t n, 
     if (i < n) d[i] = int64_t(home[i]) - i;
 }
 
+__global__ void k_zero_i32(int32_t *a) { *a = 0; }
+
 __global__ void k_fill_empty(int4 *__restrict__ slots, int64_t n)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -311,64 +288,63 @@ static int bits_for(uint64_t v)
     return b;
 }
 
+InsertScratch carve_insert(Bump &b, int64_t n_cand, int64_t n_blocks)
+{
+    InsertScratch x;
+    x.flags = b.take<uint8_t>(size_t(n_cand));
+    x.newraw = b.take<uint64_t>(size_t(n_cand));
+    x.sorted = b.take<uint64_t>(size_t(n_cand));
+    x.newk = b.take<uint64_t>(size_t(n_cand));
+    x.ksorted = b.take<uint64_t>(size_t(n_blocks));
+    x.ids0 = b.take<int32_t>(size_t(n_blocks));
+    x.ids1 = b.take<int32_t>(size_t(n_blocks));
+    x.home = b.take<uint32_t>(size_t(n_blocks));
+    x.home2 = b.take<uint32_t>(size_t(n_blocks));
+    x.dm = b.take<int64_t>(size_t(n_blocks));
+    x.runmax = b.take<int64_t>(size_t(n_blocks));
+    x.tmp_bytes = std::max(std::max(tmp_sort(size_t(n_cand), 8), tmp_light(size_t(n_cand))),
+                           std::max(tmp_sort(size_t(n_blocks), 12), tmp_light(size_t(n_blocks))));
+    x.tmp = b.take<char>(x.tmp_bytes);
+    return x;
+}
+
 // Insert a packed candidate list (device, n_cand entries, repeats allowed).
 // Appends the keys not yet present in ascending order, rebuilds hash +
 // neighbours.  The raw list is first filtered against the table, so only
 // candidates of new blocks are sorted (after the first frames of a sequence
 // almost every candidate is a block that exists); the ascending list of all
 // distinct candidates is built from the same raw list only when it is
-// extracted (ensure_candidates).
+// extracted (build_candidates).  All buffers come from the volume's scratch.
 static int insert_packed(dn_volume *v, uint64_t *cand, int64_t n_cand, int32_t *n_new_out)
 {
     hipStream_t st = v->stream;
     if (n_new_out) *n_new_out = 0;
-    v->last_nuniq = 0;
-    v->cand_src = cand;
     v->cand_n = n_cand;
-    v->cand_pending = n_cand > 0;
     if (n_cand == 0) return DN_OK;
-    int rc;
-    // 1) the candidates of blocks not in the table (repeats kept)
-    if ((rc = v->s_flags.ensure(n_cand))) return rc;
-    if ((rc = v->s_new.ensure(n_cand * sizeof(uint64_t)))) return rc;
-    if ((rc = v->s_misc.ensure(64))) return rc;
-    int64_t *d_nraw = v->s_misc.as<int64_t>();
+    Bump bump(v->scratch, v->scratch_bytes);
+    InsertScratch x = carve_insert(bump, n_cand, v->cap_blocks);
+    if (!bump.fits()) { set_error("scratch too small for %lld candidates", (long long)n_cand); return DN_E_CAPACITY; }
+    int64_t *d_nraw = v->misc;
     int64_t *d_nnew = d_nraw + 1;
+    size_t tbytes;
+    // 1) the candidates of blocks not in the table (repeats kept)
     const int4 *slots = reinterpret_cast<const int4 *>(v->hash[v->cur_hash]);
     hipLaunchKernelGGL(k_flag_unknown, dim3(grid1(n_cand)), dim3(256), 0, st, cand, n_cand, slots,
-                       v->hash_slots, v->hash_cap, v->s_flags.as<uint8_t>());
+                       v->hash_slots, v->hash_cap, x.flags);
     DN_HIP(hipGetLastError());
-    size_t tb = 0;
-    DN_HIP(rocprim::select(nullptr, tb, cand, v->s_flags.as<uint8_t>(), v->s_new.as<uint64_t>(), d_nraw,
-                           size_t(n_cand), st));
-    if ((rc = v->s_tmp.ensure(tb))) return rc;
-    size_t tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::select(v->s_tmp.ptr, tbytes, cand, v->s_flags.as<uint8_t>(), v->s_new.as<uint64_t>(),
-                           d_nraw, size_t(n_cand), st));
-    if ((rc = v->host.ensure(64))) return rc;
-    DN_HIP(hipMemcpyAsync(v->host.ptr, d_nraw, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    DN_HIP(hipStreamSynchronize(st));
-    const int64_t n_raw = v->host.as<int64_t>()[0];
+    tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::select(x.tmp, tbytes, cand, x.flags, x.newraw, d_nraw, size_t(n_cand), st));
+    int rc = read_back(v, d_nraw, sizeof(int64_t));
+    if (rc) return rc;
+    const int64_t n_raw = v->host_stage[0];
     if (n_raw == 0) return DN_OK;
     // 2) the distinct new keys, ascending
-    if ((rc = v->s_sorted.ensure(n_raw * sizeof(uint64_t)))) return rc;
-    if ((rc = v->s_newk.ensure(n_raw * sizeof(uint64_t)))) return rc;
-    uint64_t *sorted = v->s_sorted.as<uint64_t>();
-    uint64_t *newk = v->s_newk.as<uint64_t>();
-    size_t t2 = 0;
-    tb = 0;
-    DN_HIP(rocprim::radix_sort_keys(nullptr, tb, v->s_new.as<uint64_t>(), sorted, size_t(n_raw), 0, 63, st));
-    DN_HIP(rocprim::unique(nullptr, t2, sorted, newk, d_nnew, size_t(n_raw), rocprim::equal_to<uint64_t>(), st));
-    if ((rc = v->s_tmp.ensure(tb > t2 ? tb : t2))) return rc;
-    tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::radix_sort_keys(v->s_tmp.ptr, tbytes, v->s_new.as<uint64_t>(), sorted, size_t(n_raw), 0, 63,
-                                    st));
-    tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::unique(v->s_tmp.ptr, tbytes, sorted, newk, d_nnew, size_t(n_raw), rocprim::equal_to<uint64_t>(),
-                           st));
-    DN_HIP(hipMemcpyAsync(v->host.ptr, d_nnew, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    DN_HIP(hipStreamSynchronize(st));
-    const int64_t n_new = v->host.as<int64_t>()[0];
+    tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::radix_sort_keys(x.tmp, tbytes, x.newraw, x.sorted, size_t(n_raw), 0, 63, st));
+    tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::unique(x.tmp, tbytes, x.sorted, x.newk, d_nnew, size_t(n_raw), rocprim::equal_to<uint64_t>(), st));
+    if ((rc = read_back(v, d_nnew, sizeof(int64_t)))) return rc;
+    const int64_t n_new = v->host_stage[0];
     if (v->nb + n_new > v->cap_blocks) {
         set_error("block pool full: %lld + %lld new blocks > max_blocks %lld", (long long)v->nb,
                   (long long)n_new, (long long)v->cap_blocks);
@@ -376,56 +352,33 @@ static int insert_packed(dn_volume *v, uint64_t *cand, int64_t n_cand, int32_t *
     }
     // 3) tentatively append (beyond nb; not committed until the hash fits)
     const int64_t nb_old = v->nb, nb_new = v->nb + n_new;
-    hipLaunchKernelGGL(k_append, dim3(grid1(n_new)), dim3(256), 0, st, newk, n_new, nb_old, v->coords, v->keys);
+    hipLaunchKernelGGL(k_append, dim3(grid1(n_new)), dim3(256), 0, st, x.newk, n_new, nb_old, v->coords, v->keys);
     DN_HIP(hipGetLastError());
     // 4) canonical table: sort (key -> id), then stable sort by bucket
-    if ((rc = v->s_vals.ensure(nb_new * sizeof(int32_t)))) return rc;
-    if ((rc = v->s_vals2.ensure(nb_new * sizeof(int32_t)))) return rc;
-    if ((rc = v->s_home.ensure(nb_new * sizeof(uint32_t)))) return rc;
-    if ((rc = v->s_home2.ensure(nb_new * sizeof(uint32_t)))) return rc;
-    if ((rc = v->s_pos.ensure(nb_new * sizeof(int64_t) * 2))) return rc;
-    if ((rc = v->s_cand2.ensure(nb_new * sizeof(uint64_t)))) return rc;
-    int32_t *ids0 = v->s_vals.as<int32_t>();
-    int32_t *ids1 = v->s_vals2.as<int32_t>();
-    uint64_t *ksorted = v->s_cand2.as<uint64_t>();
-    uint32_t *home = v->s_home.as<uint32_t>();
-    uint32_t *home2 = v->s_home2.as<uint32_t>();
-    int64_t *dm = v->s_pos.as<int64_t>();
-    int64_t *runmax = dm + nb_new;
-    hipLaunchKernelGGL(k_iota, dim3(grid1(nb_new)), dim3(256), 0, st, ids0, nb_new);
+    hipLaunchKernelGGL(k_iota, dim3(grid1(nb_new)), dim3(256), 0, st, x.ids0, nb_new);
     DN_HIP(hipGetLastError());
-    tb = 0;
-    DN_HIP(rocprim::radix_sort_pairs(nullptr, tb, v->keys, ksorted, ids0, ids1, size_t(nb_new), 0, 63, st));
     const int hbits = bits_for(v->hash_cap - 1);
-    t2 = 0;
-    DN_HIP(rocprim::radix_sort_pairs(nullptr, t2, home, home2, ids1, ids0, size_t(nb_new), 0, hbits, st));
-    tb = tb > t2 ? tb : t2;
-    t2 = 0;
-    DN_HIP(rocprim::inclusive_scan(nullptr, t2, dm, runmax, size_t(nb_new), rocprim::maximum<int64_t>(), st));
-    tb = tb > t2 ? tb : t2;
-    if ((rc = v->s_tmp.ensure(tb))) return rc;
-    tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::radix_sort_pairs(v->s_tmp.ptr, tbytes, v->keys, ksorted, ids0, ids1, size_t(nb_new), 0, 63, st));
-    hipLaunchKernelGGL(k_bucket_of_keys, dim3(grid1(nb_new)), dim3(256), 0, st, ksorted, nb_new, v->hash_cap, home);
+    tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::radix_sort_pairs(x.tmp, tbytes, v->keys, x.ksorted, x.ids0, x.ids1, size_t(nb_new), 0, 63, st));
+    hipLaunchKernelGGL(k_bucket_of_keys, dim3(grid1(nb_new)), dim3(256), 0, st, x.ksorted, nb_new, v->hash_cap, x.home);
     DN_HIP(hipGetLastError());
-    tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::radix_sort_pairs(v->s_tmp.ptr, tbytes, home, home2, ids1, ids0, size_t(nb_new), 0, hbits, st));
-    hipLaunchKernelGGL(k_home_minus_rank, dim3(grid1(nb_new)), dim3(256), 0, st, home2, nb_new, dm);
+    tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::radix_sort_pairs(x.tmp, tbytes, x.home, x.home2, x.ids1, x.ids0, size_t(nb_new), 0, hbits, st));
+    hipLaunchKernelGGL(k_home_minus_rank, dim3(grid1(nb_new)), dim3(256), 0, st, x.home2, nb_new, x.dm);
     DN_HIP(hipGetLastError());
-    tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::inclusive_scan(v->s_tmp.ptr, tbytes, dm, runmax, size_t(nb_new), rocprim::maximum<int64_t>(), st));
+    tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::inclusive_scan(x.tmp, tbytes, x.dm, x.runmax, size_t(nb_new), rocprim::maximum<int64_t>(), st));
     int other = 1 - v->cur_hash;
     int4 *dst = reinterpret_cast<int4 *>(v->hash[other]);
     int32_t *d_ovf = reinterpret_cast<int32_t *>(d_nraw + 2);
-    DN_HIP(hipMemsetAsync(d_ovf, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, st, d_ovf);
     hipLaunchKernelGGL(k_fill_empty, dim3(grid1(v->hash_slots)), dim3(256), 0, st, dst, v->hash_slots);
     DN_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_scatter_slots, dim3(grid1(nb_new)), dim3(256), 0, st, runmax, ids0, v->coords, nb_new,
+    hipLaunchKernelGGL(k_scatter_slots, dim3(grid1(nb_new)), dim3(256), 0, st, x.runmax, x.ids0, v->coords, nb_new,
                        v->hash_slots, dst, d_ovf);
     DN_HIP(hipGetLastError());
-    DN_HIP(hipMemcpyAsync(v->host.ptr, d_ovf, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    DN_HIP(hipStreamSynchronize(st));
-    if (*v->host.as<int32_t>() != 0) {
+    if ((rc = read_back(v, d_ovf, sizeof(int32_t)))) return rc;
+    if (int32_t(v->host_stage[0] & 0xFFFFFFFF) != 0) {
         set_error("hash table full: %lld keys do not fit 2^%d buckets + %d tail slots", (long long)nb_new,
                   v->prm.hash_cap_log2, v->prm.hash_tail);
         return DN_E_CAPACITY;
@@ -699,35 +652,266 @@ static int make_lgeo(const dn_volume *v, const double *T, LGeo &g)
     return DN_OK;
 }
 
-// The ascending distinct keys of the last candidate list, in s_uniq
-// (last_nuniq of them), built on first request.
-int ensure_candidates(dn_volume *v)
+// Scratch of one laser fusion call: per-return counts and offsets, the
+// observation lists (voxel key, psi) and their sorted copies, the per-voxel
+// counts and the rocprim storage.
+struct LaserScratch {
+    int64_t *counts, *offs;
+    uint32_t *k_in, *k_out, *counts32, *nruns;
+    double *v_in, *v_out;
+    void *tmp;
+    size_t tmp_bytes;
+};
+static LaserScratch carve_laser(Bump &b, int64_t n, int64_t m)
 {
-    if (!v->cand_pending) return DN_OK;
-    hipStream_t st = v->stream;
+    LaserScratch x;
+    x.counts = b.take<int64_t>(size_t(n));
+    x.offs = b.take<int64_t>(size_t(n) + 1);
+    x.k_in = b.take<uint32_t>(size_t(m));
+    x.k_out = b.take<uint32_t>(size_t(m));
+    x.counts32 = b.take<uint32_t>(size_t(m));
+    x.nruns = b.take<uint32_t>(1);
+    x.v_in = b.take<double>(size_t(m));
+    x.v_out = b.take<double>(size_t(m));
+    x.tmp_bytes = std::max(std::max(tmp_light(size_t(n)), tmp_light(size_t(m))), tmp_sort(size_t(m), 12));
+    x.tmp = b.take<char>(x.tmp_bytes);
+    return x;
+}
+
+// Scratch of the band count of one frame (or scan) of n points.
+struct FrameScratch {
+    int32_t *counts, *offs;
+    void *tmp;
+    size_t tmp_bytes;
+};
+static FrameScratch carve_frame(Bump &b, int64_t n)
+{
+    FrameScratch x;
+    x.counts = b.take<int32_t>(size_t(n));
+    x.offs = b.take<int32_t>(size_t(n) + 2);
+    x.tmp_bytes = tmp_light(size_t(n));
+    x.tmp = b.take<char>(x.tmp_bytes);
+    return x;
+}
+
+struct CandScratch {
+    uint64_t *sorted, *uniq;
+    void *tmp;
+    size_t tmp_bytes;
+};
+static CandScratch carve_cand(Bump &b, int64_t n)
+{
+    CandScratch x;
+    x.sorted = b.take<uint64_t>(size_t(n));
+    x.uniq = b.take<uint64_t>(size_t(n));
+    x.tmp_bytes = std::max(tmp_sort(size_t(n), 8), tmp_light(size_t(n)));
+    x.tmp = b.take<char>(x.tmp_bytes);
+    return x;
+}
+
+size_t candidates_scratch(int64_t n_cand)
+{
+    Bump b(nullptr, 0);
+    carve_cand(b, n_cand);
+    return b.off;
+}
+
+// The ascending distinct keys of the last candidate list, built in the
+// scratch on request (*uniq points into it until the next call uses it).
+int build_candidates(dn_volume *v, uint64_t **uniq, int64_t *n_uniq)
+{
+    *uniq = nullptr;
+    *n_uniq = 0;
     const int64_t n = v->cand_n;
-    int rc;
-    if ((rc = v->s_sorted.ensure(n * sizeof(uint64_t)))) return rc;
-    if ((rc = v->s_uniq.ensure(n * sizeof(uint64_t)))) return rc;
-    if ((rc = v->s_misc.ensure(64))) return rc;
-    int64_t *d_n = v->s_misc.as<int64_t>() + 3;
-    uint64_t *sorted = v->s_sorted.as<uint64_t>();
-    size_t tb = 0, t2 = 0;
-    DN_HIP(rocprim::radix_sort_keys(nullptr, tb, v->cand_src, sorted, size_t(n), 0, 63, st));
-    DN_HIP(rocprim::unique(nullptr, t2, sorted, v->s_uniq.as<uint64_t>(), d_n, size_t(n),
-                           rocprim::equal_to<uint64_t>(), st));
-    if ((rc = v->s_tmp.ensure(tb > t2 ? tb : t2))) return rc;
-    size_t tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::radix_sort_keys(v->s_tmp.ptr, tbytes, v->cand_src, sorted, size_t(n), 0, 63, st));
-    tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::unique(v->s_tmp.ptr, tbytes, sorted, v->s_uniq.as<uint64_t>(), d_n, size_t(n),
-                           rocprim::equal_to<uint64_t>(), st));
-    if ((rc = v->host.ensure(64))) return rc;
-    DN_HIP(hipMemcpyAsync(v->host.ptr, d_n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    DN_HIP(hipStreamSynchronize(st));
-    v->last_nuniq = v->host.as<int64_t>()[0];
-    v->cand_pending = false;
+    if (n == 0) return DN_OK;
+    hipStream_t st = v->stream;
+    Bump bump(v->scratch, v->scratch_bytes);
+    CandScratch x = carve_cand(bump, n);
+    if (!bump.fits()) { set_error("scratch too small for the candidate list"); return DN_E_CAPACITY; }
+    int64_t *d_n = v->misc + 3;
+    size_t tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::radix_sort_keys(x.tmp, tbytes, v->cand, x.sorted, size_t(n), 0, 63, st));
+    tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::unique(x.tmp, tbytes, x.sorted, x.uniq, d_n, size_t(n), rocprim::equal_to<uint64_t>(), st));
+    int rc = read_back(v, d_n, sizeof(int64_t));
+    if (rc) return rc;
+    *uniq = x.uniq;
+    *n_uniq = v->host_stage[0];
     return DN_OK;
+}
+
+// Placement of everything a volume keeps in its arena (base == nullptr:
+// measure only).  Returns the arena size; with v != nullptr the volume's
+// pointers are set.
+static size_t volume_layout(const dn_volume_params &p, void *base, dn_volume *v)
+{
+    const size_t mb = size_t(p.max_blocks), vox = mb * kBlockVox;
+    const size_t slots = (size_t(1) << p.hash_cap_log2) + size_t(p.hash_tail);
+    Bump b(base, ~size_t(0));
+    int32_t *coords = b.take<int32_t>(mb * 4);
+    uint64_t *keys = b.take<uint64_t>(mb);
+    int32_t *h0 = b.take<int32_t>(slots * 4);
+    int32_t *h1 = b.take<int32_t>(slots * 4);
+    int32_t *nbr = b.take<int32_t>(mb * kNbr);
+    float *f = b.take<float>(vox);
+    float *w = b.take<float>(vox);
+    float *u = b.take<float>(vox);
+    float *ub0 = b.take<float>(vox);
+    float *ub1 = b.take<float>(vox);
+    float *p0 = b.take<float>(vox * 3);
+    float *p1 = b.take<float>(vox * 3);
+    uint8_t *emask = b.take<uint8_t>(vox);
+    int32_t *order = b.take<int32_t>(mb);
+    double *partials = b.take<double>(mb * 2 + 2 * ((mb + 1023) / 1024 + 1) * 2 + 8);
+    double *energy2 = b.take<double>(8);
+    int64_t *misc = b.take<int64_t>(32);
+    uint64_t *cand = b.take<uint64_t>(size_t(p.max_candidates));
+    void *u16 = nullptr, *ub16a = nullptr, *ub16b = nullptr, *p16a = nullptr, *p16b = nullptr;
+    if (p.state16) {
+        u16 = b.take<uint16_t>(vox);
+        ub16a = b.take<uint16_t>(vox);
+        ub16b = b.take<uint16_t>(vox);
+        p16a = b.take<uint16_t>(vox * 3);
+        p16b = b.take<uint16_t>(vox * 3);
+    }
+    // scratch: the largest of the per-call needs
+    size_t need = 0;
+    auto upd = [&](size_t n) { need = std::max(need, n); };
+    {
+        Bump m(nullptr, 0);
+        carve_frame(m, p.max_points);
+        upd(m.off);
+    }
+    {
+        Bump m(nullptr, 0);
+        carve_insert(m, std::max<int64_t>(p.max_candidates, 1), p.max_blocks);
+        upd(m.off);
+    }
+    upd(candidates_scratch(std::max<int64_t>(p.max_candidates, 1)));
+    upd(masks_scratch(p.max_blocks));
+    upd(extract_scratch(p.max_blocks));
+    if (p.max_observations > 0) {
+        Bump m(nullptr, 0);
+        carve_laser(m, p.max_points, p.max_observations);
+        upd(m.off);
+    }
+    char *scratch = b.take<char>(need);
+    if (v) {
+        v->coords = coords; v->keys = keys; v->hash[0] = h0; v->hash[1] = h1; v->nbr = nbr;
+        v->f = f; v->w = w; v->u = u; v->ubar[0] = ub0; v->ubar[1] = ub1; v->p[0] = p0; v->p[1] = p1;
+        v->emask = emask; v->order = order; v->partials = partials; v->energy2 = energy2; v->misc = misc;
+        v->cand = cand;
+        v->u16 = u16; v->ubar16[0] = ub16a; v->ubar16[1] = ub16b; v->p16[0] = p16a; v->p16[1] = p16b;
+        v->scratch = scratch;
+        v->scratch_bytes = need;
+    }
+    return (b.off + 255) & ~size_t(255);
+}
+
+static bool params_ok(const dn_volume_params *p)
+{
+    return p && p->voxel_size > 0 && p->mu > 0 && p->max_depth > 0 && p->max_blocks >= 1 &&
+           p->hash_cap_log2 >= 4 && p->hash_cap_log2 <= 30 && p->hash_tail >= 0 &&
+           (p->state16 == 0 || p->state16 == 1) && p->max_points >= 0 && p->max_candidates >= 0 &&
+           p->max_observations >= 0 && p->max_points < (int64_t(1) << 31) &&
+           p->max_candidates < (int64_t(1) << 40) && p->max_observations < (int64_t(1) << 32) &&
+           std::isfinite(p->voxel_size) && std::isfinite(p->mu) && std::isfinite(p->max_depth);
+}
+
+// The rocprim calls' own storage figures at the largest sizes this volume
+// can ask for, against the bounds its scratch was sized with.
+static int verify_tmp_bounds(dn_volume *v)
+{
+    const dn_volume_params &p = v->prm;
+    hipStream_t st = v->stream;
+    const size_t nc = size_t(std::max<int64_t>(p.max_candidates, 1)), mb = size_t(p.max_blocks);
+    const size_t np = size_t(std::max<int64_t>(p.max_points, 1)), no = size_t(std::max<int64_t>(p.max_observations, 1));
+    struct Q { const char *what; size_t need, have; };
+    std::vector<Q> q;
+    size_t t = 0;
+    int32_t *i32 = nullptr; int64_t *i64 = nullptr; uint64_t *u64 = nullptr; uint32_t *u32 = nullptr;
+    uint8_t *u8 = nullptr; double *f64 = nullptr;
+    DN_HIP(rocprim::exclusive_scan(nullptr, t, i32, i32, 0, np, rocprim::plus<int32_t>(), st));
+    q.push_back({"point scan", t, tmp_light(np)});
+    t = 0;
+    DN_HIP(rocprim::select(nullptr, t, u64, u8, u64, i64, nc, st));
+    q.push_back({"candidate selection", t, tmp_light(nc)});
+    t = 0;
+    DN_HIP(rocprim::radix_sort_keys(nullptr, t, u64, u64, nc, 0, 63, st));
+    q.push_back({"candidate sort", t, tmp_sort(nc, 8)});
+    t = 0;
+    DN_HIP(rocprim::unique(nullptr, t, u64, u64, i64, nc, rocprim::equal_to<uint64_t>(), st));
+    q.push_back({"candidate unique", t, tmp_light(nc)});
+    t = 0;
+    DN_HIP(rocprim::radix_sort_pairs(nullptr, t, u64, u64, i32, i32, mb, 0, 63, st));
+    q.push_back({"key sort", t, tmp_sort(mb, 12)});
+    t = 0;
+    DN_HIP(rocprim::radix_sort_pairs(nullptr, t, u32, u32, i32, i32, mb, 0, 31, st));
+    q.push_back({"bucket sort", t, tmp_sort(mb, 8)});
+    t = 0;
+    DN_HIP(rocprim::inclusive_scan(nullptr, t, i64, i64, mb, rocprim::maximum<int64_t>(), st));
+    q.push_back({"slot scan", t, tmp_light(mb)});
+    t = 0;
+    DN_HIP(rocprim::exclusive_scan(nullptr, t, i64, i64, int64_t(0), mb + 1, rocprim::plus<int64_t>(), st));
+    q.push_back({"extraction scan", t, tmp_light(mb + 1)});
+    if (p.max_observations > 0) {
+        t = 0;
+        DN_HIP(rocprim::exclusive_scan(nullptr, t, i64, i64, int64_t(0), np, rocprim::plus<int64_t>(), st));
+        q.push_back({"return scan", t, tmp_light(np)});
+        t = 0;
+        DN_HIP(rocprim::radix_sort_pairs(nullptr, t, u32, u32, f64, f64, no, 0, 32, st));
+        q.push_back({"observation sort", t, tmp_sort(no, 12)});
+        t = 0;
+        DN_HIP(rocprim::reduce_by_key(nullptr, t, u32, f64, no, u32, f64, u32, rocprim::plus<double>(),
+                                      rocprim::equal_to<uint32_t>(), st));
+        q.push_back({"observation sums", t, tmp_light(no)});
+        t = 0;
+        DN_HIP(rocprim::run_length_encode(nullptr, t, u32, no, u32, u32, u32, st));
+        q.push_back({"observation counts", t, tmp_light(no)});
+    }
+    for (const Q &e : q)
+        if (e.need > e.have) {
+            set_error("rocprim %s needs %zu bytes of storage, the scratch bound is %zu", e.what, e.need, e.have);
+            return DN_E_CAPACITY;
+        }
+    return DN_OK;
+}
+
+// Band cells of n points (depth pixels or laser returns): count, scan, check
+// the limit, emit into v->cand; then the shared insertion.
+template <class Count, class Emit>
+static int alloc_points(dn_volume *v, int64_t n, Count count, Emit emit, int32_t *n_new_out)
+{
+    if (n_new_out) *n_new_out = 0;
+    v->cand_n = 0;
+    if (n == 0) return DN_OK;
+    if (n > v->prm.max_points) {
+        set_error("%lld points exceed the volume's max_points %lld", (long long)n, (long long)v->prm.max_points);
+        return DN_E_CAPACITY;
+    }
+    hipStream_t st = v->stream;
+    Bump bump(v->scratch, v->scratch_bytes);
+    FrameScratch x = carve_frame(bump, n);
+    if (!bump.fits()) { set_error("scratch too small for %lld points", (long long)n); return DN_E_CAPACITY; }
+    count(x.counts);
+    DN_HIP(hipGetLastError());
+    size_t tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::exclusive_scan(x.tmp, tbytes, x.counts, x.offs, 0, size_t(n), rocprim::plus<int32_t>(), st));
+    int32_t pair[2];
+    DN_HIP(hipMemcpyAsync(reinterpret_cast<char *>(v->host_stage), x.offs + n - 1, 4, hipMemcpyDeviceToHost, st));
+    DN_HIP(hipMemcpyAsync(reinterpret_cast<char *>(v->host_stage) + 4, x.counts + n - 1, 4, hipMemcpyDeviceToHost, st));
+    DN_HIP(hipStreamSynchronize(st));
+    memcpy(pair, v->host_stage, 8);
+    const int64_t total = int64_t(pair[0]) + pair[1];
+    if (total == 0) return DN_OK;
+    if (total > v->prm.max_candidates) {
+        set_error("%lld band cells exceed the volume's max_candidates %lld", (long long)total,
+                  (long long)v->prm.max_candidates);
+        return DN_E_CAPACITY;
+    }
+    emit(x.offs, total);
+    DN_HIP(hipGetLastError());
+    return insert_packed(v, v->cand, total, n_new_out);
 }
 
 }  // namespace dn
@@ -739,7 +923,13 @@ extern "C" {
 
 const char *dn_last_error(void) { return g_err; }
 
-int dn_volume_create(const dn_volume_params *p, void *hip_stream, dn_volume **out)
+size_t dn_volume_bytes(const dn_volume_params *p)
+{
+    if (!params_ok(p)) return 0;
+    return volume_layout(*p, nullptr, nullptr);
+}
+
+int dn_volume_create(const dn_volume_params *p, void *arena, size_t arena_bytes, void *hip_stream, dn_volume **out)
 {
     DN_REQUIRE(p && out, "null argument");
     *out = nullptr;
@@ -747,44 +937,31 @@ int dn_volume_create(const dn_volume_params *p, void *hip_stream, dn_volume **ou
     DN_REQUIRE(p->max_blocks >= 1, "max_blocks must be >= 1");
     DN_REQUIRE(p->hash_cap_log2 >= 4 && p->hash_cap_log2 <= 30, "hash_cap_log2 must be in [4, 30]");
     DN_REQUIRE(p->hash_tail >= 0, "hash_tail must be >= 0");
+    DN_REQUIRE(params_ok(p), "bad limits (state16 0/1; max_points, max_candidates, max_observations >= 0 and in range)");
+    DN_REQUIRE(arena, "null arena");
+    DN_REQUIRE((reinterpret_cast<uintptr_t>(arena) & 255) == 0, "the arena must be 256-byte aligned");
+    const size_t need = volume_layout(*p, nullptr, nullptr);
+    if (arena_bytes < need) {
+        set_error("arena of %zu bytes is short: the volume needs %zu (dn_volume_bytes)", arena_bytes, need);
+        return DN_E_CAPACITY;
+    }
     dn_volume *v = new dn_volume();
     v->prm = *p;
     v->stream = static_cast<hipStream_t>(hip_stream);
     v->cap_blocks = p->max_blocks;
     v->hash_cap = 1u << p->hash_cap_log2;
     v->hash_slots = int64_t(v->hash_cap) + p->hash_tail;
-    auto fail = [&](int rc) { dn_volume_destroy(v); return rc; };
+    v->arena = arena;
+    v->arena_bytes = arena_bytes;
+    volume_layout(*p, arena, v);
+    auto fail = [&](int rc) { delete v; return rc; };
     if (hipGetDevice(&v->device) != hipSuccess) { set_error("hipGetDevice failed"); return fail(DN_E_DEVICE); }
-    const size_t vox = size_t(v->cap_blocks) * kBlockVox;
-    struct { void **ptr; size_t bytes; } allocs[] = {
-        {(void **)&v->coords, size_t(v->cap_blocks) * 16},
-        {(void **)&v->keys, size_t(v->cap_blocks) * 8},
-        {(void **)&v->hash[0], size_t(v->hash_slots) * 16},
-        {(void **)&v->hash[1], size_t(v->hash_slots) * 16},
-        {(void **)&v->nbr, size_t(v->cap_blocks) * kNbr * 4},
-        {(void **)&v->f, vox * 4},
-        {(void **)&v->w, vox * 4},
-        {(void **)&v->u, vox * 4},
-        {(void **)&v->ubar[0], vox * 4},
-        {(void **)&v->ubar[1], vox * 4},
-        {(void **)&v->p[0], vox * 12},
-        {(void **)&v->p[1], vox * 12},
-        {(void **)&v->emask, vox},
-        {(void **)&v->order, size_t(v->cap_blocks) * 4},
-        {(void **)&v->partials, size_t(v->cap_blocks) * 16 + 2 * (size_t((v->cap_blocks + 1023) / 1024) + 1) * 16 + 64},
-        {(void **)&v->energy2, 64},
-    };
-    for (auto &a : allocs) {
-        if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
-            set_error("hipMalloc of %zu bytes failed", a.bytes);
-            return fail(DN_E_DEVICE);
-        }
-    }
+    int rc = verify_tmp_bounds(v);
+    if (rc) return fail(rc);
     hipStream_t st = v->stream;
-    if (hipMemsetAsync(v->f, 0, vox * 4, st) != hipSuccess || hipMemsetAsync(v->w, 0, vox * 4, st) != hipSuccess) {
-        set_error("hipMemsetAsync failed");
-        return fail(DN_E_DEVICE);
-    }
+    const int64_t vox = int64_t(v->cap_blocks) * kBlockVox;
+    hipLaunchKernelGGL(k_zero_blocks, dim3(grid1(vox)), dim3(256), 0, st, v->f, int64_t(0), v->cap_blocks);
+    hipLaunchKernelGGL(k_zero_blocks, dim3(grid1(vox)), dim3(256), 0, st, v->w, int64_t(0), v->cap_blocks);
     hipLaunchKernelGGL(k_fill_empty, dim3(grid1(v->hash_slots)), dim3(256), 0, st,
                        reinterpret_cast<int4 *>(v->hash[0]), v->hash_slots);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
@@ -799,16 +976,6 @@ void dn_volume_destroy(dn_volume *v)
 {
     if (!v) return;
     (void)hipStreamSynchronize(v->stream);
-    void *ptrs[] = {v->coords, v->keys, v->hash[0], v->hash[1], v->nbr, v->f, v->w, v->u,
-                    v->ubar[0], v->ubar[1], v->p[0], v->p[1], v->emask, v->order, v->partials,
-                    v->energy2, v->u16, v->ubar16[0], v->ubar16[1], v->p16[0], v->p16[1]};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-    dn::Buf *bufs[] = {&v->s_cand, &v->s_cand2, &v->s_counts, &v->s_offsets, &v->s_tmp, &v->s_uniq,
-                       &v->s_flags, &v->s_new, &v->s_sorted, &v->s_vals, &v->s_vals2, &v->s_home,
-                       &v->s_home2, &v->s_pos, &v->s_misc, &v->s_laser, &v->s_newk};
-    for (auto *b : bufs) b->release();
-    v->host.release();
     delete v;
 }
 
@@ -827,8 +994,7 @@ int dn_volume_clear(dn_volume *v)
     v->nb = 0;
     v->nb_state = 0;
     v->emask_nb = -1;
-    v->last_nuniq = 0;
-    v->cand_pending = false;
+    v->cand_n = 0;
     v->state_storage = DN_F32;
     return DN_OK;
 }
@@ -855,46 +1021,32 @@ int dn_alloc_blocks(dn_volume *v, const float *depth, const dn_intrinsics *K, co
     Geo g;
     int rc = make_geo(v, K, T, g);
     if (rc) return rc;
-    if (n_new_out) *n_new_out = 0;
     hipStream_t st = v->stream;
     const int64_t npx = int64_t(g.W) * g.H;
-    if ((rc = v->s_counts.ensure(npx * 4))) return rc;
-    if ((rc = v->s_offsets.ensure(npx * 4 + 8))) return rc;
-    int32_t *counts = v->s_counts.as<int32_t>();
-    int32_t *offs = v->s_offsets.as<int32_t>();
-    hipLaunchKernelGGL(k_dda_count, dim3(grid1(npx)), dim3(256), 0, st, g, depth, counts);
-    DN_HIP(hipGetLastError());
-    size_t tb = 0;
-    DN_HIP(rocprim::exclusive_scan(nullptr, tb, counts, offs, 0, size_t(npx), rocprim::plus<int32_t>(), st));
-    if ((rc = v->s_tmp.ensure(tb))) return rc;
-    size_t tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::exclusive_scan(v->s_tmp.ptr, tbytes, counts, offs, 0, size_t(npx), rocprim::plus<int32_t>(), st));
-    if ((rc = v->host.ensure(64))) return rc;
-    DN_HIP(hipMemcpyAsync(v->host.as<int32_t>(), offs + npx - 1, 4, hipMemcpyDeviceToHost, st));
-    DN_HIP(hipMemcpyAsync(v->host.as<int32_t>() + 1, counts + npx - 1, 4, hipMemcpyDeviceToHost, st));
-    DN_HIP(hipStreamSynchronize(st));
-    int64_t total = int64_t(v->host.as<int32_t>()[0]) + v->host.as<int32_t>()[1];
-    if (total == 0) { v->last_nuniq = 0; v->cand_pending = false; return DN_OK; }
-    v->cand_pending = false;
-    v->last_nuniq = 0;
-    if ((rc = v->s_cand.ensure(total * 8))) return rc;
-    hipLaunchKernelGGL(k_dda_emit, dim3(grid1(npx)), dim3(256), 0, st, g, depth, offs, v->s_cand.as<uint64_t>(), total);
-    DN_HIP(hipGetLastError());
-    return insert_packed(v, v->s_cand.as<uint64_t>(), total, n_new_out);
+    return alloc_points(
+        v, npx,
+        [&](int32_t *counts) {
+            hipLaunchKernelGGL(k_dda_count, dim3(grid1(npx)), dim3(256), 0, st, g, depth, counts);
+        },
+        [&](const int32_t *offs, int64_t total) {
+            hipLaunchKernelGGL(k_dda_emit, dim3(grid1(npx)), dim3(256), 0, st, g, depth, offs, v->cand, total);
+        },
+        n_new_out);
 }
 
 int dn_insert_blocks(dn_volume *v, const int32_t *coords, int64_t n, int32_t *n_new_out)
 {
     DN_REQUIRE(v && (coords || n == 0) && n >= 0, "bad argument");
     if (n_new_out) *n_new_out = 0;
+    v->cand_n = 0;
     if (n == 0) return DN_OK;
-    int rc;
-    v->cand_pending = false;
-    v->last_nuniq = 0;
-    if ((rc = v->s_cand.ensure(n * 8))) return rc;
-    hipLaunchKernelGGL(k_pack_coords, dim3(grid1(n)), dim3(256), 0, v->stream, coords, n, v->s_cand.as<uint64_t>());
+    if (n > v->prm.max_candidates) {
+        set_error("%lld keys exceed the volume's max_candidates %lld", (long long)n, (long long)v->prm.max_candidates);
+        return DN_E_CAPACITY;
+    }
+    hipLaunchKernelGGL(k_pack_coords, dim3(grid1(n)), dim3(256), 0, v->stream, coords, n, v->cand);
     DN_HIP(hipGetLastError());
-    return insert_packed(v, v->s_cand.as<uint64_t>(), n, n_new_out);
+    return insert_packed(v, v->cand, n, n_new_out);
 }
 
 int dn_fuse_depth(dn_volume *v, const float *depth, const dn_intrinsics *K, const double T[16])
@@ -928,34 +1080,16 @@ int dn_alloc_laser(dn_volume *v, const float *pts, int64_t n, const double T[16]
     LGeo g;
     int rc = make_lgeo(v, T, g);
     if (rc) return rc;
-    if (n_new_out) *n_new_out = 0;
-    if (n == 0) { v->last_nuniq = 0; v->cand_pending = false; return DN_OK; }
-    DN_REQUIRE(n < (int64_t(1) << 31), "too many returns in one scan");
     hipStream_t st = v->stream;
-    if ((rc = v->s_counts.ensure(n * 4))) return rc;
-    if ((rc = v->s_offsets.ensure(n * 4 + 8))) return rc;
-    int32_t *counts = v->s_counts.as<int32_t>();
-    int32_t *offs = v->s_offsets.as<int32_t>();
-    hipLaunchKernelGGL(k_laser_cand_count, dim3(grid1(n)), dim3(256), 0, st, g, pts, n, counts);
-    DN_HIP(hipGetLastError());
-    size_t tb = 0;
-    DN_HIP(rocprim::exclusive_scan(nullptr, tb, counts, offs, 0, size_t(n), rocprim::plus<int32_t>(), st));
-    if ((rc = v->s_tmp.ensure(tb))) return rc;
-    size_t tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::exclusive_scan(v->s_tmp.ptr, tbytes, counts, offs, 0, size_t(n), rocprim::plus<int32_t>(), st));
-    if ((rc = v->host.ensure(64))) return rc;
-    DN_HIP(hipMemcpyAsync(v->host.as<int32_t>(), offs + n - 1, 4, hipMemcpyDeviceToHost, st));
-    DN_HIP(hipMemcpyAsync(v->host.as<int32_t>() + 1, counts + n - 1, 4, hipMemcpyDeviceToHost, st));
-    DN_HIP(hipStreamSynchronize(st));
-    const int64_t total = int64_t(v->host.as<int32_t>()[0]) + v->host.as<int32_t>()[1];
-    if (total == 0) { v->last_nuniq = 0; v->cand_pending = false; return DN_OK; }
-    v->cand_pending = false;
-    v->last_nuniq = 0;
-    if ((rc = v->s_cand.ensure(total * 8))) return rc;
-    hipLaunchKernelGGL(k_laser_cand_emit, dim3(grid1(n)), dim3(256), 0, st, g, pts, n, offs,
-                       v->s_cand.as<uint64_t>(), total);
-    DN_HIP(hipGetLastError());
-    return insert_packed(v, v->s_cand.as<uint64_t>(), total, n_new_out);
+    return alloc_points(
+        v, n,
+        [&](int32_t *counts) {
+            hipLaunchKernelGGL(k_laser_cand_count, dim3(grid1(n)), dim3(256), 0, st, g, pts, n, counts);
+        },
+        [&](const int32_t *offs, int64_t total) {
+            hipLaunchKernelGGL(k_laser_cand_emit, dim3(grid1(n)), dim3(256), 0, st, g, pts, n, offs, v->cand, total);
+        },
+        n_new_out);
 }
 
 int dn_fuse_laser(dn_volume *v, const float *pts, int64_t n, const double T[16])
@@ -965,58 +1099,49 @@ int dn_fuse_laser(dn_volume *v, const float *pts, int64_t n, const double T[16])
     int rc = make_lgeo(v, T, g);
     if (rc) return rc;
     if (n == 0 || v->nb == 0) return DN_OK;
+    if (n > v->prm.max_points) {
+        set_error("%lld returns exceed the volume's max_points %lld", (long long)n, (long long)v->prm.max_points);
+        return DN_E_CAPACITY;
+    }
+    if (v->prm.max_observations <= 0) { set_error("the volume was created without laser observations"); return DN_E_CAPACITY; }
     DN_REQUIRE(v->nb * int64_t(kBlockVox) < (int64_t(1) << 32), "volume too large for 32-bit voxel keys");
     hipStream_t st = v->stream;
     const int4 *slots = reinterpret_cast<const int4 *>(v->hash[v->cur_hash]);
-    if ((rc = v->s_counts.ensure(n * 8))) return rc;
-    if ((rc = v->s_offsets.ensure(n * 8 + 8))) return rc;
-    int64_t *counts = v->s_counts.as<int64_t>();
-    int64_t *offs = v->s_offsets.as<int64_t>();
+    Bump bump(v->scratch, v->scratch_bytes);
+    LaserScratch x = carve_laser(bump, n, v->prm.max_observations);
+    if (!bump.fits()) { set_error("scratch too small for the laser observations"); return DN_E_CAPACITY; }
     hipLaunchKernelGGL(k_laser_obs_count, dim3(grid1(n)), dim3(256), 0, st, g, pts, n, slots, v->hash_slots,
-                       v->hash_cap, counts);
+                       v->hash_cap, x.counts);
     DN_HIP(hipGetLastError());
-    size_t tb = 0;
-    DN_HIP(rocprim::exclusive_scan(nullptr, tb, counts, offs, int64_t(0), size_t(n), rocprim::plus<int64_t>(), st));
-    if ((rc = v->s_tmp.ensure(tb))) return rc;
-    size_t tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::exclusive_scan(v->s_tmp.ptr, tbytes, counts, offs, int64_t(0), size_t(n),
+    size_t tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::exclusive_scan(x.tmp, tbytes, x.counts, x.offs, int64_t(0), size_t(n),
                                    rocprim::plus<int64_t>(), st));
-    if ((rc = v->host.ensure(64))) return rc;
-    DN_HIP(hipMemcpyAsync(v->host.as<int64_t>(), offs + n - 1, 8, hipMemcpyDeviceToHost, st));
-    DN_HIP(hipMemcpyAsync(v->host.as<int64_t>() + 1, counts + n - 1, 8, hipMemcpyDeviceToHost, st));
+    DN_HIP(hipMemcpyAsync(v->host_stage, x.offs + n - 1, 8, hipMemcpyDeviceToHost, st));
+    DN_HIP(hipMemcpyAsync(v->host_stage + 1, x.counts + n - 1, 8, hipMemcpyDeviceToHost, st));
     DN_HIP(hipStreamSynchronize(st));
-    const int64_t m = v->host.as<int64_t>()[0] + v->host.as<int64_t>()[1];
+    const int64_t m = v->host_stage[0] + v->host_stage[1];
     if (m == 0) return DN_OK;
-    DN_REQUIRE(m < (int64_t(1) << 32), "too many observations in one scan");
-    // keys, values, their sorted copies, the counts and the run count
-    if ((rc = v->s_laser.ensure(size_t(m) * 48 + 1024))) return rc;
-    uint32_t *k_in = reinterpret_cast<uint32_t *>(v->s_laser.ptr);
-    uint32_t *k_out = k_in + m;
-    double *v_in = reinterpret_cast<double *>(static_cast<char *>(v->s_laser.ptr) + ((size_t(m) * 8 + 255) / 256) * 256);
-    double *v_out = v_in + m;
+    if (m > v->prm.max_observations) {
+        set_error("%lld laser observations exceed the volume's max_observations %lld", (long long)m,
+                  (long long)v->prm.max_observations);
+        return DN_E_CAPACITY;
+    }
     hipLaunchKernelGGL(k_laser_obs_emit, dim3(grid1(n)), dim3(256), 0, st, g, pts, n, slots, v->hash_slots,
-                       v->hash_cap, offs, k_in, v_in, m);
+                       v->hash_cap, x.offs, x.k_in, x.v_in, m);
     DN_HIP(hipGetLastError());
     int bits = 1;
     while ((int64_t(1) << bits) < v->nb * int64_t(kBlockVox)) ++bits;
     // sort by voxel, then the sum and the count of each voxel's observations
-    // (distinct voxels into k_in / v_in, counts after the sorted values)
-    uint32_t *counts32 = reinterpret_cast<uint32_t *>(v_out + m);
-    uint32_t *nruns = counts32 + ((m + 63) / 64) * 64;
-    size_t t1 = 0, t2 = 0, t3 = 0;
-    DN_HIP(rocprim::radix_sort_pairs(nullptr, t1, k_in, k_out, v_in, v_out, size_t(m), 0, bits, st));
-    DN_HIP(rocprim::reduce_by_key(nullptr, t2, k_out, v_out, size_t(m), k_in, v_in, nruns, rocprim::plus<double>(),
-                                  rocprim::equal_to<uint32_t>(), st));
-    DN_HIP(rocprim::run_length_encode(nullptr, t3, k_out, size_t(m), k_in, counts32, nruns, st));
-    if ((rc = v->s_tmp.ensure(std::max(t1, std::max(t2, t3))))) return rc;
-    tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::radix_sort_pairs(v->s_tmp.ptr, tbytes, k_in, k_out, v_in, v_out, size_t(m), 0, bits, st));
-    tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::reduce_by_key(v->s_tmp.ptr, tbytes, k_out, v_out, size_t(m), k_in, v_in, nruns,
+    // (distinct voxels into k_in / v_in, counts into counts32)
+    tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::radix_sort_pairs(x.tmp, tbytes, x.k_in, x.k_out, x.v_in, x.v_out, size_t(m), 0, bits, st));
+    tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::reduce_by_key(x.tmp, tbytes, x.k_out, x.v_out, size_t(m), x.k_in, x.v_in, x.nruns,
                                   rocprim::plus<double>(), rocprim::equal_to<uint32_t>(), st));
-    tbytes = v->s_tmp.bytes;
-    DN_HIP(rocprim::run_length_encode(v->s_tmp.ptr, tbytes, k_out, size_t(m), k_in, counts32, nruns, st));
-    hipLaunchKernelGGL(k_laser_apply, dim3(grid1(m)), dim3(256), 0, st, k_in, v_in, counts32, nruns, m, v->f, v->w);
+    tbytes = x.tmp_bytes;
+    DN_HIP(rocprim::run_length_encode(x.tmp, tbytes, x.k_out, size_t(m), x.k_in, x.counts32, x.nruns, st));
+    hipLaunchKernelGGL(k_laser_apply, dim3(grid1(m)), dim3(256), 0, st, x.k_in, x.v_in, x.counts32, x.nruns, m,
+                       v->f, v->w);
     DN_HIP(hipGetLastError());
     v->emask_nb = -1;
     return DN_OK;

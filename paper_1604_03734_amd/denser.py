@@ -42,7 +42,9 @@ class Intrinsics(ctypes.Structure):
 class VolumeParams(ctypes.Structure):
     _fields_ = [("voxel_size", ctypes.c_double), ("mu", ctypes.c_double), ("max_depth", ctypes.c_double),
                 ("max_blocks", ctypes.c_int32), ("hash_cap_log2", ctypes.c_int32),
-                ("hash_tail", ctypes.c_int32)]
+                ("hash_tail", ctypes.c_int32), ("state16", ctypes.c_int32),
+                ("max_points", ctypes.c_int64), ("max_candidates", ctypes.c_int64),
+                ("max_observations", ctypes.c_int64)]
 
 
 class RegParams(ctypes.Structure):
@@ -82,8 +84,13 @@ def lib():
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1604_03734_amd.build`")
     L = ctypes.CDLL(LIB_PATH)
     P, i32, i64, f64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_float
+    sz = ctypes.c_size_t
     sig = {
-        "dn_volume_create": (i32, [P, P, P]),
+        "dn_volume_bytes": (sz, [P]),
+        "dn_volume_create": (i32, [P, P, sz, P, P]),
+        "dn_regularize_batch_bytes": (sz, [i32, i64]),
+        "dn_net_bytes": (sz, [i64, i32]),
+        "dn_warm_start_bytes": (sz, [i64]),
         "dn_volume_destroy": (None, [P]),
         "dn_set_stream": (i32, [P, P]),
         "dn_volume_clear": (i32, [P]),
@@ -97,15 +104,15 @@ def lib():
         "dn_fuse_laser": (i32, [P, P, i64, P]),
         "dn_load_fused": (i32, [P, P, P]),
         "dn_regularize": (i32, [P, P, P, P, P]),
-        "dn_regularize_batch": (i32, [P, i32, P, P]),
+        "dn_regularize_batch": (i32, [P, i32, P, P, sz, P]),
         "dn_energy": (i32, [P, f64, i32, P]),
         "dn_mesh_area": (i32, [P, P, P]),
         "dn_extract": (i32, [P, i32, P, ctypes.c_size_t, P]),
         "dn_net_gather": (i32, [P, P, i64, i32, P]),
-        "dn_net_forward": (i32, [P, i64, P, P, P]),
-        "dn_net_loss_grad": (i32, [P, i64, P, P, P, i32, P, P, P]),
+        "dn_net_forward": (i32, [P, i64, P, P, P, sz, P]),
+        "dn_net_loss_grad": (i32, [P, i64, P, P, P, i32, P, P, sz, P, P]),
         "dn_net_adam": (i32, [P, P, P, P, i64, f32, f32, f32, f32, i32, P]),
-        "dn_net_warm_start": (i32, [P, P, i32, f64, P, P]),
+        "dn_net_warm_start": (i32, [P, P, i32, f64, P, P, P, sz]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name, None)
@@ -139,6 +146,49 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def device_bytes(nbytes, device=None):
+    """A device buffer of at least nbytes whose address is 256-byte
+    aligned: (owning tensor, aligned address)."""
+    import torch
+    if device is None:
+        device = torch.device("cuda", torch.cuda.current_device())
+    t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    addr = t.data_ptr()
+    return t, addr + (-addr) % 256
+
+
+_workspaces = {}
+
+
+def workspace(purpose, nbytes):
+    """A cached workspace (grown on demand) per (device, purpose): the
+    library never allocates device memory; the binding keeps one buffer per
+    use so that repeated calls (and the batched solver's captured graph)
+    see the same address."""
+    import torch
+    key = (torch.cuda.current_device(), purpose)
+    cur = _workspaces.get(key)
+    if cur is None or cur[2] < nbytes:
+        t, addr = device_bytes(max(int(nbytes), 256))
+        cur = (t, addr, int(nbytes))
+        _workspaces[key] = cur
+    return ctypes.c_void_p(cur[1]), ctypes.c_size_t(cur[2])
+
+
+def band_cells_per_point(voxel_size, mu, ray_norm=2.0):
+    """Most blocks one pixel's band [d - mu, d + mu] can cross: 4 plus the
+    band's L1 length in block units, for rays r = ((x - cx)/fx, (y - cy)/fy,
+    1) with |r| <= ray_norm."""
+    return 4 + int(np.floor(np.sqrt(3.0) * 2.0 * mu * ray_norm / (8.0 * voxel_size)))
+
+
+def laser_observations_bound(n_returns, voxel_size, mu, max_depth):
+    """Most voxel observations n_returns laser returns can make: each ray is
+    walked from the sensor to range + mu <= max_depth + mu, at most 4 plus
+    its L1 length in voxels."""
+    return int(n_returns) * (4 + int(np.floor(np.sqrt(3.0) * (max_depth + mu) / voxel_size)))
+
+
 def intrinsics(fx, fy, cx, cy, width, height) -> Intrinsics:
     return Intrinsics(fx, fy, cx, cy, width, height)
 
@@ -149,21 +199,39 @@ def _pose(T):
 
 
 class Volume:
-    """A hashed-block TSDF volume living on the GPU."""
+    """A hashed-block TSDF volume living on the GPU, in one arena that this
+    object allocates with torch and hands to the library.
+
+    max_points: most pixels of a depth map (or returns of a laser scan) one
+    call takes; max_candidates: most band cells one allocation call lists
+    (default: max_points times the band bound of band_cells_per_point, at
+    least max_blocks); max_observations: most voxel observations of one
+    laser fusion call (0: no laser fusion); state16: room for FP16/BF16
+    solver state."""
 
     def __init__(self, voxel_size, mu, max_depth, max_blocks, hash_cap_log2=20, hash_tail=1024,
-                 stream=None):
+                 stream=None, *, max_points=1 << 19, max_candidates=None, max_observations=0, state16=True):
         import torch
-        self.params = VolumeParams(voxel_size, mu, max_depth, max_blocks, hash_cap_log2, hash_tail)
+        if max_candidates is None:
+            max_candidates = max(int(max_blocks), int(max_points) * band_cells_per_point(voxel_size, mu))
+        self.params = VolumeParams(voxel_size, mu, max_depth, max_blocks, hash_cap_log2, hash_tail,
+                                   1 if state16 else 0, int(max_points), int(max_candidates),
+                                   int(max_observations))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.arena_bytes = int(lib().dn_volume_bytes(ctypes.byref(self.params)))
+        if self.arena_bytes == 0:
+            raise DenserError(DN_E_INVALID, "invalid volume parameters")
+        self._arena, addr = device_bytes(self.arena_bytes)
         h = ctypes.c_void_p()
-        check(lib().dn_volume_create(ctypes.byref(self.params), _stream_handle(self.stream), ctypes.byref(h)))
+        check(lib().dn_volume_create(ctypes.byref(self.params), ctypes.c_void_p(addr), self.arena_bytes,
+                                     _stream_handle(self.stream), ctypes.byref(h)))
         self.handle = h
 
     def close(self):
         if getattr(self, "handle", None):
             lib().dn_volume_destroy(self.handle)
             self.handle = None
+        self._arena = None
 
     def __del__(self):
         try:
@@ -266,25 +334,32 @@ class Volume:
         check(lib().dn_net_gather(self.handle, _ptr(blocks), blocks.shape[0], int(perm), _ptr(tiles)))
 
     def net_warm_start(self, params, u0, p0=None, mode=DN_WARM_DUAL, delta=0.1):
-        check(lib().dn_net_warm_start(self.handle, _ptr(params), int(mode), float(delta), _ptr(u0), _ptr(p0)))
+        ws, nbytes = workspace("warm_start", lib().dn_warm_start_bytes(self.num_blocks))
+        check(lib().dn_net_warm_start(self.handle, _ptr(params), int(mode), float(delta), _ptr(u0), _ptr(p0),
+                                      ws, nbytes))
 
 
 def regularize_batch(volumes, params: RegParams):
     arr = (ctypes.c_void_p * len(volumes))(*[v.handle.value for v in volumes])
     stats = (RegStats * len(volumes))()
-    check(lib().dn_regularize_batch(arr, len(volumes), ctypes.byref(params), stats))
+    total = sum(v.num_blocks for v in volumes)
+    ws, nbytes = workspace("batch", lib().dn_regularize_batch_bytes(len(volumes), total))
+    check(lib().dn_regularize_batch(arr, len(volumes), ctypes.byref(params), ws, nbytes, stats))
     return list(stats)
 
 
 def net_forward(tiles, params, out, stream=None):
-    check(lib().dn_net_forward(_ptr(tiles), tiles.shape[0], _ptr(params), _ptr(out), _stream_handle(stream)))
+    ws, nbytes = workspace("net", lib().dn_net_bytes(tiles.shape[0], 0))
+    check(lib().dn_net_forward(_ptr(tiles), tiles.shape[0], _ptr(params), _ptr(out), ws, nbytes,
+                               _stream_handle(stream)))
 
 
 def net_loss_grad(tiles, params, targets, mask, grad, kind=0, stream=None, sync=True):
     """Loss (returned when sync, which waits for it) and gradient into grad."""
     loss = ctypes.c_double(0)
+    ws, nbytes = workspace("net_train", lib().dn_net_bytes(tiles.shape[0], 1))
     check(lib().dn_net_loss_grad(_ptr(tiles), tiles.shape[0], _ptr(params), _ptr(targets), _ptr(mask),
-                                 int(kind), _ptr(grad), ctypes.byref(loss) if sync else None,
+                                 int(kind), _ptr(grad), ws, nbytes, ctypes.byref(loss) if sync else None,
                                  _stream_handle(stream)))
     return loss.value if sync else None
 

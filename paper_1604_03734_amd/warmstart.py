@@ -63,7 +63,8 @@ def fuse_frames(frames, max_blocks=16384):
     import torch
     cam = frames.camera
     K = D.intrinsics(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height)
-    vol = D.Volume(frames.voxel_size, frames.mu, frames.max_depth, max_blocks, 16, 1024)
+    vol = D.Volume(frames.voxel_size, frames.mu, frames.max_depth, max_blocks, 16, 1024,
+                   max_points=cam.width * cam.height)
     for d, T in zip(frames.depths, frames.poses):
         vol.integrate(torch.from_numpy(d).cuda(), K, T)
     return vol

@@ -44,7 +44,8 @@ def fuse_both(fr, max_blocks=8192, cap_log2=12, tail=256, check_each_frame=True)
     D = dn()
     cam = fr.camera
     ov = oracle.OracleVolume(fr.voxel_size, fr.mu, fr.max_depth, max_blocks, cap_log2, tail)
-    gv = D.Volume(fr.voxel_size, fr.mu, fr.max_depth, max_blocks, cap_log2, tail)
+    gv = D.Volume(fr.voxel_size, fr.mu, fr.max_depth, max_blocks, cap_log2, tail,
+                  max_points=cam.width * cam.height)
     K = intr(D, cam)
     for d, T in zip(fr.depths, fr.poses):
         n_o = ov.alloc(d, K4(cam), T)

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 def _make(D, nb, seed, extent):
     import torch
     coords, f, w = scenes.random_block_field(nb, seed, extent=extent, omega_frac=0.75)
-    gv = D.Volume(0.1, 0.3, 10.0, nb, 8, 64)
+    gv = D.Volume(0.1, 0.3, 10.0, nb, 8, 64, max_points=0)
     gv.insert_blocks(to_dev(coords.astype(np.int32)))
     c = host(gv.extract(D.DN_X_COORDS))
     order = np.array([np.nonzero((coords == x).all(1))[0][0] for x in c])

@@ -94,7 +94,7 @@ def test_l1_batch_matches_single_and_oracle():
     vols = []
     for nb, seed, ext in [(3, 0, 2), (40, 1, 4), (7, 2, 3)]:
         coords, f, w = scenes.random_block_field(nb, seed, extent=ext, omega_frac=0.75)
-        gv = D.Volume(0.1, 0.3, 10.0, nb, 8, 64)
+        gv = D.Volume(0.1, 0.3, 10.0, nb, 8, 64, max_points=0)
         gv.insert_blocks(to_dev(coords.astype(np.int32)))
         c = host(gv.extract(D.DN_X_COORDS))
         order = np.array([np.nonzero((coords == x).all(1))[0][0] for x in c])

@@ -11,6 +11,9 @@ from gpu_common import K4, dn, host, intr, to_dev
 
 pytestmark = pytest.mark.gpu
 
+# room for scans of up to 24 x 720 returns within 20 m (and 320 x 96 depth maps)
+LASER = dict(max_points=1 << 15, max_observations=24 * 720 * (4 + int(np.sqrt(3.0) * 20.3 / 0.1)))
+
 
 def _check(D, ov, gv):
     assert gv.num_blocks == ov.nb
@@ -32,7 +35,7 @@ def test_laser_scans_match_the_oracle():
     D = dn()
     boxes = scenes.scene_c1()
     ov = oracle.OracleVolume(0.1, 0.3, 20.0, 8192, 12, 256)
-    gv = D.Volume(0.1, 0.3, 20.0, 8192, 12, 256)
+    gv = D.Volume(0.1, 0.3, 20.0, 8192, 12, 256, **LASER)
     for k, T in enumerate(_poses()):
         pts = scenes.laser_scan(boxes, T, k, n_rings=24, n_azimuth=720)
         n_o = ov.alloc_laser(pts, T)
@@ -53,7 +56,7 @@ def test_laser_and_depth_share_the_block_pool():
     boxes = scenes.scene_c1()
     cam = fr.camera
     ov = oracle.OracleVolume(0.1, 0.3, 20.0, 8192, 12, 256)
-    gv = D.Volume(0.1, 0.3, 20.0, 8192, 12, 256)
+    gv = D.Volume(0.1, 0.3, 20.0, 8192, 12, 256, **LASER)
     K = intr(D, cam)
     for k, (d, T) in enumerate(zip(fr.depths, fr.poses)):
         assert ov.alloc(d, K4(cam), T) == gv.alloc_blocks(to_dev(d), K, T)
@@ -70,7 +73,7 @@ def test_invalid_and_empty_scans_change_nothing():
     D = dn()
     boxes = scenes.scene_c1()
     T = _poses()[1]
-    gv = D.Volume(0.1, 0.3, 20.0, 4096, 12, 256)
+    gv = D.Volume(0.1, 0.3, 20.0, 4096, 12, 256, **LASER)
     pts = scenes.laser_scan(boxes, T, 3)
     gv.integrate_laser(to_dev(pts), T)
     nb = gv.num_blocks
@@ -88,7 +91,7 @@ def test_scans_of_one_and_three_returns():
     holds them, their sorted copies, the per-voxel counts and the count)."""
     D = dn()
     ov = oracle.OracleVolume(0.1, 0.3, 20.0, 1024, 10, 128)
-    gv = D.Volume(0.1, 0.3, 20.0, 1024, 10, 128)
+    gv = D.Volume(0.1, 0.3, 20.0, 1024, 10, 128, **LASER)
     T = _poses()[0]
     for pts in (np.array([[2.0, 0.1, 0.05]], np.float32),
                 np.array([[1.5, 0.0, 0.0], [0.3, 1.1, 0.2], [-0.7, 0.2, 2.5]], np.float32)):

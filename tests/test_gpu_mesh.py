@@ -47,7 +47,7 @@ def test_mesh_of_the_fused_and_regularised_c1(c1):
 def test_mesh_of_random_fields(nb, seed, extent):
     D = dn()
     coords, f, w = scenes.random_block_field(nb, seed, extent=extent, omega_frac=0.9)
-    gv = D.Volume(0.05, 0.3, 10.0, nb, 8, 64)
+    gv = D.Volume(0.05, 0.3, 10.0, nb, 8, 64, max_points=0)
     gv.insert_blocks(to_dev(coords.astype(np.int32)))
     c = host(gv.extract(D.DN_X_COORDS))
     order = np.array([np.nonzero((coords == x).all(1))[0][0] for x in c])
@@ -59,6 +59,6 @@ def test_mesh_of_random_fields(nb, seed, extent):
 
 def test_mesh_of_an_empty_volume():
     D = dn()
-    gv = D.Volume(0.1, 0.3, 10.0, 16, 6, 16)
+    gv = D.Volume(0.1, 0.3, 10.0, 16, 6, 16, max_points=0)
     assert gv.extract(D.DN_X_MESH).shape == (0, 3, 3)
     assert gv.mesh_area() == (0.0, 0)
