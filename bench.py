@@ -169,8 +169,14 @@ class BatchedWorkload(Workload):
     translated copies of the fused street.  All regularised by one
     persistent launch of 300 iterations (HIP graph, autotuned)."""
 
-    def __init__(self, args):
-        super().__init__(args)
+    def __init__(self, args, base=None):
+        if base is None:
+            super().__init__(args)
+        else:
+            # share the generated frames and the fused street of a street workload
+            self.D, self.torch, self.args = base.D, base.torch, args
+            self.fr, self.K, self.depths, self.street = base.fr, base.K, base.depths, base.street
+            self.big, self.kernel = base.big, base.kernel
         import scenes
         self.counts = scenes.c4_block_counts(args.submaps, seed=0)
         self.subs = []
@@ -179,7 +185,8 @@ class BatchedWorkload(Workload):
             self.subs.append(self.D.Volume(self.fr.voxel_size, self.fr.mu, self.fr.max_depth, int(n),
                                            max(10, int(np.ceil(np.log2(n))) + 1), 4096, max_points=0,
                                            state16=False))
-        self.fuse_street()
+        if base is None:
+            self.fuse_street()
         self._layout()
 
     def _layout(self):
@@ -218,10 +225,25 @@ class BatchedWorkload(Workload):
         return int(sum(v.num_blocks for v in self.subs)) * 512
 
 
-def cpu_baseline(wl):
-    """The FP64 oracle on one street (the same frames): allocation + fusion
-    of every frame and the same number of iterations, all host cores."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, cp_iters=20):
+    """The FP64 oracle on the host's cores on a bounded sample of the same
+    step: allocation + fusion of the 100 depth maps of the street, then
+    cp_iters iterations over the whole map of translated copies (the same
+    blocks the GPU regularises); the step rate is extrapolated to the
+    step's 500 iterations."""
     import oracle
+    D = wl.D
     fr = wl.fr
     cam = fr.camera
     K4 = [cam.fx, cam.fy, cam.cx, cam.cy]
@@ -232,18 +254,25 @@ def cpu_baseline(wl):
         ov.alloc(d, K4, T)
         ov.fuse(d, K4, T, nthreads=nt)
     t_fuse = time.time() - t0
-    u = np.zeros_like(ov.f); ub = np.zeros_like(u); p = np.zeros((3,) + u.shape)
-    iters = wl.args.iters
+    # the map: the GPU map's keys (the same translated copies), f and w
+    coords = wl.big.extract(D.DN_X_COORDS).cpu().numpy()
+    f = wl.big.extract(D.DN_X_F).cpu().numpy().astype(np.float64)
+    w = wl.big.extract(D.DN_X_W).cpu().numpy().astype(np.float64)
+    big = oracle.OracleVolume(fr.voxel_size, fr.mu, fr.max_depth, len(coords), 19, 8192)
+    big.insert(coords)
+    u = np.zeros_like(f); ub = np.zeros_like(u); p = np.zeros((3,) + u.shape)
     t1 = time.time()
-    oracle.cp(ov.nbr, ov.f, ov.w, u, ub, p, iters, 0.5, 12 ** -0.5, 12 ** -0.5, 1.0, nthreads=nt)
+    oracle.cp(big.nbr, f, w, u, ub, p, cp_iters, 0.5, 12 ** -0.5, 12 ** -0.5, 1.0, nthreads=nt)
     t_cp = time.time() - t1
-    vox = ov.nb * 512
+    vox = len(coords) * 512
+    iters = wl.args.iters
+    t_step = t_fuse + t_cp * iters / cp_iters
     return {
-        "value": vox * iters / (t_fuse + t_cp), "unit": "voxel-iterations/s", "cores": nt,
-        "kind": "oracle",
-        "sample": f"one 100 m street ({ov.nb} blocks, not the {wl.args.copies} copies): "
-                  f"alloc+fuse {len(fr.depths)} frames {t_fuse:.1f}s + {iters} iterations {t_cp:.1f}s",
-        "cp_only_voxel_iters_per_s": vox * iters / t_cp,
+        "value": vox * iters / t_step, "unit": "voxel-iterations/s", "cores": nt,
+        "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+        "sample": f"alloc+fuse of the {len(fr.depths)} street frames ({t_fuse:.1f}s) + {cp_iters} iterations "
+                  f"over the whole {len(coords)}-block map ({t_cp:.1f}s), extrapolated to {iters} iterations",
+        "cp_only_voxel_iters_per_s": vox * cp_iters / t_cp,
     }
 
 
@@ -251,7 +280,9 @@ def accuracy(wl, iters=500):
     """Synthetic analogue of the paper's error statistics (Section V,
     Tables III and IV): distance of the zero-crossing surface of the street
     to the analytic scene and area of its mesh, before (u = f) and after
-    regularisation."""
+    regularisation.  Points inside a solid box are counted apart (their
+    distance to the nearest face is capped by the box's half thickness), and
+    the median / 75th percentile are also given over the points outside."""
     import scenes
     D, torch = wl.D, wl.torch
     vol = wl.street
@@ -263,13 +294,20 @@ def accuracy(wl, iters=500):
         vol.regularize(prm, u0=u0)
         pts = vol.extract(D.DN_X_SURFACE).cpu().numpy()
         d = scenes.distance_to_scene(pts, boxes) * 100.0
+        ins = scenes.inside_scene(pts, boxes)
+        do = d[~ins]
         area, ntri = vol.mesh_area()
-        out[name] = {"points": int(len(pts)), "median_cm": float(np.median(d)),
-                     "p75_cm": float(np.percentile(d, 75)), "mean_cm": float(d.mean()),
+        out[name] = {"points": int(len(pts)), "inside_share": float(ins.mean()),
+                     "median_cm": float(np.median(d)), "p75_cm": float(np.percentile(d, 75)),
+                     "mean_cm": float(d.mean()),
+                     "outside_points": int(len(do)), "outside_median_cm": float(np.median(do)),
+                     "outside_p75_cm": float(np.percentile(do, 75)),
                      "mesh_area_m2": area, "mesh_triangles": ntri}
     r, g = out["raw"], out["regularised"]
     out["median_change"] = g["median_cm"] / r["median_cm"] - 1.0
     out["p75_change"] = g["p75_cm"] / r["p75_cm"] - 1.0
+    out["outside_median_change"] = g["outside_median_cm"] / r["outside_median_cm"] - 1.0
+    out["outside_p75_change"] = g["outside_p75_cm"] / r["outside_p75_cm"] - 1.0
     out["points_change"] = g["points"] / r["points"] - 1.0
     out["area_change"] = g["mesh_area_m2"] / r["mesh_area_m2"] - 1.0
     return out
@@ -281,58 +319,133 @@ def time_to_gap(wl, tol=1e-3, k=100):
     the fallback to a cold start), both with their gap checks (every 10
     iterations).  For the configured fixed steps (tau = sigma = 1/sqrt(12)),
     for the accelerated variant (gamma = lambda), and with each solver at its
-    fastest step ratio among the same candidates."""
+    fastest step ratio among the same candidates.  The fallback compares the
+    warm gap after k iterations with the plain solver's after k iterations
+    at the same steps; that reference run is timed separately
+    (reference_s) and the speedup is given without and with it."""
     D = wl.D
     torch = wl.torch
     from paper_1604_03734_amd import warmstart
     w = warmstart.load_default_weights()
     wt = torch.from_numpy(w).cuda() if w is not None else None
     out = {"tol": tol, "k": k, "weights": "paper_1604_03734_amd/weights/warmstart.npy" if w is not None else None}
-    for name, gam in (("fixed_steps", 0.0), ("accelerated", 0.5)):
-        r = {}
+
+    def timed(fn):
         torch.cuda.synchronize()
         t0 = time.time()
-        st = warmstart.solve_plain(wl.big, tol, gamma=gam)
+        r = fn()
         torch.cuda.synchronize()
-        r["plain_s"] = time.time() - t0
+        return r, time.time() - t0
+
+    def warm_vs(tau, gam):
+        ref, ref_s = timed(lambda: wl.big.regularize(D.reg_params(0.5, tau, 1.0 / (12.0 * tau), iters=k,
+                                                                  gamma=gam)))
+        res, warm_s = timed(lambda: warmstart.solve_warm(wl.big, wt, tol=tol, k=k, plain_rel_gap_at_k=ref.rel_gap,
+                                                         gamma=gam, tau0=tau))
+        return res, warm_s, ref_s
+
+    t0 = 1.0 / np.sqrt(12.0)
+    for name, gam in (("fixed_steps", 0.0), ("accelerated", 0.5)):
+        r = {}
+        st, r["plain_s"] = timed(lambda: warmstart.solve_plain(wl.big, tol, gamma=gam))
         r["plain_iters"] = st.iters_run
         r["plain_converged"] = bool(st.converged)
         if wt is not None:
-            ref = wl.big.regularize(D.reg_params(0.5, iters=k, gamma=gam))
-            torch.cuda.synchronize()
-            t0 = time.time()
-            res = warmstart.solve_warm(wl.big, wt, tol=tol, k=k, plain_rel_gap_at_k=ref.rel_gap, gamma=gam)
-            torch.cuda.synchronize()
-            r["warm_s"] = time.time() - t0
-            r["warm_iters"] = res["iters"]
-            r["warm_converged"] = res["converged"]
-            r["warm_fallback"] = res["fallback"]
-            r["speedup"] = r["plain_s"] / r["warm_s"]
+            res, warm_s, ref_s = warm_vs(t0, gam)
+            r.update(warm_s=warm_s, warm_iters=res["iters"], warm_converged=res["converged"],
+                     warm_fallback=res["fallback"], reference_s=ref_s,
+                     speedup=r["plain_s"] / warm_s, speedup_incl_reference=r["plain_s"] / (warm_s + ref_s))
         out[name] = r
     # each solver at its best step ratio: tau from the same candidates,
     # sigma = 1 / (12 tau), both with the fixed schedule
     if wt is not None:
-        cand = (0.02, 0.03, 0.05, 0.1, 1.0 / np.sqrt(12.0))
-        ref = wl.big.regularize(D.reg_params(0.5, iters=k))
+        cand = (0.02, 0.03, 0.05, 0.1, t0)
         plain, warm = {}, {}
         for tau in cand:
-            torch.cuda.synchronize()
-            t0 = time.time()
-            st = wl.big.regularize(D.reg_params(0.5, tau, 1.0 / (12.0 * tau), iters=20000, gap_every=10,
-                                                gap_tol=tol))
-            torch.cuda.synchronize()
-            plain[tau] = (time.time() - t0, st.iters_run, bool(st.converged))
-            torch.cuda.synchronize()
-            t0 = time.time()
-            res = warmstart.solve_warm(wl.big, wt, tol=tol, k=k, plain_rel_gap_at_k=ref.rel_gap, tau0=tau)
-            torch.cuda.synchronize()
-            warm[tau] = (time.time() - t0, res["iters"], bool(res["converged"]), bool(res["fallback"]))
+            st, ps = timed(lambda: wl.big.regularize(D.reg_params(0.5, tau, 1.0 / (12.0 * tau), iters=20000,
+                                                                  gap_every=10, gap_tol=tol)))
+            plain[tau] = (ps, st.iters_run, bool(st.converged))
+            res, ws, rs = warm_vs(tau, 0.0)
+            warm[tau] = (ws, res["iters"], bool(res["converged"]), bool(res["fallback"]), rs)
         bp = min((v[0], t) for t, v in plain.items() if v[2])[1]
         bw = min((v[0], t) for t, v in warm.items() if v[2])[1]
         out["best_steps"] = {"tau_candidates": list(cand),
                              "plain_tau": bp, "plain_s": plain[bp][0], "plain_iters": plain[bp][1],
                              "warm_tau": bw, "warm_s": warm[bw][0], "warm_iters": warm[bw][1],
-                             "warm_fallback": warm[bw][3], "speedup": plain[bp][0] / warm[bw][0]}
+                             "warm_fallback": warm[bw][3], "reference_s": warm[bw][4],
+                             "speedup": plain[bp][0] / warm[bw][0],
+                             "speedup_incl_reference": plain[bp][0] / (warm[bw][0] + warm[bw][4])}
+    return out
+
+
+def x1_mixed_precision(wl, fp32_ms, iters=100):
+    """FP16 / BF16 storage of u, ubar, p (FP32 arithmetic, stochastic
+    rounding, FP32 refinement sweep every 50 iterations): time per iteration
+    on the street map with its roofline (28 algorithmic bytes per
+    voxel-iteration; the loop average includes the sweeps), and the error
+    against the FP64 oracle on the small scene after 200 iterations."""
+    import oracle
+    import scenes
+    D = wl.D
+    nvox = wl.big.num_blocks * 512
+    out = {}
+    for name, s in (("f16", D.DN_F16), ("bf16", D.DN_BF16)):
+        prm = D.reg_params(0.5, iters=iters, storage=s, refine_every=50)
+        wl.big.regularize(prm)                    # the tuner's first call
+        st = wl.big.regularize(prm)
+        ms = st.ms_loop / iters
+        ach = ALG_BYTES_PER_VOXEL_ITER_16 * nvox / (ms / 1000.0) / 1e9
+        out[name] = {"ms_per_iter": ms, "speedup_vs_f32": fp32_ms / ms,
+                     "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": ach / HBM_PEAK_GBS,
+                                  "traffic": load_traffic(nvox, "street", name, st.kernel_used),
+                                  "alg_bytes_per_launch": ALG_BYTES_PER_VOXEL_ITER_16 * nvox}}
+    fr = scenes.frames_c1(0)
+    cam = fr.camera
+    K4 = [cam.fx, cam.fy, cam.cx, cam.cy]
+    ov = oracle.OracleVolume(fr.voxel_size, fr.mu, fr.max_depth, 8192, 12, 256)
+    gv = D.Volume(fr.voxel_size, fr.mu, fr.max_depth, 8192, 12, 256, max_points=cam.width * cam.height)
+    for d, T in zip(fr.depths, fr.poses):
+        ov.integrate(d, K4, T)
+        gv.integrate(wl.torch.from_numpy(d).cuda(), D.intrinsics(*K4, cam.width, cam.height), T)
+    u = np.zeros_like(ov.f); ub = np.zeros_like(u); p = np.zeros((3,) + u.shape)
+    oracle.cp(ov.nbr, ov.f, ov.w, u, ub, p, 200, 0.5, 12 ** -0.5, 12 ** -0.5, 1.0)
+    om = ov.w > 0
+    for name, s in (("f32", D.DN_F32), ("f16", D.DN_F16), ("bf16", D.DN_BF16)):
+        gv.regularize(D.reg_params(0.5, iters=200, storage=s, refine_every=50))
+        e = np.abs(gv.extract(D.DN_X_U).cpu().numpy().astype(np.float64) - u)[om]
+        out.setdefault(name, {})["error_vs_oracle"] = {"max": float(e.max()), "median": float(np.median(e)),
+                                                       "scene": "small scene (4 maps 320x96), 200 iterations"}
+    gv.close()
+    return out
+
+
+def batched_run(wl, submaps=64, iters=300, steps=2):
+    """Batched sub-maps in the default run: 64 street segments with block
+    counts log-uniform in [1e3, 5e4], regularised for 300 iterations in one
+    persistent launch (HIP graph, autotuned)."""
+    import types
+    D = wl.D
+    bw = BatchedWorkload(types.SimpleNamespace(submaps=submaps, iters=iters), base=wl)
+    st, _ = bw.step()                                 # tuner + graph capture
+    ms = []
+    for _ in range(steps):
+        st, _ = bw.step()
+        ms.append(st.ms_loop / iters)
+    nvox = bw.voxels()
+    per = float(np.mean(ms))
+    ach = ALG_BYTES_PER_VOXEL_ITER * nvox / (per / 1000.0) / 1e9
+    kid = st.kernel_used // 100
+    out = {"submaps": submaps, "blocks": nvox // 512, "voxels": nvox, "iters": iters,
+           "ms_per_iter": per, "voxel_iters_per_s": nvox / (per / 1000.0),
+           "kernel": {257: "k_cp_persistent_lean", 256: "k_cp_persistent<256>",
+                      512: "k_cp_persistent<512>"}.get(kid, "k_cp_persistent"),
+           "wg_per_cu": st.kernel_used % 100,
+           "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "traffic": load_traffic(nvox, "batched", "f32", kid),
+                        "alg_bytes_per_launch": ALG_BYTES_PER_VOXEL_ITER * nvox}}
+    for v in bw.subs:
+        v.close()
     return out
 
 
@@ -554,6 +667,11 @@ def main():
     if args.workload == "street" and not args.profile:
         log("accuracy against the analytic scene ...")
         line["accuracy"] = accuracy(wl)
+    if args.workload == "street" and not args.profile and args.storage == "f32":
+        log("16-bit storage ...")
+        line["x1"] = x1_mixed_precision(wl, kern_ms)
+        log("batched sub-maps ...")
+        line["batched"] = batched_run(wl)
     if args.workload == "street" and not args.profile:
         log("laser fusion ...")
         line["laser_fusion"] = laser_throughput(wl)

@@ -162,6 +162,7 @@ __device__ __forceinline__ void item_args(const BatchArgs &a, const VolDesc *__r
     A.p_in = uni(d.p[c]); A.p_out = uni(d.p[1 - c]); A.u32 = nullptr; A.ubar32 = nullptr; A.p32 = nullptr;
     A.sigma = sigma; A.tau = tau; A.lambda = a.lambda; A.theta = theta;
     A.l1 = a.l1;
+    A.seed = 0u;
 }
 
 // All iterations of all sub-maps.  Without kPrefetch the workgroups take

@@ -10,14 +10,23 @@ namespace dn {
 
 // ---------------------------------------------------------- storage types
 // State storage: float, IEEE half or bfloat16 (16-bit kept as raw bits).
+// sr(x, r) rounds stochastically with the 16 random bits r: the magnitude
+// goes up one step with probability equal to the fraction of the step it
+// has past the lower neighbour (adding random bits below the kept mantissa,
+// then truncating), so rounding errors have mean zero and increments far
+// below one step still accumulate.  Rounding to nearest (or toward zero)
+// stalls the iteration once its increments drop below half a step.
 struct SF32 {
     using T = float;
+    static constexpr bool kLow = false;
     static __device__ __forceinline__ float ld(float v) { return v; }
     static __device__ __forceinline__ float rn(float x) { return x; }
     static __device__ __forceinline__ float rz(float x) { return x; }
+    static __device__ __forceinline__ float sr(float x, uint32_t) { return x; }
 };
 struct SF16 {
     using T = uint16_t;
+    static constexpr bool kLow = true;
     static __device__ __forceinline__ float ld(uint16_t v) { return float(__builtin_bit_cast(_Float16, v)); }
     static __device__ __forceinline__ uint16_t rn(float x) { return __builtin_bit_cast(uint16_t, _Float16(x)); }
     static __device__ __forceinline__ uint16_t rz(float x)
@@ -25,9 +34,16 @@ struct SF16 {
         auto h2 = __builtin_amdgcn_cvt_pkrtz(x, 0.0f);
         return __builtin_bit_cast(uint16_t, h2[0]);
     }
+    // 13 float mantissa bits fall away for a normal half (exact stochastic
+    // rounding there; below 2^-14 the step is finer than the noise)
+    static __device__ __forceinline__ uint16_t sr(float x, uint32_t r)
+    {
+        return rz(__uint_as_float(__float_as_uint(x) + (r & 0x1FFFu)));
+    }
 };
 struct SBF16 {
     using T = uint16_t;
+    static constexpr bool kLow = true;
     static __device__ __forceinline__ float ld(uint16_t v) { return __uint_as_float(uint32_t(v) << 16); }
     static __device__ __forceinline__ uint16_t rn(float x)
     {
@@ -36,7 +52,29 @@ struct SBF16 {
         return uint16_t(u >> 16);
     }
     static __device__ __forceinline__ uint16_t rz(float x) { return uint16_t(__float_as_uint(x) >> 16); }
+    static __device__ __forceinline__ uint16_t sr(float x, uint32_t r)
+    {
+        return uint16_t((__float_as_uint(x) + (r & 0xFFFFu)) >> 16);
+    }
 };
+
+// Counter-based random bits of one voxel and iteration: an integer hash
+// (xor-shift / multiply rounds) of the global voxel index, a stream number
+// and the iteration seed.  Deterministic, so a run is reproducible and a
+// voxel's stored value does not depend on which workgroup wrote it.
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+__device__ __forceinline__ uint32_t voxel_bits(int64_t gi, uint32_t stream, uint32_t seed)
+{
+    return mix32(uint32_t(gi) * 3u + stream + mix32(seed ^ uint32_t(uint64_t(gi) >> 32)));
+}
 
 template <class S> struct CPArgs {
     int64_t nb;                 // blocks
@@ -54,6 +92,7 @@ template <class S> struct CPArgs {
     float *u32, *ubar32, *p32;  // FP32 copies written by a refinement sweep
     float sigma, tau, lambda, theta;
     int32_t l1;                 // data term lambda w |u - f| (with u in [-1, 1]) instead of (lambda/2) w (u - f)^2
+    uint32_t seed;              // 16-bit storage: this iteration's seed of the stochastic rounding
 };
 
 __device__ __forceinline__ int i10(int x, int y, int z) { return ((z + 1) * 10 + (y + 1)) * 10 + (x + 1); }
@@ -218,7 +257,16 @@ __device__ __forceinline__ void cp_compute(const CPArgs<S> &A, int64_t b, const 
         project(a0, a1, a2);
         const int q = i9(lx, ly, lz);
         sh.p[0][q] = a0; sh.p[1][q] = a1; sh.p[2][q] = a2;
-        A.p_out[gi] = S::rz(a0); A.p_out[gi + ps] = S::rz(a1); A.p_out[gi + 2 * ps] = S::rz(a2);
+        if constexpr (S::kLow) {
+            // stochastic rounding; where it would leave the unit ball, toward zero
+            const uint32_t r0 = voxel_bits(gi, 0, A.seed), r1 = voxel_bits(gi, 1, A.seed);
+            typename S::T s0 = S::sr(a0, r0), s1 = S::sr(a1, r0 >> 16), s2 = S::sr(a2, r1);
+            const float b0 = S::ld(s0), b1 = S::ld(s1), b2 = S::ld(s2);
+            if ((b0 * b0 + b1 * b1) + b2 * b2 > 1.0f) { s0 = S::rz(a0); s1 = S::rz(a1); s2 = S::rz(a2); }
+            A.p_out[gi] = s0; A.p_out[gi + ps] = s1; A.p_out[gi + 2 * ps] = s2;
+        } else {
+            A.p_out[gi] = a0; A.p_out[gi + ps] = a1; A.p_out[gi + 2 * ps] = a2;
+        }
         if (kRefine) { A.p32[gi] = a0; A.p32[gi + ps] = a1; A.p32[gi + 2 * ps] = a2; }
     }
     // ... and on the -1 faces, which the divergence needs
@@ -261,8 +309,14 @@ __device__ __forceinline__ void cp_compute(const CPArgs<S> &A, int64_t b, const 
             }
         }
         float ubn = un + A.theta * (un - R.uo[k]);
-        A.u[gi] = S::rn(un);
-        A.ubar_out[gi] = S::rn(ubn);
+        if constexpr (S::kLow) {
+            const uint32_t r2 = voxel_bits(gi, 2, A.seed);
+            A.u[gi] = S::sr(un, r2);
+            A.ubar_out[gi] = S::sr(ubn, r2 >> 16);
+        } else {
+            A.u[gi] = un;
+            A.ubar_out[gi] = ubn;
+        }
         if (kRefine) { A.u32[gi] = un; A.ubar32[gi] = ubn; }
     }
 }

@@ -112,6 +112,7 @@ struct dn_volume {
     void *ubar16[2] = {nullptr, nullptr};
     void *p16[2] = {nullptr, nullptr};
     int state_storage = DN_F32;         // where the current state lives
+    uint64_t lowp_iter = 0;             // 16-bit iterations run (seeds the stochastic rounding)
     double acc_tau = 0, acc_sigma = 0;  // accelerated schedule (tau_n, sigma_n)
     int64_t nb_state = 0;               // blocks whose solver state a regularize call set
 

@@ -423,6 +423,7 @@ static CPArgs<S> make_args(dn_volume *v, const dn_reg_params *prm, typename S::T
     A.sigma = float(prm->sigma); A.tau = float(prm->tau); A.lambda = float(prm->lambda);
     A.theta = float(prm->theta);
     A.l1 = prm->data_term == DN_DATA_L1;
+    A.seed = 0u;
     return A;
 }
 
@@ -461,6 +462,7 @@ static int step_lowp(dn_volume *v, const dn_reg_params *prm, bool refine, int ke
     using T = typename S::T;
     auto A = make_args<S>(v, prm, (T *)v->u16, (T *)v->ubar16[c], (T *)v->ubar16[n], (T *)v->p16[c],
                           (T *)v->p16[n]);
+    A.seed = uint32_t(v->lowp_iter++);
     const dim3 grid(fused_grid(v->nb));
     if (refine) {
         A.u32 = v->u; A.ubar32 = v->ubar[n]; A.p32 = v->p[n];
@@ -638,6 +640,7 @@ template <class S> static int autotune_lowp(dn_volume *v, const dn_reg_params *p
     DN_HIP(hipEventCreate(&e0));
     DN_HIP(hipEventCreate(&e1));
     const int cur = v->cur;
+    const uint64_t seed_iter = v->lowp_iter;   // the trials are discarded, so are their seeds
     float best_ms = 1e30f;
     AutoChoice best{DN_K_FUSED, 0};
     const int trial = 6;
@@ -657,6 +660,7 @@ template <class S> static int autotune_lowp(dn_volume *v, const dn_reg_params *p
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     v->cur = cur;
+    v->lowp_iter = seed_iter;
     if (rc) return rc;
     store_choice(g_auto_lowp, key, best);
     *choice = best.kernel;
@@ -724,6 +728,9 @@ int dn_regularize(dn_volume *v, const dn_reg_params *prm, const float *u0, const
         v->acc_tau = prm->tau;
         v->acc_sigma = prm->sigma;
     }
+    // the stochastic rounding restarts its seeds with the solve (a call that
+    // keeps the state continues them), so equal calls give equal results
+    if (prm->init != DN_INIT_KEEP) v->lowp_iter = 0;
     int kernel = prm->kernel;
     bool fresh16 = false;     // the 16-bit state was just demoted from FP32
     if (storage != DN_F32) {

@@ -10,8 +10,9 @@ library consume exactly the arrays produced here.
 from .synth import (Camera, Frames, render_depth, scene_c1, scene_street,
                     frames_c1, frames_c2, frames_street, pose_translation,
                     pose_yaw, random_block_field, c4_block_counts, distance_to_scene,
-                    scene_street, laser_scan)
+                    inside_scene, scene_street, laser_scan)
 
 __all__ = ["Camera", "Frames", "render_depth", "scene_c1", "scene_street",
            "frames_c1", "frames_c2", "frames_street", "pose_translation",
-           "pose_yaw", "random_block_field", "c4_block_counts", "distance_to_scene", "laser_scan"]
+           "pose_yaw", "random_block_field", "c4_block_counts", "distance_to_scene", "inside_scene",
+           "laser_scan"]

@@ -278,6 +278,19 @@ def c4_block_counts(n: int = 64, seed: int = 0, lo: float = 1e3, hi: float = 5e4
     return np.round(np.exp(rng.uniform(np.log(lo), np.log(hi), size=n))).astype(np.int64)
 
 
+def inside_scene(points: np.ndarray, boxes: np.ndarray, chunk: int = 65536) -> np.ndarray:
+    """True for each point (float [n][3], metres) strictly inside one of the
+    scene's solid boxes."""
+    out = np.zeros(len(points), bool)
+    for s0 in range(0, len(points), chunk):
+        P = np.asarray(points[s0:s0 + chunk], np.float64)
+        hit = np.zeros(len(P), bool)
+        for lo, hi in boxes:
+            hit |= np.all((P > lo) & (P < hi), axis=1)
+        out[s0:s0 + chunk] = hit
+    return out
+
+
 def distance_to_scene(points: np.ndarray, boxes: np.ndarray, chunk: int = 65536) -> np.ndarray:
     """Unsigned distance of each point (float [n][3], metres) to the nearest
     box surface of the scene (ground truth for accuracy statistics)."""

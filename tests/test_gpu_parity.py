@@ -252,11 +252,16 @@ def test_mixed_precision_error_is_reported_and_bounded(c1, storage):
     om = ov.w > 0
     err = np.abs(gu - u)[om]
     print(f"{storage}: max {err.max():.3e} median {np.median(err):.3e} rel_gap {st.rel_gap:.3e}")
-    bound = 2e-2 if storage == "f16" else 1.5e-1
-    assert err.max() <= bound
+    # stochastic rounding of the stored state: no stagnation, errors near
+    # the rounding noise (FP16 step 2^-11 at |u| ~ 0.5, BF16 2^-8)
+    bound, med = (5e-3, 4e-4) if storage == "f16" else (3e-2, 3e-3)
+    assert err.max() <= bound and np.median(err) <= med
     assert st.gap >= 0
     gp = host(gv.extract(D.DN_X_P))
     assert np.sqrt((gp.astype(np.float64) ** 2).sum(0)).max() <= 1.0 + 1e-6
+    # the rounding bits are a function of (voxel, iteration): equal calls agree
+    gv.regularize(D.reg_params(LAM, iters=200, storage=s, refine_every=50))
+    np.testing.assert_array_equal(host(gv.extract(D.DN_X_U)).astype(np.float64), gu)
 
 
 def test_accelerated_variant_parity_and_resume(c1):
