@@ -356,6 +356,18 @@ size_t dn_net_bytes(int64_t n_tiles, int32_t training);
 int dn_net_forward(const float *tiles_dev, int64_t n, const float *params_dev, float *out_dev,
                    void *workspace_dev, size_t workspace_bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * forward pass of dn_net_forward with no workspace argument.  Its scratch
+ * is a static device array inside the library (one per GPU, about 3.4 MB,
+ * held until the process ends), so it takes at most DN_NET_STATIC_TILES
+ * tiles per call (else DN_E_CAPACITY) and calls that overlap on one GPU
+ * race (they share that array).  Same arguments and result as
+ * dn_net_forward; enqueue only. */
+#define DN_NET_STATIC_TILES 32
+int dn_net_forward_static(const float *tiles_dev, int64_t n, const float *params_dev, float *out_dev,
+                          void *hip_stream);
+
 /* Masked mean-squared loss on the centre 8^3 and its gradient: the
  * prediction is f + r (kind 0, a primal residual) or r (kind 1, a dual
  * component); targets_dev, mask_dev float [n][512] in the tile's centre

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "dn_internal.h"
@@ -831,6 +832,49 @@ static int forward_tiles(hipStream_t st, const float *params, int64_t n, const N
     return DN_OK;
 }
 
+// One forward pass of n tiles in the given workspace (sized by the caller).
+static int forward_into(const float *tiles, int64_t n, const float *params, float *out, void *workspace,
+                        size_t workspace_bytes, hipStream_t st)
+{
+    Bump bump(workspace, workspace_bytes);
+    const NetWS ws = carve_net(bump, n, false);
+    if (!bump.fits()) { set_error("network workspace too small"); return DN_E_CAPACITY; }
+    int rc;
+    if ((rc = pack_all(st, params, false, ws.wpack))) return rc;
+    hipLaunchKernelGGL(k_tiles_to_bf16, dim3(grid1(n * kT)), dim3(256), 0, st, tiles, n, ws.x0);
+    DN_HIP(hipGetLastError());
+    if ((rc = forward_tiles(st, params, n, ws))) return rc;
+    DN_HIP(hipMemcpyAsync(out, ws.r, size_t(n) * kT * 4, hipMemcpyDeviceToDevice, st));
+    return DN_OK;
+}
+
+// Scratch of dn_net_forward_static: a file-scope device array, one copy per
+// GPU, held until the process ends.  In host code its name is only a
+// stand-in; the address each device's copy has is looked up once per device
+// (with that device current) and kept.
+constexpr size_t kNetStaticBytes = size_t(DN_NET_STATIC_TILES) * (size_t(kT) * kC * 2 * 3 + size_t(kT) * 4 + 1024) +
+                                   size_t(6) * kWPack * 2 + 4096;
+static __device__ __align__(256) unsigned char scratch[kNetStaticBytes];
+constexpr int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mutex;
+
+static int static_scratch(void **out)
+{
+    int dev = 0;
+    DN_HIP(hipGetDevice(&dev));
+    DN_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        DN_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        DN_REQUIRE(p && (reinterpret_cast<uintptr_t>(p) & 255) == 0, "static scratch misaligned");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DN_OK;
+}
+
 }  // namespace dn
 
 using namespace dn;
@@ -859,22 +903,28 @@ int dn_net_forward(const float *tiles, int64_t n, const float *params, float *ou
                    size_t workspace_bytes, void *stream)
 {
     DN_REQUIRE(tiles && params && out && n >= 0, "bad argument");
-    hipStream_t st = static_cast<hipStream_t>(stream);
     if (n == 0) return DN_OK;
     DN_REQUIRE(ws_ok(workspace), "the workspace must be non-null and 256-byte aligned");
     if (workspace_bytes < dn_net_bytes(n, 0)) {
         set_error("workspace of %zu bytes is short: %zu needed (dn_net_bytes)", workspace_bytes, dn_net_bytes(n, 0));
         return DN_E_CAPACITY;
     }
-    Bump bump(workspace, workspace_bytes);
-    const NetWS ws = carve_net(bump, n, false);
-    int rc;
-    if ((rc = pack_all(st, params, false, ws.wpack))) return rc;
-    hipLaunchKernelGGL(k_tiles_to_bf16, dim3(grid1(n * kT)), dim3(256), 0, st, tiles, n, ws.x0);
-    DN_HIP(hipGetLastError());
-    if ((rc = forward_tiles(st, params, n, ws))) return rc;
-    DN_HIP(hipMemcpyAsync(out, ws.r, size_t(n) * kT * 4, hipMemcpyDeviceToDevice, st));
-    return DN_OK;
+    return forward_into(tiles, n, params, out, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+int dn_net_forward_static(const float *tiles, int64_t n, const float *params, float *out, void *stream)
+{
+    DN_REQUIRE(tiles && params && out && n >= 0, "bad argument");
+    if (n > DN_NET_STATIC_TILES) {
+        set_error("dn_net_forward_static takes at most %d tiles per call (%lld given)", DN_NET_STATIC_TILES,
+                  (long long)n);
+        return DN_E_CAPACITY;
+    }
+    if (n == 0) return DN_OK;
+    void *ws = nullptr;
+    int rc = static_scratch(&ws);
+    if (rc) return rc;
+    return forward_into(tiles, n, params, out, ws, kNetStaticBytes, static_cast<hipStream_t>(stream));
 }
 
 int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const float *targets, const float *mask,

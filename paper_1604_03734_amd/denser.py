@@ -110,6 +110,7 @@ def lib():
         "dn_extract": (i32, [P, i32, P, ctypes.c_size_t, P]),
         "dn_net_gather": (i32, [P, P, i64, i32, P]),
         "dn_net_forward": (i32, [P, i64, P, P, P, sz, P]),
+        "dn_net_forward_static": (i32, [P, i64, P, P, P]),
         "dn_net_loss_grad": (i32, [P, i64, P, P, P, i32, P, P, sz, P, P]),
         "dn_net_adam": (i32, [P, P, P, P, i64, f32, f32, f32, f32, i32, P]),
         "dn_net_warm_start": (i32, [P, P, i32, f64, P, P, P, sz]),
@@ -352,6 +353,16 @@ def net_forward(tiles, params, out, stream=None):
     ws, nbytes = workspace("net", lib().dn_net_bytes(tiles.shape[0], 0))
     check(lib().dn_net_forward(_ptr(tiles), tiles.shape[0], _ptr(params), _ptr(out), ws, nbytes,
                                _stream_handle(stream)))
+
+
+NET_STATIC_TILES = 32
+
+
+def net_forward_static(tiles, params, out, stream=None):
+    """dn_net_forward_static: the forward pass with the library's static
+    scratch (no workspace; at most NET_STATIC_TILES tiles per call)."""
+    check(lib().dn_net_forward_static(_ptr(tiles), tiles.shape[0], _ptr(params), _ptr(out),
+                                      _stream_handle(stream)))
 
 
 def net_loss_grad(tiles, params, targets, mask, grad, kind=0, stream=None, sync=True):
