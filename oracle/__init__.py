@@ -21,7 +21,12 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "denser_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# DN_ORACLE_SANITIZE=1: an AddressSanitizer + UndefinedBehaviorSanitizer
+# build of the same source (the process must preload libasan; see
+# tests/test_oracle_sanitized.py)
+_SANITIZE = os.environ.get("DN_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
 
 OK = 0
 E_CAPACITY = -2
@@ -32,7 +37,8 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-                               "-fPIC", "-shared", "-std=c11", _SRC, "-o", tmp, "-lm"])
+                               "-fPIC", "-shared", "-std=c11"] + (SAN_FLAGS if _SANITIZE else []) +
+                              [_SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

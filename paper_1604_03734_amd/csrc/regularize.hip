@@ -16,6 +16,7 @@
 #include <rocprim/rocprim.hpp>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -612,6 +613,8 @@ static int autotune_single(dn_volume *v, const dn_reg_params *prm, int *choice)
             DN_HIP(hipEventSynchronize(e1));
             float ms = 0;
             DN_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (getenv("DN_VERBOSE"))
+                fprintf(stderr, "[denser] tune: kernel %d layout %d: %.4f ms per iteration\n", k, layout, ms / trial);
             if (ms < best_ms) { best_ms = ms; best = AutoChoice{k, layout}; }
         }
     (void)hipEventDestroy(e0);
@@ -655,6 +658,8 @@ template <class S> static int autotune_lowp(dn_volume *v, const dn_reg_params *p
             DN_HIP(hipEventSynchronize(e1));
             float ms = 0;
             DN_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (getenv("DN_VERBOSE"))
+                fprintf(stderr, "[denser] tune16: kernel %d layout %d: %.4f ms per iteration\n", k, layout, ms / trial);
             if (ms < best_ms) { best_ms = ms; best = AutoChoice{k, layout}; }
         }
     (void)hipEventDestroy(e0);

@@ -87,8 +87,57 @@ __device__ inline bool depth_ok(float d, double maxd)
     return isfinite(d) && d > 0.0f && double(d) <= maxd;
 }
 
-// Grid traversal of one pixel's band over the block grid.  Emits the
-// visited block keys through `emit` and returns how many were visited.
+// Amanatides-Woo traversal of a -> b on the unit grid (ties x before y
+// before z, only axes with steps left towards the end cell); nothing is
+// visited if an end point lies beyond `limit` cells.  Shared by the depth
+// band, the laser band and the laser fusion walks.
+template <class Emit>
+__device__ int64_t walk_segment(const double a[3], const double b[3], double limit, Emit emit)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (!(fabs(a[i]) < limit && fabs(b[i]) < limit)) return 0;
+    int64_t k[3], left[3];
+    int step[3];
+    double tmax[3], tdel[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        k[i] = int64_t(floor(a[i]));
+        const int64_t e = int64_t(floor(b[i]));
+        const double dir = b[i] - a[i];
+        if (e > k[i]) {
+            step[i] = 1; left[i] = e - k[i];
+            tmax[i] = (double(k[i] + 1) - a[i]) / dir;
+            tdel[i] = 1.0 / dir;
+        } else if (e < k[i]) {
+            step[i] = -1; left[i] = k[i] - e;
+            tmax[i] = (double(k[i]) - a[i]) / dir;
+            tdel[i] = -1.0 / dir;
+        } else {
+            step[i] = 0; left[i] = 0; tmax[i] = 0.0; tdel[i] = 0.0;
+        }
+    }
+    int64_t n = 0;
+    for (;;) {
+        emit(n, k[0], k[1], k[2]);
+        ++n;
+        int c = -1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (left[i] == 0) continue;
+            if (c < 0 || tmax[i] < tmax[c]) c = i;
+        }
+        if (c < 0) break;
+        k[c] += step[c];
+        tmax[c] += tdel[c];
+        left[c] -= 1;
+    }
+    return n;
+}
+
+// Grid traversal of one pixel's band [max(d - mu, 1e-3), d + mu] over the
+// block grid (edge 8 s).  Emits the visited block keys through `emit` and
+// returns how many were visited.
 template <class Emit>
 __device__ int dda_pixel(const Geo &g, int px, int py, float d, Emit emit)
 {
@@ -106,45 +155,9 @@ __device__ int dda_pixel(const Geo &g, int px, int py, float d, Emit emit)
         a[i] = pa / bs;
         b[i] = pb / bs;
     }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        if (!(fabs(a[i]) < 1e6 && fabs(b[i]) < 1e6)) return 0;
-    int64_t k[3], left[3];
-    int step[3];
-    double tmax[3], tdel[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        k[i] = int64_t(floor(a[i]));
-        int64_t e = int64_t(floor(b[i]));
-        double dir = b[i] - a[i];
-        if (e > k[i]) {
-            step[i] = 1; left[i] = e - k[i];
-            tmax[i] = (double(k[i] + 1) - a[i]) / dir;
-            tdel[i] = 1.0 / dir;
-        } else if (e < k[i]) {
-            step[i] = -1; left[i] = k[i] - e;
-            tmax[i] = (double(k[i]) - a[i]) / dir;
-            tdel[i] = -1.0 / dir;
-        } else {
-            step[i] = 0; left[i] = 0; tmax[i] = 0.0; tdel[i] = 0.0;
-        }
-    }
-    int n = 0;
-    for (;;) {
-        emit(n, int32_t(k[0]), int32_t(k[1]), int32_t(k[2]));
-        ++n;
-        int c = -1;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            if (left[i] == 0) continue;
-            if (c < 0 || tmax[i] < tmax[c]) c = i;
-        }
-        if (c < 0) break;
-        k[c] += step[c];
-        tmax[c] += tdel[c];
-        left[c] -= 1;
-    }
-    return n;
+    return int(walk_segment(a, b, 1e6, [&](int64_t j, int64_t x, int64_t y, int64_t z) {
+        emit(int(j), int32_t(x), int32_t(y), int32_t(z));
+    }));
 }
 
 __global__ void k_dda_count(Geo g, const float *__restrict__ depth, int32_t *__restrict__ counts)
@@ -487,52 +500,6 @@ __device__ inline void ray_point(const double *T, const double d[3], double rho,
                  T[4 * i + 3];
 }
 
-// Amanatides-Woo traversal of a -> b on the unit grid (the allocation
-// traversal: ties x before y before z, only axes with steps left).
-template <class Emit>
-__device__ int64_t walk_segment(const double a[3], const double b[3], Emit emit)
-{
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        if (!(fabs(a[i]) < 1e9 && fabs(b[i]) < 1e9)) return 0;
-    int64_t k[3], left[3];
-    int step[3];
-    double tmax[3], tdel[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        k[i] = int64_t(floor(a[i]));
-        const int64_t e = int64_t(floor(b[i]));
-        const double dir = b[i] - a[i];
-        if (e > k[i]) {
-            step[i] = 1; left[i] = e - k[i];
-            tmax[i] = (double(k[i] + 1) - a[i]) / dir;
-            tdel[i] = 1.0 / dir;
-        } else if (e < k[i]) {
-            step[i] = -1; left[i] = k[i] - e;
-            tmax[i] = (double(k[i]) - a[i]) / dir;
-            tdel[i] = -1.0 / dir;
-        } else {
-            step[i] = 0; left[i] = 0; tmax[i] = 0.0; tdel[i] = 0.0;
-        }
-    }
-    int64_t n = 0;
-    for (;;) {
-        emit(n, k[0], k[1], k[2]);
-        ++n;
-        int c = -1;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            if (left[i] == 0) continue;
-            if (c < 0 || tmax[i] < tmax[c]) c = i;
-        }
-        if (c < 0) break;
-        k[c] += step[c];
-        tmax[c] += tdel[c];
-        left[c] -= 1;
-    }
-    return n;
-}
-
 template <class Emit>
 __device__ int64_t laser_band(const LGeo &g, const float *p, Emit emit)
 {
@@ -545,7 +512,7 @@ __device__ int64_t laser_band(const LGeo &g, const float *p, Emit emit)
     const double bs = 8.0 * g.s;
 #pragma unroll
     for (int i = 0; i < 3; ++i) { a[i] = pa[i] / bs; b[i] = pb[i] / bs; }
-    return walk_segment(a, b, emit);
+    return walk_segment(a, b, 1e9, emit);
 }
 
 __global__ void k_laser_cand_count(LGeo g, const float *__restrict__ pts, int64_t n, int32_t *__restrict__ counts)
@@ -583,7 +550,7 @@ __device__ int64_t laser_obs(const LGeo &g, const float *p, const int4 *slots, i
     int64_t m = 0;
     int64_t kb[3] = {INT64_MIN, 0, 0};
     int32_t id = -1;
-    walk_segment(a, b, [&](int64_t, int64_t x, int64_t y, int64_t z) {
+    walk_segment(a, b, 1e9, [&](int64_t, int64_t x, int64_t y, int64_t z) {
         const int64_t bx = x >> 3, by = y >> 3, bz = z >> 3;   // floor division
         if (bx != kb[0] || by != kb[1] || bz != kb[2]) {
             kb[0] = bx; kb[1] = by; kb[2] = bz;
