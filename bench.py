@@ -493,7 +493,7 @@ NET_FWD_FLOP_PER_TILE = 2.0 * (1000 * 16 * 54 + 1000 * 16 * 432 + 1000 * 432)
 NET_TRAIN_FLOP_PER_TILE = 2 * NET_FWD_FLOP_PER_TILE + 2.0 * (1000 * 16 * 432 + 1000 * 432)
 
 
-def net_rooflines(wl, reps=3, batch=256, train_steps=20):
+def net_rooflines(wl, reps=3, batch=1024, train_steps=20):
     """Matrix-core throughput of the network, timed with HIP events on the
     stream the library launches on: the dual warm start of the street map
     (gather pre-pass, one fused inference launch per axis, projection) and

@@ -8,7 +8,7 @@
 // channels of one tap), activations stored channel-last in bfloat16,
 // [tile][1000][16], unused channels zero.
 //
-// Inference path (warm start): one fused launch per axis, k_net_infer, on
+// Inference path (warm start): one fused launch per axis, k_net_fwd, on
 // v_mfma_f32_16x16x32_bf16 with all activations in LDS and the weights in
 // registers.  Its layer loops read one 1 KiB activation operand from LDS per
 // MFMA; at the measured ~140 B/clk of 16-byte LDS reads per CU that bounds
@@ -32,6 +32,17 @@ constexpr int kC = 16;        // channels of a stored activation
 constexpr int kTaps = 27;
 constexpr int kWPack = kTaps * kC * kC;   // one packed layer: [tap][co][ci]
 constexpr int kMT = 63;       // 16-voxel row tiles covering 1000 voxels
+// Training layouts: an activation channel-first on the tile's 10^3 grid
+// padded by one zero voxel on every side (12^3 = 1728 entries per channel,
+// index (x+1) + 12 (y+1) + 144 (z+1)); a gradient channel-first on the
+// compact rows of that grid (the 100 rows (y, z) of 12 entries, padding
+// entries x = -1 and x = 10 zero, index (x+1) + 12 (10 z + y), 1216 entries
+// with the tail zero).
+constexpr int kPadVox = 1728;
+// offsets of the layers in the canonical 8241-float parameter vector
+constexpr int kW1 = 0, kB1 = 16 * 2 * 27, kW2 = kB1 + 16, kB2 = kW2 + 16 * 16 * 27, kW3 = kB2 + 16,
+              kB3 = kW3 + 16 * 27;
+constexpr int kRowVox = 1216;
 
 __device__ __forceinline__ uint16_t f2bf(float x)
 {
@@ -121,60 +132,6 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, in
     }
 }
 
-// Weight and bias gradient of one layer: dW[t][co][ci] = sum over tiles and
-// voxels of X[v + off(t)][ci] dY[v][co]; db[co] = sum dY[v][co].  Each
-// workgroup accumulates its tiles and writes one partial
-// [27*256 + 16] floats; k_grad_reduce sums the partials in a fixed order.
-__global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, const uint16_t *__restrict__ dY,
-                                               int64_t n, float *__restrict__ partials)
-{
-    __shared__ __align__(16) uint16_t sx[kT * kC];
-    __shared__ __align__(16) uint16_t sd[kT * kC];
-    __shared__ float sb[256];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = lane & 15, kg = lane >> 4;
-    v4f acc[7];
-    for (int j = 0; j < 7; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f;
-    for (int64_t tile = blockIdx.x; tile < n; tile += gridDim.x) {
-        load_tile(sx, X + tile * kT * kC);
-        load_tile(sd, dY + tile * kT * kC);
-        __syncthreads();
-        for (int ks = 0; ks < kMT; ++ks) {
-            const int v0 = ks * 16 + 4 * kg;
-            v4s b;
-            for (int q = 0; q < 4; ++q) b[q] = (v0 + q < kT) ? short(sd[(v0 + q) * kC + i]) : short(0);
-            for (int j = 0; j < 7; ++j) {
-                const int t = wave + 4 * j;
-                if (t >= kTaps) break;
-                v4s a;
-                for (int q = 0; q < 4; ++q) {
-                    int nv = (v0 + q < kT) ? tap_neighbour(v0 + q, t) : -1;
-                    a[q] = nv >= 0 ? short(sx[nv * kC + i]) : short(0);
-                }
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
-            }
-        }
-        // bias: channel c = tid % 16 summed over voxels tid/16, +16, ...
-        for (int v = threadIdx.x >> 4; v < kT; v += 16) bsum += bf2f(sd[v * kC + (threadIdx.x & 15)]);
-        __syncthreads();
-    }
-    float *out = partials + int64_t(blockIdx.x) * (kWPack + kC);
-    // D layout: lane holds rows (ci) 4*kg + r, column (co) i
-    for (int j = 0; j < 7; ++j) {
-        const int t = wave + 4 * j;
-        if (t >= kTaps) break;
-        for (int r = 0; r < 4; ++r) out[(t * kC + i) * kC + 4 * kg + r] = acc[j][r];
-    }
-    sb[threadIdx.x] = bsum;
-    __syncthreads();
-    if (threadIdx.x < kC) {
-        float s = 0.f;
-        for (int k = 0; k < 16; ++k) s += sb[k * 16 + threadIdx.x];
-        out[kWPack + threadIdx.x] = s;
-    }
-}
-
 // First level of the partial reduction: chunk c of the partials (parts
 // [c*per, (c+1)*per)) summed in order, per entry, into out[c][...].
 __global__ void k_sum_parts(const float *__restrict__ partials, int nparts, int per, float *__restrict__ out)
@@ -209,22 +166,16 @@ __global__ void k_grad_reduce(const float *__restrict__ partials, int nparts, in
 }
 
 // Pack the float parameters into bfloat16 [tap][co][ci] layers, zero padded
-// to 16x16; flipped = 1 gives the input-gradient weights
-// W'[t][a][b] = W[26 - t][b][a]; flipped = 2 gives the unflipped low part
-// bfloat16(W - bfloat16(W)) (layer 1 runs on the pair hi + lo).
-__global__ void k_pack(const float *__restrict__ W, int cout, int cin, int flipped, uint16_t *__restrict__ out)
+// to 16x16; lo = 1 gives the low part bfloat16(W - bfloat16(W)) (layer 1
+// runs on the pair hi + lo).
+__global__ void k_pack(const float *__restrict__ W, int cout, int cin, int lo, uint16_t *__restrict__ out)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= kWPack) return;
     int t = k / (kC * kC), a = (k / kC) % kC, b = k % kC;
     float val = 0.f;
-    if (flipped != 1) {
-        if (a < cout && b < cin) val = W[(a * cin + b) * kTaps + t];
-        if (flipped == 2) val -= bf2f(f2bf(val));
-    } else {
-        // a indexes the forward input channel, b the forward output channel
-        if (b < cout && a < cin) val = W[(b * cin + a) * kTaps + (kTaps - 1 - t)];
-    }
+    if (a < cout && b < cin) val = W[(a * cin + b) * kTaps + t];
+    if (lo) val -= bf2f(f2bf(val));
     out[k] = f2bf(val);
 }
 
@@ -292,7 +243,6 @@ __global__ void k_gather(const int32_t *__restrict__ nbr, const float *__restric
     }
 }
 
-__device__ __forceinline__ int centre_of(int v) { return ((v / 64 + 1) * 10 + ((v / 8) % 8 + 1)) * 10 + (v % 8 + 1); }
 
 // Number of mask entries set: workgroup g sums its 4096-entry chunk in a
 // fixed order (thread-strided, then a tree) into part[g]; then one
@@ -327,36 +277,40 @@ __global__ void k_mask_count(const double *__restrict__ part, int64_t nparts, do
     if (threadIdx.x == 0) out[0] = s[0];
 }
 
-// Loss of one tile per workgroup (512 threads, one per centre voxel) and the
-// output gradient dY3 (bfloat16, channel 0 only).
-__global__ __launch_bounds__(512) void k_loss(const float *__restrict__ tiles, const float *__restrict__ R,
-                                              const float *__restrict__ targets, const float *__restrict__ mask,
-                                              const double *__restrict__ count, int64_t n, int kind,
-                                              uint16_t *__restrict__ dY, double *__restrict__ tile_loss)
+// The gradient of all 8241 parameters from the per-workgroup partials of
+// the three layers (parts[layer][p][27 * 256 + 16], summed over p in order):
+// one thread per partial entry, so the reads are contiguous across threads,
+// written to the canonical parameter layout.
+__global__ void k_grad_final(const float *__restrict__ parts, int nparts, float *__restrict__ grad)
 {
-    __shared__ double sl[8];
-    const int64_t tile = blockIdx.x;
-    const int v = threadIdx.x;
-    const double N = count[0] > 1.0 ? count[0] : 1.0;
-    const int c = centre_of(v);
-    const double m = mask[tile * 512 + v];
-    double e = (kind == 0 ? double(tiles[tile * 2 * kT + c]) : 0.0) + double(R[tile * kT + c]) -
-               double(targets[tile * 512 + v]);
-    double l = m != 0.0 ? e * e / N : 0.0;
-    // clear the tile's gradient, then write the centre voxels
-    uint4 z = make_uint4(0, 0, 0, 0);
-    uint4 *d = reinterpret_cast<uint4 *>(dY + tile * kT * kC);
-    for (int k = threadIdx.x; k < kT * kC / 8; k += 512) d[k] = z;
-    __syncthreads();
-    if (m != 0.0) dY[(tile * kT + c) * kC] = f2bf(float(2.0 * e / N));
-    for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
-    if ((v & 63) == 0) sl[v >> 6] = l;
-    __syncthreads();
-    if (v == 0) {
-        double s = 0.0;
-        for (int k = 0; k < 8; ++k) s += sl[k];
-        tile_loss[tile] = s;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 3 * (kWPack + kC)) return;
+    const int layer = k / (kWPack + kC), idx = k - layer * (kWPack + kC);
+    const int cout = layer == 2 ? 1 : 16, cin = layer == 0 ? 2 : 16;
+    const int wbase = layer == 0 ? kW1 : (layer == 1 ? kW2 : kW3);
+    const int bbase = layer == 0 ? kB1 : (layer == 1 ? kB2 : kB3);
+    int dst;
+    if (idx < kWPack) {
+        const int t = idx / (kC * kC), co = (idx / kC) % kC, ci = idx % kC;
+        if (co >= cout || ci >= cin) return;
+        dst = wbase + (co * cin + ci) * kTaps + t;
+    } else {
+        const int co = idx - kWPack;
+        if (co >= cout) return;
+        dst = bbase + co;
     }
+    const float *src = parts + int64_t(layer) * nparts * (kWPack + kC) + idx;
+    float a = 0.f;
+    int p = 0;
+    for (; p + 8 <= nparts; p += 8) {          // eight loads in flight, added in order
+        float q[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) q[e] = src[int64_t(p + e) * (kWPack + kC)];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a += q[e];
+    }
+    for (; p < nparts; ++p) a += src[int64_t(p) * (kWPack + kC)];
+    grad[dst] = a;
 }
 
 __global__ void k_sum_loss(const double *__restrict__ tl, int64_t n, double *__restrict__ out)
@@ -419,49 +373,9 @@ __global__ void k_warm_finish(int64_t n, int64_t ps, const uint8_t *__restrict__
     u0[g] = (emask[g] & 1) ? f[g] : 0.f;
 }
 
-// The workspace of one network call (caller device memory): packed
-// weights, activations of n tiles and, for training, their gradients and
-// the weight-gradient partial sums.
-struct NetWS {
-    uint16_t *wpack, *x0, *h1, *h2, *d3, *d2, *d1;
-    float *r, *parts, *chunks;
-    double *misc, *tl, *mparts;
-    int nparts, nchunks;
-    int64_t nmask;
-};
-constexpr int kPartsPer = 16;   // partials summed per chunk
-static NetWS carve_net(Bump &b, int64_t n, bool training)
-{
-    NetWS x{};
-    const size_t act = size_t(n) * kT * kC;
-    x.wpack = b.take<uint16_t>(size_t(6) * kWPack);
-    x.x0 = b.take<uint16_t>(act);
-    x.h1 = b.take<uint16_t>(act);
-    x.h2 = b.take<uint16_t>(act);
-    x.r = b.take<float>(size_t(n) * kT);
-    if (training) {
-        x.d3 = b.take<uint16_t>(act);
-        x.d2 = b.take<uint16_t>(act);
-        x.d1 = b.take<uint16_t>(act);
-        x.nparts = int(n < 512 ? n : 512);
-        x.nchunks = (x.nparts + kPartsPer - 1) / kPartsPer;
-        x.parts = b.take<float>(size_t(x.nparts) * (kWPack + kC));
-        x.chunks = b.take<float>(size_t(x.nchunks) * (kWPack + kC));
-        x.misc = b.take<double>(8);
-        x.tl = b.take<double>(size_t(n));
-        x.nmask = (n * 512 + 4095) / 4096;
-        x.mparts = b.take<double>(size_t(x.nmask));
-    }
-    return x;
-}
-
-static bool ws_ok(const void *ws) { return ws && (reinterpret_cast<uintptr_t>(ws) & 255) == 0; }
 
 static inline unsigned grid1(int64_t n, int bs = 256) { return unsigned((n + bs - 1) / bs); }
 
-// offsets of the layers in the canonical 8241-float parameter vector
-constexpr int kW1 = 0, kB1 = 16 * 2 * 27, kW2 = kB1 + 16, kB2 = kW2 + 16 * 16 * 27, kW3 = kB2 + 16,
-              kB3 = kW3 + 16 * 27;
 
 // ---------------------------------------------------------------------------
 // Fused inference: gather, three layers and the warm-start epilogue of one
@@ -481,6 +395,55 @@ constexpr int kL3M = 2;       // layer 3: rows = the 9 (y, z) tap pairs, K = 3 x
 // the rounding of W1, and the second MFMA per K step costs little
 constexpr int kLaneW = (2 * kL1M + kL2M + kL3M) * 64 * 8;
 
+// The workspace of one network call (caller device memory): packed
+// weights, activations of n tiles and, for training, their gradients and
+// the weight-gradient partial sums.
+struct NetWS {
+    // forward (dn_net_forward)
+    uint16_t *wpack, *x0, *h1, *h2;
+    float *r;
+    // training step (dn_net_loss_grad)
+    uint16_t *lanew, *lanef, *gates, *x1cf, *h1cf, *h2cf, *d3cf, *d2cf, *d1cf;
+    float *rc, *d3, *parts;
+    double *misc, *tl, *mparts;
+    int64_t nmask;
+    int nparts;
+};
+constexpr int kMaxWgradGroups = 256;
+static NetWS carve_net(Bump &b, int64_t n, bool training)
+{
+    NetWS x{};
+    if (!training) {
+        const size_t act = size_t(n) * kT * kC;
+        x.wpack = b.take<uint16_t>(size_t(4) * kWPack);
+        x.x0 = b.take<uint16_t>(act);
+        x.h1 = b.take<uint16_t>(act);
+        x.h2 = b.take<uint16_t>(act);
+        x.r = b.take<float>(size_t(n) * kT);
+        return x;
+    }
+    x.lanew = b.take<uint16_t>(size_t(kLaneW));
+    x.lanef = b.take<uint16_t>(size_t(kL2M) * 64 * 8);
+    x.gates = b.take<uint16_t>(size_t(n) * 2 * kT);
+    x.x1cf = b.take<uint16_t>(size_t(n) * 2 * kPadVox);
+    x.h1cf = b.take<uint16_t>(size_t(n) * 16 * kPadVox);
+    x.h2cf = b.take<uint16_t>(size_t(n) * 16 * kPadVox);
+    x.rc = b.take<float>(size_t(n) * kBlockVox);
+    x.d3 = b.take<float>(size_t(n) * kBlockVox);
+    x.d3cf = b.take<uint16_t>(size_t(n) * kRowVox);
+    x.d2cf = b.take<uint16_t>(size_t(n) * 16 * kRowVox);
+    x.d1cf = b.take<uint16_t>(size_t(n) * 16 * kRowVox);
+    x.nparts = int(n < kMaxWgradGroups ? n : kMaxWgradGroups);
+    x.parts = b.take<float>(size_t(3) * x.nparts * (kWPack + kC));
+    x.misc = b.take<double>(8);
+    x.tl = b.take<double>(size_t(n));
+    x.nmask = (n * 512 + 4095) / 4096;
+    x.mparts = b.take<double>(size_t(x.nmask));
+    return x;
+}
+
+static bool ws_ok(const void *ws) { return ws && (reinterpret_cast<uintptr_t>(ws) & 255) == 0; }
+
 // Lane-ready weights [mfma][lane][8] (bfloat16).  The K slots of lane
 // group g = lane / 16, entry j, of MFMA m: layer 1 -> tap 16m + 4g + j/2,
 // channel j%2; layer 2 -> tap 2m + g/2, channel 8(g%2) + j; the output
@@ -489,10 +452,8 @@ constexpr int kLaneW = (2 * kL1M + kL2M + kL3M) * 64 * 8;
 // pair, and the K slots of MFMA m, group g are x tap kx = 2m + g/2 (kx < 3),
 // channel 8(g%2) + j.  The activation operand uses the same map, so the
 // products pair up whatever order the hardware sums them in.
-__global__ void k_pack_lanes(const float *__restrict__ params, uint16_t *__restrict__ out)
+__device__ void pack_lane(const float *__restrict__ params, int k, uint16_t *__restrict__ out)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= kLaneW) return;
     const int j = k & 7, lane = (k >> 3) & 63, m = k >> 9;
     const int g = lane >> 4, n = lane & 15;
     float val = 0.f;
@@ -509,6 +470,12 @@ __global__ void k_pack_lanes(const float *__restrict__ params, uint16_t *__restr
         if (kx < 3 && n < 9) val = params[kW3 + ci * kTaps + 3 * n + kx];
     }
     out[k] = f2bf(val);
+}
+
+__global__ void k_pack_lanes(const float *__restrict__ params, uint16_t *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < kLaneW) pack_lane(params, k, out);
 }
 
 // LDS activation: two planes of 8 channels, [2][1001][8] bfloat16 (row
@@ -626,10 +593,56 @@ __global__ void k_voxel_pairs(const float *__restrict__ f, const float *__restri
 // clamp(f + r, -1, 1) on Omega, 0 elsewhere.  Workgroups loop over tiles;
 // the layer-1 input of the next tile is loaded while the current one is
 // computed.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_net_infer(
+//
+// kTrain: the forward pass of a training step on n given tiles (f holds the
+// float tiles [n][2][1000]); the layer inputs are also written to global
+// memory on the zero-padded 12^3 grid for the backward pass (x1cf: the two
+// input channels channel-first, [n][2][1728]; h1cf, h2cf channel-last,
+// [n][1728][16]), and out receives the residual r on the centre, [n][512]
+// (voxel x + 8y + 64z).
+__device__ __forceinline__ int pad_index(int x, int y, int z) { return (x + 1) + 12 * (y + 1) + 144 * (z + 1); }
+
+// Channel-last copy of an LDS activation (two planes of 8 channels) onto the
+// padded grid: dst[1728][16], 32 bytes per padded voxel, zero on the padding.
+__device__ __forceinline__ void copy_act_cl(const uint16_t *h, uint16_t *__restrict__ dst, int tid)
+{
+    for (int p = tid; p < kPadVox; p += 256) {
+        const int x = p % 12 - 1, y = (p / 12) % 12 - 1, z = p / 144 - 1;
+        uint4 lo = make_uint4(0, 0, 0, 0), hi = lo;
+        if (x >= 0 && x < 10 && y >= 0 && y < 10 && z >= 0 && z < 10) {
+            const int v = x + 10 * y + 100 * z;
+            lo = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(h) + act_byte(v, 0));
+            hi = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(h) + act_byte(v, 1));
+        }
+        reinterpret_cast<uint4 *>(dst)[2 * p] = lo;
+        reinterpret_cast<uint4 *>(dst)[2 * p + 1] = hi;
+    }
+}
+
+// Bit ch of dst[v] set when channel ch of the LDS activation is positive at
+// tile voxel v (the open ReLUs the backward pass gates with).
+__device__ __forceinline__ void gate_bits(const uint16_t *h, uint16_t *__restrict__ dst, int tid)
+{
+    for (int v = tid; v < kT; v += 256) {
+        const uint4 lo = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(h) + act_byte(v, 0));
+        const uint4 hi = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(h) + act_byte(v, 1));
+        const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+        uint32_t m = 0;
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t a = w[k] & 0xFFFFu, c = w[k] >> 16;
+            if (!(a & 0x8000u) && (a & 0x7FFFu)) m |= 1u << (2 * k);
+            if (!(c & 0x8000u) && (c & 0x7FFFu)) m |= 1u << (2 * k + 1);
+        }
+        dst[v] = uint16_t(m);
+    }
+}
+
+template <bool kTrain>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_net_fwd(
     const int32_t *__restrict__ nbr, const uint32_t *__restrict__ pair, const float *__restrict__ f,
     const uint8_t *__restrict__ emask, int64_t nb, int perm, int mode, const uint16_t *__restrict__ lw,
-    const float *__restrict__ params, int64_t ps, float *__restrict__ out)
+    const float *__restrict__ params, int64_t ps, float *__restrict__ out, uint16_t *__restrict__ x1cf,
+    uint16_t *__restrict__ h1cf, uint16_t *__restrict__ h2cf, uint16_t *__restrict__ gates)
 {
     __shared__ __align__(16) uint16_t h1[2 * kPlane / 2];
     __shared__ __align__(16) uint16_t h2[2 * kPlane / 2];
@@ -680,6 +693,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     constexpr int kGet = (kT + 255) / 256;
     uint32_t nxt[kGet];
     auto fetch = [&](int64_t bb) {
+        if constexpr (kTrain) {
+            // the tiles are float [n][2][1000] (f, then the weight channel)
+            for (int e = 0; e < kGet; ++e) {
+                const int k = tid + 256 * e;
+                nxt[e] = k < kT ? (uint32_t(f2bf(f[bb * 2 * kT + k])) | (uint32_t(f2bf(f[bb * 2 * kT + kT + k])) << 16))
+                                : 0u;
+            }
+            return;
+        }
         const int32_t *nb27 = nbr + bb * kNbr;
         for (int e = 0; e < kGet; ++e) {
             const int k = tid + 256 * e;
@@ -721,6 +743,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             store_act(h1, v, g, acc, bias1);
         }
         __syncthreads();
+        if constexpr (kTrain) {
+            // layer inputs for the backward pass (read-only use of h1 and x0
+            // until the barrier after layer 2), and which ReLUs are open
+            copy_act_cl(h1, h1cf + b * (16 * kPadVox), tid);
+            gate_bits(h1, gates + b * (2 * kT), tid);
+            for (int e = tid; e < 2 * kPadVox; e += 256) {
+                const int ch = e / kPadVox, p = e - ch * kPadVox;
+                const int x = p % 12 - 1, y = (p / 12) % 12 - 1, z = p / 144 - 1;
+                uint16_t val = 0;
+                if (x >= 0 && x < 10 && y >= 0 && y < 10 && z >= 0 && z < 10)
+                    val = uint16_t(x0[x + 10 * y + 100 * z] >> (16 * ch));
+                x1cf[b * (2 * kPadVox) + e] = val;
+            }
+        }
 
         // layer 2: 16 -> 16, ReLU; interior tiles read every tap at a fixed
         // offset from the voxel (the past-the-end tap 27 reads the zero row)
@@ -749,6 +785,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             store_act(h2, v, g, acc, bias2);
         }
         __syncthreads();
+        if constexpr (kTrain) {
+            copy_act_cl(h2, h2cf + b * (16 * kPadVox), tid);
+            gate_bits(h2, gates + b * (2 * kT) + kT, tid);
+        }
 
         // layer 3: 16 -> 1 on the centre 8^3, as partial sums over the x taps.
         // P[n][u] = sum over kx, ci of W3[ci][3n + kx] h2[u + kx - 1][ci] for
@@ -778,11 +818,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 const int row = (cz + n / 3) * 10 + (cy + n % 3);   // (z + kz - 1 + 1, y + ky - 1 + 1)
                 acc += P[n * 800 + 8 * row + cx];
             }
+            const float rv = acc + bias3;
+            if constexpr (kTrain) {
+                out[b * kBlockVox + c] = rv;
+                continue;
+            }
             int x = cx, y = cy, z = cz;
             if (perm == 1) { const int sw = x; x = y; y = sw; }
             if (perm == 2) { const int sw = x; x = z; z = sw; }
             const int64_t gi = b * kBlockVox + x + 8 * y + 64 * z;
-            const float rv = acc + bias3;
             const uint8_t em = emask[gi];
             if (mode == DN_WARM_DUAL) {
                 out[perm * ps + gi] = ((em >> (perm + 1)) & 1) ? rv : 0.f;
@@ -801,16 +845,519 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 }
 
-static int pack_all(hipStream_t st, const float *params, bool with_flipped, uint16_t *wp)
+// ---------------------------------------------------------------------------
+// Training step kernels (after k_net_fwd<true>).
+
+// Lane-ready weights of a training step: the forward's (as k_pack_lanes)
+// and those of the input gradient of layer 2, d1 = conv(d2, W') with
+// W'[ci][co][t] = W2[co][ci][26 - t] (the layer-2 map of k_pack_lanes).
+__device__ void pack_lane(const float *__restrict__ params, int k, uint16_t *__restrict__ out);
+__global__ void k_pack_train(const float *__restrict__ params, uint16_t *__restrict__ lw, uint16_t *__restrict__ out)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < kLaneW) {
+        pack_lane(params, k, lw);
+        return;
+    }
+    k -= kLaneW;
+    if (k >= kL2M * 64 * 8) return;
+    const int j = k & 7, lane = (k >> 3) & 63, m = k >> 9;
+    const int g = lane >> 4, n = lane & 15;
+    const int t = 2 * m + (g >> 1), c = 8 * (g & 1) + j;
+    float val = 0.f;
+    if (t < kTaps) val = params[kW2 + (c * 16 + n) * kTaps + (kTaps - 1 - t)];
+    out[k] = f2bf(val);
+}
+
+__device__ __forceinline__ bool bf_pos(uint16_t h) { return !(h & 0x8000u) && (h & 0x7FFFu) != 0; }
+
+// Compact-row index of tile voxel (x, y, z), and its decoding (false for
+// padding entries).
+__device__ __forceinline__ int row_index(int x, int y, int z) { return (x + 1) + 12 * (10 * z + y); }
+__device__ __forceinline__ bool row_voxel(int c, int &x, int &y, int &z)
+{
+    if (c >= 1200) return false;
+    const int xr = c % 12, r = c / 12;
+    x = xr - 1; y = r % 10; z = r / 10;
+    return xr >= 1 && xr <= 10;
+}
+
+// Masked squared loss of one tile per workgroup (512 threads, one per
+// centre voxel): d3 = dL/dr on the centre (float [n][512]) and the same in
+// the compact-row layout for the weight gradient of layer 3 (d3cf [n][1216],
+// bfloat16, zero off the centre).
+__global__ __launch_bounds__(512) void k_loss_train(const float *__restrict__ tiles, const float *__restrict__ R,
+                                                    const float *__restrict__ targets, const float *__restrict__ mask,
+                                                    const double *__restrict__ count, int64_t n, int kind,
+                                                    float *__restrict__ d3, uint16_t *__restrict__ d3cf,
+                                                    double *__restrict__ tile_loss)
+{
+    __shared__ double sl[8];
+    __shared__ uint16_t sg[kT];
+    const int64_t tile = blockIdx.x;
+    const int v = threadIdx.x;
+    const double N = count[0] > 1.0 ? count[0] : 1.0;
+    const int cx = v & 7, cy = (v >> 3) & 7, cz = v >> 6;
+    const int tv = (cx + 1) + 10 * (cy + 1) + 100 * (cz + 1);
+    const double m = mask[tile * 512 + v];
+    const double e = (kind == 0 ? double(tiles[tile * 2 * kT + tv]) : 0.0) + double(R[tile * 512 + v]) -
+                     double(targets[tile * 512 + v]);
+    double l = m != 0.0 ? e * e / N : 0.0;
+    const float gv = m != 0.0 ? float(2.0 * e / N) : 0.f;
+    d3[tile * 512 + v] = gv;
+    for (int k = v; k < kT; k += 512) sg[k] = 0;
+    __syncthreads();
+    sg[tv] = f2bf(gv);
+    for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
+    if ((v & 63) == 0) sl[v >> 6] = l;
+    __syncthreads();
+    uint16_t *dst = d3cf + tile * kRowVox;
+    for (int k = v; k < kRowVox; k += 512) {
+        uint16_t val = 0;
+        int x, y, z;
+        if (row_voxel(k, x, y, z)) val = sg[x + 10 * y + 100 * z];
+        dst[k] = val;
+    }
+    if (v == 0) {
+        double s = 0.0;
+        for (int k = 0; k < 8; ++k) s += sl[k];
+        tile_loss[tile] = s;
+    }
+}
+
+// Backward through layers 3 and 2 of one tile per iteration of a
+// workgroup, on MFMA: d2 = (W3 applied backwards to d3) gated by [h2 > 0],
+// as one 16 (channels) x 16 (voxels) x 32 (taps) product per row tile (the
+// lane's 8 taps read d3 shifted back by the tap), then d1 = conv(d2, W')
+// gated by [h1 > 0] as layer 2 of k_net_fwd (flipped weights W' in
+// registers, d2 in LDS).  d2 and d1 go to global memory on the compact
+// rows, channel-last ([n][1216][16] bfloat16, 32 bytes per entry).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_net_bwd(
+    const float *__restrict__ d3, const uint16_t *__restrict__ gates, int64_t n, const uint16_t *__restrict__ lwf,
+    const float *__restrict__ params, uint16_t *__restrict__ d2cf, uint16_t *__restrict__ d1cf)
+{
+    __shared__ __align__(16) uint16_t dd[2 * kPlane / 2];
+    __shared__ uint16_t s3[kT + 8];          // d3 on the tile (bfloat16; entry kT stays zero)
+    __shared__ __align__(16) uint16_t sg[2 * kT];    // open ReLUs of layers 1 and 2 (bit = channel)
+    __shared__ uint32_t okt[kMT * 16];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int v = tid; v < kMT * 16; v += 256) okt[v] = v < kT ? tap_mask(v % 10, (v / 10) % 10, v / 100) : 0u;
+    for (int v = tid; v < kT + 8; v += 256) s3[v] = 0;
+    const int i = lane & 15, g = lane >> 4;
+    const int half = g & 1, par = g >> 1;
+    const v4u *lw4 = reinterpret_cast<const v4u *>(lwf);
+    v8bf W2[kL2M];
+    for (int m = 0; m < kL2M; ++m) W2[m] = as_v8bf(lw4[m * 64 + lane]);
+    // W3 as the first operand: row ci = i, K slots = taps 8g .. 8g + 7
+    v8bf W3r;
+    {
+        uint16_t w[8];
+        for (int j = 0; j < 8; ++j) {
+            const int t = 8 * g + j;
+            w[j] = t < kTaps ? f2bf(params[kW3 + i * kTaps + t]) : uint16_t(0);
+        }
+        W3r = as_v8bf(*reinterpret_cast<const v4u *>(&w[0]));
+    }
+    int toff[8];
+    for (int j = 0; j < 8; ++j) {
+        const int t = 8 * g + j;
+        toff[j] = t < kTaps ? tap_off(t) : 0;
+    }
+    if (tid < 8) reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(dd) + (tid >> 2) * kPlane + kT * 16)[tid & 3] = 0u;
+    // the next tile's d3 (2 centre values per thread) and gate words (one
+    // 16-byte chunk per thread) are loaded while the current one is computed
+    float2 nd3 = make_float2(0.f, 0.f);
+    uint4 ngt = make_uint4(0, 0, 0, 0);
+    auto fetch = [&](int64_t bb) {
+        nd3 = reinterpret_cast<const float2 *>(d3 + bb * 512)[tid];
+        if (tid < 2 * kT / 8) ngt = reinterpret_cast<const uint4 *>(gates + bb * (2 * kT))[tid];
+    };
+    if (blockIdx.x < n) fetch(blockIdx.x);
+    __syncthreads();
+    for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
+        {
+            const int c0 = 2 * tid;       // centre voxels c0, c0 + 1 (same x row)
+            const int cx = c0 & 7, cy = (c0 >> 3) & 7, cz = c0 >> 6;
+            const int v = (cx + 1) + 10 * (cy + 1) + 100 * (cz + 1);
+            s3[v] = f2bf(nd3.x);
+            s3[v + 1] = f2bf(nd3.y);
+            if (tid < 2 * kT / 8) reinterpret_cast<uint4 *>(sg)[tid] = ngt;
+        }
+        const int64_t bn = b + gridDim.x;
+        if (bn < n) fetch(bn);
+        __syncthreads();
+        uint16_t *o2 = d2cf + b * (16 * kRowVox);
+        uint16_t *o1 = d1cf + b * (16 * kRowVox);
+        // d2 = W3^T d3 (shifted back), gated by [h2 > 0]
+        for (int mt = wave; mt < kMT; mt += 4) {
+            const int v = mt * 16 + i;
+            const uint32_t ok = okt[v < kT ? v : kT];
+            uint16_t q[8];
+            for (int j = 0; j < 8; ++j) {
+                const int t = 8 * g + j;
+                // d3 at v - off(t): inside the tile when tap 26 - t of v is
+                q[j] = s3[(t < kTaps && ((ok >> (kTaps - 1 - t)) & 1u)) ? v - toff[j] : kT];
+            }
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W3r, as_v8bf(*reinterpret_cast<const v4u *>(&q[0])), acc,
+                                                         0, 0, 0);
+            if (v < kT) {
+                // lane: voxel v, channels 4g .. 4g + 3
+                const uint32_t open2 = sg[kT + v];
+                uint16_t r4[4];
+                for (int r = 0; r < 4; ++r) r4[r] = ((open2 >> (4 * g + r)) & 1u) ? f2bf(acc[r]) : uint16_t(0);
+                const uint2 pk = *reinterpret_cast<const uint2 *>(&r4[0]);
+                *reinterpret_cast<uint2 *>(reinterpret_cast<char *>(dd) + act_byte(v, g >> 1) + 8 * (g & 1)) = pk;
+                const int x = v % 10, y = (v / 10) % 10, z = v / 100;
+                reinterpret_cast<uint2 *>(o2 + row_index(x, y, z) * 16)[g] = pk;
+            }
+        }
+        for (int c = tid; c < kRowVox; c += 256) {
+            int x, y, z;
+            if (!row_voxel(c, x, y, z)) {
+                reinterpret_cast<uint4 *>(o2)[2 * c] = make_uint4(0, 0, 0, 0);
+                reinterpret_cast<uint4 *>(o2)[2 * c + 1] = make_uint4(0, 0, 0, 0);
+                reinterpret_cast<uint4 *>(o1)[2 * c] = make_uint4(0, 0, 0, 0);
+                reinterpret_cast<uint4 *>(o1)[2 * c + 1] = make_uint4(0, 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        // d1 = conv(d2, W') gated by [h1 > 0]
+        for (int mt = wave; mt < kMT; mt += 4) {
+            const int v = mt * 16 + i;
+            const uint32_t ok = okt[v < kT ? v : kT];
+            const v4f acc = mfma_chain<kL2M, 5, false>(
+                [&](int m) {
+                    const int o = par ? tap_off(2 * m + 1) : tap_off(2 * m);
+                    const int nv = ((ok >> (2 * m + par)) & 1u) ? v + o : kT;
+                    return as_v8bf(lds_row(dd, act_byte(nv, half)));
+                },
+                [&](int m) { return W2[m]; });
+            if (v < kT) {
+                const int x = v % 10, y = (v / 10) % 10, z = v / 100;
+                const int c = row_index(x, y, z);
+                const uint32_t open1 = sg[v];
+                uint16_t q[4];
+                for (int r = 0; r < 4; ++r) q[r] = ((open1 >> (4 * g + r)) & 1u) ? f2bf(acc[r]) : uint16_t(0);
+                reinterpret_cast<uint2 *>(o1 + c * 16)[g] = *reinterpret_cast<const uint2 *>(&q[0]);
+            }
+        }
+        // d3 entries back to zero for the next tile
+        {
+            const int c0 = 2 * tid;
+            const int cx = c0 & 7, cy = (c0 >> 3) & 7, cz = c0 >> 6;
+            const int v = (cx + 1) + 10 * (cy + 1) + 100 * (cz + 1);
+            s3[v] = 0;
+            s3[v + 1] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// LDS rows: X channel rows of 1928 entries (8 + 1728 + zero margin; 964
+// words, 4 modulo 64 banks, so the 16 lanes of a 16-byte read start on 16
+// distinct groups of 4 banks), dY rows of 1224 entries (612 words, 36 modulo
+// 64, likewise).
+constexpr int kXRow = 1928;
+constexpr int kDRow = 1224;
+
+// Eight channel values (one 16-byte chunk of a channel-last entry) into
+// eight channel rows of an LDS tile: row0[j * stride + pos] = channel j.
+__device__ __forceinline__ void scatter8(uint16_t *row0, int stride, int pos, uint4 v)
+{
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        row0[(2 * j) * stride + pos] = uint16_t(w[j] & 0xFFFFu);
+        row0[(2 * j + 1) * stride + pos] = uint16_t(w[j] >> 16);
+    }
+}
+
+// Weight and bias gradient of layer 3 (one output channel):
+//   dW3[ci][t] = sum over tile voxels v of h2[ci][v] d3[v - off(t)],
+// as (taps, 16 rows) x (input channels, 16 columns) x (32 voxels) MFMAs:
+// the rows read d3, kept on the padded grid, shifted back by their own tap
+// (unaligned 16-byte reads), the columns read h2 unshifted.  Two MFMAs per
+// 32 voxels instead of 27 with one used row.  Partials in the
+// [tap][co][ci] layout (co = 0), bias db3 = sum of d3.
+constexpr int kD3Row = 2080;   // LDS entries of d3: 168 zero margin + 1728 + margin
+__global__ __launch_bounds__(256) void k_wgrad3(const uint16_t *__restrict__ X, const uint16_t *__restrict__ d3cf,
+                                                int64_t n, float *__restrict__ partials)
+{
+    __shared__ __align__(16) uint16_t sx[16 * kXRow];
+    __shared__ __align__(16) uint16_t sd[kD3Row];
+    __shared__ float sb[256];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i = lane & 15, g = lane >> 4;
+    for (int k = tid; k < 16 * kXRow / 8; k += 256) reinterpret_cast<uint4 *>(sx)[k] = make_uint4(0, 0, 0, 0);
+    for (int k = tid; k < kD3Row / 8; k += 256) reinterpret_cast<uint4 *>(sd)[k] = make_uint4(0, 0, 0, 0);
+    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+    float bsum = 0.f;
+    __syncthreads();
+    constexpr int kXc = kPadVox / 8;
+    constexpr int kPer = (16 * kXc + 255) / 256;
+    constexpr int kDPer = (kRowVox + 255) / 256;
+    uint4 nxt[kPer];
+    uint16_t nd[kDPer];
+    auto fetch = [&](int64_t tl) {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int k = tid + 256 * e;
+            if (k < 16 * kXc) nxt[e] = reinterpret_cast<const uint4 *>(X + tl * 16 * kPadVox)[k];
+        }
+#pragma unroll
+        for (int e = 0; e < kDPer; ++e) {
+            const int c = tid + 256 * e;
+            nd[e] = c < kRowVox ? d3cf[tl * kRowVox + c] : uint16_t(0);
+        }
+    };
+    if (blockIdx.x < n) fetch(blockIdx.x);
+    for (int64_t tile = blockIdx.x; tile < n; tile += gridDim.x) {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int k = tid + 256 * e;
+            if (k < 16 * kXc) scatter8(sx + (k & 1) * 8 * kXRow + 8, kXRow, k >> 1, nxt[e]);
+        }
+        // d3 from its compact rows onto the padded grid (zero elsewhere)
+#pragma unroll
+        for (int e = 0; e < kDPer; ++e) {
+            const int c = tid + 256 * e;
+            int x, y, z;
+            if (c < kRowVox && row_voxel(c, x, y, z)) {
+                sd[168 + pad_index(x, y, z)] = nd[e];
+                bsum += bf2f(nd[e]);
+            }
+        }
+        __syncthreads();
+        if (tile + gridDim.x < n) fetch(tile + gridDim.x);
+        // wave w takes the 32-voxel chunks w, w + 4, ...
+        for (int c0 = 32 * wave; c0 < kRowVox; c0 += 128) {
+            const int c = c0 + 8 * g;
+            const int plane = c / 120, within = c - 120 * plane;
+            const int pc = within + 12 + 144 * (plane + 1);          // padded index of entry c
+            const v8bf b = as_v8bf(*reinterpret_cast<const v4u *>(sx + i * kXRow + 8 + pc));
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t = 16 * h + i;
+                v4u q = {0u, 0u, 0u, 0u};
+                if (t < kTaps) {
+                    const int off = (t % 3 - 1) + 12 * ((t / 3) % 3 - 1) + 144 * (t / 9 - 1);
+                    q = *reinterpret_cast<const v4u *>(sd + 168 + pc - off);
+                }
+                acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_v8bf(q), b, acc[h], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        for (int c = tid; c < kRowVox; c += 256) {      // clear d3's entries for the next tile
+            int x, y, z;
+            if (row_voxel(c, x, y, z)) sd[168 + pad_index(x, y, z)] = 0;
+        }
+    }
+    // the four waves' sums of each (tap, ci), then one partial per workgroup
+    __shared__ float red[4][32][16];
+    for (int h = 0; h < 2; ++h)
+        for (int r = 0; r < 4; ++r) red[wave][16 * h + 4 * g + r][i] = acc[h][r];
+    sb[tid] = bsum;
+    __syncthreads();
+    float *out = partials + int64_t(blockIdx.x) * (kWPack + kC);
+    for (int e = tid; e < kWPack + kC; e += 256) {
+        float v = 0.f;
+        if (e < kWPack) {
+            const int t = e / (kC * kC), co = (e / kC) % kC, ci = e % kC;
+            if (co == 0) v = ((red[0][t][ci] + red[1][t][ci]) + red[2][t][ci]) + red[3][t][ci];
+        } else if (e == kWPack) {
+            for (int k = 0; k < 256; ++k) v += sb[k];
+        }
+        out[e] = v;
+    }
+}
+
+// Weight and bias gradient of layer 1 (two input channels):
+//   dW1[co][ci][t] = sum over v of d1[co][v] x[ci][v + off(t)],
+// as (output channels) x (54 (ci, t) columns in four MFMAs) x (32 voxels):
+// each column reads the input channel shifted by its own tap.
+__global__ __launch_bounds__(256) void k_wgrad1(const uint16_t *__restrict__ X, const uint16_t *__restrict__ dY,
+                                                int64_t n, float *__restrict__ partials)
+{
+    __shared__ __align__(16) uint16_t sx[2 * kXRow];
+    __shared__ __align__(16) uint16_t sd[16 * kDRow];
+    __shared__ float sb[256];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i = lane & 15, g = lane >> 4;
+    for (int k = tid; k < 2 * kXRow / 8; k += 256) reinterpret_cast<uint4 *>(sx)[k] = make_uint4(0, 0, 0, 0);
+    for (int k = tid; k < 16 * kDRow / 8; k += 256) reinterpret_cast<uint4 *>(sd)[k] = make_uint4(0, 0, 0, 0);
+    v4f acc[4];
+    for (int q = 0; q < 4; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    int coff[4];                     // LDS offset of column 16 q + i: channel row + tap shift
+    bool cuse[4];
+    for (int q = 0; q < 4; ++q) {
+        const int col = 16 * q + i, ci = col / kTaps, t = col % kTaps;
+        cuse[q] = col < 2 * kTaps;
+        coff[q] = cuse[q] ? ci * kXRow + 8 + (t % 3 - 1) + 12 * ((t / 3) % 3 - 1) + 144 * (t / 9 - 1) : 0;
+    }
+    __syncthreads();
+    constexpr int kXc = kPadVox / 8, kDc = kRowVox / 8;
+    constexpr int kChunks = 2 * kXc + 16 * kDc;
+    constexpr int kPer = (kChunks + 255) / 256;
+    uint4 nxt[kPer];
+    auto fetch = [&](int64_t tl) {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int k = tid + 256 * e;
+            if (k < 2 * kXc) nxt[e] = reinterpret_cast<const uint4 *>(X + tl * 2 * kPadVox)[k];
+            else if (k < kChunks) nxt[e] = reinterpret_cast<const uint4 *>(dY + tl * 16 * kRowVox)[k - 2 * kXc];
+        }
+    };
+    if (blockIdx.x < n) fetch(blockIdx.x);
+    for (int64_t tile = blockIdx.x; tile < n; tile += gridDim.x) {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int k = tid + 256 * e;
+            if (k < 2 * kXc) {
+                const int ch = k / kXc, r = k - ch * kXc;
+                reinterpret_cast<uint4 *>(sx + ch * kXRow + 8)[r] = nxt[e];
+            } else if (k < kChunks) {
+                const int kk = k - 2 * kXc;
+                scatter8(sd + (kk & 1) * 8 * kDRow, kDRow, kk >> 1, nxt[e]);
+            }
+        }
+        __syncthreads();
+        if (tile + gridDim.x < n) fetch(tile + gridDim.x);
+        for (int c = tid >> 4; c < kRowVox; c += 16) bsum += bf2f(sd[(tid & 15) * kDRow + c]);
+        for (int c0 = 32 * wave; c0 < kRowVox; c0 += 128) {
+            const int c = c0 + 8 * g;
+            const v8bf a = as_v8bf(*reinterpret_cast<const v4u *>(sd + i * kDRow + c));
+            const int plane = c / 120, within = c - 120 * plane;
+            const int pc = within + 12 + 144 * (plane + 1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v4u bq = {0u, 0u, 0u, 0u};
+                if (cuse[q]) bq = *reinterpret_cast<const v4u *>(sx + coff[q] + pc);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_v8bf(bq), acc[q], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // D[co][col]: lane holds column 16 q + i, rows co = 4g .. 4g + 3; the
+    // four waves' sums, then one partial per workgroup in [tap][co][ci]
+    __shared__ float red[4][16][64];
+    for (int q = 0; q < 4; ++q)
+        for (int r = 0; r < 4; ++r) red[wave][4 * g + r][16 * q + i] = acc[q][r];
+    sb[tid] = bsum;
+    __syncthreads();
+    float *out = partials + int64_t(blockIdx.x) * (kWPack + kC);
+    for (int e = tid; e < kWPack + kC; e += 256) {
+        float v = 0.f;
+        if (e < kWPack) {
+            const int t = e / (kC * kC), co = (e / kC) % kC, ci = e % kC;
+            if (ci < 2) {
+                const int col = ci * kTaps + t;
+                v = ((red[0][co][col] + red[1][co][col]) + red[2][co][col]) + red[3][co][col];
+            }
+        } else {
+            const int co = e - kWPack;
+            for (int k = 0; k < 16; ++k) v += sb[k * 16 + co];
+        }
+        out[e] = v;
+    }
+}
+
+// Weight and bias gradient of layer 2 on MFMA (X = h1 channel-last on the
+// padded grid, dY = d2 channel-last on the compact rows, both turned
+// channel-first as they enter LDS):
+//   dW[co][ci][t] = sum over tile voxels v of dY[co][v] X[ci][v + off(t)],
+//   db[co] = sum over v of dY[co][v],
+// the products as 16 (co) x 16 (ci) x 32 (voxels) MFMAs: 32 consecutive
+// compact-row entries of dY (aligned 16-byte reads) against the same
+// entries of the padded X shifted by the tap (unaligned 16-byte reads; a
+// run of 8 entries never leaves its z plane, where the two layouts are
+// contiguous alike).  One workgroup per compute unit loops over tiles and
+// keeps every tap's 16 x 16 block in registers (wave w: taps w, w + 8, ...);
+// one partial [27][16][16] + [16] per workgroup.
+template <int CI, int CO>
+__global__ __launch_bounds__(512) void k_wgrad_mfma(const uint16_t *__restrict__ X, const uint16_t *__restrict__ dY,
+                                                    int64_t n, float *__restrict__ partials)
+{
+    __shared__ __align__(16) uint16_t sx[16 * kXRow];
+    __shared__ __align__(16) uint16_t sd[16 * kDRow];
+    __shared__ float sb[512];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int i = lane & 15, g = lane >> 4;
+    for (int k = tid; k < 16 * kXRow / 8; k += 512) reinterpret_cast<uint4 *>(sx)[k] = make_uint4(0, 0, 0, 0);
+    for (int k = tid; k < 16 * kDRow / 8; k += 512) reinterpret_cast<uint4 *>(sd)[k] = make_uint4(0, 0, 0, 0);
+    v4f acc[4];
+    for (int j = 0; j < 4; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    __syncthreads();
+    // 16-byte chunks of a tile: X (CI channels) then dY (CO channels), the
+    // next tile's held in registers while the current one is computed
+    constexpr int kXc = kPadVox / 8, kDc = kRowVox / 8;
+    constexpr int kChunks = CI * kXc + CO * kDc;
+    constexpr int kPer = (kChunks + 511) / 512;
+    uint4 nxt[kPer];
+    auto fetch = [&](int64_t tl) {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int k = tid + 512 * e;
+            if (k < CI * kXc) nxt[e] = reinterpret_cast<const uint4 *>(X + tl * CI * kPadVox)[k];
+            else if (k < kChunks) nxt[e] = reinterpret_cast<const uint4 *>(dY + tl * CO * kRowVox)[k - CI * kXc];
+        }
+    };
+    if (blockIdx.x < n) fetch(blockIdx.x);
+    for (int64_t tile = blockIdx.x; tile < n; tile += gridDim.x) {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int k = tid + 512 * e;
+            if (k < CI * kXc) {
+                scatter8(sx + (k & 1) * 8 * kXRow + 8, kXRow, k >> 1, nxt[e]);
+            } else if (k < kChunks) {
+                const int kk = k - CI * kXc;
+                scatter8(sd + (kk & 1) * 8 * kDRow, kDRow, kk >> 1, nxt[e]);
+            }
+        }
+        __syncthreads();
+        if (tile + gridDim.x < n) fetch(tile + gridDim.x);
+        for (int c = tid >> 4; c < kRowVox; c += 32) bsum += bf2f(sd[(tid & 15) * kDRow + c]);
+        for (int c0 = 0; c0 < kRowVox; c0 += 32) {
+            const int c = c0 + 8 * g;
+            const v8bf a = as_v8bf(*reinterpret_cast<const v4u *>(sd + i * kDRow + c));
+            const int plane = c / 120, within = c - 120 * plane;
+            const int pc = 8 + within + 12 + 144 * (plane + 1);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int t = wave + 8 * j;
+                if (t < kTaps) {
+                    const int off = (t % 3 - 1) + 12 * ((t / 3) % 3 - 1) + 144 * (t / 9 - 1);
+                    const v8bf bq = as_v8bf(*reinterpret_cast<const v4u *>(sx + i * kXRow + pc + off));
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq, acc[j], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float *out = partials + int64_t(blockIdx.x) * (kWPack + kC);
+    // lane: column ci = i, rows co = 4g .. 4g + 3
+    for (int j = 0; j < 4; ++j) {
+        const int t = wave + 8 * j;
+        if (t < kTaps)
+            for (int r = 0; r < 4; ++r) out[(t * kC + 4 * g + r) * kC + i] = acc[j][r];
+    }
+    sb[tid] = bsum;
+    __syncthreads();
+    if (tid < kC) {
+        float sum = 0.f;
+        for (int k = 0; k < 32; ++k) sum += sb[k * 16 + tid];
+        out[kWPack + tid] = sum;
+    }
+}
+
+static int pack_all(hipStream_t st, const float *params, uint16_t *wp)
 {
     hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW1, 16, 2, 0, wp);
     hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW2, 16, 16, 0, wp + kWPack);
     hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW3, 1, 16, 0, wp + 2 * kWPack);
-    hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW1, 16, 2, 2, wp + 5 * kWPack);
-    if (with_flipped) {
-        hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW2, 16, 16, 1, wp + 3 * kWPack);
-        hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW3, 1, 16, 1, wp + 4 * kWPack);
-    }
+    hipLaunchKernelGGL(k_pack, dim3(grid1(kWPack)), dim3(256), 0, st, params + kW1, 16, 2, 1, wp + 3 * kWPack);
     DN_HIP(hipGetLastError());
     return DN_OK;
 }
@@ -822,7 +1369,7 @@ static int forward_tiles(hipStream_t st, const float *params, int64_t n, const N
     if (n <= 0) return DN_OK;
     const uint16_t *wp = ws.wpack;
     uint16_t *x0 = ws.x0, *h1 = ws.h1, *h2 = ws.h2;
-    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, x0, n, wp, wp + 5 * kWPack, params + kB1, 1,
+    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, x0, n, wp, wp + 3 * kWPack, params + kB1, 1,
                        (const uint16_t *)nullptr, h1, (float *)nullptr);
     hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, h1, n, wp + kWPack, (const uint16_t *)nullptr,
                        params + kB2, 1, (const uint16_t *)nullptr, h2, (float *)nullptr);
@@ -840,7 +1387,7 @@ static int forward_into(const float *tiles, int64_t n, const float *params, floa
     const NetWS ws = carve_net(bump, n, false);
     if (!bump.fits()) { set_error("network workspace too small"); return DN_E_CAPACITY; }
     int rc;
-    if ((rc = pack_all(st, params, false, ws.wpack))) return rc;
+    if ((rc = pack_all(st, params, ws.wpack))) return rc;
     hipLaunchKernelGGL(k_tiles_to_bf16, dim3(grid1(n * kT)), dim3(256), 0, st, tiles, n, ws.x0);
     DN_HIP(hipGetLastError());
     if ((rc = forward_tiles(st, params, n, ws))) return rc;
@@ -853,7 +1400,7 @@ static int forward_into(const float *tiles, int64_t n, const float *params, floa
 // stand-in; the address each device's copy has is looked up once per device
 // (with that device current) and kept.
 constexpr size_t kNetStaticBytes = size_t(DN_NET_STATIC_TILES) * (size_t(kT) * kC * 2 * 3 + size_t(kT) * 4 + 1024) +
-                                   size_t(6) * kWPack * 2 + 4096;
+                                   size_t(4) * kWPack * 2 + 4096;
 static __device__ __align__(256) unsigned char scratch[kNetStaticBytes];
 constexpr int kMaxDevices = 64;
 static void *g_scratch_ptr[kMaxDevices] = {};
@@ -940,45 +1487,36 @@ int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const f
     hipStream_t st = static_cast<hipStream_t>(stream);
     Bump bump(workspace, workspace_bytes);
     const NetWS ws = carve_net(bump, n, true);
-    int rc;
-    if ((rc = pack_all(st, params, true, ws.wpack))) return rc;
-    const int nparts = ws.nparts, per = kPartsPer, nchunks = ws.nchunks;
-    float *chunks = ws.chunks;
-    const dim3 cgrid(grid1(kWPack + kC), unsigned(nchunks));
-    uint16_t *x0 = ws.x0, *h1 = ws.h1, *h2 = ws.h2;
-    uint16_t *d3 = ws.d3, *d2 = ws.d2, *d1 = ws.d1;
-    const uint16_t *wp = ws.wpack;
-    double *cnt = ws.misc, *lsum = cnt + 1;
-    float *parts = ws.parts;
-    hipLaunchKernelGGL(k_tiles_to_bf16, dim3(grid1(n * kT)), dim3(256), 0, st, tiles, n, x0);
+    int dev = 0, cus = 0;
+    DN_HIP(hipGetDevice(&dev));
+    DN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const unsigned grid2 = unsigned(std::min<int64_t>(n, int64_t(2) * std::max(cus, 1)));
+    // weights, forward with the layer inputs kept
+    hipLaunchKernelGGL(k_pack_train, dim3(grid1(kLaneW + kL2M * 64 * 8)), dim3(256), 0, st, params, ws.lanew,
+                       ws.lanef);
+    hipLaunchKernelGGL(k_net_fwd<true>, dim3(grid2), dim3(256), 0, st, (const int32_t *)nullptr,
+                       (const uint32_t *)nullptr, tiles, (const uint8_t *)nullptr, n, 0, 0, ws.lanew, params,
+                       int64_t(0), ws.rc, ws.x1cf, ws.h1cf, ws.h2cf, ws.gates);
     DN_HIP(hipGetLastError());
-    if ((rc = forward_tiles(st, params, n, ws))) return rc;
-    const int64_t nmask = ws.nmask;
-    hipLaunchKernelGGL(k_mask_part, dim3(unsigned(nmask)), dim3(256), 0, st, mask, n * 512, ws.mparts);
-    hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(256), 0, st, ws.mparts, nmask, cnt);
-    hipLaunchKernelGGL(k_loss, dim3(unsigned(n)), dim3(512), 0, st, tiles, ws.r, targets, mask, cnt, n,
-                       int(kind), d3, ws.tl);
+    // loss and its gradient on the centre
+    double *cnt = ws.misc, *lsum = cnt + 1;
+    hipLaunchKernelGGL(k_mask_part, dim3(unsigned(ws.nmask)), dim3(256), 0, st, mask, n * 512, ws.mparts);
+    hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(256), 0, st, ws.mparts, ws.nmask, cnt);
+    hipLaunchKernelGGL(k_loss_train, dim3(unsigned(n)), dim3(512), 0, st, tiles, ws.rc, targets, mask, cnt, n,
+                       int(kind), ws.d3, ws.d3cf, ws.tl);
     hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, st, ws.tl, n, lsum);
     DN_HIP(hipGetLastError());
-    // layer 3: weights from (h2, d3); input gradient d2 = conv(d3, W3 flipped) * [h2 > 0]
-    hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, st, h2, d3, n, parts);
-    hipLaunchKernelGGL(k_sum_parts, cgrid, dim3(256), 0, st, parts, nparts, per, chunks);
-    hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 27 + 1)), dim3(256), 0, st, chunks, nchunks, 1, 16,
-                       grad + kW3, grad + kB3);
-    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, d3, n, wp + 4 * kWPack, (const uint16_t *)nullptr,
-                       (const float *)nullptr, 0, h2, d2, (float *)nullptr);
-    // layer 2
-    hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, st, h1, d2, n, parts);
-    hipLaunchKernelGGL(k_sum_parts, cgrid, dim3(256), 0, st, parts, nparts, per, chunks);
-    hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 16 * 27 + 16)), dim3(256), 0, st, chunks, nchunks, 16, 16,
-                       grad + kW2, grad + kB2);
-    hipLaunchKernelGGL(k_conv, dim3(unsigned(n)), dim3(256), 0, st, d2, n, wp + 3 * kWPack, (const uint16_t *)nullptr,
-                       (const float *)nullptr, 0, h1, d1, (float *)nullptr);
-    // layer 1
-    hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(256), 0, st, x0, d1, n, parts);
-    hipLaunchKernelGGL(k_sum_parts, cgrid, dim3(256), 0, st, parts, nparts, per, chunks);
-    hipLaunchKernelGGL(k_grad_reduce, dim3(grid1(16 * 2 * 27 + 16)), dim3(256), 0, st, chunks, nchunks, 16, 2,
-                       grad + kW1, grad + kB1);
+    // input gradients of layers 3 and 2
+    hipLaunchKernelGGL(k_net_bwd, dim3(grid2), dim3(256), 0, st, ws.d3, ws.gates, n, ws.lanef, params, ws.d2cf,
+                       ws.d1cf);
+    DN_HIP(hipGetLastError());
+    // weight gradients, one partial per workgroup and layer, summed in a fixed order
+    const unsigned gw = unsigned(ws.nparts);
+    const size_t lp = size_t(ws.nparts) * (kWPack + kC);
+    hipLaunchKernelGGL(k_wgrad1, dim3(gw), dim3(256), 0, st, ws.x1cf, ws.d1cf, n, ws.parts);
+    hipLaunchKernelGGL((k_wgrad_mfma<16, 16>), dim3(gw), dim3(512), 0, st, ws.h1cf, ws.d2cf, n, ws.parts + lp);
+    hipLaunchKernelGGL(k_wgrad3, dim3(gw), dim3(256), 0, st, ws.h2cf, ws.d3cf, n, ws.parts + 2 * lp);
+    hipLaunchKernelGGL(k_grad_final, dim3(grid1(3 * (kWPack + kC))), dim3(256), 0, st, ws.parts, ws.nparts, grad);
     DN_HIP(hipGetLastError());
     if (loss_host) {
         double h = 0.0;
@@ -1037,9 +1575,10 @@ int dn_net_warm_start(dn_volume *v, const float *params, int32_t mode, double de
     const int axes = mode == DN_WARM_DUAL ? 3 : 1;
     hipLaunchKernelGGL(k_voxel_pairs, dim3(grid1(ps)), dim3(256), 0, st, v->f, v->w, ps, vp);
     for (int a = 0; a < axes; ++a) {
-        hipLaunchKernelGGL(k_net_infer, dim3(grid), dim3(256), 0, st, v->nbr, vp, v->f, v->emask, v->nb,
+        hipLaunchKernelGGL(k_net_fwd<false>, dim3(grid), dim3(256), 0, st, v->nbr, vp, v->f, v->emask, v->nb,
                            mode == DN_WARM_DUAL ? a : 0, int(mode), lanew, params, ps,
-                           mode == DN_WARM_DUAL ? p0 : u0);
+                           mode == DN_WARM_DUAL ? p0 : u0, (uint16_t *)nullptr, (uint16_t *)nullptr,
+                           (uint16_t *)nullptr, (uint16_t *)nullptr);
         DN_HIP(hipGetLastError());
     }
     if (mode == DN_WARM_DUAL) {

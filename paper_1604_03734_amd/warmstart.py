@@ -121,7 +121,7 @@ def make_pairs(seeds=(1001, 1002), n_pairs=5000, iters=1000, min_omega=64, lengt
     return torch.cat(tiles_l).contiguous(), torch.cat(tgt_l).contiguous(), torch.cat(msk_l).contiguous()
 
 
-def train(tiles, targets, masks, epochs=30, batch=256, lr=2e-3, seed=0, params=None, log=None, kind=1):
+def train(tiles, targets, masks, epochs=60, batch=1024, lr=4e-3, seed=0, params=None, log=None, kind=1):
     """Adam on the masked squared error (of r for kind 1, of f + r for
     kind 0), all on the GPU with the library's kernels."""
     import torch
@@ -202,9 +202,9 @@ def main():
     ap = argparse.ArgumentParser(description="train the warm-start network on the GPU")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--pairs", type=int, default=5000)
-    ap.add_argument("--epochs", type=int, default=30)
-    ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--lr", type=float, default=4e-3)
+    ap.add_argument("--batch", type=int, default=1024)
     args = ap.parse_args()
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
     t0 = time.time()

@@ -200,3 +200,27 @@ def test_dual_warm_start_matches_oracle():
         print(f"dual warm start axis {a}: rel-L2 {rel:.3e} max-abs {np.abs(gp[a] - ref[a]).max():.3e}")
         assert rel <= BAR, a
     assert np.array_equal(host(u0), np.where(ov.w > 0, f, 0.0).astype(np.float32))
+
+
+def test_loss_gradient_over_more_tiles_than_workgroups():
+    """The weight-gradient kernel keeps one partial per workgroup and loops
+    over tiles: 260 tiles (more than its 256 workgroups) against the oracle."""
+    D = dn()
+    import torch
+    rng = np.random.default_rng(13)
+    B = 260
+    tiles = rng.normal(0, 0.5, (B, 2, 10, 10, 10))
+    targets = rng.normal(0, 0.5, (B, 512))
+    mask = (rng.random((B, 512)) < 0.5).astype(np.float64)
+    prm = _params(14, 0.12)
+    grad = torch.empty(oracle.NET_PARAMS, device="cuda")
+    loss = D.net_loss_grad(to_dev(tiles, torch.float32), to_dev(prm, torch.float32),
+                           to_dev(targets, torch.float32), to_dev(mask, torch.float32), grad, kind=1)
+    L, g_ref = oracle.net_loss_grad(tiles, prm, targets, mask, kind=1, gate=1)
+    g = host(grad).astype(np.float64)
+    print(f"260 tiles: loss {loss:.6e} oracle {L:.6e}")
+    assert abs(loss - L) <= BAR * abs(L)
+    for lo, hi, name in [(0, 880, "layer1"), (880, 7808, "layer2"), (7808, 8241, "layer3")]:
+        rel = _rel_l2(g[lo:hi], g_ref[lo:hi])
+        print(f"260 tiles {name}: rel-L2 {rel:.3e}")
+        assert rel <= BAR, name
