@@ -121,9 +121,11 @@ def make_pairs(seeds=(1001, 1002), n_pairs=5000, iters=1000, min_omega=64, lengt
     return torch.cat(tiles_l).contiguous(), torch.cat(tgt_l).contiguous(), torch.cat(msk_l).contiguous()
 
 
-def train(tiles, targets, masks, epochs=60, batch=1024, lr=4e-3, seed=0, params=None, log=None, kind=1):
+def train(tiles, targets, masks, epochs=60, batch=1024, lr=4e-3, seed=0, params=None, log=None, kind=1,
+          lr_final=None):
     """Adam on the masked squared error (of r for kind 1, of f + r for
-    kind 0), all on the GPU with the library's kernels."""
+    kind 0), all on the GPU with the library's kernels.  With lr_final the
+    step size follows a cosine from lr down to lr_final over the run."""
     import torch
     n = tiles.shape[0]
     p = torch.from_numpy(init_params(seed) if params is None else params).cuda().contiguous()
@@ -133,6 +135,7 @@ def train(tiles, targets, masks, epochs=60, batch=1024, lr=4e-3, seed=0, params=
     rng = np.random.default_rng(seed)
     step = 0
     hist = []
+    total = epochs * max(1, (n - batch) // batch + 1)
     for ep in range(epochs):
         perm = torch.from_numpy(rng.permutation(n)).cuda()
         tot, nb = 0.0, 0
@@ -140,8 +143,9 @@ def train(tiles, targets, masks, epochs=60, batch=1024, lr=4e-3, seed=0, params=
             idx = perm[i:i + batch]
             loss = D.net_loss_grad(tiles[idx].contiguous(), p, targets[idx].contiguous(),
                                    masks[idx].contiguous(), g, kind=kind)
+            a = lr if lr_final is None else lr_final + 0.5 * (lr - lr_final) * (1 + np.cos(np.pi * step / total))
             step += 1
-            D.net_adam(p, g, m, v, lr, step)
+            D.net_adam(p, g, m, v, a, step)
             tot += loss
             nb += 1
         hist.append(tot / max(1, nb))
@@ -201,17 +205,20 @@ def main():
     import sys
     ap = argparse.ArgumentParser(description="train the warm-start network on the GPU")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
-    ap.add_argument("--pairs", type=int, default=5000)
-    ap.add_argument("--epochs", type=int, default=60)
-    ap.add_argument("--lr", type=float, default=4e-3)
-    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--streets", type=int, default=6, help="training streets (seeds 1001, 1002, ...)")
+    ap.add_argument("--pairs", type=int, default=48000, help="sampled blocks over all streets (x3 axes)")
+    ap.add_argument("--epochs", type=int, default=800)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr-final", type=float, default=5e-5)
+    ap.add_argument("--batch", type=int, default=256)
     args = ap.parse_args()
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
     t0 = time.time()
-    tiles, tgt, msk = make_pairs(n_pairs=args.pairs)
+    tiles, tgt, msk = make_pairs(seeds=tuple(1001 + i for i in range(args.streets)), n_pairs=args.pairs)
     log(f"{tiles.shape[0]} pairs in {time.time() - t0:.1f}s")
     t1 = time.time()
-    p, hist = train(tiles, tgt, msk, epochs=args.epochs, lr=args.lr, batch=args.batch, log=log)
+    p, hist = train(tiles, tgt, msk, epochs=args.epochs, lr=args.lr, batch=args.batch, log=log,
+                    lr_final=args.lr_final)
     log(f"trained in {time.time() - t1:.1f}s")
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     np.save(args.out, p.cpu().numpy().astype(np.float32), allow_pickle=False)
