@@ -72,6 +72,7 @@ def lib():
             "or_candidates_laser": (i64, [P, i64, P, f64, f64, f64, P, i64]),
             "or_fuse_laser": (None, [P, i32, i32, i64, P, P, P, i64, P, f64, f64, f64]),
             "or_net_forward": (None, [P, i64, P, P, P, P, i32]),
+            "or_net_error_rms": (None, [P, i64, P, P]),
             "or_net_loss_grad": (f64, [P, i64, P, P, P, P, i32, i32]),
             "or_net_gather": (None, [P, P, P, P, i64, P, i32]),
         }
@@ -257,11 +258,24 @@ NET_PARAMS = 8241
 def net_forward(tiles, params, gate=0):
     """gate 0: ReLUs open where the float64 pre-activation is > 0; gate 1:
     the open/closed decision is taken with bfloat16 operands (the network's
-    own precision), the values stay float64."""
+    own precision), the values stay float64; gate 2: the whole network with
+    bfloat16 operands and float64 sums."""
     tiles = _c(tiles, np.float64)
     B = tiles.shape[0]
     out = np.empty((B, 10, 10, 10))
     lib().or_net_forward(_p(tiles), B, _p(_c(params, np.float64)), _p(out), None, None, int(gate))
+    return out
+
+
+def net_error_rms(tiles, params):
+    """Element-wise standard deviation [B][10][10][10] of the difference
+    between net_forward(tiles, params, gate=0) and an evaluation with
+    bfloat16 operands, from propagating the variances of the roundings
+    through the layers (the model is stated in the C source)."""
+    tiles = _c(tiles, np.float64)
+    B = tiles.shape[0]
+    out = np.empty((B, 10, 10, 10))
+    lib().or_net_error_rms(_p(tiles), B, _p(_c(params, np.float64)), _p(out))
     return out
 
 

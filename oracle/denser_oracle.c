@@ -910,7 +910,12 @@ static double to_bf16(double v)
  *   ReLUs are open; the values themselves stay float64.  The layer-1
  *   weights, to which the output is most sensitive, are the pair
  *   bf16(W) + bf16(W - bf16(W)) in that pass (the network's layer-1
- *   operands). */
+ *   operands).
+ * gate 2: the output is that second pass itself, carried through layer 3
+ *   (its input and weights rounded to bfloat16 too): the network evaluated
+ *   with every operand in its own precision and float64 sums, so that it
+ *   differs from a float32-accumulating evaluation only by the order and
+ *   precision of the sums. */
 void or_net_forward(const double *tiles, int64_t B, const double *params, double *out, double *acts,
                     double *gates, int32_t gate)
 {
@@ -924,8 +929,10 @@ void or_net_forward(const double *tiles, int64_t B, const double *params, double
     double *xr = (double *)malloc(sizeof(double) * 2 * T3);
     double *W1r = (double *)malloc(sizeof(double) * nw1);
     double *W2r = (double *)malloc(sizeof(double) * nw2);
+    double W3r[HID * 27];
     for (int i = 0; i < nw1; ++i) W1r[i] = to_bf16(W1[i]) + to_bf16(W1[i] - to_bf16(W1[i]));
     for (int i = 0; i < nw2; ++i) W2r[i] = to_bf16(W2[i]);
+    for (int i = 0; i < HID * 27; ++i) W3r[i] = to_bf16(W3[i]);
     for (int64_t bi = 0; bi < B; ++bi) {
         const double *x = tiles + bi * 2 * T3;
         conv_same(x, 2, W1, b1, HID, h1);
@@ -950,10 +957,84 @@ void or_net_forward(const double *tiles, int64_t B, const double *params, double
             memcpy(acts + (bi * 2 + 1) * HID * T3, h2, sizeof(double) * HID * T3);
             memcpy(gates + (bi * 2 + 1) * HID * T3, g2, sizeof(double) * HID * T3);
         }
+        if (gate == 2) {
+            for (int i = 0; i < HID * T3; ++i) g2[i] = g2[i] > 0.0 ? to_bf16(g2[i]) : 0.0;
+            conv_same(g2, HID, W3r, b3, 1, out + bi * T3);
+            continue;
+        }
         for (int i = 0; i < HID * T3; ++i) h2[i] = g2[i] > 0.0 ? h2[i] : 0.0;
         conv_same(h2, HID, W3, b3, 1, out + bi * T3);
     }
     free(h1); free(h2); free(g1); free(g2); free(xr); free(W1r); free(W2r);
+}
+
+/* Variance of rounding a value to bfloat16 (round to nearest): the error
+ * is spread evenly over one spacing of the bfloat16 grid at v, whose
+ * 8-bit significand gives the spacing 2^(e - 8) for |v| in [2^(e-1), 2^e). */
+static double bf16_round_var(double v)
+{
+    if (v == 0.0) return 0.0;
+    int e;
+    frexp(v, &e);
+    double ulp = ldexp(1.0, e - 8);
+    return ulp * ulp / 12.0;
+}
+
+/* Standard deviation, element by element over the 10^3 output of each
+ * tile, of the difference between the float64 network (gate 0) and an
+ * evaluation that rounds the inputs, the layer-2 and layer-3 weights and
+ * the inputs of layers 2 and 3 to bfloat16, modelling every rounding error
+ * as an independent zero-mean variable of variance bf16_round_var of the
+ * rounded value and propagating the variances through the layers (a
+ * convolution with the squared weights; a closed ReLU, taken from the
+ * float64 pre-activation, passes nothing).  The layer-1 weight pair
+ * (relative error 2^-16), the biases (not rounded) and float32 sums (unit
+ * roundoff 2^-24) are below this model's resolution and left out:
+ *   V1 = (W1^2) * var(x)
+ *   V_{l+1} = (W_{l+1}^2) * (open_l (V_l + var(h_l))) + (var(W_{l+1})) * h_l^2
+ * The L2 norm of the returned field is the expected L2 norm of the
+ * difference. */
+void or_net_error_rms(const double *tiles, int64_t B, const double *params, double *out)
+{
+    const double *W1 = params, *b1 = W1 + HID * 2 * 27, *W2 = b1 + HID, *b2 = W2 + HID * HID * 27,
+                 *W3 = b2 + HID;
+    const int nw1 = HID * 2 * 27, nw2 = HID * HID * 27;
+    double *sW1 = (double *)malloc(sizeof(double) * nw1), *sW2 = (double *)malloc(sizeof(double) * nw2);
+    double *vW2 = (double *)malloc(sizeof(double) * nw2);
+    double sW3[HID * 27], vW3[HID * 27], zero[HID];
+    for (int i = 0; i < nw1; ++i) sW1[i] = W1[i] * W1[i];
+    for (int i = 0; i < nw2; ++i) { sW2[i] = W2[i] * W2[i]; vW2[i] = bf16_round_var(W2[i]); }
+    for (int i = 0; i < HID * 27; ++i) { sW3[i] = W3[i] * W3[i]; vW3[i] = bf16_round_var(W3[i]); }
+    for (int i = 0; i < HID; ++i) zero[i] = 0.0;
+    double *h = (double *)malloc(sizeof(double) * HID * T3), *hn = (double *)malloc(sizeof(double) * HID * T3);
+    double *V = (double *)malloc(sizeof(double) * HID * T3), *h2sq = (double *)malloc(sizeof(double) * HID * T3);
+    double *c = (double *)malloc(sizeof(double) * HID * T3), *a = (double *)malloc(sizeof(double) * HID * T3);
+    double *vx = (double *)malloc(sizeof(double) * 2 * T3);
+    for (int64_t bi = 0; bi < B; ++bi) {
+        const double *x = tiles + bi * 2 * T3;
+        for (int i = 0; i < 2 * T3; ++i) vx[i] = bf16_round_var((double)(float)x[i]);
+        conv_same(x, 2, W1, b1, HID, h);
+        conv_same(vx, 2, sW1, zero, HID, V);
+        for (int layer = 2; layer <= 3; ++layer) {
+            const int cout = layer == 2 ? HID : 1;
+            for (int i = 0; i < HID * T3; ++i) {
+                const int open = h[i] > 0.0;
+                h[i] = open ? h[i] : 0.0;
+                V[i] = open ? V[i] + bf16_round_var(h[i]) : 0.0;
+                h2sq[i] = h[i] * h[i];
+            }
+            conv_same(V, HID, layer == 2 ? sW2 : sW3, zero, cout, c);
+            conv_same(h2sq, HID, layer == 2 ? vW2 : vW3, zero, cout, a);
+            if (layer == 2) {
+                conv_same(h, HID, W2, b2, HID, hn);
+                memcpy(h, hn, sizeof(double) * HID * T3);
+                for (int i = 0; i < HID * T3; ++i) V[i] = c[i] + a[i];
+            } else {
+                for (int i = 0; i < T3; ++i) out[bi * T3 + i] = sqrt(c[i] + a[i]);
+            }
+        }
+    }
+    free(sW1); free(sW2); free(vW2); free(h); free(hn); free(V); free(h2sq); free(c); free(a); free(vx);
 }
 
 /* Gradient of a same-padded convolution y = conv(x, W) + b given dy:

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_common import LAM, SIG, TAU, dn, host
+from gpu_common import LAM, SIG, TAU, dn, dual_warm_start_checks, host
 
 pytestmark = pytest.mark.gpu
 
@@ -86,8 +86,9 @@ def test_street_map_regularised_properties_and_copy_parity(street):
 def test_street_map_dual_warm_start_spot_check(street):
     """The dual warm start of the whole 35-copy map (the launch the bench
     times) on a seeded sample of blocks, against the oracle network on the
-    same tiles (ReLU decisions in bfloat16 operand precision, float64
-    values): relative L2 <= 1e-2 over the masked voxels of every axis."""
+    same tiles: the network on the same bfloat16 operands within relative
+    L2 1e-3, the float64 network within twice the modelled bfloat16
+    rounding (gpu_common.dual_warm_start_checks)."""
     D = dn()
     import torch
     from paper_1604_03734_amd import warmstart as W
@@ -106,22 +107,7 @@ def test_street_map_dual_warm_start_spot_check(street):
     f = host(big.extract(D.DN_X_F))
     w = host(big.extract(D.DN_X_W))
     em = host(big.extract(D.DN_X_EMASK))[blocks]
-    ref = np.zeros((3, len(blocks), 512))
-    for a in range(3):
-        r = oracle.net_forward(oracle.net_gather(nbr, f, w, blocks, a), prm.astype(np.float64), gate=1)
-        c = r[:, 1:9, 1:9, 1:9]
-        if a == 1:
-            c = c.transpose(0, 1, 3, 2)
-        elif a == 2:
-            c = c.transpose(0, 3, 2, 1)
-        ref[a] = np.where((em >> (a + 1)) & 1, c.reshape(len(blocks), 512), 0.0)
-    ref = ref / np.maximum(1.0, np.sqrt((ref ** 2).sum(0)))
     gp = host(p0[:, torch.from_numpy(blocks).long().cuda()]).astype(np.float64)
-    for a in range(3):
-        ma = ((em >> (a + 1)) & 1).astype(bool)
-        rel = np.linalg.norm(gp[a][ma] - ref[a][ma]) / np.linalg.norm(ref[a][ma])
-        print(f"map warm start axis {a}: {int(ma.sum())} voxels, rel-L2 {rel:.3e}, "
-              f"max-abs {np.abs(gp[a] - ref[a]).max():.3e}")
-        assert rel <= 1e-2, a
+    dual_warm_start_checks(gp, nbr, f, w, blocks, em, prm.astype(np.float64), "map warm start (200 blocks)")
     gu = host(u0[torch.from_numpy(blocks).long().cuda()])
     np.testing.assert_array_equal(gu, np.where(w[blocks] > 0, f[blocks], 0.0).astype(np.float32))

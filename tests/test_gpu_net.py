@@ -1,19 +1,22 @@
 """Network kernels (BF16 MFMA, FP32 accumulation) against the FP64 oracle:
 gather, forward, loss gradient (all three layers), Adam, warm start.
 
-Bar: relative L2 error <= 1e-2 against the float64 oracle for the forward
-output, the gradient of every layer and the warm-start fields.  Whether a
-ReLU is open is a discrete decision that floating point takes; it is taken
-in the network's own precision on both sides (the oracle's gate 1: the sign
-of a pre-activation computed from bfloat16-rounded operands), the values
-are compared in float64.  The errors against the oracle with float64
-decisions (gate 0) are printed beside them."""
+Forward output and warm-start fields: against the oracle network on the
+same bfloat16 operands (relative L2 <= 1e-3) and against the float64
+network (L2 within twice the oracle's model of the bfloat16 rounding); see
+gpu_common.net_forward_checks.  Gradients: relative L2 <= 1e-2 against the
+float64 oracle for every layer.  Whether a ReLU is open is a discrete
+decision that floating point takes; for the gradients it is taken in the
+network's own precision on both sides (the oracle's gate 1: the sign of a
+pre-activation computed from bfloat16-rounded operands), the values are
+compared in float64.  The errors against the oracle with float64 decisions
+(gate 0) are printed beside them."""
 import numpy as np
 import pytest
 
 import oracle
 import scenes
-from gpu_common import dn, fuse_both, host, to_dev
+from gpu_common import dn, dual_warm_start_checks, fuse_both, host, net_forward_checks, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -57,12 +60,7 @@ def test_forward_matches_oracle(seed, B):
     out = torch.empty((B, 10, 10, 10), device="cuda")
     D.net_forward(to_dev(tiles, torch.float32), to_dev(prm, torch.float32), out)
     torch.cuda.synchronize()
-    ref = oracle.net_forward(tiles, prm, gate=1)
-    ref0 = oracle.net_forward(tiles, prm)
-    g = host(out).astype(np.float64)
-    print(f"forward B={B}: rel-L2 {_rel_l2(g, ref):.3e} max-abs {np.abs(g - ref).max():.3e} "
-          f"(float64 decisions: rel-L2 {_rel_l2(g, ref0):.3e})")
-    assert _rel_l2(g, ref) <= BAR and _cos(g, ref) >= 0.999
+    net_forward_checks(host(out).astype(np.float64), tiles, prm, f"forward B={B}")
 
 
 def test_loss_gradient_matches_oracle():
@@ -119,12 +117,19 @@ def test_warm_start_fields():
     f = host(gv.extract(D.DN_X_F)).astype(np.float64)
     w = ov.w
     tiles = oracle.net_gather(ov.nbr, f, w, np.arange(nb, dtype=np.int32))
-    r = oracle.net_forward(tiles, prm, gate=1)[:, 1:9, 1:9, 1:9].reshape(nb, 512)
-    ref = np.where(w > 0, np.clip(f + r, -1, 1), 0.0)
     gu = host(u0).astype(np.float64)
     om = w > 0
-    print(f"primal warm start: rel-L2 {_rel_l2(gu[om], ref[om]):.3e} max-abs {np.abs(gu - ref).max():.3e}")
-    assert _rel_l2(gu[om], ref[om]) <= BAR
+    # u0 = clip(f + r) on Omega: compare the network part r = u0 - f where
+    # the clip is inactive on both sides
+    r_dev = np.zeros((nb, 10, 10, 10))
+    r_dev[:, 1:9, 1:9, 1:9] = (gu - f).reshape(nb, 8, 8, 8)
+    keep = np.zeros((nb, 10, 10, 10), bool)
+    r64 = oracle.net_forward(tiles, prm, gate=0)[:, 1:9, 1:9, 1:9].reshape(nb, 512)
+    inner = om & (np.abs(gu) < 1) & (np.abs(f + r64) < 1)
+    keep[:, 1:9, 1:9, 1:9] = inner.reshape(nb, 8, 8, 8)
+    net_forward_checks(r_dev, tiles, prm, "primal warm start", region=lambda a: a[keep])
+    ref = np.where(om, np.clip(f + r64, -1, 1), 0.0)
+    print(f"primal warm start: rel-L2 to the float64 fields {_rel_l2(gu[om], ref[om]):.3e}")
     assert (gu[w == 0] == 0).all()
     g = oracle.grad(ov.nbr, w, gu) / 0.1
     nrm = np.maximum(1.0, np.sqrt((g ** 2).sum(0)))
@@ -182,23 +187,8 @@ def test_dual_warm_start_matches_oracle():
     torch.cuda.synchronize()
     f = host(gv.extract(D.DN_X_F)).astype(np.float64)
     em = host(gv.extract(D.DN_X_EMASK))
-    ref = np.zeros((3, nb, 512))
-    for a in range(3):
-        r = oracle.net_forward(oracle.net_gather(ov.nbr, f, ov.w, np.arange(nb, dtype=np.int32), a), prm,
-                               gate=1)
-        c = r[:, 1:9, 1:9, 1:9]                     # tile centre [z'][y'][x']
-        if a == 1:
-            c = c.transpose(0, 1, 3, 2)
-        elif a == 2:
-            c = c.transpose(0, 3, 2, 1)
-        ref[a] = np.where((em >> (a + 1)) & 1, c.reshape(nb, 512), 0.0)
-    ref = ref / np.maximum(1.0, np.sqrt((ref ** 2).sum(0)))
-    gp = host(p0).astype(np.float64)
-    for a in range(3):
-        ma = ((em >> (a + 1)) & 1).astype(bool)
-        rel = _rel_l2(gp[a][ma], ref[a][ma])
-        print(f"dual warm start axis {a}: rel-L2 {rel:.3e} max-abs {np.abs(gp[a] - ref[a]).max():.3e}")
-        assert rel <= BAR, a
+    dual_warm_start_checks(host(p0).astype(np.float64), ov.nbr, f, ov.w, np.arange(nb, dtype=np.int32), em, prm,
+                           "dual warm start")
     assert np.array_equal(host(u0), np.where(ov.w > 0, f, 0.0).astype(np.float32))
 
 

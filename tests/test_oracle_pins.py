@@ -2,12 +2,15 @@
 itself: closed forms, invariants, textbook special cases, brute force on
 tiny inputs and library routines.  CPU only."""
 import itertools
+import os
 
 import numpy as np
 import pytest
 
 import oracle
 import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 LAM, TAU, SIG = 0.5, 1.0 / np.sqrt(12.0), 1.0 / np.sqrt(12.0)
 
@@ -680,6 +683,61 @@ def test_net_gated_forward_and_gradient_match_torch(gate):
         # the two decisions differ somewhere (else this pin would not pin the gate)
         _, _, (f1, f2) = _torch_gated_net(torch, tiles, prm, 0)
         assert int((m1 != f1).sum()) + int((m2 != f2).sum()) > 0
+
+
+def _torch_bf16_net(torch, tiles, prm, acc):
+    """The network with every operand rounded float64 -> float32 ->
+    bfloat16 by torch's conversions (layer-1 weights as a bfloat16 pair,
+    biases unrounded) and the sums in `acc` (torch.float64 or
+    torch.float32)."""
+    import torch.nn.functional as F
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(acc)
+    bf = lambda x: x.float().bfloat16().to(acc)
+    W1 = t(prm[:864].reshape(16, 2, 3, 3, 3)); b1 = t(prm[864:880])
+    W2 = t(prm[880:7792].reshape(16, 16, 3, 3, 3)); b2 = t(prm[7792:7808])
+    W3 = t(prm[7808:8240].reshape(1, 16, 3, 3, 3)); b3 = t(prm[8240:8241])
+    W1p = torch.cat([bf(W1), bf(W1 - bf(W1))], 1)          # the pair as two input channels each
+    x = bf(t(tiles))
+    g1 = F.conv3d(torch.cat([x, x], 1), W1p, b1, padding=1)
+    g2 = F.conv3d(bf(torch.relu(g1)), bf(W2), b2, padding=1)
+    return F.conv3d(bf(torch.relu(g2)), bf(W3), b3, padding=1)[:, 0]
+
+
+def test_net_bf16_operand_forward_matches_torch():
+    """gate 2 (every operand bfloat16, float64 sums) against the same
+    network written with torch's own rounding and conv3d in float64."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(41)
+    prm = _rand_params(rng, 0.25)
+    tiles = rng.normal(0, 0.6, size=(3, 2, 10, 10, 10))
+    ref = _torch_bf16_net(torch, tiles, prm, torch.float64).numpy()
+    out = oracle.net_forward(tiles, prm, gate=2)
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    # it is not the float64 network (the rounding is really there)
+    assert np.abs(out - oracle.net_forward(tiles, prm, gate=0)).max() > 1e-3 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("seed,scale,weights", [(42, 0.25, None), (43, 0.12, None), (44, 0.3, "trained")])
+def test_net_error_rms_predicts_bf16_error(seed, scale, weights):
+    """The variance model of bfloat16 operand rounding against two
+    evaluations that really round (float64 sums: gate 2; float32 sums:
+    torch conv3d in float32): the L2 norm of their difference from the
+    float64 network is within a factor 2 of the model's, for random weights
+    and for the trained network's (whose cancellation is larger)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(seed)
+    if weights == "trained":
+        prm = np.load(os.path.join(ROOT, "paper_1604_03734_amd", "weights", "warmstart.npy")).astype(np.float64)
+        tiles = np.stack([rng.normal(0, 0.3, size=(4, 10, 10, 10)), rng.random((4, 10, 10, 10))], 1)
+    else:
+        prm = _rand_params(rng, scale)
+        tiles = rng.normal(0, 0.6, size=(4, 2, 10, 10, 10))
+    r64 = oracle.net_forward(tiles, prm, gate=0)
+    sig = np.linalg.norm(oracle.net_error_rms(tiles, prm))
+    e2 = np.linalg.norm(oracle.net_forward(tiles, prm, gate=2) - r64)
+    e32 = np.linalg.norm(_torch_bf16_net(torch, tiles, prm, torch.float32).double().numpy() - r64)
+    print(f"model {sig:.3e}, gate 2 {e2:.3e}, float32 sums {e32:.3e}, |r| {np.linalg.norm(r64):.3e}")
+    assert 0.5 * sig <= e2 <= 2 * sig and 0.5 * sig <= e32 <= 2 * sig
 
 
 def test_net_gather_halo_comes_from_neighbours():
