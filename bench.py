@@ -378,6 +378,24 @@ def time_to_gap(wl, tol=1e-3, k=100):
     return out
 
 
+def fusion_scaling(wl):
+    """Per-frame cost of depth fusion (Eq. 1) into the fused street and into
+    the whole map (35 copies, the street is one of them): fusion culls the
+    blocks out of view, so the map costs the street's visible blocks plus
+    one cheap test per block.  Changes the f/w of both volumes (runs last)."""
+    torch = wl.torch
+    out = {}
+    for name, vol in (("street", wl.street), ("map", wl.big)):
+        vol.fuse_depth(wl.depths[0], wl.K, wl.fr.poses[0])
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for d, T in zip(wl.depths, wl.fr.poses):
+            vol.fuse_depth(d, wl.K, T)
+        torch.cuda.synchronize()
+        out[name] = {"blocks": vol.num_blocks, "ms_per_frame": 1000.0 * (time.time() - t0) / len(wl.depths)}
+    return out
+
+
 def x1_mixed_precision(wl, fp32_ms, iters=100):
     """FP16 / BF16 storage of u, ubar, p (FP32 arithmetic, stochastic
     rounding, FP32 refinement sweep every 50 iterations): time per iteration
@@ -680,6 +698,9 @@ def main():
     if not args.no_gap:
         log("time to gap ...")
         line["time_to_gap"] = time_to_gap(wl)
+    if args.workload == "street" and not args.profile:
+        log("fusion into the map ...")
+        line["fusion_scaling"] = fusion_scaling(wl)
     print(json.dumps(line), flush=True)
 
 

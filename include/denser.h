@@ -232,7 +232,12 @@ int dn_insert_blocks(dn_volume *vol, const int32_t *coords_dev, int64_t n, int32
  * depth map, Eq. (1): p_c = T_gc^-1 p_g for the voxel centre (g + 0.5) s,
  * nearest pixel floor(X + 0.5), eta = d - z_c; if the pixel is inside the
  * map and valid and eta >= -mu: w += 1 and f = (min(1, eta/mu) + w_old f)/w.
- * Geometry and decisions in float64, f and w in float32.  Enqueue only. */
+ * Geometry and decisions in float64, f and w in float32.  Blocks that no
+ * voxel centre of which can pass these tests (all behind the camera, all
+ * beyond max_depth + mu, or projecting outside the image; a conservative
+ * test on the block's corners) are skipped without reading their voxels,
+ * so the cost of a frame follows the blocks in view, not the map; the
+ * result is the same as updating every block.  Enqueue only. */
 int dn_fuse_depth(dn_volume *vol, const float *depth_dev, const dn_intrinsics *K,
                   const double T_gc[16]);
 

@@ -420,13 +420,19 @@ static int insert_packed(dn_volume *v, uint64_t *cand, int64_t n_cand, int32_t *
 }
 
 // ---------------------------------------------------------------- fusion
-__global__ void k_fuse(Geo g, const float *__restrict__ depth, const int32_t *__restrict__ coords,
-                       int64_t nb, float *__restrict__ f, float *__restrict__ w)
+constexpr int kMiscFuseCount = 16;      // v->misc slot of the in-view block count
+constexpr int64_t kFuseGrid = 4096;     // workgroups striding over the in-view list
+
+// Eq. 1 for one voxel (k in 0..511, x fastest) of block b: project its
+// centre, take the depth of the pixel it falls in, and average the
+// truncated signed distance in with weight 1.  Voxels behind the camera,
+// outside the image, with an invalid depth or more than mu behind the
+// observed surface keep their values; free space in front of the surface
+// is updated with the truncated value 1.
+__device__ inline void fuse_voxel(const Geo &g, const float *__restrict__ depth, const int32_t *__restrict__ coords,
+                                  int64_t b, int k, float *__restrict__ f, float *__restrict__ w)
 {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= nb * kBlockVox) return;
-    int64_t b = i >> 9;
-    int vx = int(i & 7), vy = int((i >> 3) & 7), vz = int((i >> 6) & 7);
+    const int vx = k & 7, vy = (k >> 3) & 7, vz = (k >> 6) & 7;
     double d0 = (double(8 * coords[4 * b + 0] + vx) + 0.5) * g.s - g.T[3];
     double d1 = (double(8 * coords[4 * b + 1] + vy) + 0.5) * g.s - g.T[7];
     double d2 = (double(8 * coords[4 * b + 2] + vz) + 0.5) * g.s - g.T[11];
@@ -445,10 +451,78 @@ __global__ void k_fuse(Geo g, const float *__restrict__ depth, const int32_t *__
     if (eta < -g.mu) return;
     double psi = eta / g.mu;
     if (psi > 1.0) psi = 1.0;
+    const int64_t i = b * kBlockVox + k;
     float wo = w[i];
     float wn = wo + 1.0f;
     f[i] = (float(psi) + wo * f[i]) / wn;
     w[i] = wn;
+}
+
+// Visibility culling for fusion: can any voxel centre of the block pass
+// the camera tests of fuse_voxel?  The centres span a box whose image in
+// camera coordinates is a parallelepiped (the pose is affine), so depth
+// ranges over the corners' depths; if all corners lie in front of the
+// camera the box projects into the convex hull of the projected corners.
+// Conservative: margins of 1e-6 m in depth and one pixel in the image
+// absorb rounding differences from the per-voxel evaluation, and a box
+// reaching behind the camera counts as visible.  A block is skipped only if
+// every centre is behind the camera, beyond max_depth + mu (where no valid
+// depth can put it within mu of a surface) or outside the image.
+__device__ inline bool block_in_view(const Geo &g, const int32_t *c)
+{
+    double zmin = 1e300, zmax = -1e300, xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+    double xs[8], ys[8], zs[8];
+    for (int k = 0; k < 8; ++k) {
+        double d0 = (double(8 * c[0] + ((k & 1) ? 7 : 0)) + 0.5) * g.s - g.T[3];
+        double d1 = (double(8 * c[1] + ((k & 2) ? 7 : 0)) + 0.5) * g.s - g.T[7];
+        double d2 = (double(8 * c[2] + ((k & 4) ? 7 : 0)) + 0.5) * g.s - g.T[11];
+        xs[k] = (g.T[0] * d0 + g.T[4] * d1) + g.T[8] * d2;
+        ys[k] = (g.T[1] * d0 + g.T[5] * d1) + g.T[9] * d2;
+        zs[k] = (g.T[2] * d0 + g.T[6] * d1) + g.T[10] * d2;
+        zmin = fmin(zmin, zs[k]);
+        zmax = fmax(zmax, zs[k]);
+    }
+    const double eps = 1e-6;
+    if (zmax <= -eps || zmin > g.maxd + g.mu + eps) return false;
+    if (zmin <= eps) return true;
+    for (int k = 0; k < 8; ++k) {
+        double X = g.fx * (xs[k] / zs[k]) + g.cx + 0.5, Y = g.fy * (ys[k] / zs[k]) + g.cy + 0.5;
+        xmin = fmin(xmin, X); xmax = fmax(xmax, X);
+        ymin = fmin(ymin, Y); ymax = fmax(ymax, Y);
+    }
+    return xmax >= -1.0 && xmin < double(g.W) + 1.0 && ymax >= -1.0 && ymin < double(g.H) + 1.0;
+}
+
+// The blocks in view, appended to `list` (one atomic per wavefront; the
+// order of the list varies, the fused values do not: every voxel is
+// updated by one thread).
+__global__ void k_cull(Geo g, const int32_t *__restrict__ coords, int64_t nb, int32_t *__restrict__ list,
+                       int32_t *__restrict__ count)
+{
+    int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    bool vis = b < nb && block_in_view(g, coords + 4 * b);
+    uint64_t m = __ballot(vis);
+    if (m == 0) return;
+    const int lane = __lane_id(), leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count, __popcll(m));
+    base = __shfl(base, leader);
+    if (vis) list[base + __popcll(m & ((uint64_t(1) << lane) - 1))] = int32_t(b);
+}
+
+// Eq. 1 over the blocks in view: workgroups stride over the list (its
+// length is read on the device, so the grid is sized from the pool).
+__global__ __launch_bounds__(256) void k_fuse_list(Geo g, const float *__restrict__ depth,
+                                                   const int32_t *__restrict__ coords,
+                                                   const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+                                                   float *__restrict__ f, float *__restrict__ w)
+{
+    const int32_t n = *count;
+    for (int32_t j = blockIdx.x; j < n; j += gridDim.x) {
+        const int64_t b = list[j];
+        fuse_voxel(g, depth, coords, b, threadIdx.x, f, w);
+        fuse_voxel(g, depth, coords, b, threadIdx.x + 256, f, w);
+    }
 }
 
 static int make_geo(const dn_volume *v, const dn_intrinsics *K, const double *T, Geo &g)
@@ -762,6 +836,7 @@ static size_t volume_layout(const dn_volume_params &p, void *base, dn_volume *v)
         carve_laser(m, p.max_points, p.max_observations);
         upd(m.off);
     }
+    upd(size_t(p.max_blocks) * sizeof(int32_t));   // the blocks in view of a fused frame
     char *scratch = b.take<char>(need);
     if (v) {
         v->coords = coords; v->keys = keys; v->hash[0] = h0; v->hash[1] = h1; v->nbr = nbr;
@@ -1023,8 +1098,13 @@ int dn_fuse_depth(dn_volume *v, const float *depth, const dn_intrinsics *K, cons
     int rc = make_geo(v, K, T, g);
     if (rc) return rc;
     if (v->nb == 0) return DN_OK;
-    hipLaunchKernelGGL(k_fuse, dim3(grid1(v->nb * kBlockVox)), dim3(256), 0, v->stream, g, depth, v->coords,
-                       v->nb, v->f, v->w);
+    int32_t *list = reinterpret_cast<int32_t *>(v->scratch);
+    int32_t *count = reinterpret_cast<int32_t *>(v->misc + kMiscFuseCount);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, v->stream, count);
+    hipLaunchKernelGGL(k_cull, dim3(grid1(v->nb)), dim3(256), 0, v->stream, g, v->coords, v->nb, list, count);
+    DN_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_fuse_list, dim3(unsigned(std::min<int64_t>(v->nb, kFuseGrid))), dim3(256), 0, v->stream,
+                       g, depth, v->coords, list, count, v->f, v->w);
     DN_HIP(hipGetLastError());
     v->emask_nb = -1;
     return DN_OK;

@@ -43,6 +43,48 @@ def test_c1_fusion_parity(c1):
     assert (w > 0).sum() > 50000
 
 
+def test_fusion_culling_keeps_every_updatable_block():
+    """Fusion skips blocks out of view; a dense cube of blocks around the
+    camera (behind it, straddling its plane, beside the image, beyond
+    max_depth + mu) fused from three poses (one rotated, one looking back
+    through the cube) matches the oracle's fusion of every block: w
+    bit-exact, f within 1e-4, and some blocks are out of view."""
+    D = dn()
+    fr = scenes.frames_c1(0)
+    cam = fr.camera
+    r = np.arange(-5, 6)
+    coords = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3).astype(np.int32)
+    max_depth = 2.6
+    gv = D.Volume(fr.voxel_size, fr.mu, max_depth, len(coords), 12, 256, max_points=0)
+    gv.insert_blocks(to_dev(coords))
+    pc = host(gv.extract(D.DN_X_COORDS))[:, :3]
+    f = np.zeros((len(pc), 512))
+    w = np.zeros((len(pc), 512))
+    K = intr(D, cam)
+    c, s_ = np.cos(0.7), np.sin(0.7)
+    R = np.array([[c, 0, s_], [0, 1, 0], [-s_, 0, c]])
+    poses = [fr.poses[0], fr.poses[1].copy(), np.eye(4)]
+    poses[1][:3, :3] = R @ poses[1][:3, :3]
+    poses[2][:3, :3] = np.diag([-1.0, 1.0, -1.0])   # at the origin, looking along -z through the cube
+    H, W = cam.height, cam.width
+    rng = np.random.default_rng(5)
+    depths = []
+    for k in range(3):   # slanted planes 1 to 2.8 m away, 5% invalid
+        d = (1.0 + 1.8 * np.arange(W)[None, :] / W + 0.2 * k + 0.0 * np.arange(H)[:, None]).astype(np.float32)
+        d[rng.random((H, W)) < 0.05] = np.nan
+        depths.append(d)
+    for d, T in zip(depths, poses):
+        oracle.fuse(pc, f, w, d, K4(cam), T, fr.voxel_size, fr.mu, max_depth)
+        gv.fuse_depth(to_dev(d), K, T)
+    gw = host(gv.extract(D.DN_X_W))
+    gf = host(gv.extract(D.DN_X_F))
+    np.testing.assert_array_equal(gw, w)
+    assert np.abs(gf - f).max() <= TOL_F
+    touched = (w > 0).any(1)
+    print(f"culling cube: {int(touched.sum())} of {len(pc)} blocks updated")
+    assert 0 < touched.sum() < len(pc)
+
+
 @pytest.mark.parametrize("kernel", ["twopass", "fused"])
 def test_c1_regularize_parity(c1, kernel):
     D = dn()
