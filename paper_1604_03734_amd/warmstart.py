@@ -19,9 +19,13 @@ seeded synthetic streets are fused and regularised for 1000 iterations, and
 blocks with enough observed voxels are sampled.
 
 The plain solver stays in charge: after K warm-started iterations the
-relative gap is compared with the plain solver's after K iterations; if it
-is more than twice that, the warm start is discarded and the solve restarts
-from zero.  Either way the solve runs until the requested gap.
+relative gap is compared with the plain solver's after K iterations from
+zero with the same steps; if it is more than twice that, the warm start is
+discarded and the solve restarts from zero.  Either way the solve runs until
+the requested gap.  The plain solver's gap after K comes from a stored
+calibration (measured on the training streets for a table of step sizes and
+written beside the weights), or, for steps the table does not hold, from a
+plain run of K iterations on the volume itself.
 
 This module only sequences calls into the library (and uses torch for
 device buffers); every computation runs in the HIP kernels.
@@ -37,7 +41,12 @@ from . import denser as D
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "warmstart.npy")
+CALIBRATION = os.path.join(HERE, "weights", "warmstart_calibration.json")
 LAM = 0.5
+# step sizes (tau, gamma) whose plain gap after K iterations is calibrated;
+# sigma = 1 / (12 tau) for the fixed schedule
+SCHEDULES = ((1.0 / np.sqrt(12.0), 0.0), (1.0 / np.sqrt(12.0), LAM), (0.02, 0.0), (0.03, 0.0), (0.05, 0.0),
+             (0.1, 0.0))
 
 
 def init_params(seed: int = 0) -> np.ndarray:
@@ -57,6 +66,44 @@ def load_default_weights():
     if w.shape != (D.NET_PARAMS,):
         return None
     return w
+
+
+def load_calibration(path=CALIBRATION):
+    if not os.path.exists(path):
+        return None
+    import json
+    with open(path) as f:
+        return json.load(f)
+
+
+def calibrated_gap(tau, gamma, k, cal=None):
+    """The stored plain relative gap after k iterations at (tau, gamma), or
+    None if the calibration does not hold these steps."""
+    cal = load_calibration() if cal is None else cal
+    if not cal or cal.get("k") != k:
+        return None
+    for e in cal["entries"]:
+        if abs(e["tau"] - tau) <= 1e-9 * tau and abs(e["gamma"] - gamma) <= 1e-12:
+            return e["plain_rel_gap"]
+    return None
+
+
+def calibrate(seeds=tuple(range(1001, 1007)), k=100, schedules=SCHEDULES, length=100.0, n_frames=100):
+    """Relative gap of the plain solver (from zero) after k iterations on
+    each seeded street, for each schedule; the largest over the streets is
+    the one the fallback compares with."""
+    import scenes
+    out = {"k": k, "lambda": LAM, "streets": list(seeds), "entries": []}
+    gaps = {sch: [] for sch in schedules}
+    for s in seeds:
+        vol = fuse_frames(scenes.frames_street(length, n_frames, seed=s, config_id=5))
+        for tau, gamma in schedules:
+            st = vol.regularize(D.reg_params(LAM, tau, 1.0 / (12.0 * tau), iters=k, gamma=gamma))
+            gaps[(tau, gamma)].append(float(st.rel_gap))
+        vol.close()
+    for (tau, gamma), g in gaps.items():
+        out["entries"].append({"tau": tau, "gamma": gamma, "plain_rel_gap": max(g), "per_street": g})
+    return out
 
 
 def fuse_frames(frames, max_blocks=16384):
@@ -170,24 +217,37 @@ def solve_plain(vol, tol=1e-3, max_iters=20000, gap_every=10, gamma=0.0, kernel=
 
 
 def solve_warm(vol, params, tol=1e-3, k=100, plain_rel_gap_at_k=None, delta=0.1, max_iters=20000,
-               gap_every=10, gamma=0.0, kernel=D.DN_K_AUTO, tau0=None, mode=D.DN_WARM_DUAL):
+               gap_every=10, gamma=0.0, kernel=D.DN_K_AUTO, tau0=None, mode=D.DN_WARM_DUAL, calibration=None):
     """Warm start, K iterations, the fallback test, then iterate to `tol`.
-    Returns a dict with iterations, timings and whether it fell back."""
+    plain_rel_gap_at_k: the plain solver's relative gap after K iterations
+    at the same steps; None: the stored calibration's, else a plain run of
+    K iterations on `vol` (counted in the time).  Returns a dict with
+    iterations, timings, whether it fell back and where the reference came
+    from."""
     import torch
     if not isinstance(params, torch.Tensor):
         params = torch.from_numpy(np.asarray(params, np.float32)).cuda()
-    t0 = time.time()
-    u0, p0 = warm_state(vol, params, mode, delta)
     # a warm start needs smaller primal and larger dual steps (tau sigma = 1/12)
     tau = 1.0 / np.sqrt(12.0) if tau0 is None else tau0
     sigma = 1.0 / (12.0 * tau)
+    t0 = time.time()
+    source = "given"
+    if plain_rel_gap_at_k is None:
+        plain_rel_gap_at_k = calibrated_gap(tau, gamma, k, calibration)
+        source = "calibration"
+        if plain_rel_gap_at_k is None:
+            ref = vol.regularize(D.reg_params(LAM, tau, sigma, iters=k, kernel=kernel, gamma=gamma))
+            plain_rel_gap_at_k = ref.rel_gap
+            source = "plain run"
+    u0, p0 = warm_state(vol, params, mode, delta)
     st = vol.regularize(D.reg_params(LAM, tau, sigma, iters=k, gap_every=gap_every, gap_tol=tol,
                                      init=D.DN_INIT_GIVEN, kernel=kernel, gamma=gamma), u0, p0)
-    out = {"k": k, "iters_warm": st.iters_run, "rel_gap_at_k": st.rel_gap, "fallback": False}
+    out = {"k": k, "iters_warm": st.iters_run, "rel_gap_at_k": st.rel_gap, "fallback": False,
+           "reference": source, "plain_rel_gap_at_k": plain_rel_gap_at_k}
     if st.converged:
         out.update(iters=st.iters_run, converged=True, rel_gap=st.rel_gap, seconds=time.time() - t0)
         return out
-    if plain_rel_gap_at_k is not None and not (st.rel_gap <= 2.0 * plain_rel_gap_at_k):
+    if not (st.rel_gap <= 2.0 * plain_rel_gap_at_k):
         out["fallback"] = True
         st2 = solve_plain(vol, tol, max_iters, gap_every, gamma, kernel)
         out.update(iters=st.iters_run + st2.iters_run, converged=bool(st2.converged), rel_gap=st2.rel_gap,
@@ -211,10 +271,27 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--lr-final", type=float, default=5e-5)
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--calibration-out", default=CALIBRATION)
+    ap.add_argument("--calibrate-only", action="store_true",
+                    help="only measure the plain solver's gap after K on the training streets")
     args = ap.parse_args()
     log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
+    seeds = tuple(1001 + i for i in range(args.streets))
+
+    def write_calibration():
+        import json
+        t = time.time()
+        cal = calibrate(seeds)
+        with open(args.calibration_out, "w") as f:
+            json.dump(cal, f, indent=1)
+        log(f"calibration of the fallback in {time.time() - t:.1f}s: " +
+            ", ".join(f"tau {e['tau']:.3f} gamma {e['gamma']}: {e['plain_rel_gap']:.3e}" for e in cal["entries"]))
+
+    if args.calibrate_only:
+        write_calibration()
+        return
     t0 = time.time()
-    tiles, tgt, msk = make_pairs(seeds=tuple(1001 + i for i in range(args.streets)), n_pairs=args.pairs)
+    tiles, tgt, msk = make_pairs(seeds=seeds, n_pairs=args.pairs)
     log(f"{tiles.shape[0]} pairs in {time.time() - t0:.1f}s")
     t1 = time.time()
     p, hist = train(tiles, tgt, msk, epochs=args.epochs, lr=args.lr, batch=args.batch, log=log,
@@ -222,6 +299,7 @@ def main():
     log(f"trained in {time.time() - t1:.1f}s")
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     np.save(args.out, p.cpu().numpy().astype(np.float32), allow_pickle=False)
+    write_calibration()
     print(args.out)
 
 

@@ -62,6 +62,40 @@ def test_warm_start_gain_on_a_held_out_street(trained, heldout, gamma):
     assert res["iters"] < plain.iters_run
 
 
+@pytest.mark.parametrize("gamma", [0.0, 0.5])
+def test_shipped_weights_gain_with_the_stored_calibration(heldout, gamma):
+    """The shipped weights on the held-out street, the fallback judged by
+    the calibration stored with them (no plain run on this volume): no
+    fallback, fewer iterations than the plain solver."""
+    D = dn()
+    from paper_1604_03734_amd import warmstart as W
+    p = W.load_default_weights()
+    assert p is not None and W.load_calibration() is not None
+    vol = heldout
+    plain = vol.regularize(D.reg_params(0.5, iters=20000, gap_every=10, gap_tol=TOL, kernel=D.DN_K_FUSED,
+                                        gamma=gamma))
+    res = W.solve_warm(vol, p, tol=TOL, k=100, gamma=gamma, kernel=D.DN_K_FUSED)
+    print(f"shipped weights, gamma {gamma}: plain {plain.iters_run}, warm {res['iters']} "
+          f"(reference {res['reference']} {res['plain_rel_gap_at_k']:.2e}, warm gap after 100 "
+          f"{res['rel_gap_at_k']:.2e})")
+    assert res["reference"] == "calibration"
+    assert res["converged"] and not res["fallback"]
+    assert res["iters"] < plain.iters_run
+
+
+def test_fallback_on_a_wrong_network_with_the_stored_calibration(trained, heldout):
+    """The wrong network of the next test, judged by the stored calibration:
+    the warm start is discarded and the solve still converges."""
+    from paper_1604_03734_amd import warmstart as W
+    bad = trained[0].clone()
+    bad[7808:8241] *= -20.0
+    res = W.solve_warm(heldout, bad, tol=TOL, k=100)
+    print(f"wrong network, calibrated reference {res['plain_rel_gap_at_k']:.3e}: gap after 100 warm "
+          f"{res['rel_gap_at_k']:.3e}, fallback {res['fallback']}")
+    assert res["reference"] == "calibration"
+    assert res["fallback"] and res["converged"] and res["rel_gap"] <= TOL
+
+
 def test_fallback_on_a_wrong_network(trained, heldout):
     """A genuinely wrong network (the trained one with its output layer
     negated and scaled by 20, so every dual component points the wrong way
