@@ -278,39 +278,51 @@ __global__ void k_mask_count(const double *__restrict__ part, int64_t nparts, do
 }
 
 // The gradient of all 8241 parameters from the per-workgroup partials of
-// the three layers (parts[layer][p][27 * 256 + 16], summed over p in order):
-// one thread per partial entry, so the reads are contiguous across threads,
-// written to the canonical parameter layout.
-__global__ void k_grad_final(const float *__restrict__ parts, int nparts, float *__restrict__ grad)
+// the three layers (parts[layer][p][27 * 256 + 16]), written to the
+// canonical parameter layout.  The sum over p has a fixed order: a
+// workgroup takes 32 consecutive partial entries (contiguous reads across
+// its threads), its 8 thread groups add consecutive eighths of the
+// partials (each in order, eight loads in flight), then the eight group
+// sums are added in group order.
+constexpr int kFinalEntries = 32, kFinalGroups = 8;
+__global__ __launch_bounds__(256) void k_grad_final(const float *__restrict__ parts, int nparts,
+                                                    float *__restrict__ grad)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= 3 * (kWPack + kC)) return;
-    const int layer = k / (kWPack + kC), idx = k - layer * (kWPack + kC);
+    __shared__ float sg[kFinalGroups][kFinalEntries];
+    const int el = threadIdx.x % kFinalEntries, grp = threadIdx.x / kFinalEntries;
+    const int k = blockIdx.x * kFinalEntries + el;
+    const bool live = k < 3 * (kWPack + kC);
+    const int layer = live ? k / (kWPack + kC) : 0, idx = k - layer * (kWPack + kC);
+    const int per = (nparts + kFinalGroups - 1) / kFinalGroups;
+    const int p0 = grp * per, p1 = min(nparts, p0 + per);
+    float a = 0.f;
+    if (live) {
+        const float *src = parts + int64_t(layer) * nparts * (kWPack + kC) + idx;
+        int p = p0;
+        for (; p + 8 <= p1; p += 8) {
+            float q[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) q[e] = src[int64_t(p + e) * (kWPack + kC)];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a += q[e];
+        }
+        for (; p < p1; ++p) a += src[int64_t(p) * (kWPack + kC)];
+    }
+    sg[grp][el] = a;
+    __syncthreads();
+    if (grp != 0 || !live) return;
+    float sum = sg[0][el];
+    for (int q = 1; q < kFinalGroups; ++q) sum += sg[q][el];
     const int cout = layer == 2 ? 1 : 16, cin = layer == 0 ? 2 : 16;
     const int wbase = layer == 0 ? kW1 : (layer == 1 ? kW2 : kW3);
     const int bbase = layer == 0 ? kB1 : (layer == 1 ? kB2 : kB3);
-    int dst;
     if (idx < kWPack) {
         const int t = idx / (kC * kC), co = (idx / kC) % kC, ci = idx % kC;
-        if (co >= cout || ci >= cin) return;
-        dst = wbase + (co * cin + ci) * kTaps + t;
+        if (co < cout && ci < cin) grad[wbase + (co * cin + ci) * kTaps + t] = sum;
     } else {
         const int co = idx - kWPack;
-        if (co >= cout) return;
-        dst = bbase + co;
+        if (co < cout) grad[bbase + co] = sum;
     }
-    const float *src = parts + int64_t(layer) * nparts * (kWPack + kC) + idx;
-    float a = 0.f;
-    int p = 0;
-    for (; p + 8 <= nparts; p += 8) {          // eight loads in flight, added in order
-        float q[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) q[e] = src[int64_t(p + e) * (kWPack + kC)];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) a += q[e];
-    }
-    for (; p < nparts; ++p) a += src[int64_t(p) * (kWPack + kC)];
-    grad[dst] = a;
 }
 
 __global__ void k_sum_loss(const double *__restrict__ tl, int64_t n, double *__restrict__ out)
@@ -1073,11 +1085,43 @@ __device__ __forceinline__ void scatter8(uint16_t *row0, int stride, int pos, ui
     }
 }
 
+// The three x shifts of a run of 8 channel-row entries starting at p
+// (p 8-byte aligned): bm = p[-1 .. 6], b0 = p[0 .. 7], bp = p[1 .. 8], from
+// four aligned 8-byte reads of p[-4 .. 11] and 16-bit funnel shifts (an
+// LDS read at a 2-byte offset is split by the hardware and costs several
+// times an aligned one).
+__device__ __forceinline__ void x_shifts(const uint16_t *p, v4u &bm, v4u &b0, v4u &bp)
+{
+    const uint2 *q = reinterpret_cast<const uint2 *>(p - 4);
+    const uint2 l0 = q[0], l1 = q[1], l2 = q[2], l3 = q[3];
+    const uint32_t s1 = __builtin_amdgcn_alignbit(l1.y, l1.x, 16), s2 = __builtin_amdgcn_alignbit(l2.x, l1.y, 16),
+                   s3 = __builtin_amdgcn_alignbit(l2.y, l2.x, 16);
+    bm = v4u{__builtin_amdgcn_alignbit(l1.x, l0.y, 16), s1, s2, s3};
+    b0 = v4u{l1.x, l1.y, l2.x, l2.y};
+    bp = v4u{s1, s2, s3, __builtin_amdgcn_alignbit(l3.x, l2.y, 16)};
+}
+
+// The shift s in {-1, 0, +1} of that run (p[s .. s + 7]), s per lane.
+__device__ __forceinline__ v4u x_shift(const uint16_t *p, int s)
+{
+    v4u bm, b0, bp;
+    x_shifts(p, bm, b0, bp);
+    return s < 0 ? bm : (s > 0 ? bp : b0);
+}
+
+// Eight entries p[0 .. 7] at an 8-byte aligned p, as two aligned reads.
+__device__ __forceinline__ v4u lds8_a8(const uint16_t *p)
+{
+    const uint2 *q = reinterpret_cast<const uint2 *>(p);
+    const uint2 l1 = q[0], l2 = q[1];
+    return v4u{l1.x, l1.y, l2.x, l2.y};
+}
+
 // Weight and bias gradient of layer 3 (one output channel):
 //   dW3[ci][t] = sum over tile voxels v of h2[ci][v] d3[v - off(t)],
 // as (taps, 16 rows) x (input channels, 16 columns) x (32 voxels) MFMAs:
 // the rows read d3, kept on the padded grid, shifted back by their own tap
-// (unaligned 16-byte reads), the columns read h2 unshifted.  Two MFMAs per
+// (x shifts per lane from x_shift), the columns read h2 unshifted.  Two MFMAs per
 // 32 voxels instead of 27 with one used row.  Partials in the
 // [tap][co][ci] layout (co = 0), bias db3 = sum of d3.
 constexpr int kD3Row = 2080;   // LDS entries of d3: 168 zero margin + 1728 + margin
@@ -1135,15 +1179,13 @@ __global__ __launch_bounds__(256) void k_wgrad3(const uint16_t *__restrict__ X, 
             const int c = c0 + 8 * g;
             const int plane = c / 120, within = c - 120 * plane;
             const int pc = within + 12 + 144 * (plane + 1);          // padded index of entry c
-            const v8bf b = as_v8bf(*reinterpret_cast<const v4u *>(sx + i * kXRow + 8 + pc));
+            const v8bf b = as_v8bf(lds8_a8(sx + i * kXRow + 8 + pc));
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int t = 16 * h + i;
                 v4u q = {0u, 0u, 0u, 0u};
-                if (t < kTaps) {
-                    const int off = (t % 3 - 1) + 12 * ((t / 3) % 3 - 1) + 144 * (t / 9 - 1);
-                    q = *reinterpret_cast<const v4u *>(sd + 168 + pc - off);
-                }
+                if (t < kTaps)
+                    q = x_shift(sd + 168 + pc - 12 * ((t / 3) % 3 - 1) - 144 * (t / 9 - 1), 1 - t % 3);
                 acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_v8bf(q), b, acc[h], 0, 0, 0);
             }
         }
@@ -1175,7 +1217,8 @@ __global__ __launch_bounds__(256) void k_wgrad3(const uint16_t *__restrict__ X, 
 // Weight and bias gradient of layer 1 (two input channels):
 //   dW1[co][ci][t] = sum over v of d1[co][v] x[ci][v + off(t)],
 // as (output channels) x (54 (ci, t) columns in four MFMAs) x (32 voxels):
-// each column reads the input channel shifted by its own tap.
+// each column reads the input channel shifted by its own tap (the y and z
+// shifts keep the reads 8-byte aligned, x shifts per lane from x_shift).
 __global__ __launch_bounds__(256) void k_wgrad1(const uint16_t *__restrict__ X, const uint16_t *__restrict__ dY,
                                                 int64_t n, float *__restrict__ partials)
 {
@@ -1189,12 +1232,13 @@ __global__ __launch_bounds__(256) void k_wgrad1(const uint16_t *__restrict__ X, 
     v4f acc[4];
     for (int q = 0; q < 4; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
-    int coff[4];                     // LDS offset of column 16 q + i: channel row + tap shift
+    int coff[4], ckx[4];             // column 16 q + i: channel row + (y, z) tap shift, and its x shift
     bool cuse[4];
     for (int q = 0; q < 4; ++q) {
         const int col = 16 * q + i, ci = col / kTaps, t = col % kTaps;
         cuse[q] = col < 2 * kTaps;
-        coff[q] = cuse[q] ? ci * kXRow + 8 + (t % 3 - 1) + 12 * ((t / 3) % 3 - 1) + 144 * (t / 9 - 1) : 0;
+        coff[q] = cuse[q] ? ci * kXRow + 8 + 12 * ((t / 3) % 3 - 1) + 144 * (t / 9 - 1) : 8;
+        ckx[q] = t % 3 - 1;
     }
     __syncthreads();
     constexpr int kXc = kPadVox / 8, kDc = kRowVox / 8;
@@ -1233,7 +1277,7 @@ __global__ __launch_bounds__(256) void k_wgrad1(const uint16_t *__restrict__ X, 
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 v4u bq = {0u, 0u, 0u, 0u};
-                if (cuse[q]) bq = *reinterpret_cast<const v4u *>(sx + coff[q] + pc);
+                if (cuse[q]) bq = x_shift(sx + coff[q] + pc, ckx[q]);
                 acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_v8bf(bq), acc[q], 0, 0, 0);
             }
         }
@@ -1270,11 +1314,11 @@ __global__ __launch_bounds__(256) void k_wgrad1(const uint16_t *__restrict__ X, 
 //   db[co] = sum over v of dY[co][v],
 // the products as 16 (co) x 16 (ci) x 32 (voxels) MFMAs: 32 consecutive
 // compact-row entries of dY (aligned 16-byte reads) against the same
-// entries of the padded X shifted by the tap (unaligned 16-byte reads; a
-// run of 8 entries never leaves its z plane, where the two layouts are
-// contiguous alike).  One workgroup per compute unit loops over tiles and
-// keeps every tap's 16 x 16 block in registers (wave w: taps w, w + 8, ...);
-// one partial [27][16][16] + [16] per workgroup.
+// entries of the padded X shifted by the tap (a run of 8 entries never
+// leaves its z plane, where the two layouts are contiguous alike; the y and
+// z shifts keep X 8-byte aligned, the x shifts come from x_shifts).  One
+// workgroup per compute unit loops over tiles and keeps every tap's 16 x 16
+// block in registers; one partial [27][16][16] + [16] per workgroup.
 template <int CI, int CO>
 __global__ __launch_bounds__(512) void k_wgrad_mfma(const uint16_t *__restrict__ X, const uint16_t *__restrict__ dY,
                                                     int64_t n, float *__restrict__ partials)
@@ -1284,6 +1328,10 @@ __global__ __launch_bounds__(512) void k_wgrad_mfma(const uint16_t *__restrict__
     __shared__ float sb[512];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int i = lane & 15, g = lane >> 4;
+    // wave w: the taps t = 3w .. 3w + 2 of the (y, z) offset pair w (x
+    // offsets -1, 0, +1, one read for the three); waves 0..2 also tap
+    // 24 + w of pair 8 (y and z offsets +1)
+    const int ky = wave % 3 - 1, kz = wave / 3 - 1;
     for (int k = tid; k < 16 * kXRow / 8; k += 512) reinterpret_cast<uint4 *>(sx)[k] = make_uint4(0, 0, 0, 0);
     for (int k = tid; k < 16 * kDRow / 8; k += 512) reinterpret_cast<uint4 *>(sd)[k] = make_uint4(0, 0, 0, 0);
     v4f acc[4];
@@ -1319,19 +1367,21 @@ __global__ __launch_bounds__(512) void k_wgrad_mfma(const uint16_t *__restrict__
         __syncthreads();
         if (tile + gridDim.x < n) fetch(tile + gridDim.x);
         for (int c = tid >> 4; c < kRowVox; c += 32) bsum += bf2f(sd[(tid & 15) * kDRow + c]);
+        const uint16_t *xrow = sx + i * kXRow;
         for (int c0 = 0; c0 < kRowVox; c0 += 32) {
             const int c = c0 + 8 * g;
             const v8bf a = as_v8bf(*reinterpret_cast<const v4u *>(sd + i * kDRow + c));
             const int plane = c / 120, within = c - 120 * plane;
             const int pc = 8 + within + 12 + 144 * (plane + 1);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int t = wave + 8 * j;
-                if (t < kTaps) {
-                    const int off = (t % 3 - 1) + 12 * ((t / 3) % 3 - 1) + 144 * (t / 9 - 1);
-                    const v8bf bq = as_v8bf(*reinterpret_cast<const v4u *>(sx + i * kXRow + pc + off));
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq, acc[j], 0, 0, 0);
-                }
+            v4u bm, b0, bp;
+            x_shifts(xrow + pc + 12 * ky + 144 * kz, bm, b0, bp);
+            acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_v8bf(bm), acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_v8bf(b0), acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_v8bf(bp), acc[2], 0, 0, 0);
+            if (wave < 3) {
+                x_shifts(xrow + pc + 12 + 144, bm, b0, bp);
+                acc[3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_v8bf(wave == 0 ? bm : (wave == 1 ? b0 : bp)),
+                                                                 acc[3], 0, 0, 0);
             }
         }
         __syncthreads();
@@ -1339,8 +1389,8 @@ __global__ __launch_bounds__(512) void k_wgrad_mfma(const uint16_t *__restrict__
     float *out = partials + int64_t(blockIdx.x) * (kWPack + kC);
     // lane: column ci = i, rows co = 4g .. 4g + 3
     for (int j = 0; j < 4; ++j) {
-        const int t = wave + 8 * j;
-        if (t < kTaps)
+        const int t = j < 3 ? 3 * wave + j : 24 + wave;
+        if (j < 3 || wave < 3)
             for (int r = 0; r < 4; ++r) out[(t * kC + 4 * g + r) * kC + i] = acc[j][r];
     }
     sb[tid] = bsum;
@@ -1516,7 +1566,8 @@ int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const f
     hipLaunchKernelGGL(k_wgrad1, dim3(gw), dim3(256), 0, st, ws.x1cf, ws.d1cf, n, ws.parts);
     hipLaunchKernelGGL((k_wgrad_mfma<16, 16>), dim3(gw), dim3(512), 0, st, ws.h1cf, ws.d2cf, n, ws.parts + lp);
     hipLaunchKernelGGL(k_wgrad3, dim3(gw), dim3(256), 0, st, ws.h2cf, ws.d3cf, n, ws.parts + 2 * lp);
-    hipLaunchKernelGGL(k_grad_final, dim3(grid1(3 * (kWPack + kC))), dim3(256), 0, st, ws.parts, ws.nparts, grad);
+    hipLaunchKernelGGL(k_grad_final, dim3((3 * (kWPack + kC) + kFinalEntries - 1) / kFinalEntries), dim3(256), 0, st,
+                       ws.parts, ws.nparts, grad);
     DN_HIP(hipGetLastError());
     if (loss_host) {
         double h = 0.0;
