@@ -62,6 +62,9 @@ def parse():
                     help="only copy 1 GiB device to device (HBM counter calibration) and exit")
     ap.add_argument("--profile", action="store_true",
                     help="short run for profilers: no CPU baseline, no time-to-gap")
+    ap.add_argument("--net-only", action="store_true",
+                    help="only the network section (warm-start inference on the street map and "
+                         "training steps), one JSON line, for profilers")
     return ap.parse_args()
 
 
@@ -597,6 +600,11 @@ def main():
         wl = BatchedWorkload(args)
     else:
         wl = Workload(args)
+    if args.net_only:
+        wl.fuse_street()
+        wl.build_map()
+        print(json.dumps({"net_roofline": net_rooflines(wl)}), flush=True)
+        return
     for i in range(args.warmup):
         st, npts = wl.step()
         torch.cuda.synchronize()
