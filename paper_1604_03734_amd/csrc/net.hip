@@ -1307,6 +1307,16 @@ __global__ __launch_bounds__(256) void k_wgrad1(const uint16_t *__restrict__ X, 
     }
 }
 
+// LDS rows of the layer-2 weight gradient.  Its X reads are 8-byte reads
+// by 16 channel rows x 4 lane groups whose runs are 64 entries (32 banks)
+// apart: a row stride of 2 banks modulo 64 (1924 entries) puts the 32 lanes
+// of each half-wave pass on 64 distinct banks.  dY rows of 1288 entries (4
+// banks modulo 64) keep its 16-byte reads conflict-free, and hold the 1280
+// entries the K steps cover (the compact rows' 1216 and zeros).
+constexpr int kXRow2 = 1924;
+constexpr int kDRow2 = 1288;
+constexpr int kRowVox2 = 1280;
+
 // Weight and bias gradient of layer 2 on MFMA (X = h1 channel-last on the
 // padded grid, dY = d2 channel-last on the compact rows, both turned
 // channel-first as they enter LDS):
@@ -1323,8 +1333,8 @@ template <int CI, int CO>
 __global__ __launch_bounds__(512) void k_wgrad_mfma(const uint16_t *__restrict__ X, const uint16_t *__restrict__ dY,
                                                     int64_t n, float *__restrict__ partials)
 {
-    __shared__ __align__(16) uint16_t sx[16 * kXRow];
-    __shared__ __align__(16) uint16_t sd[16 * kDRow];
+    __shared__ __align__(16) uint16_t sx[16 * kXRow2];
+    __shared__ __align__(16) uint16_t sd[16 * kDRow2];
     __shared__ float sb[512];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int i = lane & 15, g = lane >> 4;
@@ -1332,8 +1342,8 @@ __global__ __launch_bounds__(512) void k_wgrad_mfma(const uint16_t *__restrict__
     // offsets -1, 0, +1, one read for the three); waves 0..2 also tap
     // 24 + w of pair 8 (y and z offsets +1)
     const int ky = wave % 3 - 1, kz = wave / 3 - 1;
-    for (int k = tid; k < 16 * kXRow / 8; k += 512) reinterpret_cast<uint4 *>(sx)[k] = make_uint4(0, 0, 0, 0);
-    for (int k = tid; k < 16 * kDRow / 8; k += 512) reinterpret_cast<uint4 *>(sd)[k] = make_uint4(0, 0, 0, 0);
+    for (int k = tid; k < 16 * kXRow2 / 8; k += 512) reinterpret_cast<uint4 *>(sx)[k] = make_uint4(0, 0, 0, 0);
+    for (int k = tid; k < 16 * kDRow2 / 8; k += 512) reinterpret_cast<uint4 *>(sd)[k] = make_uint4(0, 0, 0, 0);
     v4f acc[4];
     for (int j = 0; j < 4; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
@@ -1358,19 +1368,21 @@ __global__ __launch_bounds__(512) void k_wgrad_mfma(const uint16_t *__restrict__
         for (int e = 0; e < kPer; ++e) {
             const int k = tid + 512 * e;
             if (k < CI * kXc) {
-                scatter8(sx + (k & 1) * 8 * kXRow + 8, kXRow, k >> 1, nxt[e]);
+                scatter8(sx + (k & 1) * 8 * kXRow2 + 8, kXRow2, k >> 1, nxt[e]);
             } else if (k < kChunks) {
                 const int kk = k - CI * kXc;
-                scatter8(sd + (kk & 1) * 8 * kDRow, kDRow, kk >> 1, nxt[e]);
+                scatter8(sd + (kk & 1) * 8 * kDRow2, kDRow2, kk >> 1, nxt[e]);
             }
         }
         __syncthreads();
         if (tile + gridDim.x < n) fetch(tile + gridDim.x);
-        for (int c = tid >> 4; c < kRowVox; c += 32) bsum += bf2f(sd[(tid & 15) * kDRow + c]);
-        const uint16_t *xrow = sx + i * kXRow;
-        for (int c0 = 0; c0 < kRowVox; c0 += 32) {
-            const int c = c0 + 8 * g;
-            const v8bf a = as_v8bf(*reinterpret_cast<const v4u *>(sd + i * kDRow + c));
+        for (int c = tid >> 4; c < kRowVox; c += 32) bsum += bf2f(sd[(tid & 15) * kDRow2 + c]);
+        const uint16_t *xrow = sx + i * kXRow2;
+        // K steps: runs of 8 entries 64 apart for the four lane groups
+        // (c = cb + j + 64 g over 1280 entries, the last 64 zero in dY)
+        for (int step = 0; step < kRowVox2 / 32; ++step) {
+            const int c = 256 * (step >> 3) + 8 * (step & 7) + 64 * g;
+            const v8bf a = as_v8bf(*reinterpret_cast<const v4u *>(sd + i * kDRow2 + c));
             const int plane = c / 120, within = c - 120 * plane;
             const int pc = 8 + within + 12 + 144 * (plane + 1);
             v4u bm, b0, bp;
