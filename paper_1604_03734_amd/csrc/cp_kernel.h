@@ -58,6 +58,32 @@ struct SBF16 {
     }
 };
 
+// Streaming accesses.  A block's f, w and u are read by that block alone
+// and every store of the iteration is read back only in the next one (from
+// HBM, the volume being far larger than the caches), whereas ubar, p and
+// the edge masks are also read by the neighbours as their halo.  Loading
+// the former and storing everything as non-temporal leaves the L2 for the
+// lines the neighbouring blocks will read.
+#ifndef DN_CP_NT
+#define DN_CP_NT 1
+#endif
+template <class T> __device__ __forceinline__ T ld_stream(const T *p)
+{
+#if DN_CP_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+template <class T> __device__ __forceinline__ void st_stream(T *p, T v)
+{
+#if DN_CP_NT
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 // Counter-based random bits of one voxel and iteration: an integer hash
 // (xor-shift / multiply rounds) of the global voxel index, a stream number
 // and the iteration seed.  Deterministic, so a run is reproducible and a
@@ -186,8 +212,8 @@ __device__ __forceinline__ void cp_load(const CPArgs<S> &A, int64_t b, CPRegs<NT
         R.ub[k] = S::ld(A.ubar_in[gi]);
         R.m[k] = A.emask[gi];
         R.p0[k] = S::ld(A.p_in[gi]); R.p1[k] = S::ld(A.p_in[gi + ps]); R.p2[k] = S::ld(A.p_in[gi + 2 * ps]);
-        R.uo[k] = S::ld(A.u[gi]);
-        R.fv[k] = A.f[gi]; R.wv[k] = A.w[gi];
+        R.uo[k] = S::ld(ld_stream(A.u + gi));
+        R.fv[k] = ld_stream(A.f + gi); R.wv[k] = ld_stream(A.w + gi);
     }
 #pragma unroll
     for (int k = 0; k < HPT; ++k) {
@@ -263,9 +289,9 @@ __device__ __forceinline__ void cp_compute(const CPArgs<S> &A, int64_t b, const 
             typename S::T s0 = S::sr(a0, r0), s1 = S::sr(a1, r0 >> 16), s2 = S::sr(a2, r1);
             const float b0 = S::ld(s0), b1 = S::ld(s1), b2 = S::ld(s2);
             if ((b0 * b0 + b1 * b1) + b2 * b2 > 1.0f) { s0 = S::rz(a0); s1 = S::rz(a1); s2 = S::rz(a2); }
-            A.p_out[gi] = s0; A.p_out[gi + ps] = s1; A.p_out[gi + 2 * ps] = s2;
+            st_stream(A.p_out + gi, s0); st_stream(A.p_out + gi + ps, s1); st_stream(A.p_out + gi + 2 * ps, s2);
         } else {
-            A.p_out[gi] = a0; A.p_out[gi + ps] = a1; A.p_out[gi + 2 * ps] = a2;
+            st_stream(A.p_out + gi, a0); st_stream(A.p_out + gi + ps, a1); st_stream(A.p_out + gi + 2 * ps, a2);
         }
         if (kRefine) { A.p32[gi] = a0; A.p32[gi + ps] = a1; A.p32[gi + 2 * ps] = a2; }
     }
@@ -311,11 +337,11 @@ __device__ __forceinline__ void cp_compute(const CPArgs<S> &A, int64_t b, const 
         float ubn = un + A.theta * (un - R.uo[k]);
         if constexpr (S::kLow) {
             const uint32_t r2 = voxel_bits(gi, 2, A.seed);
-            A.u[gi] = S::sr(un, r2);
-            A.ubar_out[gi] = S::sr(ubn, r2 >> 16);
+            st_stream(A.u + gi, S::sr(un, r2));
+            st_stream(A.ubar_out + gi, S::sr(ubn, r2 >> 16));
         } else {
-            A.u[gi] = un;
-            A.ubar_out[gi] = ubn;
+            st_stream(A.u + gi, un);
+            st_stream(A.ubar_out + gi, ubn);
         }
         if (kRefine) { A.u32[gi] = un; A.ubar32[gi] = ubn; }
     }
