@@ -163,7 +163,7 @@ __device__ __forceinline__ void halo_pos(int t, int &x, int &y, int &z)
     }
 }
 
-// -1 face voxel t < 192: face 0 (-x), 1 (-y), 2 (-z)
+// -1 face voxel e < 192: face 0 (-x), 1 (-y), 2 (-z)
 __device__ __forceinline__ void face_pos(int t, int &x, int &y, int &z)
 {
     int f = t >> 6, i = t & 63, a = i & 7, b = i >> 3;
@@ -186,16 +186,17 @@ __device__ __forceinline__ void project(float &a, float &b, float &c)
 
 // Per-thread registers of one block's iteration: the thread's own voxels
 // (VPT = 512 / NT of them), its share of the ubar halo (432 voxels: six
-// faces and the six (-a, +b) edges) and, for t < 192, one voxel of the -1
-// faces (its edge mask and the three dual components).
+// faces and the six (-a, +b) edges) and its share of the 192 voxels of the
+// -1 faces (their edge masks and the three dual components).
 template <int NT> struct CPRegs {
     static constexpr int VPT = kBlockVox / NT;
     static constexpr int HPT = (432 + NT - 1) / NT;
+    static constexpr int FPT = (192 + NT - 1) / NT;
     float ub[VPT], p0[VPT], p1[VPT], p2[VPT], uo[VPT], fv[VPT], wv[VPT];
     uint8_t m[VPT];
     float hu[HPT];
-    float h0, h1, h2;
-    uint8_t hm;
+    float h0[FPT], h1[FPT], h2[FPT];
+    uint8_t hm[FPT];
 };
 
 // Global loads of one block's iteration (issued; used by cp_compute).
@@ -226,15 +227,19 @@ __device__ __forceinline__ void cp_load(const CPArgs<S> &A, int64_t b, CPRegs<NT
             if (j >= 0) R.hu[k] = S::ld(A.ubar_in[j]);
         }
     }
-    R.h0 = R.h1 = R.h2 = 0.f;
-    R.hm = 0;
-    if (t < 192) {
-        int fx, fy, fz;
-        face_pos(t, fx, fy, fz);
-        int64_t j = halo_index(nb27, fx, fy, fz);
-        if (j >= 0) {
-            R.hm = A.emask[j];
-            R.h0 = S::ld(A.p_in[j]); R.h1 = S::ld(A.p_in[j + ps]); R.h2 = S::ld(A.p_in[j + 2 * ps]);
+#pragma unroll
+    for (int k = 0; k < CPRegs<NT>::FPT; ++k) {
+        const int e = t + k * NT;
+        R.h0[k] = R.h1[k] = R.h2[k] = 0.f;
+        R.hm[k] = 0;
+        if (e < 192) {
+            int fx, fy, fz;
+            face_pos(e, fx, fy, fz);
+            int64_t j = halo_index(nb27, fx, fy, fz);
+            if (j >= 0) {
+                R.hm[k] = A.emask[j];
+                R.h0[k] = S::ld(A.p_in[j]); R.h1[k] = S::ld(A.p_in[j + ps]); R.h2[k] = S::ld(A.p_in[j + 2 * ps]);
+            }
         }
     }
 }
@@ -263,10 +268,14 @@ __device__ __forceinline__ void cp_compute(const CPArgs<S> &A, int64_t b, const 
             sh.u[i10(hx, hy, hz)] = R.hu[k];
         }
     }
-    int fx = 0, fy = 0, fz = 0;
-    if (t < 192) {
-        face_pos(t, fx, fy, fz);
-        sh.m[i9(fx, fy, fz)] = R.hm;
+#pragma unroll
+    for (int k = 0; k < CPRegs<NT>::FPT; ++k) {
+        const int e = t + k * NT;
+        if (e < 192) {
+            int fx, fy, fz;
+            face_pos(e, fx, fy, fz);
+            sh.m[i9(fx, fy, fz)] = R.hm[k];
+        }
     }
     __syncthreads();
 
@@ -296,16 +305,22 @@ __device__ __forceinline__ void cp_compute(const CPArgs<S> &A, int64_t b, const 
         if (kRefine) { A.p32[gi] = a0; A.p32[gi + ps] = a1; A.p32[gi + 2 * ps] = a2; }
     }
     // ... and on the -1 faces, which the divergence needs
-    if (t < 192) {
-        const uint8_t hm = R.hm;
-        float uh = sh.u[i10(fx, fy, fz)];
-        float g0 = (hm & 2) ? sh.u[i10(fx + 1, fy, fz)] - uh : 0.0f;
-        float g1 = (hm & 4) ? sh.u[i10(fx, fy + 1, fz)] - uh : 0.0f;
-        float g2 = (hm & 8) ? sh.u[i10(fx, fy, fz + 1)] - uh : 0.0f;
-        float h0 = R.h0 + A.sigma * g0, h1 = R.h1 + A.sigma * g1, h2 = R.h2 + A.sigma * g2;
-        project(h0, h1, h2);
-        const int q = i9(fx, fy, fz);
-        sh.p[0][q] = h0; sh.p[1][q] = h1; sh.p[2][q] = h2;
+#pragma unroll
+    for (int k = 0; k < CPRegs<NT>::FPT; ++k) {
+        const int e = t + k * NT;
+        if (e < 192) {
+            int fx, fy, fz;
+            face_pos(e, fx, fy, fz);
+            const uint8_t hm = R.hm[k];
+            float uh = sh.u[i10(fx, fy, fz)];
+            float g0 = (hm & 2) ? sh.u[i10(fx + 1, fy, fz)] - uh : 0.0f;
+            float g1 = (hm & 4) ? sh.u[i10(fx, fy + 1, fz)] - uh : 0.0f;
+            float g2 = (hm & 8) ? sh.u[i10(fx, fy, fz + 1)] - uh : 0.0f;
+            float h0 = R.h0[k] + A.sigma * g0, h1 = R.h1[k] + A.sigma * g1, h2 = R.h2[k] + A.sigma * g2;
+            project(h0, h1, h2);
+            const int q = i9(fx, fy, fz);
+            sh.p[0][q] = h0; sh.p[1][q] = h1; sh.p[2][q] = h2;
+        }
     }
     __syncthreads();
 
