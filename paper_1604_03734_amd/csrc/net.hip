@@ -247,46 +247,17 @@ __global__ void k_gather(const int32_t *__restrict__ nbr, const float *__restric
 // Number of mask entries set: workgroup g sums its 4096-entry chunk in a
 // fixed order (thread-strided, then a tree) into part[g]; then one
 // workgroup sums the parts in order.
-__global__ void k_mask_part(const float *__restrict__ mask, int64_t n, double *__restrict__ part)
-{
-    __shared__ double s[256];
-    const int64_t base = int64_t(blockIdx.x) * 4096;
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < 4096; k += 256)
-        if (base + k < n) acc += mask[base + k];
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
-}
-
-__global__ void k_mask_count(const double *__restrict__ part, int64_t nparts, double *__restrict__ out)
-{
-    __shared__ double s[256];
-    double acc = 0.0;
-    for (int64_t k = threadIdx.x; k < nparts; k += 256) acc += part[k];
-    s[threadIdx.x] = acc;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = s[0];
-}
-
 // The gradient of all 8241 parameters from the per-workgroup partials of
 // the three layers (parts[layer][p][27 * 256 + 16]), written to the
-// canonical parameter layout.  The sum over p has a fixed order: a
+// canonical parameter layout and scaled by inv_n[0] (the partials are of
+// the unnormalised loss: every entry is linear in d3).  The sum over p has a fixed order: a
 // workgroup takes 32 consecutive partial entries (contiguous reads across
 // its threads), its 8 thread groups add consecutive eighths of the
 // partials (each in order, eight loads in flight), then the eight group
 // sums are added in group order.
 constexpr int kFinalEntries = 32, kFinalGroups = 8;
 __global__ __launch_bounds__(256) void k_grad_final(const float *__restrict__ parts, int nparts,
-                                                    float *__restrict__ grad)
+                                                    const double *__restrict__ inv_n, float *__restrict__ grad)
 {
     __shared__ float sg[kFinalGroups][kFinalEntries];
     const int el = threadIdx.x % kFinalEntries, grp = threadIdx.x / kFinalEntries;
@@ -313,6 +284,7 @@ __global__ __launch_bounds__(256) void k_grad_final(const float *__restrict__ pa
     if (grp != 0 || !live) return;
     float sum = sg[0][el];
     for (int q = 1; q < kFinalGroups; ++q) sum += sg[q][el];
+    sum = float(double(sum) * inv_n[0]);
     const int cout = layer == 2 ? 1 : 16, cin = layer == 0 ? 2 : 16;
     const int wbase = layer == 0 ? kW1 : (layer == 1 ? kW2 : kW3);
     const int bbase = layer == 0 ? kB1 : (layer == 1 ? kB2 : kB3);
@@ -325,18 +297,33 @@ __global__ __launch_bounds__(256) void k_grad_final(const float *__restrict__ pa
     }
 }
 
-__global__ void k_sum_loss(const double *__restrict__ tl, int64_t n, double *__restrict__ out)
+// The loss and its normaliser from the per-tile sums, in a fixed order:
+// out[0] = sum of squared errors / N, out[1] = 1 / N, N = max(1, sum of the
+// mask).
+__global__ void k_sum_loss(const double *__restrict__ tl, const double *__restrict__ tc, int64_t n,
+                           double *__restrict__ out)
 {
-    __shared__ double s[256];
-    double acc = 0.0;
-    for (int64_t k = threadIdx.x; k < n; k += 256) acc += tl[k];
+    __shared__ double s[256], c[256];
+    double acc = 0.0, cnt = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += 256) {
+        acc += tl[k];
+        cnt += tc[k];
+    }
     s[threadIdx.x] = acc;
+    c[threadIdx.x] = cnt;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        if (threadIdx.x < h) {
+            s[threadIdx.x] += s[threadIdx.x + h];
+            c[threadIdx.x] += c[threadIdx.x + h];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = s[0];
+    if (threadIdx.x == 0) {
+        const double N = c[0] > 1.0 ? c[0] : 1.0;
+        out[0] = s[0] / N;
+        out[1] = 1.0 / N;
+    }
 }
 
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
@@ -417,8 +404,7 @@ struct NetWS {
     // training step (dn_net_loss_grad)
     uint16_t *lanew, *lanef, *gates, *x1cf, *h1cf, *h2cf, *d3cf, *d2cf, *d1cf;
     float *rc, *d3, *parts;
-    double *misc, *tl, *mparts;
-    int64_t nmask;
+    double *misc, *tl, *tc;
     int nparts;
 };
 constexpr int kMaxWgradGroups = 256;
@@ -449,8 +435,7 @@ static NetWS carve_net(Bump &b, int64_t n, bool training)
     x.parts = b.take<float>(size_t(3) * x.nparts * (kWPack + kC));
     x.misc = b.take<double>(8);
     x.tl = b.take<double>(size_t(n));
-    x.nmask = (n * 512 + 4095) / 4096;
-    x.mparts = b.take<double>(size_t(x.nmask));
+    x.tc = b.take<double>(size_t(n));
     return x;
 }
 
@@ -895,33 +880,40 @@ __device__ __forceinline__ bool row_voxel(int c, int &x, int &y, int &z)
 }
 
 // Masked squared loss of one tile per workgroup (512 threads, one per
-// centre voxel): d3 = dL/dr on the centre (float [n][512]) and the same in
-// the compact-row layout for the weight gradient of layer 3 (d3cf [n][1216],
-// bfloat16, zero off the centre).
+// centre voxel), before the division by N = max(1, sum of the mask), which
+// k_sum_loss forms and k_grad_final applies: d3 = N dL/dr on the centre
+// (float [n][512]) and the same in the compact-row layout for the weight
+// gradient of layer 3 (d3cf [n][1216], bfloat16, zero off the centre), the
+// tile's sum of squared errors and of the mask.
 __global__ __launch_bounds__(512) void k_loss_train(const float *__restrict__ tiles, const float *__restrict__ R,
                                                     const float *__restrict__ targets, const float *__restrict__ mask,
-                                                    const double *__restrict__ count, int64_t n, int kind,
-                                                    float *__restrict__ d3, uint16_t *__restrict__ d3cf,
-                                                    double *__restrict__ tile_loss)
+                                                    int64_t n, int kind, float *__restrict__ d3,
+                                                    uint16_t *__restrict__ d3cf, double *__restrict__ tile_loss,
+                                                    double *__restrict__ tile_count)
 {
-    __shared__ double sl[8];
+    __shared__ double sl[8], sc[8];
     __shared__ uint16_t sg[kT];
     const int64_t tile = blockIdx.x;
     const int v = threadIdx.x;
-    const double N = count[0] > 1.0 ? count[0] : 1.0;
     const int cx = v & 7, cy = (v >> 3) & 7, cz = v >> 6;
     const int tv = (cx + 1) + 10 * (cy + 1) + 100 * (cz + 1);
     const double m = mask[tile * 512 + v];
     const double e = (kind == 0 ? double(tiles[tile * 2 * kT + tv]) : 0.0) + double(R[tile * 512 + v]) -
                      double(targets[tile * 512 + v]);
-    double l = m != 0.0 ? e * e / N : 0.0;
-    const float gv = m != 0.0 ? float(2.0 * e / N) : 0.f;
+    double l = m != 0.0 ? e * e : 0.0, c = m;
+    const float gv = m != 0.0 ? float(2.0 * e) : 0.f;
     d3[tile * 512 + v] = gv;
     for (int k = v; k < kT; k += 512) sg[k] = 0;
     __syncthreads();
     sg[tv] = f2bf(gv);
-    for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o, 64);
-    if ((v & 63) == 0) sl[v >> 6] = l;
+    for (int o = 32; o > 0; o >>= 1) {
+        l += __shfl_xor(l, o, 64);
+        c += __shfl_xor(c, o, 64);
+    }
+    if ((v & 63) == 0) {
+        sl[v >> 6] = l;
+        sc[v >> 6] = c;
+    }
     __syncthreads();
     uint16_t *dst = d3cf + tile * kRowVox;
     for (int k = v; k < kRowVox; k += 512) {
@@ -931,9 +923,13 @@ __global__ __launch_bounds__(512) void k_loss_train(const float *__restrict__ ti
         dst[k] = val;
     }
     if (v == 0) {
-        double s = 0.0;
-        for (int k = 0; k < 8; ++k) s += sl[k];
+        double s = 0.0, t = 0.0;
+        for (int k = 0; k < 8; ++k) {
+            s += sl[k];
+            t += sc[k];
+        }
         tile_loss[tile] = s;
+        tile_count[tile] = t;
     }
 }
 
@@ -1561,12 +1557,10 @@ int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const f
                        int64_t(0), ws.rc, ws.x1cf, ws.h1cf, ws.h2cf, ws.gates);
     DN_HIP(hipGetLastError());
     // loss and its gradient on the centre
-    double *cnt = ws.misc, *lsum = cnt + 1;
-    hipLaunchKernelGGL(k_mask_part, dim3(unsigned(ws.nmask)), dim3(256), 0, st, mask, n * 512, ws.mparts);
-    hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(256), 0, st, ws.mparts, ws.nmask, cnt);
-    hipLaunchKernelGGL(k_loss_train, dim3(unsigned(n)), dim3(512), 0, st, tiles, ws.rc, targets, mask, cnt, n,
-                       int(kind), ws.d3, ws.d3cf, ws.tl);
-    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, st, ws.tl, n, lsum);
+    double *lsum = ws.misc;   // [0] loss, [1] 1 / N
+    hipLaunchKernelGGL(k_loss_train, dim3(unsigned(n)), dim3(512), 0, st, tiles, ws.rc, targets, mask, n, int(kind),
+                       ws.d3, ws.d3cf, ws.tl, ws.tc);
+    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, st, ws.tl, ws.tc, n, lsum);
     DN_HIP(hipGetLastError());
     // input gradients of layers 3 and 2
     hipLaunchKernelGGL(k_net_bwd, dim3(grid2), dim3(256), 0, st, ws.d3, ws.gates, n, ws.lanef, params, ws.d2cf,
@@ -1579,7 +1573,7 @@ int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const f
     hipLaunchKernelGGL((k_wgrad_mfma<16, 16>), dim3(gw), dim3(512), 0, st, ws.h1cf, ws.d2cf, n, ws.parts + lp);
     hipLaunchKernelGGL(k_wgrad3, dim3(gw), dim3(256), 0, st, ws.h2cf, ws.d3cf, n, ws.parts + 2 * lp);
     hipLaunchKernelGGL(k_grad_final, dim3((3 * (kWPack + kC) + kFinalEntries - 1) / kFinalEntries), dim3(256), 0, st,
-                       ws.parts, ws.nparts, grad);
+                       ws.parts, ws.nparts, lsum + 1, grad);
     DN_HIP(hipGetLastError());
     if (loss_host) {
         double h = 0.0;
