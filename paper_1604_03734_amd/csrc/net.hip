@@ -249,17 +249,45 @@ __global__ void k_gather(const int32_t *__restrict__ nbr, const float *__restric
 // workgroup sums the parts in order.
 // The gradient of all 8241 parameters from the per-workgroup partials of
 // the three layers (parts[layer][p][27 * 256 + 16]), written to the
-// canonical parameter layout and scaled by inv_n[0] (the partials are of
-// the unnormalised loss: every entry is linear in d3).  The sum over p has a fixed order: a
+// canonical parameter layout and scaled by 1 / N (the partials are of the
+// loss before its division by N: every entry is linear in d3).  The sum over p has a fixed order: a
 // workgroup takes 32 consecutive partial entries (contiguous reads across
 // its threads), its 8 thread groups add consecutive eighths of the
 // partials (each in order, eight loads in flight), then the eight group
 // sums are added in group order.
 constexpr int kFinalEntries = 32, kFinalGroups = 8;
 __global__ __launch_bounds__(256) void k_grad_final(const float *__restrict__ parts, int nparts,
-                                                    const double *__restrict__ inv_n, float *__restrict__ grad)
+                                                    const double *__restrict__ tile_loss,
+                                                    const double *__restrict__ tile_count, int64_t ntiles,
+                                                    double *__restrict__ loss, float *__restrict__ grad)
 {
     __shared__ float sg[kFinalGroups][kFinalEntries];
+    __shared__ double sl[256], sc[256];
+    // N = max(1, sum of the mask) and the loss, the same fixed-order sums
+    // in every workgroup; workgroup 0 writes loss[0] = squared errors / N,
+    // loss[1] = 1 / N
+    {
+        double l = 0.0, c = 0.0;
+        for (int64_t k = threadIdx.x; k < ntiles; k += 256) {
+            l += tile_loss[k];
+            c += tile_count[k];
+        }
+        sl[threadIdx.x] = l;
+        sc[threadIdx.x] = c;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                sl[threadIdx.x] += sl[threadIdx.x + h];
+                sc[threadIdx.x] += sc[threadIdx.x + h];
+            }
+            __syncthreads();
+        }
+    }
+    const double N = sc[0] > 1.0 ? sc[0] : 1.0, inv_n = 1.0 / N;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        loss[0] = sl[0] / N;
+        loss[1] = inv_n;
+    }
     const int el = threadIdx.x % kFinalEntries, grp = threadIdx.x / kFinalEntries;
     const int k = blockIdx.x * kFinalEntries + el;
     const bool live = k < 3 * (kWPack + kC);
@@ -284,7 +312,7 @@ __global__ __launch_bounds__(256) void k_grad_final(const float *__restrict__ pa
     if (grp != 0 || !live) return;
     float sum = sg[0][el];
     for (int q = 1; q < kFinalGroups; ++q) sum += sg[q][el];
-    sum = float(double(sum) * inv_n[0]);
+    sum = float(double(sum) * inv_n);
     const int cout = layer == 2 ? 1 : 16, cin = layer == 0 ? 2 : 16;
     const int wbase = layer == 0 ? kW1 : (layer == 1 ? kW2 : kW3);
     const int bbase = layer == 0 ? kB1 : (layer == 1 ? kB2 : kB3);
@@ -294,35 +322,6 @@ __global__ __launch_bounds__(256) void k_grad_final(const float *__restrict__ pa
     } else {
         const int co = idx - kWPack;
         if (co < cout) grad[bbase + co] = sum;
-    }
-}
-
-// The loss and its normaliser from the per-tile sums, in a fixed order:
-// out[0] = sum of squared errors / N, out[1] = 1 / N, N = max(1, sum of the
-// mask).
-__global__ void k_sum_loss(const double *__restrict__ tl, const double *__restrict__ tc, int64_t n,
-                           double *__restrict__ out)
-{
-    __shared__ double s[256], c[256];
-    double acc = 0.0, cnt = 0.0;
-    for (int64_t k = threadIdx.x; k < n; k += 256) {
-        acc += tl[k];
-        cnt += tc[k];
-    }
-    s[threadIdx.x] = acc;
-    c[threadIdx.x] = cnt;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
-            s[threadIdx.x] += s[threadIdx.x + h];
-            c[threadIdx.x] += c[threadIdx.x + h];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double N = c[0] > 1.0 ? c[0] : 1.0;
-        out[0] = s[0] / N;
-        out[1] = 1.0 / N;
     }
 }
 
@@ -881,7 +880,7 @@ __device__ __forceinline__ bool row_voxel(int c, int &x, int &y, int &z)
 
 // Masked squared loss of one tile per workgroup (512 threads, one per
 // centre voxel), before the division by N = max(1, sum of the mask), which
-// k_sum_loss forms and k_grad_final applies: d3 = N dL/dr on the centre
+// k_grad_final forms and applies: d3 = N dL/dr on the centre
 // (float [n][512]) and the same in the compact-row layout for the weight
 // gradient of layer 3 (d3cf [n][1216], bfloat16, zero off the centre), the
 // tile's sum of squared errors and of the mask.
@@ -1557,10 +1556,9 @@ int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const f
                        int64_t(0), ws.rc, ws.x1cf, ws.h1cf, ws.h2cf, ws.gates);
     DN_HIP(hipGetLastError());
     // loss and its gradient on the centre
-    double *lsum = ws.misc;   // [0] loss, [1] 1 / N
+    double *lsum = ws.misc;   // [0] loss, [1] 1 / N (written by k_grad_final)
     hipLaunchKernelGGL(k_loss_train, dim3(unsigned(n)), dim3(512), 0, st, tiles, ws.rc, targets, mask, n, int(kind),
                        ws.d3, ws.d3cf, ws.tl, ws.tc);
-    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, st, ws.tl, ws.tc, n, lsum);
     DN_HIP(hipGetLastError());
     // input gradients of layers 3 and 2
     hipLaunchKernelGGL(k_net_bwd, dim3(grid2), dim3(256), 0, st, ws.d3, ws.gates, n, ws.lanef, params, ws.d2cf,
@@ -1573,7 +1571,7 @@ int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const f
     hipLaunchKernelGGL((k_wgrad_mfma<16, 16>), dim3(gw), dim3(512), 0, st, ws.h1cf, ws.d2cf, n, ws.parts + lp);
     hipLaunchKernelGGL(k_wgrad3, dim3(gw), dim3(256), 0, st, ws.h2cf, ws.d3cf, n, ws.parts + 2 * lp);
     hipLaunchKernelGGL(k_grad_final, dim3((3 * (kWPack + kC) + kFinalEntries - 1) / kFinalEntries), dim3(256), 0, st,
-                       ws.parts, ws.nparts, lsum + 1, grad);
+                       ws.parts, ws.nparts, ws.tl, ws.tc, n, lsum, grad);
     DN_HIP(hipGetLastError());
     if (loss_host) {
         double h = 0.0;
