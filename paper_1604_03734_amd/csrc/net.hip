@@ -385,7 +385,7 @@ static inline unsigned grid1(int64_t n, int bs = 256) { return unsigned((n + bs 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
-constexpr int kL1M = 2;       // layer 1: 27 taps x 2 channels = 54 of 64 K slots
+constexpr int kL1M = 3;       // layer 1: per lane group a (y, z) tap pair, its 3 x taps + 1 zero slot x 2 channels
 constexpr int kL2M = 14;      // layer 2: 27 taps x 16 channels, two taps per MFMA
 constexpr int kL3M = 2;       // layer 3: rows = the 9 (y, z) tap pairs, K = 3 x taps x 16 channels
 // layer 1 runs on the weight pair hi + lo (bfloat16(W) and bfloat16(W -
@@ -455,8 +455,8 @@ __device__ void pack_lane(const float *__restrict__ params, int k, uint16_t *__r
     float val = 0.f;
     if (m < kL1M || m >= kL1M + kL2M + kL3M) {
         const int ml = m < kL1M ? m : m - (kL1M + kL2M + kL3M);
-        const int t = 16 * ml + 4 * g + (j >> 1), ci = j & 1;
-        if (t < kTaps) val = params[kW1 + (n * 2 + ci) * kTaps + t];
+        const int pr = 4 * ml + g, e = j >> 1, ci = j & 1;   // (y, z) pair, x slot, channel
+        if (pr < 9 && e < 3) val = params[kW1 + (n * 2 + ci) * kTaps + e + 3 * pr];
         if (m >= kL1M) val -= bf2f(f2bf(val));
     } else if (m < kL1M + kL2M) {
         const int t = 2 * (m - kL1M) + (g >> 1), ci = 8 * (g & 1) + j;
@@ -642,7 +642,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 {
     __shared__ __align__(16) uint16_t h1[2 * kPlane / 2];
     __shared__ __align__(16) uint16_t h2[2 * kPlane / 2];
-    __shared__ __align__(16) uint32_t x0[kT + 4];
+    __shared__ __align__(16) uint32_t x0[kPadVox + 4];   // layer-1 input words on the zero-bordered 12^3 grid
+                                                        // (+ the last x slot of the last voxel)
     __shared__ uint32_t okt[kMT * 16];   // tap masks of the tile voxels (0 past the tile)
     __shared__ uint16_t vt[kMT * 16];    // voxel of each (row tile, lane column)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -681,7 +682,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const float bias3 = params[kB3];
     __builtin_amdgcn_s_waitcnt(0);
     if (tid < 8) reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(h1) + (tid >> 2) * kPlane + kT * 16)[tid & 3] = 0u;
-    if (tid == 0) x0[kT] = 0u;
+    for (int k = tid; k < kPadVox + 4; k += 256) x0[k] = 0u;
 
     // the layer-1 input of a tile, read from the pool's pair words through
     // the neighbour table (tile voxels of unallocated blocks give 0), the
@@ -715,26 +716,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
     for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
         for (int e = 0; e < kGet; ++e)
-            if (tid + 256 * e < kT) x0[tid + 256 * e] = nxt[e];
+            if (tid + 256 * e < kT) {
+                const int k = tid + 256 * e;
+                x0[pad_index(k % 10, (k / 10) % 10, k / 100)] = nxt[e];
+            }
         __syncthreads();
         const int64_t bn = b + gridDim.x;
         if (bn < nb) fetch(bn);
 
-        // layer 1: 2 -> 16, ReLU
+        // layer 1: 2 -> 16, ReLU.  Lane group g of MFMA m takes the (y, z)
+        // tap pair 4m + g: the input words of its x taps -1, 0, +1 (and +2,
+        // whose weights are zero) are 4 consecutive words of the padded
+        // grid, zero wherever the tap leaves the tile.
         for (int mt = wave; mt < kMT; mt += 4) {
             const int v = vt[mt * 16 + i];
-            const uint32_t ok = mt < 32 ? 0x7FFFFFFu : okt[v];
-            v4u q[kL1M];
-            for (int m = 0; m < kL1M; ++m)
-                for (int e = 0; e < 4; ++e) {
-                    const int t = 16 * m + 4 * g + e;
-                    const int o = (t % 3 - 1) + 10 * ((t / 3) % 3 - 1) + 100 * (t / 9 - 1);
-                    q[m][e] = x0[t < kTaps && ((ok >> t) & 1u) ? v + o : kT];
-                }
+            const int pv = v < kT ? pad_index(v % 10, (v / 10) % 10, v / 100) : pad_index(0, 0, 0);
             v4f acc = {0.f, 0.f, 0.f, 0.f};
             for (int m = 0; m < kL1M; ++m) {
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W1[m], as_v8bf(q[m]), acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W1l[m], as_v8bf(q[m]), acc, 0, 0, 0);
+                const int pr = 4 * m + g;
+                const int at = pr < 9 ? pv - 1 + 12 * (pr % 3 - 1) + 144 * (pr / 3 - 1) : 0;
+                const v4u q = {x0[at], x0[at + 1], x0[at + 2], x0[at + 3]};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W1[m], as_v8bf(q), acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W1l[m], as_v8bf(q), acc, 0, 0, 0);
             }
             store_act(h1, v, g, acc, bias1);
         }
@@ -746,11 +749,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             gate_bits(h1, gates + b * (2 * kT), tid);
             for (int e = tid; e < 2 * kPadVox; e += 256) {
                 const int ch = e / kPadVox, p = e - ch * kPadVox;
-                const int x = p % 12 - 1, y = (p / 12) % 12 - 1, z = p / 144 - 1;
-                uint16_t val = 0;
-                if (x >= 0 && x < 10 && y >= 0 && y < 10 && z >= 0 && z < 10)
-                    val = uint16_t(x0[x + 10 * y + 100 * z] >> (16 * ch));
-                x1cf[b * (2 * kPadVox) + e] = val;
+                x1cf[b * (2 * kPadVox) + e] = uint16_t(x0[p] >> (16 * ch));
             }
         }
 
