@@ -342,7 +342,7 @@ int dn_mesh_area(dn_volume *vol, double *area_host, int64_t *n_tris_host);
  * u0 = clamp(f + r, -1, 1) on Omega.  Parameters are 8241 float32 values:
  * W1[16][2][27] b1[16] W2[16][16][27] b2[16] W3[1][16][27] b3[1], tap
  * (dz*3 + dy)*3 + dx.  Convolutions run on MFMA in bfloat16 with float32
- * accumulation. */
+ * accumulation (the layer-1 weights as the pair bf16(W) + bf16(W - bf16(W))). */
 #define DN_NET_PARAMS 8241
 
 /* Gather the input tiles of the listed blocks: float [n][2][10][10][10]

@@ -228,6 +228,21 @@ __global__ void k_append(const uint64_t *__restrict__ newk, int64_t n_new, int64
     coords[4 * b + 0] = x; coords[4 * b + 1] = y; coords[4 * b + 2] = z; coords[4 * b + 3] = 0;
 }
 
+// The per-voxel fields of blocks [first, first + count) in several arrays
+// at once (the new blocks of an allocation: f, w, u, both ubar and both
+// sets of dual planes), one launch instead of one per array.
+struct FieldSet {
+    float *a[16];
+    int n;
+};
+__global__ void k_zero_fields(FieldSet fs, int64_t first, int64_t count)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count * kBlockVox) return;
+    const int64_t off = first * kBlockVox + i;
+    for (int k = 0; k < fs.n; ++k) fs.a[k][off] = 0.f;
+}
+
 __global__ void k_zero_blocks(float *__restrict__ a, int64_t first, int64_t count)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -398,17 +413,13 @@ static int insert_packed(dn_volume *v, uint64_t *cand, int64_t n_cand, int32_t *
     }
     // 5) commit: new table, zeroed fields of the new blocks, neighbours
     v->cur_hash = other;
+    FieldSet fs{};
     float *fields[] = {v->f, v->w, v->u, v->ubar[0], v->ubar[1]};
-    for (float *a : fields) {
-        hipLaunchKernelGGL(k_zero_blocks, dim3(grid1(n_new * kBlockVox)), dim3(256), 0, st, a, nb_old, n_new);
-        DN_HIP(hipGetLastError());
-    }
+    for (float *a : fields) fs.a[fs.n++] = a;
     for (int pp = 0; pp < 2; ++pp)
-        for (int a = 0; a < 3; ++a) {
-            hipLaunchKernelGGL(k_zero_blocks, dim3(grid1(n_new * kBlockVox)), dim3(256), 0, st,
-                               v->p[pp] + size_t(a) * v->cap_blocks * kBlockVox, nb_old, n_new);
-            DN_HIP(hipGetLastError());
-        }
+        for (int a = 0; a < 3; ++a) fs.a[fs.n++] = v->p[pp] + size_t(a) * v->cap_blocks * kBlockVox;
+    hipLaunchKernelGGL(k_zero_fields, dim3(grid1(n_new * kBlockVox)), dim3(256), 0, st, fs, nb_old, n_new);
+    DN_HIP(hipGetLastError());
     v->nb = nb_new;
     v->emask_nb = -1;
     v->state_storage = DN_F32;
