@@ -444,11 +444,17 @@ def x1_mixed_precision(wl, fp32_ms, iters=100):
     u = np.zeros_like(ov.f); ub = np.zeros_like(u); p = np.zeros((3,) + u.shape)
     oracle.cp(ov.nbr, ov.f, ov.w, u, ub, p, 200, 0.5, 12 ** -0.5, 12 ** -0.5, 1.0)
     om = ov.w > 0
+    band = om & (np.abs(u) < 1.0)          # the TSDF band, away from the truncation
+    E, Dd = oracle.energy(ov.nbr, ov.f, ov.w, u, p, 0.5)
     for name, s in (("f32", D.DN_F32), ("f16", D.DN_F16), ("bf16", D.DN_BF16)):
-        gv.regularize(D.reg_params(0.5, iters=200, storage=s, refine_every=50))
-        e = np.abs(gv.extract(D.DN_X_U).cpu().numpy().astype(np.float64) - u)[om]
-        out.setdefault(name, {})["error_vs_oracle"] = {"max": float(e.max()), "median": float(np.median(e)),
-                                                       "scene": "small scene (4 maps 320x96), 200 iterations"}
+        st = gv.regularize(D.reg_params(0.5, iters=200, storage=s, refine_every=50))
+        err = np.abs(gv.extract(D.DN_X_U).cpu().numpy().astype(np.float64) - u)
+        e, eb = err[om], err[band]
+        out.setdefault(name, {})["error_vs_oracle"] = {
+            "max": float(e.max()), "median": float(np.median(e)),
+            "band_max": float(eb.max()), "band_median": float(np.median(eb)),
+            "rel_gap": float(st.rel_gap), "oracle_rel_gap": float((E - Dd) / E),
+            "scene": "small scene (4 maps 320x96), 200 iterations; band: voxels of Omega with |u| < 1"}
     gv.close()
     return out
 
@@ -677,6 +683,14 @@ def main():
                      "avg_launch_ms": kern_ms},
         "cp_voxel_iters_per_s": nvox / (kern_ms / 1000.0),
     }
+    if traffic is not None:
+        # bytes leaving L2 per launch (rocprofv3 counters) over the live launch time
+        line["roofline"]["traffic_gbs"] = traffic / (kern_ms / 1000.0) / 1e9
+    if args.workload == "street":
+        # the same rate per observed voxel (Omega: w > 0)
+        n_omega = int((wl.big.extract(D.DN_X_W) > 0).sum().item())
+        line["omega_voxels"] = n_omega
+        line["cp_omega_voxel_iters_per_s"] = n_omega / (kern_ms / 1000.0)
     if args.workload == "batched":
         line["config"]["kernel_used"] = {"threads": 256 if st.kernel_used // 100 == 257 else st.kernel_used // 100,
                                          "lean": st.kernel_used // 100 == 257,
