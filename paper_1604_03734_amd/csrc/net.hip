@@ -132,39 +132,6 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, in
     }
 }
 
-// First level of the partial reduction: chunk c of the partials (parts
-// [c*per, (c+1)*per)) summed in order, per entry, into out[c][...].
-__global__ void k_sum_parts(const float *__restrict__ partials, int nparts, int per, float *__restrict__ out)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (k >= kWPack + kC) return;
-    float s = 0.f;
-    const int p1 = min(nparts, (c + 1) * per);
-    for (int p = c * per; p < p1; ++p) s += partials[int64_t(p) * (kWPack + kC) + k];
-    out[int64_t(c) * (kWPack + kC) + k] = s;
-}
-
-// Sum the per-workgroup partials (fixed order) into the canonical parameter
-// layout W[co][ci][tap], b[co] of a layer with cout x cin real channels.
-__global__ void k_grad_reduce(const float *__restrict__ partials, int nparts, int cout, int cin,
-                              float *__restrict__ gW, float *__restrict__ gb)
-{
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nw = cout * cin * kTaps;
-    if (k < nw) {
-        int co = k / (cin * kTaps), ci = (k / kTaps) % cin, t = k % kTaps;
-        float s = 0.f;
-        for (int p = 0; p < nparts; ++p) s += partials[int64_t(p) * (kWPack + kC) + (t * kC + co) * kC + ci];
-        gW[k] = s;
-    } else if (k < nw + cout) {
-        int co = k - nw;
-        float s = 0.f;
-        for (int p = 0; p < nparts; ++p) s += partials[int64_t(p) * (kWPack + kC) + kWPack + co];
-        gb[co] = s;
-    }
-}
-
 // Pack the float parameters into bfloat16 [tap][co][ci] layers, zero padded
 // to 16x16; lo = 1 gives the low part bfloat16(W - bfloat16(W)) (layer 1
 // runs on the pair hi + lo).
@@ -1119,12 +1086,15 @@ __device__ __forceinline__ v4u lds8_a8(const uint16_t *p)
 // 32 voxels instead of 27 with one used row.  Partials in the
 // [tap][co][ci] layout (co = 0), bias db3 = sum of d3.
 constexpr int kD3Row = 2080;   // LDS entries of d3: 168 zero margin + 1728 + margin
-__global__ __launch_bounds__(256) void k_wgrad3(const uint16_t *__restrict__ X, const uint16_t *__restrict__ d3cf,
-                                                int64_t n, float *__restrict__ partials)
+constexpr int kWgrad3Lds = 2 * 16 * kXRow + 2 * kD3Row + 4 * 256 + 4 * 4 * 32 * 16;
+__device__ __forceinline__ void wgrad3_body(const uint16_t *__restrict__ X, const uint16_t *__restrict__ d3cf,
+                                            int64_t n, float *__restrict__ partials, int wg, int ngroups,
+                                            uint8_t *lds)
 {
-    __shared__ __align__(16) uint16_t sx[16 * kXRow];
-    __shared__ __align__(16) uint16_t sd[kD3Row];
-    __shared__ float sb[256];
+    uint16_t *sx = reinterpret_cast<uint16_t *>(lds);                  // [16][kXRow]
+    uint16_t *sd = sx + 16 * kXRow;                                     // [kD3Row]
+    float *sb = reinterpret_cast<float *>(sd + kD3Row);                 // [256]
+    float(*red)[32][16] = reinterpret_cast<float(*)[32][16]>(sb + 256);  // [4][32][16]
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int i = lane & 15, g = lane >> 4;
     for (int k = tid; k < 16 * kXRow / 8; k += 256) reinterpret_cast<uint4 *>(sx)[k] = make_uint4(0, 0, 0, 0);
@@ -1149,8 +1119,8 @@ __global__ __launch_bounds__(256) void k_wgrad3(const uint16_t *__restrict__ X, 
             nd[e] = c < kRowVox ? d3cf[tl * kRowVox + c] : uint16_t(0);
         }
     };
-    if (blockIdx.x < n) fetch(blockIdx.x);
-    for (int64_t tile = blockIdx.x; tile < n; tile += gridDim.x) {
+    if (wg < n) fetch(wg);
+    for (int64_t tile = wg; tile < n; tile += ngroups) {
 #pragma unroll
         for (int e = 0; e < kPer; ++e) {
             const int k = tid + 256 * e;
@@ -1167,7 +1137,7 @@ __global__ __launch_bounds__(256) void k_wgrad3(const uint16_t *__restrict__ X, 
             }
         }
         __syncthreads();
-        if (tile + gridDim.x < n) fetch(tile + gridDim.x);
+        if (tile + ngroups < n) fetch(tile + ngroups);
         // wave w takes the 32-voxel chunks w, w + 4, ...
         for (int c0 = 32 * wave; c0 < kRowVox; c0 += 128) {
             const int c = c0 + 8 * g;
@@ -1190,12 +1160,11 @@ __global__ __launch_bounds__(256) void k_wgrad3(const uint16_t *__restrict__ X, 
         }
     }
     // the four waves' sums of each (tap, ci), then one partial per workgroup
-    __shared__ float red[4][32][16];
     for (int h = 0; h < 2; ++h)
         for (int r = 0; r < 4; ++r) red[wave][16 * h + 4 * g + r][i] = acc[h][r];
     sb[tid] = bsum;
     __syncthreads();
-    float *out = partials + int64_t(blockIdx.x) * (kWPack + kC);
+    float *out = partials + int64_t(wg) * (kWPack + kC);
     for (int e = tid; e < kWPack + kC; e += 256) {
         float v = 0.f;
         if (e < kWPack) {
@@ -1213,12 +1182,15 @@ __global__ __launch_bounds__(256) void k_wgrad3(const uint16_t *__restrict__ X, 
 // as (output channels) x (54 (ci, t) columns in four MFMAs) x (32 voxels):
 // each column reads the input channel shifted by its own tap (the y and z
 // shifts keep the reads 8-byte aligned, x shifts per lane from x_shift).
-__global__ __launch_bounds__(256) void k_wgrad1(const uint16_t *__restrict__ X, const uint16_t *__restrict__ dY,
-                                                int64_t n, float *__restrict__ partials)
+constexpr int kWgrad1Lds = 2 * 2 * kXRow + 2 * 16 * kDRow + 4 * 256 + 4 * 4 * 16 * 64;
+__device__ __forceinline__ void wgrad1_body(const uint16_t *__restrict__ X, const uint16_t *__restrict__ dY,
+                                            int64_t n, float *__restrict__ partials, int wg, int ngroups,
+                                            uint8_t *lds)
 {
-    __shared__ __align__(16) uint16_t sx[2 * kXRow];
-    __shared__ __align__(16) uint16_t sd[16 * kDRow];
-    __shared__ float sb[256];
+    uint16_t *sx = reinterpret_cast<uint16_t *>(lds);                  // [2][kXRow]
+    uint16_t *sd = sx + 2 * kXRow;                                      // [16][kDRow]
+    float *sb = reinterpret_cast<float *>(sd + 16 * kDRow);             // [256]
+    float(*red)[16][64] = reinterpret_cast<float(*)[16][64]>(sb + 256);  // [4][16][64]
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int i = lane & 15, g = lane >> 4;
     for (int k = tid; k < 2 * kXRow / 8; k += 256) reinterpret_cast<uint4 *>(sx)[k] = make_uint4(0, 0, 0, 0);
@@ -1247,8 +1219,8 @@ __global__ __launch_bounds__(256) void k_wgrad1(const uint16_t *__restrict__ X, 
             else if (k < kChunks) nxt[e] = reinterpret_cast<const uint4 *>(dY + tl * 16 * kRowVox)[k - 2 * kXc];
         }
     };
-    if (blockIdx.x < n) fetch(blockIdx.x);
-    for (int64_t tile = blockIdx.x; tile < n; tile += gridDim.x) {
+    if (wg < n) fetch(wg);
+    for (int64_t tile = wg; tile < n; tile += ngroups) {
 #pragma unroll
         for (int e = 0; e < kPer; ++e) {
             const int k = tid + 256 * e;
@@ -1261,7 +1233,7 @@ __global__ __launch_bounds__(256) void k_wgrad1(const uint16_t *__restrict__ X, 
             }
         }
         __syncthreads();
-        if (tile + gridDim.x < n) fetch(tile + gridDim.x);
+        if (tile + ngroups < n) fetch(tile + ngroups);
         for (int c = tid >> 4; c < kRowVox; c += 16) bsum += bf2f(sd[(tid & 15) * kDRow + c]);
         for (int c0 = 32 * wave; c0 < kRowVox; c0 += 128) {
             const int c = c0 + 8 * g;
@@ -1279,12 +1251,11 @@ __global__ __launch_bounds__(256) void k_wgrad1(const uint16_t *__restrict__ X, 
     }
     // D[co][col]: lane holds column 16 q + i, rows co = 4g .. 4g + 3; the
     // four waves' sums, then one partial per workgroup in [tap][co][ci]
-    __shared__ float red[4][16][64];
     for (int q = 0; q < 4; ++q)
         for (int r = 0; r < 4; ++r) red[wave][4 * g + r][16 * q + i] = acc[q][r];
     sb[tid] = bsum;
     __syncthreads();
-    float *out = partials + int64_t(blockIdx.x) * (kWPack + kC);
+    float *out = partials + int64_t(wg) * (kWPack + kC);
     for (int e = tid; e < kWPack + kC; e += 256) {
         float v = 0.f;
         if (e < kWPack) {
@@ -1299,6 +1270,22 @@ __global__ __launch_bounds__(256) void k_wgrad1(const uint16_t *__restrict__ X, 
         }
         out[e] = v;
     }
+}
+
+// The layer-1 and layer-3 weight gradients in one launch: workgroups
+// [0, g1) take layer 1, the rest layer 3.  Each is latency-bound with one
+// workgroup per compute unit; sharing one LDS allocation (the larger of the
+// two) lets a unit hold one of each, so the two run side by side.
+constexpr int kWgrad13Lds = kWgrad1Lds > kWgrad3Lds ? kWgrad1Lds : kWgrad3Lds;
+__global__ __launch_bounds__(256) void k_wgrad13(const uint16_t *__restrict__ X1, const uint16_t *__restrict__ d1,
+                                                 const uint16_t *__restrict__ X3, const uint16_t *__restrict__ d3,
+                                                 int64_t n, float *__restrict__ parts1, float *__restrict__ parts3,
+                                                 int g1)
+{
+    __shared__ __align__(16) uint8_t lds[kWgrad13Lds];
+    const int wg = int(blockIdx.x);
+    if (wg < g1) wgrad1_body(X1, d1, n, parts1, wg, g1, lds);
+    else wgrad3_body(X3, d3, n, parts3, wg - g1, int(gridDim.x) - g1, lds);
 }
 
 // LDS rows of the layer-2 weight gradient.  Its X reads are 8-byte reads
@@ -1566,9 +1553,9 @@ int dn_net_loss_grad(const float *tiles, int64_t n, const float *params, const f
     // weight gradients, one partial per workgroup and layer, summed in a fixed order
     const unsigned gw = unsigned(ws.nparts);
     const size_t lp = size_t(ws.nparts) * (kWPack + kC);
-    hipLaunchKernelGGL(k_wgrad1, dim3(gw), dim3(256), 0, st, ws.x1cf, ws.d1cf, n, ws.parts);
+    hipLaunchKernelGGL(k_wgrad13, dim3(2 * gw), dim3(256), 0, st, ws.x1cf, ws.d1cf, ws.h2cf, ws.d3cf, n, ws.parts,
+                       ws.parts + 2 * lp, int(gw));
     hipLaunchKernelGGL((k_wgrad_mfma<16, 16>), dim3(gw), dim3(512), 0, st, ws.h1cf, ws.d2cf, n, ws.parts + lp);
-    hipLaunchKernelGGL(k_wgrad3, dim3(gw), dim3(256), 0, st, ws.h2cf, ws.d3cf, n, ws.parts + 2 * lp);
     hipLaunchKernelGGL(k_grad_final, dim3((3 * (kWPack + kC) + kFinalEntries - 1) / kFinalEntries), dim3(256), 0, st,
                        ws.parts, ws.nparts, ws.tl, ws.tc, n, lsum, grad);
     DN_HIP(hipGetLastError());
