@@ -47,7 +47,9 @@ def parse():
     ap.add_argument("--iters", type=int, default=500)
     ap.add_argument("--copies", type=int, default=35)
     ap.add_argument("--frames", type=int, default=100)
-    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused256", "twopass"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused256", "twopass"],
+                    help="iteration kernel; with --workload batched: fused = the persistent kernel, "
+                         "fused256 = one launch per iteration")
     ap.add_argument("--data-term", default="l2", choices=["l2", "l1"],
                     help="quadratic data term (the paper's) or the TV-L1 variant")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"],
@@ -56,7 +58,7 @@ def parse():
     ap.add_argument("--no-gap", action="store_true", help="skip the time-to-gap comparison")
     ap.add_argument("--workload", default="street", choices=["street", "batched"],
                     help="street: the street-scale map (default); batched: 64 uneven sub-maps "
-                         "in one persistent launch")
+                         "in one HIP graph")
     ap.add_argument("--submaps", type=int, default=64)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only copy 1 GiB device to device (HBM counter calibration) and exit")
@@ -85,7 +87,9 @@ TRAFFIC_FILES = {
     ("street", "f32"): ("cp_fused_street35_traffic.json", ("cp_kernel.h", "regularize.hip")),
     ("street", "f16"): ("cp_fused_street35_f16_traffic.json", ("cp_kernel.h", "regularize.hip")),
     ("street", "bf16"): ("cp_fused_street35_bf16_traffic.json", ("cp_kernel.h", "regularize.hip")),
-    ("batched", "f32"): ("cp_persistent_batched64_traffic.json", ("cp_kernel.h", "batch.hip")),
+    # by the variant that ran: the persistent kernel, one launch per iteration
+    ("batched", "f32"): ({257: "cp_persistent_batched64_traffic.json", 1: "cp_batch_step_batched64_traffic.json"},
+                         ("cp_kernel.h", "batch.hip")),
 }
 
 
@@ -97,6 +101,10 @@ def load_traffic(nvox, workload, storage, kernel_id):
     if entry is None:
         return None
     name, srcs = entry
+    if isinstance(name, dict):
+        name = name.get(kernel_id)
+        if name is None:
+            return None
     p = os.path.join(ROOT, "profiles", name)
     try:
         with open(p) as f:
@@ -175,8 +183,9 @@ class Workload:
 class BatchedWorkload(Workload):
     """64 sub-maps with block counts drawn log-uniform in [1e3, 5e4]; each is
     a street segment: the n_i blocks nearest the start of a row of
-    translated copies of the fused street.  All regularised by one
-    persistent launch of 300 iterations (HIP graph, autotuned)."""
+    translated copies of the fused street.  All regularised together for
+    300 iterations in one HIP graph (the persistent kernel or one launch per
+    iteration, autotuned)."""
 
     def __init__(self, args, base=None):
         if base is None:
@@ -188,6 +197,9 @@ class BatchedWorkload(Workload):
             self.big, self.kernel = base.big, base.kernel
         import scenes
         self.counts = scenes.c4_block_counts(args.submaps, seed=0)
+        # the tuner's choice, or the persistent kernel / one launch per iteration
+        self.batch_kernel = {"auto": self.D.DN_K_AUTO, "fused": self.D.DN_K_FUSED,
+                             "fused256": self.D.DN_K_FUSED256}.get(getattr(args, "kernel", "auto"), self.D.DN_K_AUTO)
         self.subs = []
         cap = int(self.counts.max())
         for n in self.counts:
@@ -227,7 +239,7 @@ class BatchedWorkload(Workload):
             vol.clear()
             vol.insert_blocks(cc)
             vol.load_fused(f, w)
-        stats = D.regularize_batch(self.subs, D.reg_params(0.5, iters=self.args.iters, kernel=D.DN_K_AUTO))
+        stats = D.regularize_batch(self.subs, D.reg_params(0.5, iters=self.args.iters, kernel=self.batch_kernel))
         return stats[0], 0
 
     def voxels(self):
@@ -459,10 +471,15 @@ def x1_mixed_precision(wl, fp32_ms, iters=100):
     return out
 
 
+# variant codes of the batched solver (kernel_used // 100)
+BATCH_KERNELS = {257: "k_cp_persistent_lean", 256: "k_cp_persistent<256>", 512: "k_cp_persistent<512>",
+                 1: "k_cp_batch_step (one launch per iteration)"}
+
+
 def batched_run(wl, submaps=64, iters=300, steps=2):
     """Batched sub-maps in the default run: 64 street segments with block
     counts log-uniform in [1e3, 5e4], regularised for 300 iterations in one
-    persistent launch (HIP graph, autotuned)."""
+    HIP graph (persistent kernel or one launch per iteration, autotuned)."""
     import types
     D = wl.D
     bw = BatchedWorkload(types.SimpleNamespace(submaps=submaps, iters=iters), base=wl)
@@ -477,8 +494,7 @@ def batched_run(wl, submaps=64, iters=300, steps=2):
     kid = st.kernel_used // 100
     out = {"submaps": submaps, "blocks": nvox // 512, "voxels": nvox, "iters": iters,
            "ms_per_iter": per, "voxel_iters_per_s": nvox / (per / 1000.0),
-           "kernel": {257: "k_cp_persistent_lean", 256: "k_cp_persistent<256>",
-                      512: "k_cp_persistent<512>"}.get(kid, "k_cp_persistent"),
+           "kernel": BATCH_KERNELS.get(kid, "k_cp_persistent"),
            "wg_per_cu": st.kernel_used % 100,
            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "traffic": load_traffic(nvox, "batched", "f32", kid),
@@ -647,13 +663,12 @@ def main():
     kernel_id = st.kernel_used // 100 if args.workload == "batched" else st.kernel_used
     traffic = load_traffic(nvox, args.workload, args.storage, kernel_id)
     if args.workload == "batched":
-        metric = f"voxel-iterations/s ({args.submaps} sub-maps, {args.iters} CP iterations, one persistent launch)"
+        metric = f"voxel-iterations/s ({args.submaps} sub-maps, {args.iters} CP iterations, one HIP graph)"
         config = {"workload": f"batched sub-maps: {args.submaps} street segments with block counts "
-                              "log-uniform in [1e3, 5e4] (0.2 m voxels), one persistent launch in a HIP "
-                              "graph, autotuned grid", "blocks": nb, "voxels": nvox,
+                              "log-uniform in [1e3, 5e4] (0.2 m voxels), one HIP graph (persistent "
+                              "kernel or one launch per iteration, autotuned)", "blocks": nb, "voxels": nvox,
                   "iters": args.iters, "lambda": 0.5}
-        kname = {257: "k_cp_persistent_lean", 256: "k_cp_persistent<256>",
-                 512: "k_cp_persistent<512>"}.get(st.kernel_used // 100, "k_cp_persistent")
+        kname = BATCH_KERNELS.get(st.kernel_used // 100, "k_cp_persistent")
         kname += " (one CP iteration of every sub-map)"
     else:
         metric = f"voxel-iterations/s (fusion + {args.iters} CP iterations + gap + surface, street map)"
@@ -692,7 +707,7 @@ def main():
         line["omega_voxels"] = n_omega
         line["cp_omega_voxel_iters_per_s"] = n_omega / (kern_ms / 1000.0)
     if args.workload == "batched":
-        line["config"]["kernel_used"] = {"threads": 256 if st.kernel_used // 100 == 257 else st.kernel_used // 100,
+        line["config"]["kernel_used"] = {"threads": 512 if st.kernel_used // 100 == 512 else 256,
                                          "lean": st.kernel_used // 100 == 257,
                                          "wg_per_cu": st.kernel_used % 100}
         line["config"]["layout_used"] = {"order": "pool" if st.layout_used & 1 else "morton",

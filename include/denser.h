@@ -288,10 +288,16 @@ int dn_regularize(dn_volume *vol, const dn_reg_params *params, const float *u0_d
  * total_blocks blocks together (0 for bad arguments). */
 size_t dn_regularize_batch_bytes(int32_t n, int64_t total_blocks);
 
-/* Regularise n independent volumes with the same parameters in ONE
- * persistent kernel launch (a grid-wide barrier separates iterations),
- * captured in a HIP graph and replayed.  Work items are (volume, block)
- * pairs balanced over the grid.  All volumes must share one device; the
+/* Regularise n independent volumes with the same parameters in one HIP
+ * graph, captured and replayed: either ONE persistent kernel launch (a
+ * grid-wide barrier separates iterations) or one launch per iteration over
+ * every volume: params->kernel DN_K_FUSED256 selects the latter, DN_K_AUTO
+ * whichever the autotuner timed faster for this problem size (timed on the
+ * first call of a size with init ZERO, the persistent kernel until then),
+ * any other value the persistent kernel.  Work items are (volume, block) pairs balanced over the grid.
+ * kernel_used of the stats: 100 x variant + workgroups per CU (variant 1:
+ * one launch per iteration; 256 / 512: persistent with that many threads
+ * per workgroup; 257: persistent, 256 threads, no prefetch).  All volumes must share one device; the
  * first volume's stream is used.  gap_every / gap_tol are ignored (the
  * gaps are computed once at the end); init must be ZERO or KEEP; storage
  * must be DN_F32.  workspace_dev: caller device memory of at least

@@ -1,11 +1,13 @@
-// Many sub-maps in one persistent launch (gfx950).
+// Many sub-maps in one launch (gfx950).
 //
 // All (sub-map, block) work items of every volume run in one kernel that
 // loops over the iterations itself; a grid-wide barrier separates one
 // iteration from the next (the fused iteration reads its neighbours' ubar
-// and p of the previous iteration).  The launch is captured in a HIP graph
-// together with the reset of the barrier state and replayed.  Grid size
-// and the item-to-workgroup mapping are picked by timing short trial runs
+// and p of the previous iteration).  The other candidate launches one
+// iteration of every sub-map per kernel, the launch boundary ordering the
+// iterations.  Either is captured in a HIP graph together with the reset
+// of the barrier state and replayed.  Kernel, grid size and the
+// item-to-workgroup mapping are picked by timing short trial runs
 // (autotuner), cached per problem size.
 #include <cstring>
 #include <cstdlib>
@@ -140,13 +142,18 @@ __device__ __forceinline__ int2 load_item(const int2 *__restrict__ items, int64_
     return make_int2(__builtin_amdgcn_readfirstlane(raw.x), __builtin_amdgcn_readfirstlane(raw.y));
 }
 
-// A value the whole wave shares, moved to scalar registers.
+// A pointer the whole wave shares, moved to scalar registers.  The volume
+// buffers are global memory; rebuilding the pointer in the global address
+// space lets the compiler address them with global instructions (through
+// a generic pointer it would emit flat ones, which count against the LDS
+// wait counter too, so every LDS wait would also wait for the loads).
 template <class T> __device__ __forceinline__ T *uni(T *p)
 {
     const uint64_t v = reinterpret_cast<uint64_t>(p);
     const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
     const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
-    return reinterpret_cast<T *>((uint64_t(hi) << 32) | lo);
+    typedef __attribute__((address_space(1))) T GT;
+    return (T *)reinterpret_cast<GT *>((uint64_t(hi) << 32) | lo);
 }
 
 __device__ __forceinline__ void item_args(const BatchArgs &a, const VolDesc *__restrict__ vols, int2 item, int it,
@@ -294,6 +301,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     k_cp_persistent_body<256, false>(a, vols, items);
 }
 
+// One iteration of every sub-map: one workgroup per item, the items
+// mapped to workgroups in XCD chunks as in the single-map kernel (so the
+// blocks in flight are a contiguous window of the item list per XCD, as
+// hardware dispatch keeps them); no barrier, the next launch is the next
+// iteration.
+constexpr int kStepKernel = 1;   // variant code of this kernel in the tuner
+__global__ __launch_bounds__(256) void k_cp_batch_step(BatchArgs a, const VolDesc *__restrict__ vols,
+                                                       const int2 *__restrict__ items, int it, float sigma,
+                                                       float tau, float theta)
+{
+    __shared__ CPShared sh;
+    const int64_t slot = block_slot(blockIdx.x, a.n_items, a.xcd_chunks);
+    if (slot >= a.n_items) return;
+    const int2 bi = load_item(items, slot);
+    CPArgs<SF32> A;
+    item_args(a, vols, bi, it, sigma, tau, theta, A);
+    cp_block<SF32, false, 256>(A, bi.y, sh, threadIdx.x);
+}
+
 __global__ void k_make_items(const int32_t *__restrict__ order, int64_t nb, int32_t vol, int2 *__restrict__ items)
 {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -348,11 +374,29 @@ static int size_bucket(int64_t n)
 
 // variant: 256 / 512 = threads per workgroup with prefetch of the next
 // block; 257 = 256 threads without prefetch (fewer registers, more
-// workgroups per CU)
+// workgroups per CU); kStepKernel = one launch per iteration (grid
+// unused).  The step sizes of the accelerated schedule are formed as the
+// persistent kernel forms them (double precision, the same operations).
 static void launch_kernel(hipStream_t st, const BatchArgs &a, int grid, int nt)
 {
     hipLaunchKernelGGL(k_batch_reset, dim3(32), dim3(256), 0, st, a.bar);
-    if (nt == 256)
+    if (nt == kStepKernel) {
+        const unsigned g = unsigned(((a.n_items + 7) / 8) * 8);
+        double acc_tau = a.tau0, acc_sigma = a.sigma0;
+        for (int it = 0; it < a.iters; ++it) {
+            float sigma = a.sigma, tau = a.tau, theta = a.theta;
+            if (a.gamma > 0.0) {
+                const double th = 1.0 / std::sqrt(1.0 + 2.0 * a.gamma * acc_tau);
+                tau = float(acc_tau);
+                sigma = float(acc_sigma);
+                theta = float(th);
+                acc_tau = th * acc_tau;
+                acc_sigma = acc_sigma / th;
+            }
+            hipLaunchKernelGGL(k_cp_batch_step, dim3(g), dim3(256), 0, st, a, a.vols, a.items, it, sigma, tau,
+                               theta);
+        }
+    } else if (nt == 256)
         hipLaunchKernelGGL((k_cp_persistent<256, true>), dim3(grid), dim3(256), 0, st, a, a.vols, a.items);
     else if (nt == 257)
         hipLaunchKernelGGL(k_cp_persistent_lean, dim3(grid), dim3(256), 0, st, a, a.vols, a.items);
@@ -534,12 +578,16 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     DN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu512, k_cp_persistent<512, true>, 512, 0));
     if (per_cu257 < 1) { set_error("persistent kernel does not fit on a compute unit"); return DN_E_DEVICE; }
 
+    // DN_K_FUSED256: one launch of the fused kernel per iteration; other
+    // explicit choices: the persistent kernel; DN_K_AUTO: the tuned choice
     TuneChoice ch = TuneChoice{257, per_cu257, 1, 0};
+    if (prm->kernel == DN_K_FUSED256) ch = TuneChoice{kStepKernel, 1, 1, 0};
     const int64_t key = (int64_t(v0->device) << 32) | size_bucket(total);
     auto it = g_tuned.find(key);
-    if (it != g_tuned.end()) {
+    if (prm->kernel != DN_K_AUTO) {
+    } else if (it != g_tuned.end()) {
         ch = it->second;
-    } else if (prm->kernel == DN_K_AUTO && prm->init == DN_INIT_ZERO && total > 0 && prm->iters > 0) {
+    } else if (prm->init == DN_INIT_ZERO && total > 0 && prm->iters > 0) {
         // autotune: a few iterations of each candidate, from the zero state
         hipEvent_t e0, e1;
         DN_HIP(hipEventCreate(&e0));
@@ -548,11 +596,12 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
         const int trial = std::min(prm->iters, 6);
         for (int pool = 0; pool <= 1; ++pool) {
             if ((rc = build_items(pool))) return rc;
-            for (int nt : {257, 256, 512}) {
-                const int pc = nt == 256 ? per_cu256 : (nt == 257 ? per_cu257 : per_cu512);
+            for (int nt : {257, 256, 512, kStepKernel}) {
+                const int pc = nt == kStepKernel ? 1 : (nt == 256 ? per_cu256 : (nt == 257 ? per_cu257 : per_cu512));
                 if (pc < 1) continue;
-                for (int wpc : {pc, (pc + 1) / 2}) {
-                    if (wpc != pc && wpc == (pc + 1) / 2 && pc == 1) continue;
+                std::vector<int> wpcs = {pc};
+                if ((pc + 1) / 2 != pc) wpcs.push_back((pc + 1) / 2);
+                for (int wpc : wpcs) {
                     for (int xcd = 0; xcd <= 1; ++xcd) {
                         BatchArgs t = a;
                         t.iters = trial;

@@ -1,5 +1,6 @@
-"""Batched persistent regularisation of uneven sub-maps (one launch, grid
-barriers, HIP graph) against the single-volume kernel and the oracle."""
+"""Batched regularisation of uneven sub-maps (one HIP graph: the persistent
+kernel with grid barriers, or one launch per iteration, or the tuner's
+choice) against the single-volume kernel and the oracle."""
 import numpy as np
 import pytest
 
@@ -23,12 +24,22 @@ def _make(D, nb, seed, extent):
 
 
 SIZES = [(3, 0, 2), (40, 1, 4), (7, 2, 3), (120, 3, 6), (1, 4, 2)]
+# tuner's choice / persistent kernel / one launch per iteration
+KERNELS = ["auto", "persistent", "per_iteration"]
 
 
-def test_batch_matches_single_volume_and_oracle():
+def _kernel(D, name):
+    return {"auto": D.DN_K_AUTO, "persistent": D.DN_K_FUSED, "per_iteration": D.DN_K_FUSED256}[name]
+
+
+@pytest.mark.parametrize("kname", KERNELS)
+def test_batch_matches_single_volume_and_oracle(kname):
     D = dn()
     vols = [_make(D, *s) for s in SIZES]
-    stats = D.regularize_batch([v[0] for v in vols], D.reg_params(LAM, iters=30, kernel=D.DN_K_AUTO))
+    stats = D.regularize_batch([v[0] for v in vols], D.reg_params(LAM, iters=30, kernel=_kernel(D, kname)))
+    want = {"persistent": 257, "per_iteration": 1}.get(kname)
+    if want is not None:
+        assert all(st.kernel_used // 100 == want for st in stats)
     for (gv, c, f, w), st in zip(vols, stats):
         gu, gub, gp = state_of(D, gv)
         nbr = host(gv.extract(D.DN_X_NBR))
@@ -43,27 +54,45 @@ def test_batch_matches_single_volume_and_oracle():
         np.testing.assert_array_equal(sp, gp)
 
 
-def test_batch_keep_resumes_and_graph_replays():
+@pytest.mark.parametrize("kname", KERNELS)
+def test_batch_keep_resumes_and_graph_replays(kname):
     D = dn()
+    k = _kernel(D, kname)
     vols = [_make(D, *s) for s in SIZES[:3]]
     handles = [v[0] for v in vols]
-    D.regularize_batch(handles, D.reg_params(LAM, iters=24, kernel=D.DN_K_AUTO))
+    D.regularize_batch(handles, D.reg_params(LAM, iters=24, kernel=k))
     whole = [state_of(D, h) for h in handles]
     for rep in range(3):  # the same configuration replays the cached graph
-        D.regularize_batch(handles, D.reg_params(LAM, iters=11, kernel=D.DN_K_AUTO))
-        D.regularize_batch(handles, D.reg_params(LAM, iters=13, kernel=D.DN_K_AUTO, init=D.DN_INIT_KEEP))
+        D.regularize_batch(handles, D.reg_params(LAM, iters=11, kernel=k))
+        D.regularize_batch(handles, D.reg_params(LAM, iters=13, kernel=k, init=D.DN_INIT_KEEP))
         for h, ref in zip(handles, whole):
             for a, b in zip(state_of(D, h), ref):
                 np.testing.assert_array_equal(a, b)
 
 
-def test_batch_accelerated_matches_single():
+@pytest.mark.parametrize("kname", KERNELS)
+def test_batch_accelerated_matches_single(kname):
     D = dn()
     vols = [_make(D, *s) for s in SIZES[:4]]
     handles = [v[0] for v in vols]
-    D.regularize_batch(handles, D.reg_params(LAM, iters=40, kernel=D.DN_K_AUTO, gamma=LAM))
+    D.regularize_batch(handles, D.reg_params(LAM, iters=40, kernel=_kernel(D, kname), gamma=LAM))
     batched = [state_of(D, h) for h in handles]
     for h, ref in zip(handles, batched):
         h.regularize(D.reg_params(LAM, iters=40, kernel=D.DN_K_FUSED, gamma=LAM))
+        for a, b in zip(state_of(D, h), ref):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_batch_of_many_small_sub_maps():
+    """70 sub-maps of one to three blocks, one launch per iteration: every
+    sub-map equals the single-volume kernel."""
+    D = dn()
+    vols = [_make(D, 1 + i % 3, 100 + i, 2) for i in range(70)]
+    handles = [v[0] for v in vols]
+    stats = D.regularize_batch(handles, D.reg_params(LAM, iters=20, kernel=D.DN_K_FUSED256))
+    assert all(st.kernel_used // 100 == 1 for st in stats)
+    batched = [state_of(D, h) for h in handles]
+    for h, ref in zip(handles, batched):
+        h.regularize(D.reg_params(LAM, iters=20, kernel=D.DN_K_FUSED))
         for a, b in zip(state_of(D, h), ref):
             np.testing.assert_array_equal(a, b)

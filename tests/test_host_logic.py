@@ -36,12 +36,20 @@ def test_calibration_lookup_misses_return_none():
     assert W.calibrated_gap(0.05 * (1 + 1e-12), 0.0, 100, cal) is not None
 
 
+def _traffic_files(bench):
+    """(workload, storage, file) of every traffic summary, one file per
+    kernel variant where the workload has several."""
+    for (workload, storage), (names, srcs) in bench.TRAFFIC_FILES.items():
+        for name in (names.values() if isinstance(names, dict) else [names]):
+            yield workload, storage, name
+
+
 def test_traffic_files_are_consistent_and_looked_up_by_digest(monkeypatch):
     """Each file's figures hang together, and the bench returns them exactly
     when the kernel sources hash to the file's digest and the kernel variant
     that ran is the one measured."""
     import bench
-    for (workload, storage), (name, srcs) in bench.TRAFFIC_FILES.items():
+    for workload, storage, name in _traffic_files(bench):
         with open(os.path.join(ROOT, "profiles", name)) as f:
             t = json.load(f)
         nvox = t["voxels"]
@@ -61,7 +69,7 @@ def test_traffic_files_are_consistent_and_looked_up_by_digest(monkeypatch):
 def test_traffic_is_dropped_when_the_sources_change(monkeypatch):
     import bench
     monkeypatch.setattr(bench, "src_digest", lambda names=None: "0" * 16)
-    for (workload, storage), (name, srcs) in bench.TRAFFIC_FILES.items():
+    for workload, storage, name in _traffic_files(bench):
         with open(os.path.join(ROOT, "profiles", name)) as f:
             t = json.load(f)
         assert bench.load_traffic(t["voxels"], workload, storage, t["kernel_id"]) is None
