@@ -93,10 +93,11 @@ TRAFFIC_FILES = {
 }
 
 
-def load_traffic(nvox, workload, storage, kernel_id):
+def load_traffic(nvox, workload, storage, kernel_id, layout=None):
     """Bytes leaving L2 per launch of the iteration kernel, from the
     committed counter summary, if it was taken on the current kernel source
-    and on the kernel variant that ran (else None)."""
+    and on the kernel variant (and, where the summary records it, the block
+    order) that ran (else None)."""
     entry = TRAFFIC_FILES.get((workload, storage))
     if entry is None:
         return None
@@ -112,6 +113,8 @@ def load_traffic(nvox, workload, storage, kernel_id):
     except OSError:
         return None
     if t.get("source_digest") != src_digest(srcs) or t.get("kernel_id") != kernel_id:
+        return None
+    if "layout_used" in t and layout is not None and t["layout_used"] != layout:
         return None
     return t["bytes_per_voxel_iter"] * nvox
 
@@ -183,9 +186,14 @@ class Workload:
 class BatchedWorkload(Workload):
     """64 sub-maps with block counts drawn log-uniform in [1e3, 5e4]; each is
     a street segment: the n_i blocks nearest the start of a row of
-    translated copies of the fused street.  All regularised together for
-    300 iterations in one HIP graph (the persistent kernel or one launch per
-    iteration, autotuned)."""
+    translated copies of the fused street.  A segment is built the way
+    fusion builds a map: its blocks are allocated in the order the fused
+    street allocated them (copy after copy), ALLOC_BATCH at a time, about
+    one frame's worth, so its block pool holds them in allocation order.
+    All regularised together for 300 iterations in one HIP graph (the
+    persistent kernel or one launch per iteration, autotuned)."""
+
+    ALLOC_BATCH = 64
 
     def __init__(self, args, base=None):
         if base is None:
@@ -212,32 +220,40 @@ class BatchedWorkload(Workload):
 
     def _layout(self):
         D, torch = self.D, self.torch
-        c = self.street.extract(D.DN_X_COORDS).long()
+        c = self.street.extract(D.DN_X_COORDS).long()      # in the street's allocation order
         f = self.street.extract(D.DN_X_F)
         w = self.street.extract(D.DN_X_W)
         zlen = int((c[:, 2].max() - c[:, 2].min()).item()) + 3
+        off = 1 << 20
+
+        def xyz_key(q):
+            return ((q[:, 0] + off) << 42) | ((q[:, 1] + off) << 21) | (q[:, 2] + off)
+
         self.parts = []
-        for n in self.counts:
+        for vol, n in zip(self.subs, self.counts):
             reps = int(np.ceil(n / c.shape[0]))
             shift = torch.zeros((reps, 1, 3), dtype=torch.long, device=c.device)
             shift[:, 0, 2] = torch.arange(reps, device=c.device) * zlen
             cc = (c[None] + shift).reshape(-1, 3)
-            # the segment: the n blocks with the smallest z (ties by x, y)
-            off = 1 << 20
+            # the segment: the n blocks with the smallest z (ties by x, y),
+            # taken in allocation order (copy, then the street's pool order)
             key = ((cc[:, 2] + off) << 42) | ((cc[:, 0] + off) << 21) | (cc[:, 1] + off)
-            sel = torch.argsort(key)[: int(n)]
-            cc = cc[sel]
-            # the library appends in ascending (x, y, z): order f, w likewise
-            key2 = ((cc[:, 0] + off) << 42) | ((cc[:, 1] + off) << 21) | (cc[:, 2] + off)
-            o2 = torch.argsort(key2)
-            src = sel[o2] % c.shape[0]
-            self.parts.append((cc[o2].to(torch.int32).contiguous(), f[src].contiguous(), w[src].contiguous()))
+            sel = torch.sort(torch.argsort(key)[: int(n)]).values
+            cs = cc[sel].to(torch.int32).contiguous()
+            vol.clear()
+            for i in range(0, cs.shape[0], self.ALLOC_BATCH):
+                vol.insert_blocks(cs[i:i + self.ALLOC_BATCH].contiguous())
+            # f, w in the order the pool holds the blocks
+            got = vol.extract(D.DN_X_COORDS).long()
+            ks, ki = torch.sort(xyz_key(cs.long()))
+            pos = torch.searchsorted(ks, xyz_key(got))
+            assert bool((ks[pos] == xyz_key(got)).all())
+            src = sel[ki[pos]] % c.shape[0]
+            self.parts.append((f[src].contiguous(), w[src].contiguous()))
 
     def step(self):
         D = self.D
-        for vol, (cc, f, w) in zip(self.subs, self.parts):
-            vol.clear()
-            vol.insert_blocks(cc)
+        for vol, (f, w) in zip(self.subs, self.parts):
             vol.load_fused(f, w)
         stats = D.regularize_batch(self.subs, D.reg_params(0.5, iters=self.args.iters, kernel=self.batch_kernel))
         return stats[0], 0
@@ -497,7 +513,8 @@ def batched_run(wl, submaps=64, iters=300, steps=2):
            "kernel": BATCH_KERNELS.get(kid, "k_cp_persistent"),
            "wg_per_cu": st.kernel_used % 100,
            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": ach / HBM_PEAK_GBS, "traffic": load_traffic(nvox, "batched", "f32", kid),
+                        "frac": ach / HBM_PEAK_GBS,
+                        "traffic": load_traffic(nvox, "batched", "f32", kid, st.layout_used),
                         "alg_bytes_per_launch": ALG_BYTES_PER_VOXEL_ITER * nvox}}
     for v in bw.subs:
         v.close()
@@ -661,7 +678,8 @@ def main():
     alg_bytes = ALG_BYTES_PER_VOXEL_ITER if args.storage == "f32" else ALG_BYTES_PER_VOXEL_ITER_16
     achieved = alg_bytes * nvox / (kern_ms / 1000.0) / 1e9
     kernel_id = st.kernel_used // 100 if args.workload == "batched" else st.kernel_used
-    traffic = load_traffic(nvox, args.workload, args.storage, kernel_id)
+    traffic = load_traffic(nvox, args.workload, args.storage, kernel_id,
+                           st.layout_used if args.workload == "batched" else None)
     if args.workload == "batched":
         metric = f"voxel-iterations/s ({args.submaps} sub-maps, {args.iters} CP iterations, one HIP graph)"
         config = {"workload": f"batched sub-maps: {args.submaps} street segments with block counts "

@@ -579,9 +579,10 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     if (per_cu257 < 1) { set_error("persistent kernel does not fit on a compute unit"); return DN_E_DEVICE; }
 
     // DN_K_FUSED256: one launch of the fused kernel per iteration; other
-    // explicit choices: the persistent kernel; DN_K_AUTO: the tuned choice
-    TuneChoice ch = TuneChoice{257, per_cu257, 1, 0};
-    if (prm->kernel == DN_K_FUSED256) ch = TuneChoice{kStepKernel, 1, 1, 0};
+    // explicit choices: the persistent kernel; both on the blocks in pool
+    // order, XCD-chunked.  DN_K_AUTO: the tuned choice
+    TuneChoice ch = TuneChoice{257, per_cu257, 1, 1};
+    if (prm->kernel == DN_K_FUSED256) ch = TuneChoice{kStepKernel, 1, 1, 1};
     const int64_t key = (int64_t(v0->device) << 32) | size_bucket(total);
     auto it = g_tuned.find(key);
     if (prm->kernel != DN_K_AUTO) {

@@ -62,8 +62,11 @@ def test_traffic_files_are_consistent_and_looked_up_by_digest(monkeypatch):
         assert t["bytes_per_voxel_iter"] >= t["algorithmic_bytes_per_voxel_iter"]
         monkeypatch.setattr(bench, "src_digest", lambda names=None, d=t["source_digest"]: d)
         assert bench.load_traffic(nvox, workload, storage, t["kernel_id"]) == t["bytes_per_voxel_iter"] * nvox
-        # another kernel variant gives no figure
+        # another kernel variant gives no figure, nor another block order
         assert bench.load_traffic(nvox, workload, storage, t["kernel_id"] + 1) is None
+        if "layout_used" in t:
+            assert bench.load_traffic(nvox, workload, storage, t["kernel_id"], t["layout_used"]) is not None
+            assert bench.load_traffic(nvox, workload, storage, t["kernel_id"], t["layout_used"] ^ 1) is None
 
 
 def test_traffic_is_dropped_when_the_sources_change(monkeypatch):
