@@ -1,7 +1,7 @@
 """Parity at the batched workload's full size, in the launch configuration
 bench.py times: 64 street segments of 1e3..5e4 blocks (1.04e6 blocks,
-5.3e8 voxels) regularised together for 300 iterations by one persistent
-launch (autotuned, graph-captured).  Checked through properties that hold
+5.3e8 voxels) regularised together for 300 iterations in one HIP graph
+(autotuned: the persistent kernel or one launch per iteration).  Checked through properties that hold
 at any size (|p| <= 1, unobserved voxels untouched), bit-exact equality of
 sub-maps with the single-volume kernel run on them alone, and the smallest
 sub-maps against the oracle."""

@@ -1,6 +1,6 @@
 """TV-L1 variant (L1 data term, u in [-1, 1]) of the regulariser on the GPU
 against the oracle's: single volume with every kernel, 16-bit storage,
-the batched persistent launch, gap stopping, and the error paths.  Bars as
+the batched launch, gap stopping, and the error paths.  Bars as
 for the quadratic data term: max-abs 1e-4 on u after the same iterations,
 energies within 1e-9 relative of the oracle on the GPU state."""
 import numpy as np
