@@ -209,7 +209,6 @@ class BatchedWorkload(Workload):
         self.batch_kernel = {"auto": self.D.DN_K_AUTO, "fused": self.D.DN_K_FUSED,
                              "fused256": self.D.DN_K_FUSED256}.get(getattr(args, "kernel", "auto"), self.D.DN_K_AUTO)
         self.subs = []
-        cap = int(self.counts.max())
         for n in self.counts:
             self.subs.append(self.D.Volume(self.fr.voxel_size, self.fr.mu, self.fr.max_depth, int(n),
                                            max(10, int(np.ceil(np.log2(n))) + 1), 4096, max_points=0,
