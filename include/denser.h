@@ -226,6 +226,15 @@ int dn_alloc_blocks(dn_volume *vol, const float *depth_dev, const dn_intrinsics 
  * Synchronises the stream. */
 int dn_insert_blocks(dn_volume *vol, const int32_t *coords_dev, int64_t n, int32_t *n_new_out);
 
+/* dn_insert_blocks, except that the new keys are appended in the order of
+ * their first occurrence in coords_dev (later repeats and keys already in
+ * the volume are ignored), so the block pool holds them in the caller's
+ * order: a map assembled from keys can keep the order in which fusion
+ * (Section III-A) allocated its blocks, which decides how often a block's
+ * halo is still in cache when its neighbours run.  n < 2^31 (else
+ * DN_E_INVALID).  Synchronises the stream. */
+int dn_insert_blocks_ordered(dn_volume *vol, const int32_t *coords_dev, int64_t n, int32_t *n_new_out);
+
 /* --------------------------------------------------------------- fusion */
 
 /* Projective TSDF update of every voxel of every allocated block with one

@@ -72,6 +72,7 @@ inline size_t tmp_light(size_t n) { return n / 16 + (size_t(1) << 20); }
 struct InsertScratch {
     uint8_t *flags;
     uint64_t *newraw, *sorted, *newk, *ksorted;
+    int32_t *pos0, *pos1;               // candidate positions (order-keeping insertion)
     int32_t *ids0, *ids1;
     uint32_t *home, *home2;
     int64_t *dm, *runmax;

@@ -323,6 +323,8 @@ InsertScratch carve_insert(Bump &b, int64_t n_cand, int64_t n_blocks)
     x.newraw = b.take<uint64_t>(size_t(n_cand));
     x.sorted = b.take<uint64_t>(size_t(n_cand));
     x.newk = b.take<uint64_t>(size_t(n_cand));
+    x.pos0 = b.take<int32_t>(size_t(n_cand));
+    x.pos1 = b.take<int32_t>(size_t(n_cand));
     x.ksorted = b.take<uint64_t>(size_t(n_blocks));
     x.ids0 = b.take<int32_t>(size_t(n_blocks));
     x.ids1 = b.take<int32_t>(size_t(n_blocks));
@@ -330,20 +332,35 @@ InsertScratch carve_insert(Bump &b, int64_t n_cand, int64_t n_blocks)
     x.home2 = b.take<uint32_t>(size_t(n_blocks));
     x.dm = b.take<int64_t>(size_t(n_blocks));
     x.runmax = b.take<int64_t>(size_t(n_blocks));
-    x.tmp_bytes = std::max(std::max(tmp_sort(size_t(n_cand), 8), tmp_light(size_t(n_cand))),
+    x.tmp_bytes = std::max(std::max(tmp_sort(size_t(n_cand), 12), tmp_light(size_t(n_cand))),
                            std::max(tmp_sort(size_t(n_blocks), 12), tmp_light(size_t(n_blocks))));
     x.tmp = b.take<char>(x.tmp_bytes);
     return x;
 }
 
+// flags[i] = 1 where sorted[i] starts a run of equal keys
+__global__ void k_run_heads(const uint64_t *__restrict__ sorted, int64_t n, uint8_t *__restrict__ flags)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) flags[i] = (i == 0 || sorted[i] != sorted[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_gather_keys(const uint64_t *__restrict__ keys, const int32_t *__restrict__ pos, int64_t n,
+                              uint64_t *__restrict__ out)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = keys[pos[i]];
+}
+
 // Insert a packed candidate list (device, n_cand entries, repeats allowed).
-// Appends the keys not yet present in ascending order, rebuilds hash +
+// Appends the keys not yet present in ascending order (keep_order: in the
+// order of their first occurrence in the list), rebuilds hash +
 // neighbours.  The raw list is first filtered against the table, so only
 // candidates of new blocks are sorted (after the first frames of a sequence
 // almost every candidate is a block that exists); the ascending list of all
 // distinct candidates is built from the same raw list only when it is
 // extracted (build_candidates).  All buffers come from the volume's scratch.
-static int insert_packed(dn_volume *v, uint64_t *cand, int64_t n_cand, int32_t *n_new_out)
+static int insert_packed(dn_volume *v, uint64_t *cand, int64_t n_cand, int32_t *n_new_out, bool keep_order = false)
 {
     hipStream_t st = v->stream;
     if (n_new_out) *n_new_out = 0;
@@ -366,13 +383,34 @@ static int insert_packed(dn_volume *v, uint64_t *cand, int64_t n_cand, int32_t *
     if (rc) return rc;
     const int64_t n_raw = v->host_stage[0];
     if (n_raw == 0) return DN_OK;
-    // 2) the distinct new keys, ascending
-    tbytes = x.tmp_bytes;
-    DN_HIP(rocprim::radix_sort_keys(x.tmp, tbytes, x.newraw, x.sorted, size_t(n_raw), 0, 63, st));
-    tbytes = x.tmp_bytes;
-    DN_HIP(rocprim::unique(x.tmp, tbytes, x.sorted, x.newk, d_nnew, size_t(n_raw), rocprim::equal_to<uint64_t>(), st));
+    // 2) the distinct new keys, ascending (keep_order: in first-occurrence
+    // order: a stable sort of (key, position), the first position of each
+    // run of equal keys, those positions sorted, the keys gathered)
+    if (!keep_order) {
+        tbytes = x.tmp_bytes;
+        DN_HIP(rocprim::radix_sort_keys(x.tmp, tbytes, x.newraw, x.sorted, size_t(n_raw), 0, 63, st));
+        tbytes = x.tmp_bytes;
+        DN_HIP(rocprim::unique(x.tmp, tbytes, x.sorted, x.newk, d_nnew, size_t(n_raw), rocprim::equal_to<uint64_t>(),
+                               st));
+    } else {
+        hipLaunchKernelGGL(k_iota, dim3(grid1(n_raw)), dim3(256), 0, st, x.pos0, n_raw);
+        DN_HIP(hipGetLastError());
+        tbytes = x.tmp_bytes;
+        DN_HIP(rocprim::radix_sort_pairs(x.tmp, tbytes, x.newraw, x.sorted, x.pos0, x.pos1, size_t(n_raw), 0, 63, st));
+        hipLaunchKernelGGL(k_run_heads, dim3(grid1(n_raw)), dim3(256), 0, st, x.sorted, n_raw, x.flags);
+        DN_HIP(hipGetLastError());
+        tbytes = x.tmp_bytes;
+        DN_HIP(rocprim::select(x.tmp, tbytes, x.pos1, x.flags, x.pos0, d_nnew, size_t(n_raw), st));
+    }
     if ((rc = read_back(v, d_nnew, sizeof(int64_t)))) return rc;
     const int64_t n_new = v->host_stage[0];
+    if (keep_order && n_new > 0) {
+        tbytes = x.tmp_bytes;
+        DN_HIP(rocprim::radix_sort_keys(x.tmp, tbytes, x.pos0, x.pos1, size_t(n_new), 0, bits_for(uint64_t(n_raw)),
+                                        st));
+        hipLaunchKernelGGL(k_gather_keys, dim3(grid1(n_new)), dim3(256), 0, st, x.newraw, x.pos1, n_new, x.newk);
+        DN_HIP(hipGetLastError());
+    }
     if (v->nb + n_new > v->cap_blocks) {
         set_error("block pool full: %lld + %lld new blocks > max_blocks %lld", (long long)v->nb,
                   (long long)n_new, (long long)v->cap_blocks);
@@ -896,6 +934,15 @@ static int verify_tmp_bounds(dn_volume *v)
     DN_HIP(rocprim::unique(nullptr, t, u64, u64, i64, nc, rocprim::equal_to<uint64_t>(), st));
     q.push_back({"candidate unique", t, tmp_light(nc)});
     t = 0;
+    DN_HIP(rocprim::radix_sort_pairs(nullptr, t, u64, u64, i32, i32, nc, 0, 63, st));
+    q.push_back({"candidate sort with positions", t, tmp_sort(nc, 12)});
+    t = 0;
+    DN_HIP(rocprim::select(nullptr, t, i32, u8, i32, i64, nc, st));
+    q.push_back({"first-occurrence selection", t, tmp_light(nc)});
+    t = 0;
+    DN_HIP(rocprim::radix_sort_keys(nullptr, t, i32, i32, nc, 0, 31, st));
+    q.push_back({"position sort", t, tmp_sort(nc, 12)});
+    t = 0;
     DN_HIP(rocprim::radix_sort_pairs(nullptr, t, u64, u64, i32, i32, mb, 0, 63, st));
     q.push_back({"key sort", t, tmp_sort(mb, 12)});
     t = 0;
@@ -1087,7 +1134,7 @@ int dn_alloc_blocks(dn_volume *v, const float *depth, const dn_intrinsics *K, co
         n_new_out);
 }
 
-int dn_insert_blocks(dn_volume *v, const int32_t *coords, int64_t n, int32_t *n_new_out)
+static int insert_keys(dn_volume *v, const int32_t *coords, int64_t n, int32_t *n_new_out, bool keep_order)
 {
     DN_REQUIRE(v && (coords || n == 0) && n >= 0, "bad argument");
     if (n_new_out) *n_new_out = 0;
@@ -1099,7 +1146,18 @@ int dn_insert_blocks(dn_volume *v, const int32_t *coords, int64_t n, int32_t *n_
     }
     hipLaunchKernelGGL(k_pack_coords, dim3(grid1(n)), dim3(256), 0, v->stream, coords, n, v->cand);
     DN_HIP(hipGetLastError());
-    return insert_packed(v, v->cand, n, n_new_out);
+    return insert_packed(v, v->cand, n, n_new_out, keep_order);
+}
+
+int dn_insert_blocks(dn_volume *v, const int32_t *coords, int64_t n, int32_t *n_new_out)
+{
+    return insert_keys(v, coords, n, n_new_out, false);
+}
+
+int dn_insert_blocks_ordered(dn_volume *v, const int32_t *coords, int64_t n, int32_t *n_new_out)
+{
+    DN_REQUIRE(n < (int64_t(1) << 31), "at most 2^31 - 1 keys per call");
+    return insert_keys(v, coords, n, n_new_out, true);
 }
 
 int dn_fuse_depth(dn_volume *v, const float *depth, const dn_intrinsics *K, const double T[16])

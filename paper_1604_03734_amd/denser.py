@@ -99,6 +99,7 @@ def lib():
         "dn_last_error": (ctypes.c_char_p, []),
         "dn_alloc_blocks": (i32, [P, P, P, P, P]),
         "dn_insert_blocks": (i32, [P, P, i64, P]),
+        "dn_insert_blocks_ordered": (i32, [P, P, i64, P]),
         "dn_fuse_depth": (i32, [P, P, P, P]),
         "dn_alloc_laser": (i32, [P, P, i64, P, P]),
         "dn_fuse_laser": (i32, [P, P, i64, P]),
@@ -256,9 +257,12 @@ class Volume:
         check(lib().dn_alloc_blocks(self.handle, _ptr(depth), ctypes.byref(K), tp, ctypes.byref(n)))
         return n.value
 
-    def insert_blocks(self, coords) -> int:
+    def insert_blocks(self, coords, keep_order=False) -> int:
+        """Append the new keys of coords (int32 [n][3], device): in ascending
+        order, or with keep_order in the order of their first occurrence."""
         n = ctypes.c_int32(0)
-        check(lib().dn_insert_blocks(self.handle, _ptr(coords), coords.shape[0], ctypes.byref(n)))
+        fn = lib().dn_insert_blocks_ordered if keep_order else lib().dn_insert_blocks
+        check(fn(self.handle, _ptr(coords), coords.shape[0], ctypes.byref(n)))
         return n.value
 
     def fuse_depth(self, depth, K: Intrinsics, T):

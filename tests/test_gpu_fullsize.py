@@ -66,19 +66,26 @@ def test_street_map_regularised_properties_and_copy_parity(street):
     assert np.sqrt((p.astype(np.float64) ** 2).sum(0)).max() <= 1.0 + 1e-6
     assert (u[w == 0] == 0).all()
     assert st.gap >= 0 and st.iters_run == 500 and npts > 0
-    # copy 0 against the oracle on the single street (same f, w, same order)
+    # copy 0 against the oracle on the single street (same f, w); the
+    # oracle holds the blocks in ascending (x, y, z), the map in the
+    # street's allocation order: compare through the permutation
     f1 = host(big.extract(D.DN_X_F)).reshape(k, nb1, 512)[0].astype(np.float64)
     c1 = host(big.extract(D.DN_X_COORDS)).reshape(k, nb1, 3)[0]
     ov = oracle.OracleVolume(0.2, 0.6, 50.0, nb1, 16, 1024)
     assert ov.insert(c1) == nb1
-    np.testing.assert_array_equal(ov.coords, c1)
-    uo = np.zeros_like(f1); ubo = np.zeros_like(uo); po = np.zeros((3,) + uo.shape)
-    oracle.cp(ov.nbr, f1, w[0].astype(np.float64), uo, ubo, po, 500, LAM, TAU, SIG, 1.0)
-    err = np.abs(u[0] - uo).max()
+    at = {tuple(c): i for i, c in enumerate(ov.coords.tolist())}
+    perm = np.array([at[tuple(c)] for c in c1.tolist()])     # oracle block of map block i
+    np.testing.assert_array_equal(ov.coords[perm], c1)
+    fo = np.empty_like(f1); fo[perm] = f1
+    wo = np.empty_like(fo); wo[perm] = w[0].astype(np.float64)
+    uo = np.zeros_like(fo); ubo = np.zeros_like(uo); po = np.zeros((3,) + uo.shape)
+    oracle.cp(ov.nbr, fo, wo, uo, ubo, po, 500, LAM, TAU, SIG, 1.0)
+    err = np.abs(u[0] - uo[perm]).max()
     print(f"street copy 0 vs oracle after 500 iterations: max |du| = {err:.3e}")
     assert err <= 1e-4
-    E1, D1 = oracle.energy(ov.nbr, f1, w[0].astype(np.float64), u[0].astype(np.float64),
-                           p[:, 0].astype(np.float64), LAM)
+    ug = np.empty_like(fo); ug[perm] = u[0].astype(np.float64)
+    pg = np.empty_like(po); pg[:, perm] = p[:, 0].astype(np.float64)
+    E1, D1 = oracle.energy(ov.nbr, fo, wo, ug, pg, LAM)
     assert abs(st.energy - k * E1) <= 1e-9 * abs(k * E1)
     assert abs(st.dual - k * D1) <= 1e-9 * abs(k * E1)
 

@@ -405,3 +405,47 @@ def test_non_finite_data_is_a_numeric_error():
     with pytest.raises(D.DenserError) as e:
         gv.regularize(D.reg_params(LAM, iters=5, kernel=D.DN_K_FUSED))
     assert e.value.code == D.DN_E_NUMERIC
+
+
+def test_ordered_insertion_keeps_first_occurrence_order():
+    """dn_insert_blocks_ordered appends the new keys in the order of their
+    first occurrence (repeats and keys already present ignored); the block
+    set, the hash lookups and the neighbour table are those of the
+    ascending insertion of the same keys, up to the permutation."""
+    D = dn()
+    rng = np.random.default_rng(5)
+    keys = rng.integers(-6, 6, size=(900, 3)).astype(np.int32)   # 12^3 cells: repeats certain
+    pre = keys[::7][:40].copy()
+    vols = []
+    for keep in (True, False):
+        v = D.Volume(0.1, 0.3, 10.0, 4096, 13, 1024, max_points=0)
+        n0 = v.insert_blocks(to_dev(pre))
+        n1 = v.insert_blocks(to_dev(keys), keep_order=keep)
+        vols.append((v, n0, n1))
+    (va, a0, a1), (vb, b0, b1) = vols
+    seen = set(map(tuple, pre.tolist()))
+    expect = []
+    for k in map(tuple, keys.tolist()):
+        if k not in seen:
+            seen.add(k)
+            expect.append(k)
+    assert a0 == b0 == len(set(map(tuple, pre.tolist())))
+    assert a1 == b1 == len(expect)
+    ca = host(va.extract(D.DN_X_COORDS))
+    cb = host(vb.extract(D.DN_X_COORDS))
+    np.testing.assert_array_equal(ca[:a0], cb[:b0])                     # the earlier blocks stay put
+    np.testing.assert_array_equal(ca[a0:], np.array(expect, np.int32))  # new ones in first-occurrence order
+    assert sorted(map(tuple, ca.tolist())) == sorted(map(tuple, cb.tolist()))
+    # neighbour tables: the same neighbour coordinates (or none) per block
+    na = host(va.extract(D.DN_X_NBR))
+    nb = host(vb.extract(D.DN_X_NBR))
+    ib = {tuple(c): i for i, c in enumerate(cb.tolist())}
+    for i, c in enumerate(ca.tolist()):
+        j = ib[tuple(c)]
+        for o in range(27):
+            x, y = na[i, o], nb[j, o]
+            assert (x < 0) == (y < 0)
+            if x >= 0:
+                assert tuple(ca[x]) == tuple(cb[y])
+    # a second ordered call with only known keys adds nothing
+    assert va.insert_blocks(to_dev(keys[::-1].copy()), keep_order=True) == 0
