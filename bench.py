@@ -184,14 +184,12 @@ class Workload:
 class BatchedWorkload(Workload):
     """64 sub-maps with block counts drawn log-uniform in [1e3, 5e4]; each is
     a street segment: the n_i blocks nearest the start of a row of
-    translated copies of the fused street.  A segment is built the way
-    fusion builds a map: its blocks are allocated in the order the fused
-    street allocated them (copy after copy), ALLOC_BATCH at a time, about
-    one frame's worth, so its block pool holds them in allocation order.
-    All regularised together for 300 iterations in one HIP graph (the
-    persistent kernel or one launch per iteration, autotuned)."""
-
-    ALLOC_BATCH = 64
+    translated copies of the fused street.  A segment's blocks are
+    allocated in the order the fused street allocated them (copy after
+    copy; one order-keeping insertion), so its block pool holds them in
+    allocation order, as a map built by fusion does.  All regularised
+    together for 300 iterations in one HIP graph (the persistent kernel or
+    one launch per iteration, autotuned)."""
 
     def __init__(self, args, base=None):
         if base is None:
@@ -222,10 +220,6 @@ class BatchedWorkload(Workload):
         w = self.street.extract(D.DN_X_W)
         zlen = int((c[:, 2].max() - c[:, 2].min()).item()) + 3
         off = 1 << 20
-
-        def xyz_key(q):
-            return ((q[:, 0] + off) << 42) | ((q[:, 1] + off) << 21) | (q[:, 2] + off)
-
         self.parts = []
         for vol, n in zip(self.subs, self.counts):
             reps = int(np.ceil(n / c.shape[0]))
@@ -236,16 +230,9 @@ class BatchedWorkload(Workload):
             # taken in allocation order (copy, then the street's pool order)
             key = ((cc[:, 2] + off) << 42) | ((cc[:, 0] + off) << 21) | (cc[:, 1] + off)
             sel = torch.sort(torch.argsort(key)[: int(n)]).values
-            cs = cc[sel].to(torch.int32).contiguous()
             vol.clear()
-            for i in range(0, cs.shape[0], self.ALLOC_BATCH):
-                vol.insert_blocks(cs[i:i + self.ALLOC_BATCH].contiguous())
-            # f, w in the order the pool holds the blocks
-            got = vol.extract(D.DN_X_COORDS).long()
-            ks, ki = torch.sort(xyz_key(cs.long()))
-            pos = torch.searchsorted(ks, xyz_key(got))
-            assert bool((ks[pos] == xyz_key(got)).all())
-            src = sel[ki[pos]] % c.shape[0]
+            vol.insert_blocks(cc[sel].to(torch.int32).contiguous(), keep_order=True)
+            src = sel % c.shape[0]
             self.parts.append((f[src].contiguous(), w[src].contiguous()))
 
     def step(self):
