@@ -449,3 +449,15 @@ def test_ordered_insertion_keeps_first_occurrence_order():
                 assert tuple(ca[x]) == tuple(cb[y])
     # a second ordered call with only known keys adds nothing
     assert va.insert_blocks(to_dev(keys[::-1].copy()), keep_order=True) == 0
+    # a full pool leaves the volume unchanged; an empty list adds nothing
+    small = D.Volume(0.1, 0.3, 10.0, 16, 8, 64, max_points=0, max_candidates=256)
+    with pytest.raises(D.DenserError) as e:
+        small.insert_blocks(to_dev(keys[:200].copy()), keep_order=True)
+    assert e.value.code == D.DN_E_CAPACITY and small.num_blocks == 0
+    assert small.insert_blocks(to_dev(np.zeros((0, 3), np.int32)), keep_order=True) == 0
+    first = []
+    for k in map(tuple, keys[:12].tolist()):
+        if k not in first:
+            first.append(k)
+    assert small.insert_blocks(to_dev(keys[:12].copy()), keep_order=True) == len(first)
+    np.testing.assert_array_equal(host(small.extract(D.DN_X_COORDS)), np.array(first, np.int32))
