@@ -1,4 +1,4 @@
-// Many sub-maps in one launch (gfx950).
+// Many sub-maps in one HIP graph (gfx950).
 //
 // All (sub-map, block) work items of every volume run in one kernel that
 // loops over the iterations itself; a grid-wide barrier separates one
@@ -585,10 +585,10 @@ extern "C" int dn_regularize_batch(dn_volume *const *vols, int32_t n, const dn_r
     if (prm->kernel == DN_K_FUSED256) ch = TuneChoice{kStepKernel, 1, 1, 1};
     const int64_t key = (int64_t(v0->device) << 32) | size_bucket(total);
     auto it = g_tuned.find(key);
-    if (prm->kernel != DN_K_AUTO) {
-    } else if (it != g_tuned.end()) {
+    const bool tuned = prm->kernel == DN_K_AUTO;
+    if (tuned && it != g_tuned.end()) {
         ch = it->second;
-    } else if (prm->init == DN_INIT_ZERO && total > 0 && prm->iters > 0) {
+    } else if (tuned && prm->init == DN_INIT_ZERO && total > 0 && prm->iters > 0) {
         // autotune: a few iterations of each candidate, from the zero state
         hipEvent_t e0, e1;
         DN_HIP(hipEventCreate(&e0));
